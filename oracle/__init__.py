@@ -1,0 +1,8 @@
+"""Exact CPU oracle (test infrastructure only).
+
+Loaded by the tests, the smoke check and the benchmark's CPU-baseline leg;
+the product library never imports it.  See ``oracle.cpp`` for what it
+computes and why it is exact.
+"""
+from .oracle import (build, join, tri_tri, orient3d, OracleError,  # noqa: F401
+                     ORACLE_E_DEGENERATE)

@@ -1,0 +1,428 @@
+// Exact CPU oracle for the closed-set mesh-pair intersection predicate.
+//
+// TEST INFRASTRUCTURE ONLY.  This file is the slow, obviously correct
+// reference that the HIP library is checked against.  Only the tests, the
+// smoke check and the CPU-baseline leg of the benchmark load it; the
+// library shares no code, header, table or helper with it.
+//
+// What is computed (the join's refinement predicate, Section 3.2 "Overlap
+// Join" read with closed sets): a candidate pair (A_i, B_j) of closed
+// triangle meshes is TRUE iff some closed triangle t of A_i and some closed
+// triangle u of B_j share a point.  Vertices are the exact real values of
+// the stored FP32 coordinates.  Touching counts (vertex-vertex, vertex on
+// face, edge-edge, coplanar contact); a mesh nested inside another without
+// contact is FALSE (containment is a separate predicate, Section 3.3).
+//
+// How: triangle-triangle intersection by the separating axis theorem,
+// evaluated in exact integer arithmetic.
+//  * Each FP32 value is m * 2^e with |m| < 2^24.  Within one test all values
+//    are scaled by 2^-emin (emin = smallest exponent present), which turns
+//    them into exact integers; every quantity compared below is a
+//    homogeneous polynomial of the same degree, so signs are unchanged.
+//  * Two compact convex sets are disjoint iff a plane separates them
+//    strictly.  For two non-degenerate triangles, the normal of such a plane
+//    can be taken among 17 candidates: the two face normals n_t, n_u, the
+//    nine cross products e_t x e_u of their edges, and the six in-plane edge
+//    normals n_t x e_t, n_u x e_u (these are the facet normals of the
+//    Minkowski difference t - u, whether or not the triangles are coplanar).
+//    The three coordinate axes are valid candidates too and are tried first
+//    as a cheap exact rejection.
+//  * An axis L separates iff max(L.t) < min(L.u) or max(L.u) < min(L.t).
+//    Degree of the compared polynomials: <= 4 in the coordinates.
+//  * Mesh pair: brute force over all triangle pairs (mode 0), or the same
+//    pairs restricted by exact closed-box sweep-and-prune (mode 1; sound
+//    because disjoint boxes imply disjoint triangles).  Stops at the first
+//    intersecting couple.
+// Degenerate triangles (exactly collinear vertices) are rejected with
+// ORACLE_E_DEGENERATE: the paper leaves them to preprocessing (Section 3.6).
+
+#include <algorithm>
+#include <atomic>
+#include <cmath>
+#include <cstdint>
+#include <cstring>
+#include <thread>
+#include <vector>
+
+enum { ORACLE_OK = 0, ORACLE_E_ARG = -1, ORACLE_E_DEGENERATE = -3, ORACLE_E_OVERFLOW = -6 };
+
+namespace {
+
+constexpr int LIMBS = 20;  // 1280 bits: enough for any finite FP32 input
+
+struct Big {
+  int n;       // used limbs of the magnitude (0 <=> zero)
+  bool neg;    // sign (false for zero)
+  uint64_t d[LIMBS];
+};
+
+thread_local bool g_overflow = false;  // set if a value would not fit (never expected)
+
+inline void big_norm(Big& r) {
+  while (r.n > 0 && r.d[r.n - 1] == 0) --r.n;
+  if (r.n == 0) r.neg = false;
+}
+
+inline Big big_zero() {
+  Big r;
+  r.n = 0; r.neg = false;
+  std::memset(r.d, 0, sizeof r.d);
+  return r;
+}
+
+// value = (neg ? -1 : 1) * mag * 2^shift
+Big big_from(uint64_t mag, bool neg, int shift) {
+  Big r = big_zero();
+  if (mag == 0) return r;
+  int q = shift / 64, s = shift % 64;
+  if (q + 1 >= LIMBS) { g_overflow = true; return r; }
+  r.d[q] = mag << s;
+  if (s) r.d[q + 1] = mag >> (64 - s);
+  r.n = q + 2;
+  r.neg = neg;
+  big_norm(r);
+  return r;
+}
+
+int mag_cmp(const Big& a, const Big& b) {
+  if (a.n != b.n) return a.n < b.n ? -1 : 1;
+  for (int i = a.n - 1; i >= 0; --i)
+    if (a.d[i] != b.d[i]) return a.d[i] < b.d[i] ? -1 : 1;
+  return 0;
+}
+
+Big mag_add(const Big& a, const Big& b) {
+  Big r = big_zero();
+  int n = std::max(a.n, b.n);
+  unsigned __int128 carry = 0;
+  for (int i = 0; i < n; ++i) {
+    unsigned __int128 t = (unsigned __int128)a.d[i] + b.d[i] + carry;
+    r.d[i] = (uint64_t)t;
+    carry = t >> 64;
+  }
+  if (carry) {
+    if (n >= LIMBS) { g_overflow = true; return r; }
+    r.d[n++] = (uint64_t)carry;
+  }
+  r.n = n;
+  big_norm(r);
+  return r;
+}
+
+// |a| - |b|, requires |a| >= |b|
+Big mag_sub(const Big& a, const Big& b) {
+  Big r = big_zero();
+  uint64_t borrow = 0;
+  for (int i = 0; i < a.n; ++i) {
+    uint64_t bi = b.d[i];
+    uint64_t t = a.d[i] - bi - borrow;
+    borrow = (a.d[i] < bi || (a.d[i] - bi) < borrow) ? 1 : 0;
+    r.d[i] = t;
+  }
+  r.n = a.n;
+  big_norm(r);
+  return r;
+}
+
+Big add(const Big& a, const Big& b) {
+  if (a.n == 0) return b;
+  if (b.n == 0) return a;
+  if (a.neg == b.neg) {
+    Big r = mag_add(a, b);
+    r.neg = r.n ? a.neg : false;
+    return r;
+  }
+  int c = mag_cmp(a, b);
+  if (c == 0) return big_zero();
+  if (c > 0) { Big r = mag_sub(a, b); r.neg = r.n ? a.neg : false; return r; }
+  Big r = mag_sub(b, a); r.neg = r.n ? b.neg : false; return r;
+}
+
+Big negate(Big a) { if (a.n) a.neg = !a.neg; return a; }
+Big sub(const Big& a, const Big& b) { return add(a, negate(b)); }
+
+Big mul(const Big& a, const Big& b) {
+  Big r = big_zero();
+  if (a.n == 0 || b.n == 0) return r;
+  if (a.n + b.n > LIMBS) { g_overflow = true; return r; }
+  for (int i = 0; i < a.n; ++i) {
+    unsigned __int128 carry = 0;
+    for (int j = 0; j < b.n; ++j) {
+      unsigned __int128 t = (unsigned __int128)a.d[i] * b.d[j] + r.d[i + j] + carry;
+      r.d[i + j] = (uint64_t)t;
+      carry = t >> 64;
+    }
+    r.d[i + b.n] = (uint64_t)carry;
+  }
+  r.n = a.n + b.n;
+  r.neg = a.neg != b.neg;
+  big_norm(r);
+  return r;
+}
+
+inline int sgn(const Big& a) { return a.n == 0 ? 0 : (a.neg ? -1 : 1); }
+inline int cmp(const Big& a, const Big& b) { return sgn(sub(a, b)); }
+
+// ---- exact scaling of FP32 values ---------------------------------------
+
+struct Dy { uint64_t m; bool neg; int e; };  // value = (neg?-1:1) * m * 2^e
+
+Dy decompose(float x) {
+  Dy r{0, false, 0};
+  if (x == 0.0f) return r;
+  int e;
+  float f = std::frexp(x, &e);             // x = f * 2^e, 0.5 <= |f| < 1
+  double m = std::ldexp((double)std::fabs(f), 24);  // exact: 24-bit integer
+  r.m = (uint64_t)m;
+  r.neg = x < 0;
+  r.e = e - 24;
+  return r;
+}
+
+struct V3 { Big x, y, z; };
+
+V3 vsub(const V3& a, const V3& b) { return {sub(a.x, b.x), sub(a.y, b.y), sub(a.z, b.z)}; }
+V3 cross(const V3& a, const V3& b) {
+  return {sub(mul(a.y, b.z), mul(a.z, b.y)),
+          sub(mul(a.z, b.x), mul(a.x, b.z)),
+          sub(mul(a.x, b.y), mul(a.y, b.x))};
+}
+Big dot(const V3& a, const V3& b) { return add(add(mul(a.x, b.x), mul(a.y, b.y)), mul(a.z, b.z)); }
+bool is_zero(const V3& a) { return a.x.n == 0 && a.y.n == 0 && a.z.n == 0; }
+
+// Scale n points (3 floats each) to exact integers sharing one exponent.
+void to_ints(const float* const* pts, int n, V3* out) {
+  Dy dy[64];
+  int emin = 1 << 20;
+  for (int i = 0; i < n; ++i)
+    for (int k = 0; k < 3; ++k) {
+      dy[3 * i + k] = decompose(pts[i][k]);
+      if (dy[3 * i + k].m) emin = std::min(emin, dy[3 * i + k].e);
+    }
+  for (int i = 0; i < n; ++i) {
+    Big c[3];
+    for (int k = 0; k < 3; ++k) {
+      const Dy& q = dy[3 * i + k];
+      c[k] = q.m ? big_from(q.m, q.neg, q.e - emin) : big_zero();
+    }
+    out[i] = {c[0], c[1], c[2]};
+  }
+}
+
+// Separating-axis test on one axis; pts relative to a common origin.
+bool separates(const V3& L, const V3* T, const V3* U) {
+  Big pt[3], pu[3];
+  for (int i = 0; i < 3; ++i) { pt[i] = dot(L, T[i]); pu[i] = dot(L, U[i]); }
+  auto mx = [](Big* p) { Big m = p[0]; for (int i = 1; i < 3; ++i) if (cmp(p[i], m) > 0) m = p[i]; return m; };
+  auto mn = [](Big* p) { Big m = p[0]; for (int i = 1; i < 3; ++i) if (cmp(p[i], m) < 0) m = p[i]; return m; };
+  if (cmp(mx(pt), mn(pu)) < 0) return true;
+  if (cmp(mx(pu), mn(pt)) < 0) return true;
+  return false;
+}
+
+std::atomic<uint64_t> g_tests{0};
+
+// 1 = closed triangles share a point, 0 = disjoint, -3 = degenerate input
+int tri_tri(const float* t, const float* u) {
+  // coordinate axes first: exact float comparisons
+  for (int k = 0; k < 3; ++k) {
+    float t0 = std::min(std::min(t[k], t[3 + k]), t[6 + k]);
+    float t1 = std::max(std::max(t[k], t[3 + k]), t[6 + k]);
+    float u0 = std::min(std::min(u[k], u[3 + k]), u[6 + k]);
+    float u1 = std::max(std::max(u[k], u[3 + k]), u[6 + k]);
+    if (t1 < u0 || u1 < t0) return 0;
+  }
+  const float* pts[6] = {t, t + 3, t + 6, u, u + 3, u + 6};
+  V3 X[6];
+  to_ints(pts, 6, X);
+  V3 T[3], U[3];
+  for (int i = 0; i < 3; ++i) { T[i] = vsub(X[i], X[0]); U[i] = vsub(X[3 + i], X[0]); }
+  V3 et[3] = {vsub(T[1], T[0]), vsub(T[2], T[1]), vsub(T[0], T[2])};
+  V3 eu[3] = {vsub(U[1], U[0]), vsub(U[2], U[1]), vsub(U[0], U[2])};
+  V3 nt = cross(et[0], vsub(T[2], T[0]));
+  V3 nu = cross(eu[0], vsub(U[2], U[0]));
+  if (is_zero(nt) || is_zero(nu)) return -3;
+  g_tests.fetch_add(1, std::memory_order_relaxed);
+  if (separates(nt, T, U)) return 0;
+  if (separates(nu, T, U)) return 0;
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j) {
+      V3 L = cross(et[i], eu[j]);
+      if (!is_zero(L) && separates(L, T, U)) return 0;
+    }
+  for (int i = 0; i < 3; ++i) {
+    V3 L = cross(nt, et[i]);
+    if (separates(L, T, U)) return 0;
+    L = cross(nu, eu[i]);
+    if (separates(L, T, U)) return 0;
+  }
+  return 1;
+}
+
+// ---- orientation signs (exported for predicate pins) ----------------------
+
+int orient3d_sign(const float* a, const float* b, const float* c, const float* d) {
+  const float* pts[4] = {a, b, c, d};
+  V3 X[4];
+  to_ints(pts, 4, X);
+  return sgn(dot(cross(vsub(X[1], X[0]), vsub(X[2], X[0])), vsub(X[3], X[0])));
+}
+
+// ---- mesh level ---------------------------------------------------------
+
+struct MeshView {
+  const float* v; const int32_t* f; int64_t nv, nf;
+};
+
+struct TriBox { float lo[3], hi[3]; int32_t id; };
+
+void tri_pts(const MeshView& m, int64_t i, float* out9) {
+  for (int k = 0; k < 3; ++k) {
+    int32_t vi = m.f[3 * i + k];
+    for (int c = 0; c < 3; ++c) out9[3 * k + c] = m.v[3 * vi + c];
+  }
+}
+
+TriBox tri_box(const MeshView& m, int64_t i) {
+  float p[9];
+  tri_pts(m, i, p);
+  TriBox b;
+  for (int c = 0; c < 3; ++c) {
+    b.lo[c] = std::min(std::min(p[c], p[3 + c]), p[6 + c]);
+    b.hi[c] = std::max(std::max(p[c], p[3 + c]), p[6 + c]);
+  }
+  b.id = (int32_t)i;
+  return b;
+}
+
+bool boxes_meet(const float* alo, const float* ahi, const float* blo, const float* bhi) {
+  for (int c = 0; c < 3; ++c)
+    if (ahi[c] < blo[c] || bhi[c] < alo[c]) return false;
+  return true;
+}
+
+bool mesh_valid(const MeshView& m) {
+  for (int64_t i = 0; i < 3 * m.nf; ++i)
+    if (m.f[i] < 0 || m.f[i] >= m.nv) return false;
+  for (int64_t i = 0; i < 3 * m.nv; ++i)
+    if (!std::isfinite(m.v[i])) return false;
+  return true;
+}
+
+// returns 1 / 0, or -3 on a degenerate triangle
+int pair_brute(const MeshView& A, const MeshView& B) {
+  float t[9], u[9];
+  for (int64_t i = 0; i < A.nf; ++i) {
+    tri_pts(A, i, t);
+    for (int64_t j = 0; j < B.nf; ++j) {
+      tri_pts(B, j, u);
+      int r = tri_tri(t, u);
+      if (r != 0) return r;
+    }
+  }
+  return 0;
+}
+
+int pair_pruned(const MeshView& A, const MeshView& B) {
+  std::vector<TriBox> ba(A.nf), bb(B.nf);
+  float alo[3] = {INFINITY, INFINITY, INFINITY}, ahi[3] = {-INFINITY, -INFINITY, -INFINITY};
+  float blo[3] = {INFINITY, INFINITY, INFINITY}, bhi[3] = {-INFINITY, -INFINITY, -INFINITY};
+  for (int64_t i = 0; i < A.nf; ++i) {
+    ba[i] = tri_box(A, i);
+    for (int c = 0; c < 3; ++c) { alo[c] = std::min(alo[c], ba[i].lo[c]); ahi[c] = std::max(ahi[c], ba[i].hi[c]); }
+  }
+  for (int64_t j = 0; j < B.nf; ++j) {
+    bb[j] = tri_box(B, j);
+    for (int c = 0; c < 3; ++c) { blo[c] = std::min(blo[c], bb[j].lo[c]); bhi[c] = std::max(bhi[c], bb[j].hi[c]); }
+  }
+  if (A.nf == 0 || B.nf == 0 || !boxes_meet(alo, ahi, blo, bhi)) return 0;
+  std::vector<TriBox> sa, sb;
+  for (auto& b : ba) if (boxes_meet(b.lo, b.hi, blo, bhi)) sa.push_back(b);
+  for (auto& b : bb) if (boxes_meet(b.lo, b.hi, alo, ahi)) sb.push_back(b);
+  auto by_x = [](const TriBox& p, const TriBox& q) { return p.lo[0] < q.lo[0] || (p.lo[0] == q.lo[0] && p.id < q.id); };
+  std::sort(sa.begin(), sa.end(), by_x);
+  std::sort(sb.begin(), sb.end(), by_x);
+  float t[9], u[9];
+  size_t i = 0, j = 0;
+  while (i < sa.size() && j < sb.size()) {
+    if (sa[i].lo[0] <= sb[j].lo[0]) {
+      const TriBox& a = sa[i];
+      for (size_t k = j; k < sb.size() && sb[k].lo[0] <= a.hi[0]; ++k) {
+        if (!boxes_meet(a.lo, a.hi, sb[k].lo, sb[k].hi)) continue;
+        tri_pts(A, a.id, t); tri_pts(B, sb[k].id, u);
+        int r = tri_tri(t, u);
+        if (r != 0) return r;
+      }
+      ++i;
+    } else {
+      const TriBox& b = sb[j];
+      for (size_t k = i; k < sa.size() && sa[k].lo[0] <= b.hi[0]; ++k) {
+        if (!boxes_meet(b.lo, b.hi, sa[k].lo, sa[k].hi)) continue;
+        tri_pts(A, sa[k].id, t); tri_pts(B, b.id, u);
+        int r = tri_tri(t, u);
+        if (r != 0) return r;
+      }
+      ++j;
+    }
+  }
+  return 0;
+}
+
+MeshView view(const float* v, const int32_t* f, const int64_t* vo, const int64_t* fo, int64_t m) {
+  return {v + 3 * vo[m], f + 3 * fo[m], vo[m + 1] - vo[m], fo[m + 1] - fo[m]};
+}
+
+}  // namespace
+
+extern "C" {
+
+int oracle_tri_tri(const float* t9, const float* u9) {
+  g_overflow = false;
+  int r = tri_tri(t9, u9);
+  return g_overflow ? ORACLE_E_OVERFLOW : r;
+}
+
+int oracle_orient3d(const float* a, const float* b, const float* c, const float* d) {
+  g_overflow = false;
+  int r = orient3d_sign(a, b, c, d);
+  return g_overflow ? ORACLE_E_OVERFLOW : r;
+}
+
+// flags[p] = 1 iff meshes A[pairs[p][0]] and B[pairs[p][1]] share a point.
+// mode 0: all triangle pairs; mode 1: exact box sweep-and-prune first.
+// Returns 0, or a negative code; *n_tests receives the exact triangle tests run.
+int oracle_join(const float* va, const int32_t* fa, const int64_t* voa, const int64_t* foa, int64_t ma,
+                const float* vb, const int32_t* fb, const int64_t* vob, const int64_t* fob, int64_t mb,
+                const int32_t* pairs, int64_t n_pairs, uint8_t* flags, int mode, int n_threads,
+                uint64_t* n_tests) {
+  if (n_pairs < 0 || (n_pairs > 0 && (!pairs || !flags)) || ma < 0 || mb < 0) return ORACLE_E_ARG;
+  for (int64_t p = 0; p < n_pairs; ++p)
+    if (pairs[2 * p] < 0 || pairs[2 * p] >= ma || pairs[2 * p + 1] < 0 || pairs[2 * p + 1] >= mb)
+      return ORACLE_E_ARG;
+  for (int64_t m = 0; m < ma; ++m) if (!mesh_valid(view(va, fa, voa, foa, m))) return ORACLE_E_ARG;
+  for (int64_t m = 0; m < mb; ++m) if (!mesh_valid(view(vb, fb, vob, fob, m))) return ORACLE_E_ARG;
+  g_tests.store(0);
+  std::atomic<int64_t> next{0};
+  std::atomic<int> status{0};
+  auto worker = [&]() {
+    for (;;) {
+      int64_t p = next.fetch_add(1);
+      if (p >= n_pairs) break;
+      MeshView A = view(va, fa, voa, foa, pairs[2 * p]);
+      MeshView B = view(vb, fb, vob, fob, pairs[2 * p + 1]);
+      g_overflow = false;
+      int r = mode == 0 ? pair_brute(A, B) : pair_pruned(A, B);
+      if (g_overflow) r = ORACLE_E_OVERFLOW;
+      if (r < 0) { status.store(r); flags[p] = 0; }
+      else flags[p] = (uint8_t)r;
+    }
+  };
+  int nt = n_threads > 0 ? n_threads : (int)std::max(1u, std::thread::hardware_concurrency());
+  std::vector<std::thread> pool;
+  for (int i = 0; i < nt; ++i) pool.emplace_back(worker);
+  for (auto& th : pool) th.join();
+  if (n_tests) *n_tests = g_tests.load();
+  return status.load();
+}
+
+}  // extern "C"

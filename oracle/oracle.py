@@ -1,0 +1,116 @@
+"""ctypes front end of the exact CPU oracle (test infrastructure only).
+
+The oracle decides, for each candidate pair of closed triangle meshes,
+whether the two surfaces share a point (Section 3.2 "Overlap Join", read
+with closed sets; see oracle.cpp).  It shares no code with the HIP library.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+import threading
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "oracle.cpp")
+_SO = os.path.join(_HERE, "_oracle.so")
+_lock = threading.Lock()
+_lib = None
+
+ORACLE_E_ARG = -1
+ORACLE_E_DEGENERATE = -3
+ORACLE_E_OVERFLOW = -6
+
+
+class OracleError(RuntimeError):
+    pass
+
+
+def build(force: bool = True) -> str:
+    """Compile oracle.cpp into _oracle.so with g++ (host code only)."""
+    if force or not os.path.exists(_SO) or os.path.getmtime(_SO) < os.path.getmtime(_SRC):
+        tmp = _SO + ".tmp%d" % os.getpid()
+        subprocess.check_call(["g++", "-O2", "-std=c++17", "-shared", "-fPIC", "-pthread",
+                               _SRC, "-o", tmp])
+        os.replace(tmp, _SO)
+    return _SO
+
+
+def _load():
+    global _lib
+    with _lock:
+        if _lib is None:
+            if not os.path.exists(_SO) or os.path.getmtime(_SO) < os.path.getmtime(_SRC):
+                build(force=True)
+            lib = ctypes.CDLL(_SO)
+            fp = ctypes.POINTER(ctypes.c_float)
+            ip = ctypes.POINTER(ctypes.c_int32)
+            lp = ctypes.POINTER(ctypes.c_int64)
+            lib.oracle_tri_tri.argtypes = [fp, fp]
+            lib.oracle_tri_tri.restype = ctypes.c_int
+            lib.oracle_orient3d.argtypes = [fp, fp, fp, fp]
+            lib.oracle_orient3d.restype = ctypes.c_int
+            lib.oracle_join.argtypes = [fp, ip, lp, lp, ctypes.c_int64,
+                                        fp, ip, lp, lp, ctypes.c_int64,
+                                        ip, ctypes.c_int64, ctypes.POINTER(ctypes.c_uint8),
+                                        ctypes.c_int, ctypes.c_int,
+                                        ctypes.POINTER(ctypes.c_uint64)]
+            lib.oracle_join.restype = ctypes.c_int
+            _lib = lib
+    return _lib
+
+
+def _ptr(a: np.ndarray, ct):
+    return a.ctypes.data_as(ctypes.POINTER(ct))
+
+
+def tri_tri(t, u) -> bool:
+    """Exact closed triangle-triangle intersection of two FP32 triangles
+    (each 3x3: rows are vertices)."""
+    t = np.ascontiguousarray(np.asarray(t, np.float32).reshape(9))
+    u = np.ascontiguousarray(np.asarray(u, np.float32).reshape(9))
+    r = _load().oracle_tri_tri(_ptr(t, ctypes.c_float), _ptr(u, ctypes.c_float))
+    if r < 0:
+        raise OracleError("oracle_tri_tri failed with code %d" % r)
+    return bool(r)
+
+
+def orient3d(a, b, c, d) -> int:
+    """Exact sign of det[b-a, c-a, d-a] for FP32 points."""
+    arrs = [np.ascontiguousarray(np.asarray(x, np.float32).reshape(3)) for x in (a, b, c, d)]
+    r = _load().oracle_orient3d(*[_ptr(x, ctypes.c_float) for x in arrs])
+    if r < -1:
+        raise OracleError("oracle_orient3d failed with code %d" % r)
+    return int(r)
+
+
+def join(A, B, pairs, mode: int = 1, threads: int = 0, return_tests: bool = False):
+    """flags u8[P]: 1 iff mesh A[i] and mesh B[j] share a point, per pair (i, j).
+
+    A, B: objects with verts f32[V,3], faces i32[F,3], vert_off i64[M+1],
+    face_off i64[M+1].  mode 0 = all triangle pairs, 1 = exact box
+    sweep-and-prune first.  threads 0 = all host cores."""
+    lib = _load()
+    pairs = np.ascontiguousarray(np.asarray(pairs, np.int32).reshape(-1, 2))
+    flags = np.zeros(pairs.shape[0], np.uint8)
+    arrs = []
+    for S in (A, B):
+        arrs.append((np.ascontiguousarray(S.verts, np.float32), np.ascontiguousarray(S.faces, np.int32),
+                     np.ascontiguousarray(S.vert_off, np.int64), np.ascontiguousarray(S.face_off, np.int64)))
+    ntests = ctypes.c_uint64(0)
+    args = []
+    for v, f, vo, fo in arrs:
+        args += [_ptr(v, ctypes.c_float), _ptr(f, ctypes.c_int32), _ptr(vo, ctypes.c_int64),
+                 _ptr(fo, ctypes.c_int64), ctypes.c_int64(vo.shape[0] - 1)]
+    r = lib.oracle_join(*args, _ptr(pairs, ctypes.c_int32), ctypes.c_int64(pairs.shape[0]),
+                        _ptr(flags, ctypes.c_uint8), ctypes.c_int(mode), ctypes.c_int(threads),
+                        ctypes.byref(ntests))
+    if r != 0:
+        raise OracleError("oracle_join failed with code %d" % r)
+    return (flags, int(ntests.value)) if return_tests else flags
+
+
+def threads_used(threads: int = 0) -> int:
+    return threads if threads > 0 else (os.cpu_count() or 1)
