@@ -1,0 +1,201 @@
+/* pierce.h - C ABI of the MI355X mesh-join refinement library (libpierce_hip.so).
+ *
+ * The library implements the refinement step of a 3D spatial join over closed
+ * triangle meshes by the edge-as-segment reformulation of Pierce (arXiv
+ * 2609.24513): the unique edges of each mesh of a candidate pair are cast as
+ * segments against a BVH built over the other mesh's triangles (Section 3.1,
+ * Steps I and II), in both directions (Section 3.2, "Bidirectional tracing").
+ * Decisions use closed sets on the exact values of the FP32 coordinates, so a
+ * pair is TRUE iff the two triangulated surfaces share at least one point
+ * (touching counts); this equals an exact triangle-triangle test over all
+ * triangle pairs.
+ *
+ * Conventions shared by every entry point:
+ *  - Pointers documented "dev" are device pointers (HIP global memory) owned
+ *    by the caller; "host" pointers are ordinary host memory.  The library
+ *    never allocates or frees memory in these calls and keeps no state
+ *    between calls; scratch space comes from the caller's workspace `ws`.
+ *  - Work is enqueued on `stream` (a hipStream_t passed as void*); nothing
+ *    synchronises the host.  Results are valid once the stream has reached
+ *    the end of the call.
+ *  - Return value: PR_OK (0) or a negative PR_E_* code.  Argument errors that
+ *    the host can see are reported before any work is enqueued (PR_E_ARG,
+ *    PR_E_CAPACITY for a too-small workspace or blob).  A HIP runtime failure
+ *    returns PR_E_DEVICE.  pr_last_error() gives a message for the calling
+ *    thread's last failure.
+ *  - Errors found on the device (bad geometry) are written to a caller-owned
+ *    device status word, read by the caller after synchronising.
+ *  - Calls are reentrant; blobs are immutable after their build and may be
+ *    read by several concurrent calls on different streams.
+ */
+#ifndef PIERCE_H
+#define PIERCE_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define PR_ABI_VERSION 1
+
+enum {
+  PR_OK = 0,
+  PR_E_ARG = -1,        /* invalid argument (null pointer, negative size, bad params) */
+  PR_E_CAPACITY = -2,   /* blob or workspace smaller than the size query returned */
+  PR_E_GEOMETRY = -3,   /* device status: non-finite coordinate, bad face id, degenerate triangle */
+  PR_E_DEVICE = -4,     /* HIP runtime error; pr_last_error() has hipGetErrorString */
+  PR_E_UNSUPPORTED = -5 /* size beyond the library's index ranges, or blob/params mismatch */
+};
+
+/* Message describing the calling thread's most recent failure ("" if none). */
+const char* pr_last_error(void);
+
+/* PR_ABI_VERSION of the loaded library. */
+int pr_abi_version(void);
+
+/* ------------------------------------------------------------------------ */
+/* BVH build (Section 3.1 Step I edge preparation; Section 2 BVH; the build
+ * replaces the paper's per-dataset acceleration-structure build, Section 4.1).
+ *
+ * One blob holds, for every mesh of a dataset: its exact box, a width-W BVH
+ * (W in {2,4,8}) over its triangles with at most `leaf_size` (1,2,4,8)
+ * triangles per leaf, the triangles in leaf order, and its unique edges
+ * (pairs of vertex ids, deduplicated within the mesh as in Section 3.1)
+ * stored as FP32 segment endpoints in groups of 64.  The blob contains only
+ * offsets, never pointers, so it can be copied or moved as raw bytes.
+ */
+typedef struct {
+  int32_t width;      /* 2, 4 or 8 children per node */
+  int32_t leaf_size;  /* 1, 2, 4 or 8 triangles per leaf at most */
+  int32_t builder;    /* 0: LBVH (Morton order) collapsed by largest-surface-area expansion */
+  int32_t reserved;   /* must be 0 */
+} pr_bvh_params;
+
+/* Upper bounds, in bytes, of the blob and of the build workspace for a
+ * dataset of n_meshes meshes with f_total faces and v_total vertices.
+ * Returns PR_OK or PR_E_ARG / PR_E_UNSUPPORTED (f_total >= 2^28,
+ * v_total >= 2^31, n_meshes >= 2^24) / PR_E_DEVICE. */
+int build_mesh_bvh_sizes(int64_t n_meshes, int64_t f_total, int64_t v_total,
+                         const pr_bvh_params* params, size_t* blob_bytes, size_t* ws_bytes);
+
+/* Builds the blob of a dataset.
+ *  verts     dev f32[v_total][3]    vertex coordinates
+ *  vert_off  dev i64[n_meshes+1]    mesh m owns verts[vert_off[m] .. vert_off[m+1])
+ *  faces     dev i32[f_total][3]    vertex ids local to the face's mesh
+ *  face_off  dev i64[n_meshes+1]    mesh m owns faces[face_off[m] .. face_off[m+1])
+ *  params    host                   see pr_bvh_params
+ *  blob      dev, blob_bytes        output; at least build_mesh_bvh_sizes' bound
+ *  ws        dev, ws_bytes          scratch; at least build_mesh_bvh_sizes' bound
+ *  dev_status dev i32[1]            out: -1 if the geometry is valid, else the
+ *                                   smallest global face index that has an id
+ *                                   out of range, a non-finite coordinate or
+ *                                   three exactly collinear vertices (the paper
+ *                                   leaves degenerate triangles to
+ *                                   preprocessing, Section 3.6).  The blob
+ *                                   must not be used when it is not -1.
+ * Offsets must be non-decreasing with vert_off[0] = face_off[0] = 0; a mesh may
+ * have zero faces (it then never intersects anything). */
+int build_mesh_bvh(const float* verts, const int64_t* vert_off, const int32_t* faces,
+                   const int64_t* face_off, int64_t n_meshes, int64_t v_total, int64_t f_total,
+                   const pr_bvh_params* params, void* blob, size_t blob_bytes, void* ws,
+                   size_t ws_bytes, int32_t* dev_status, void* stream);
+
+/* Copies the exact per-mesh boxes out of a blob:
+ * boxes dev f32[n_meshes][6] = (lo_x, lo_y, lo_z, hi_x, hi_y, hi_z). */
+int blob_mesh_boxes(const void* blob, int64_t n_meshes, float* boxes, void* stream);
+
+/* Copies each mesh's unique-edge count out of a blob: counts dev i32[n_meshes]. */
+int blob_edge_counts(const void* blob, int64_t n_meshes, int32_t* counts, void* stream);
+
+/* ------------------------------------------------------------------------ */
+/* Candidate filter (the classic filter step that the paper's single traversal
+ * fuses with refinement, Section 1 "Challenges" and Section 3 introduction).
+ *
+ * Writes every (i, j), i a mesh of blob_a and j a mesh of blob_b, whose
+ * closed boxes overlap on all three axes (touching boxes are candidates), and,
+ * when query_box is given, whose boxes both overlap the closed query box and
+ * whose common box part meets it.  Output is sorted by (i, j).
+ *  query_box dev f32[6] or NULL
+ *  pairs     dev i32[cap][2]   out: first min(total, cap) pairs
+ *  dev_count dev i64[1]        out: exact total (may exceed cap; the caller
+ *                              relaunches with a larger buffer, the paper's
+ *                              abort-and-relaunch convention of Section 3.5)
+ *  ws, ws_bytes                scratch of at least filter_aabb_pairs_ws_bytes */
+int filter_aabb_pairs_ws_bytes(int64_t n_meshes_a, int64_t n_meshes_b, size_t* ws_bytes);
+int filter_aabb_pairs(const void* blob_a, int64_t n_meshes_a, const void* blob_b,
+                      int64_t n_meshes_b, const float* query_box, int32_t* pairs, int64_t cap,
+                      int64_t* dev_count, void* ws, size_t ws_bytes, void* stream);
+
+/* ------------------------------------------------------------------------ */
+/* Refinement (Section 3.1 Steps I-II, Section 3.2 bidirectional tracing).
+ *
+ * For every candidate pair (i, j) the edges of A_i are traced as closed
+ * segments against the BVH of B_j and the edges of B_j against the BVH of
+ * A_i.  Internal nodes use a conservative segment-box test (never rejects a
+ * box the segment touches); leaves use a closed segment-triangle test whose
+ * orientation signs are filtered in FP32 with a forward error bound; signs
+ * the bound cannot certify are re-decided on the GPU in FP64 and, if still
+ * uncertain, in exact FP64 expansion arithmetic (the exact arithmetic the
+ * paper calls for on degenerate configurations, Section 3.6).  Any hit
+ * decides the pair, so the search stops early per pair.
+ */
+typedef struct {
+  int32_t bvh_width;   /* width the blobs were built with (2, 4 or 8) */
+  int32_t persistent;  /* 1: one persistent launch over all pairs (batched);
+                          0: one launch per pair (plain) */
+  int32_t precision;   /* 0: FP32 filter, uncertain tests re-decided in FP64/exact
+                          1: every leaf test decided in FP64/exact directly
+                          2: every leaf test deferred to the FP64/exact pass (test mode) */
+  int32_t queue_cap;   /* capacity of the deferred-test queue (0 = default 1<<20);
+                          tests beyond it are decided in place, in FP64/exact */
+  int32_t grid_blocks; /* persistent launch: blocks of 256 threads (0 = default) */
+  int32_t chunks_per_pop; /* persistent launch: 64-segment groups per queue pop (0 = default) */
+  int32_t reserved[2]; /* must be 0 */
+} pr_refine_params;
+
+typedef struct {
+  uint64_t segments;              /* segments started (64-segment groups picked up x live lanes) */
+  uint64_t node_visits;           /* wave-level BVH node fetches */
+  uint64_t tri_tests;             /* segment-triangle tests (per segment) */
+  uint64_t fp32_ambiguous;        /* tests the FP32 bound could not decide */
+  uint64_t fp64_filter_ambiguous; /* tests needing exact expansions after the FP64 bound */
+  uint64_t exact_decided;         /* tests decided in FP64/exact (deferred or in place) */
+  uint64_t pairs_true;            /* pairs found intersecting */
+  uint64_t queue_overflow;        /* deferred tests that did not fit in the queue */
+} pr_refine_stats;
+
+/* Workspace bytes for refine_intersects on n_pairs pairs. */
+int refine_workspace_bytes(int64_t n_pairs, const pr_refine_params* params, size_t* ws_bytes);
+
+/*  blob_a, blob_b dev   blobs from build_mesh_bvh with width params->bvh_width
+ *  n_meshes_a/b         mesh counts of the two blobs (pairs are range-checked
+ *                       on the device: an out-of-range pair yields flag 0 and
+ *                       dev_status PR_E_ARG)
+ *  pairs   dev i32[n_pairs][2]   (i in A, j in B)
+ *  flags   dev u8[n_pairs]       out: 1 iff the closed surfaces share a point
+ *  params  host
+ *  dev_stats dev pr_refine_stats or NULL (counters are overwritten)
+ *  dev_status dev i32[1] or NULL  out: PR_OK, or PR_E_ARG / PR_E_UNSUPPORTED
+ *                       when a pair index is out of range or a blob was
+ *                       built with another width (those pairs get flag 0)
+ *  ws, ws_bytes dev     scratch of at least refine_workspace_bytes */
+int refine_intersects(const void* blob_a, int64_t n_meshes_a, const void* blob_b,
+                      int64_t n_meshes_b, const int32_t* pairs, int64_t n_pairs, uint8_t* flags,
+                      const pr_refine_params* params, pr_refine_stats* dev_stats,
+                      int32_t* dev_status, void* ws, size_t ws_bytes, void* stream);
+
+/* ------------------------------------------------------------------------ */
+/* Result materialisation (Section 3.5): keeps the pairs whose flag is 1, in
+ * input order.  out dev i32[cap][2]; dev_count dev i64[1] gets the exact
+ * total even if it exceeds cap.  ws of at least compact_pairs_ws_bytes. */
+int compact_pairs_ws_bytes(int64_t n_pairs, size_t* ws_bytes);
+int compact_pairs(const int32_t* pairs, const uint8_t* flags, int64_t n_pairs, int32_t* out,
+                  int64_t cap, int64_t* dev_count, void* ws, size_t ws_bytes, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PIERCE_H */

@@ -1,0 +1,205 @@
+"""MI355X-native refinement of a 3D spatial join over closed triangle meshes.
+
+Python front end of libpierce_hip.so (see include/pierce.h).  Every step of
+the join runs in the library's HIP kernels; this module only marshals
+arguments and uses PyTorch for device memory and streams.
+
+    A = MeshBlob.build(meshset_a, width=4, leaf_size=4)
+    B = MeshBlob.build(meshset_b, width=4, leaf_size=4)
+    pairs = filter_pairs(A, B)                 # closed-box candidates, sorted
+    flags, stats = refine(A, B, pairs)         # 1 iff the surfaces share a point
+    result = compact(pairs, flags)             # intersecting pairs, sorted
+"""
+from __future__ import annotations
+
+import ctypes
+from typing import Optional, Tuple
+
+import numpy as np
+
+from . import _lib
+from ._lib import PierceError, RefineStats, STATS_FIELDS  # noqa: F401
+
+__all__ = ["MeshBlob", "filter_pairs", "refine", "compact", "refine_workspace", "PierceError",
+           "RefineConfig"]
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _stream_ptr(stream=None) -> int:
+    torch = _torch()
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return int(s.cuda_stream)
+
+
+def _dev(a, dtype):
+    torch = _torch()
+    if isinstance(a, torch.Tensor):
+        t = a.to(device="cuda", dtype=dtype)
+    else:
+        t = torch.as_tensor(np.ascontiguousarray(a)).to(device="cuda", dtype=dtype)
+    return t.contiguous()
+
+
+def _ws(nbytes: int):
+    torch = _torch()
+    return torch.empty(max(int(nbytes), 256), dtype=torch.uint8, device="cuda")
+
+
+class MeshBlob:
+    """A dataset's device-resident BVH blob (build_mesh_bvh)."""
+
+    def __init__(self, blob, n_meshes: int, width: int, leaf_size: int, status):
+        self.blob = blob
+        self.n_meshes = int(n_meshes)
+        self.width = int(width)
+        self.leaf_size = int(leaf_size)
+        self._status = status
+
+    @property
+    def ptr(self) -> int:
+        return int(self.blob.data_ptr())
+
+    @classmethod
+    def build(cls, meshes, width: int = 4, leaf_size: int = 4, stream=None, check_status: bool = True):
+        """meshes: object with verts f32[V,3], faces i32[F,3] (mesh-local ids),
+        vert_off i64[M+1], face_off i64[M+1] (numpy arrays or tensors)."""
+        torch = _torch()
+        lib = _lib.load()
+        verts = _dev(meshes.verts, torch.float32).reshape(-1, 3)
+        faces = _dev(meshes.faces, torch.int32).reshape(-1, 3)
+        vo = _dev(meshes.vert_off, torch.int64)
+        fo = _dev(meshes.face_off, torch.int64)
+        M, V, F = int(vo.numel() - 1), int(verts.shape[0]), int(faces.shape[0])
+        prm = _lib.BvhParams(width, leaf_size, 0, 0)
+        bb, wb = ctypes.c_size_t(0), ctypes.c_size_t(0)
+        _lib.check(lib.build_mesh_bvh_sizes(M, F, V, ctypes.byref(prm), ctypes.byref(bb), ctypes.byref(wb)))
+        blob = torch.empty(int(bb.value), dtype=torch.uint8, device="cuda")
+        ws = _ws(wb.value)
+        status = torch.empty(1, dtype=torch.int32, device="cuda")
+        _lib.check(lib.build_mesh_bvh(verts.data_ptr(), vo.data_ptr(), faces.data_ptr(), fo.data_ptr(),
+                                      M, V, F, ctypes.byref(prm), blob.data_ptr(), bb.value,
+                                      ws.data_ptr(), wb.value, status.data_ptr(), _stream_ptr(stream)))
+        out = cls(blob, M, width, leaf_size, status)
+        if check_status:
+            st = int(status.item())
+            if st != -1:
+                raise PierceError(_lib.PR_E_GEOMETRY, "invalid geometry at face %d" % st)
+        del ws
+        return out
+
+    def status(self) -> int:
+        return int(self._status.item())
+
+    def boxes(self, stream=None):
+        torch = _torch()
+        out = torch.empty((self.n_meshes, 6), dtype=torch.float32, device="cuda")
+        _lib.check(_lib.load().blob_mesh_boxes(self.ptr, self.n_meshes, out.data_ptr(), _stream_ptr(stream)))
+        return out
+
+    def edge_counts(self, stream=None):
+        torch = _torch()
+        out = torch.empty(self.n_meshes, dtype=torch.int32, device="cuda")
+        _lib.check(_lib.load().blob_edge_counts(self.ptr, self.n_meshes, out.data_ptr(), _stream_ptr(stream)))
+        return out
+
+
+def filter_pairs(A: MeshBlob, B: MeshBlob, query_box=None, cap: Optional[int] = None, stream=None):
+    """Closed-box candidate pairs (i in A, j in B), sorted; int32 [P, 2] on the device.
+    Synchronises to read the count; relaunches once if `cap` was too small."""
+    torch = _torch()
+    lib = _lib.load()
+    wb = ctypes.c_size_t(0)
+    _lib.check(lib.filter_aabb_pairs_ws_bytes(A.n_meshes, B.n_meshes, ctypes.byref(wb)))
+    ws = _ws(wb.value)
+    q = None if query_box is None else _dev(np.asarray(query_box, np.float32).reshape(6), torch.float32)
+    cnt = torch.zeros(1, dtype=torch.int64, device="cuda")
+    cap = int(cap) if cap is not None else max(1024, 4 * (A.n_meshes + B.n_meshes))
+    for _ in range(2):
+        out = torch.empty((max(cap, 1), 2), dtype=torch.int32, device="cuda")
+        _lib.check(lib.filter_aabb_pairs(A.ptr, A.n_meshes, B.ptr, B.n_meshes,
+                                         None if q is None else q.data_ptr(), out.data_ptr(), cap,
+                                         cnt.data_ptr(), ws.data_ptr(), wb.value, _stream_ptr(stream)))
+        n = int(cnt.item())
+        if n <= cap:
+            return out[:n]
+        cap = n
+    raise RuntimeError("filter count changed between launches")
+
+
+class RefineConfig:
+    def __init__(self, persistent: int = 1, precision: int = 0, queue_cap: int = 0, grid_blocks: int = 0,
+                 chunks_per_pop: int = 0):
+        self.persistent = persistent
+        self.precision = precision
+        self.queue_cap = queue_cap
+        self.grid_blocks = grid_blocks
+        self.chunks_per_pop = chunks_per_pop
+
+    def params(self, width: int) -> _lib.RefineParams:
+        p = _lib.RefineParams()
+        p.bvh_width = width
+        p.persistent = self.persistent
+        p.precision = self.precision
+        p.queue_cap = self.queue_cap
+        p.grid_blocks = self.grid_blocks
+        p.chunks_per_pop = self.chunks_per_pop
+        return p
+
+
+def refine_workspace(n_pairs: int, width: int, cfg: Optional[RefineConfig] = None):
+    cfg = cfg or RefineConfig()
+    prm = cfg.params(width)
+    wb = ctypes.c_size_t(0)
+    _lib.check(_lib.load().refine_workspace_bytes(int(n_pairs), ctypes.byref(prm), ctypes.byref(wb)))
+    return _ws(wb.value)
+
+
+def refine(A: MeshBlob, B: MeshBlob, pairs, cfg: Optional[RefineConfig] = None, ws=None, stream=None,
+           flags=None, stats=None, status=None) -> Tuple[object, object, object]:
+    """Runs refine_intersects.  Returns (flags u8[P], stats u64[8], status i32[1]),
+    all device tensors, without synchronising."""
+    torch = _torch()
+    cfg = cfg or RefineConfig()
+    if A.width != B.width:
+        raise ValueError("blobs built with different widths")
+    pairs = _dev(pairs, torch.int32).reshape(-1, 2)
+    P = int(pairs.shape[0])
+    prm = cfg.params(A.width)
+    if ws is None:
+        ws = refine_workspace(P, A.width, cfg)
+    if flags is None:
+        flags = torch.empty(max(P, 1), dtype=torch.uint8, device="cuda")
+    if stats is None:
+        stats = torch.zeros(len(STATS_FIELDS), dtype=torch.int64, device="cuda")
+    if status is None:
+        status = torch.zeros(1, dtype=torch.int32, device="cuda")
+    _lib.check(_lib.load().refine_intersects(A.ptr, A.n_meshes, B.ptr, B.n_meshes, pairs.data_ptr(), P,
+                                             flags.data_ptr(), ctypes.byref(prm), stats.data_ptr(),
+                                             status.data_ptr(), ws.data_ptr(), ws.numel(),
+                                             _stream_ptr(stream)))
+    return flags[:P], stats, status
+
+
+def stats_dict(stats) -> dict:
+    vals = stats.cpu().numpy().astype(np.uint64)
+    return {k: int(v) for k, v in zip(STATS_FIELDS, vals)}
+
+
+def compact(pairs, flags, stream=None):
+    """Pairs whose flag is 1, in input order (synchronises to read the count)."""
+    torch = _torch()
+    lib = _lib.load()
+    pairs = _dev(pairs, torch.int32).reshape(-1, 2)
+    P = int(pairs.shape[0])
+    wb = ctypes.c_size_t(0)
+    _lib.check(lib.compact_pairs_ws_bytes(P, ctypes.byref(wb)))
+    ws = _ws(wb.value)
+    out = torch.empty((max(P, 1), 2), dtype=torch.int32, device="cuda")
+    cnt = torch.zeros(1, dtype=torch.int64, device="cuda")
+    _lib.check(lib.compact_pairs(pairs.data_ptr(), flags.data_ptr(), P, out.data_ptr(), P, cnt.data_ptr(),
+                                 ws.data_ptr(), wb.value, _stream_ptr(stream)))
+    return out[:int(cnt.item())]

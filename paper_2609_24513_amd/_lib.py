@@ -1,0 +1,102 @@
+"""ctypes declarations of the C ABI in include/pierce.h (argument marshalling only).
+
+The shared library is loaded from this directory.  There is no fallback:
+if libpierce_hip.so is missing, every call raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import threading
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libpierce_hip.so")
+
+PR_OK = 0
+PR_E_ARG = -1
+PR_E_CAPACITY = -2
+PR_E_GEOMETRY = -3
+PR_E_DEVICE = -4
+PR_E_UNSUPPORTED = -5
+ABI_VERSION = 1
+
+EXPORTS = [
+    "pr_last_error", "pr_abi_version", "build_mesh_bvh_sizes", "build_mesh_bvh", "blob_mesh_boxes",
+    "blob_edge_counts", "filter_aabb_pairs_ws_bytes", "filter_aabb_pairs", "refine_workspace_bytes",
+    "refine_intersects", "compact_pairs_ws_bytes", "compact_pairs",
+]
+
+
+class PierceError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__("pierce error %d: %s" % (code, msg))
+        self.code = code
+
+
+class BvhParams(ctypes.Structure):
+    _fields_ = [("width", ctypes.c_int32), ("leaf_size", ctypes.c_int32),
+                ("builder", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+
+class RefineParams(ctypes.Structure):
+    _fields_ = [("bvh_width", ctypes.c_int32), ("persistent", ctypes.c_int32),
+                ("precision", ctypes.c_int32), ("queue_cap", ctypes.c_int32),
+                ("grid_blocks", ctypes.c_int32), ("chunks_per_pop", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 2)]
+
+
+class RefineStats(ctypes.Structure):
+    _fields_ = [("segments", ctypes.c_uint64), ("node_visits", ctypes.c_uint64),
+                ("tri_tests", ctypes.c_uint64), ("fp32_ambiguous", ctypes.c_uint64),
+                ("fp64_filter_ambiguous", ctypes.c_uint64), ("exact_decided", ctypes.c_uint64),
+                ("pairs_true", ctypes.c_uint64), ("queue_overflow", ctypes.c_uint64)]
+
+
+STATS_FIELDS = [f for f, _ in RefineStats._fields_]
+
+_lock = threading.Lock()
+_lib = None
+
+vp = ctypes.c_void_p
+i64 = ctypes.c_int64
+i32 = ctypes.c_int32
+szp = ctypes.POINTER(ctypes.c_size_t)
+
+
+def load():
+    """Loads libpierce_hip.so (raises if it has not been built)."""
+    global _lib
+    with _lock:
+        if _lib is not None:
+            return _lib
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError("libpierce_hip.so is not built (run __graft_entry__.build() or "
+                               "python -m paper_2609_24513_amd.build_ext)")
+        lib = ctypes.CDLL(LIB_PATH)
+        lib.pr_last_error.restype = ctypes.c_char_p
+        lib.pr_last_error.argtypes = []
+        lib.pr_abi_version.restype = ctypes.c_int
+        lib.build_mesh_bvh_sizes.argtypes = [i64, i64, i64, ctypes.POINTER(BvhParams), szp, szp]
+        lib.build_mesh_bvh.argtypes = [vp, vp, vp, vp, i64, i64, i64, ctypes.POINTER(BvhParams),
+                                       vp, ctypes.c_size_t, vp, ctypes.c_size_t, vp, vp]
+        lib.blob_mesh_boxes.argtypes = [vp, i64, vp, vp]
+        lib.blob_edge_counts.argtypes = [vp, i64, vp, vp]
+        lib.filter_aabb_pairs_ws_bytes.argtypes = [i64, i64, szp]
+        lib.filter_aabb_pairs.argtypes = [vp, i64, vp, i64, vp, vp, i64, vp, vp, ctypes.c_size_t, vp]
+        lib.refine_workspace_bytes.argtypes = [i64, ctypes.POINTER(RefineParams), szp]
+        lib.refine_intersects.argtypes = [vp, i64, vp, i64, vp, i64, vp, ctypes.POINTER(RefineParams),
+                                          vp, vp, vp, ctypes.c_size_t, vp]
+        lib.compact_pairs_ws_bytes.argtypes = [i64, szp]
+        lib.compact_pairs.argtypes = [vp, vp, i64, vp, i64, vp, vp, ctypes.c_size_t, vp]
+        for name in EXPORTS[2:]:
+            getattr(lib, name).restype = ctypes.c_int
+        if lib.pr_abi_version() != ABI_VERSION:
+            raise RuntimeError("libpierce_hip.so ABI %d != %d" % (lib.pr_abi_version(), ABI_VERSION))
+        _lib = lib
+        return lib
+
+
+def check(code: int) -> None:
+    if code != PR_OK:
+        msg = load().pr_last_error().decode(errors="replace")
+        raise PierceError(code, msg)

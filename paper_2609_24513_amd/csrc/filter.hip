@@ -1,0 +1,297 @@
+// filter_aabb_pairs and compact_pairs.
+//
+// Filter: all (i, j) whose closed mesh boxes overlap (touching boxes count),
+// optionally restricted to pairs whose common box part meets a closed query
+// box.  Meshes are first reduced to those meeting the query box (one flag
+// pass and a scan per dataset), then every kept row i of A is matched against
+// the kept meshes of B by one block; counts are scanned and a second pass
+// writes each row's pairs in ascending j with a block-wide ordered
+// compaction, so the output is sorted by (i, j) and identical run to run.
+// The exact total is always written; output beyond `cap` is dropped (the
+// caller relaunches with a larger buffer, as the paper does for its result
+// structure, Section 3.5).
+//
+// Compaction (Section 3.5 result materialisation): pairs whose flag is 1,
+// in input order, by the same count/scan/write scheme.
+#include <hip/hip_runtime.h>
+#include <hipcub/hipcub.hpp>
+
+#include "common.h"
+
+namespace pr {
+namespace {
+
+constexpr int kBlock = 256;
+
+__device__ __forceinline__ const MeshDesc* meshes_of(const void* blob) {
+  const BlobHeader* h = reinterpret_cast<const BlobHeader*>(blob);
+  return reinterpret_cast<const MeshDesc*>(reinterpret_cast<const char*>(blob) + h->off_mesh);
+}
+
+__device__ __forceinline__ bool meet(const float* a, const float* b) {
+  return a[0] <= b[3] && b[0] <= a[3] && a[1] <= b[4] && b[1] <= a[4] && a[2] <= b[5] && b[2] <= a[5];
+}
+
+// triple overlap of closed boxes a, b, q
+__device__ __forceinline__ bool meet3(const float* a, const float* b, const float* q) {
+  for (int k = 0; k < 3; ++k) {
+    float lo = fmaxf(fmaxf(a[k], b[k]), q[k]);
+    float hi = fminf(fminf(a[3 + k], b[3 + k]), q[3 + k]);
+    if (!(lo <= hi)) return false;
+  }
+  return true;
+}
+
+__global__ void k_keep(const void* blob, int64_t M, const float* query, int32_t* flag) {
+  const MeshDesc* md = meshes_of(blob);
+  int64_t m = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  for (; m < M; m += (int64_t)gridDim.x * blockDim.x) {
+    bool ok = md[m].n_tris > 0;
+    if (query) ok = ok && meet(md[m].box, query);
+    flag[m] = ok ? 1 : 0;
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) flag[M] = 0;
+}
+
+__global__ void k_list(const int32_t* flag, const int32_t* pos, int64_t M, int32_t* ids) {
+  int64_t m = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  for (; m < M; m += (int64_t)gridDim.x * blockDim.x)
+    if (flag[m]) ids[pos[m]] = (int32_t)m;
+}
+
+struct RowArgs {
+  const void* blob_a;
+  const void* blob_b;
+  const int32_t* ids_a;
+  const int32_t* ids_b;
+  const int32_t* na;  // device counts
+  const int32_t* nb;
+  const float* query;
+  int64_t rows;       // capacity of the row arrays (n_meshes_a)
+  int64_t* rowcnt;    // [rows + 1]
+  const int64_t* rowoff;
+  int32_t* pairs;
+  int64_t cap;
+};
+
+__device__ __forceinline__ bool test_pair(const RowArgs& r, const MeshDesc* mb, const MeshDesc& a, int32_t jb) {
+  const MeshDesc& b = mb[jb];
+  return r.query ? meet3(a.box, b.box, r.query) : meet(a.box, b.box);
+}
+
+__global__ void k_row_count(RowArgs r) {
+  __shared__ unsigned long long sh[kBlock / 64];
+  const int32_t na = *r.na, nb = *r.nb;
+  const MeshDesc* ma = meshes_of(r.blob_a);
+  const MeshDesc* mb = meshes_of(r.blob_b);
+  for (int64_t row = blockIdx.x; row < r.rows; row += gridDim.x) {
+    unsigned long long c = 0;
+    if (row < na) {
+      const MeshDesc a = ma[r.ids_a[row]];
+      for (int32_t k = threadIdx.x; k < nb; k += blockDim.x) c += test_pair(r, mb, a, r.ids_b[k]) ? 1 : 0;
+    }
+    for (int o = 32; o > 0; o >>= 1) c += __shfl_xor(c, o);
+    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = c;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      unsigned long long t = 0;
+      for (int w = 0; w < kBlock / 64; ++w) t += sh[w];
+      r.rowcnt[row] = (int64_t)t;
+    }
+    __syncthreads();
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) r.rowcnt[r.rows] = 0;
+}
+
+__global__ void k_row_write(RowArgs r) {
+  __shared__ int32_t wsum[kBlock / 64];
+  const int32_t na = *r.na, nb = *r.nb;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const MeshDesc* ma = meshes_of(r.blob_a);
+  const MeshDesc* mb = meshes_of(r.blob_b);
+  for (int64_t row = blockIdx.x; row < na; row += gridDim.x) {
+    const int32_t ia = r.ids_a[row];
+    const MeshDesc a = ma[ia];
+    int64_t out = r.rowoff[row];
+    for (int32_t base = 0; base < nb; base += kBlock) {
+      const int32_t k = base + threadIdx.x;
+      const int32_t jb = k < nb ? r.ids_b[k] : 0;
+      const bool ok = k < nb && test_pair(r, mb, a, jb);
+      const uint64_t m = __ballot(ok);
+      const int below = __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+      __syncthreads();
+      if (lane == 0) wsum[wv] = __popcll(m);
+      __syncthreads();
+      int32_t before = 0, tot = 0;
+      for (int w = 0; w < kBlock / 64; ++w) {
+        if (w < wv) before += wsum[w];
+        tot += wsum[w];
+      }
+      if (ok) {
+        const int64_t pos = out + before + below;
+        if (pos < r.cap) {
+          r.pairs[2 * pos] = ia;
+          r.pairs[2 * pos + 1] = jb;
+        }
+      }
+      out += tot;
+    }
+  }
+}
+
+__global__ void k_total(const int64_t* scan, int64_t n, int64_t* out) { *out = scan[n]; }
+
+__global__ void k_flag_i32(const uint8_t* flags, int64_t n, int32_t* f) {
+  int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  for (; i < n; i += (int64_t)gridDim.x * blockDim.x) f[i] = flags[i] ? 1 : 0;
+  if (blockIdx.x == 0 && threadIdx.x == 0) f[n] = 0;
+}
+
+__global__ void k_compact(const int32_t* pairs, const int32_t* f, const int64_t* pos, int64_t n, int32_t* out,
+                          int64_t cap) {
+  int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  for (; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    if (f[i] && pos[i] < cap) {
+      out[2 * pos[i]] = pairs[2 * i];
+      out[2 * pos[i] + 1] = pairs[2 * i + 1];
+    }
+}
+
+struct FilterWs {
+  int32_t *flag_a, *flag_b, *pos_a, *pos_b, *ids_a, *ids_b;
+  int64_t *rowcnt, *rowoff;
+  void* tmp;
+  size_t tmp_bytes;
+};
+
+int carve_filter(Carve& cv, FilterWs& w, int64_t MA, int64_t MB) {
+  w.flag_a = cv.take<int32_t>(MA + 1);
+  w.flag_b = cv.take<int32_t>(MB + 1);
+  w.pos_a = cv.take<int32_t>(MA + 1);
+  w.pos_b = cv.take<int32_t>(MB + 1);
+  w.ids_a = cv.take<int32_t>(MA + 1);
+  w.ids_b = cv.take<int32_t>(MB + 1);
+  w.rowcnt = cv.take<int64_t>(MA + 1);
+  w.rowoff = cv.take<int64_t>(MA + 1);
+  size_t b1 = 0, b2 = 0;
+  int64_t mx = MA > MB ? MA : MB;
+  hipError_t e = hipcub::DeviceScan::ExclusiveSum(nullptr, b1, (int32_t*)nullptr, (int32_t*)nullptr, (int)(mx + 1));
+  if (e != hipSuccess) return hip_fail(e, "hipcub scan size");
+  e = hipcub::DeviceScan::ExclusiveSum(nullptr, b2, (int64_t*)nullptr, (int64_t*)nullptr, (int)(MA + 1));
+  if (e != hipSuccess) return hip_fail(e, "hipcub scan size");
+  w.tmp_bytes = b1 > b2 ? b1 : b2;
+  w.tmp = cv.take<char>((int64_t)w.tmp_bytes);
+  return PR_OK;
+}
+
+struct CompactWs {
+  int32_t* f;
+  int64_t* pos;
+  void* tmp;
+  size_t tmp_bytes;
+};
+
+int carve_compact(Carve& cv, CompactWs& w, int64_t n) {
+  w.f = cv.take<int32_t>(n + 1);
+  w.pos = cv.take<int64_t>(n + 1);
+  size_t b = 0;
+  hipError_t e = hipcub::DeviceScan::ExclusiveSum(nullptr, b, (int32_t*)nullptr, (int64_t*)nullptr, (int)(n + 1));
+  if (e != hipSuccess) return hip_fail(e, "hipcub scan size");
+  w.tmp_bytes = b;
+  w.tmp = cv.take<char>((int64_t)b);
+  return PR_OK;
+}
+
+}  // namespace
+}  // namespace pr
+
+using namespace pr;
+
+extern "C" int filter_aabb_pairs_ws_bytes(int64_t n_meshes_a, int64_t n_meshes_b, size_t* ws_bytes) {
+  if (n_meshes_a < 0 || n_meshes_b < 0 || !ws_bytes) { set_error("bad argument"); return PR_E_ARG; }
+  if (n_meshes_a >= ((int64_t)1 << 30) || n_meshes_b >= ((int64_t)1 << 30)) { set_error("too many meshes"); return PR_E_UNSUPPORTED; }
+  Carve cv{nullptr, 0};
+  FilterWs w{};
+  int r = carve_filter(cv, w, n_meshes_a, n_meshes_b);
+  if (r) return r;
+  *ws_bytes = cv.used + 256;
+  return PR_OK;
+}
+
+extern "C" int filter_aabb_pairs(const void* blob_a, int64_t n_meshes_a, const void* blob_b, int64_t n_meshes_b,
+                                 const float* query_box, int32_t* pairs, int64_t cap, int64_t* dev_count, void* ws,
+                                 size_t ws_bytes, void* stream) {
+  if (!blob_a || !blob_b || !dev_count || !ws || cap < 0 || (cap > 0 && !pairs) || n_meshes_a < 0 || n_meshes_b < 0) {
+    set_error("bad argument");
+    return PR_E_ARG;
+  }
+  if (n_meshes_a >= ((int64_t)1 << 30) || n_meshes_b >= ((int64_t)1 << 30)) { set_error("too many meshes"); return PR_E_UNSUPPORTED; }
+  hipStream_t s = (hipStream_t)stream;
+  Carve cv{(char*)ws, ws_bytes};
+  FilterWs w{};
+  int r = carve_filter(cv, w, n_meshes_a, n_meshes_b);
+  if (r) return r;
+  if (cv.used > ws_bytes || !w.tmp) { set_error("ws_bytes %zu < required %zu", ws_bytes, cv.used); return PR_E_CAPACITY; }
+  const int64_t MA = n_meshes_a, MB = n_meshes_b;
+  hipLaunchKernelGGL(k_keep, dim3(grid_for(MA + 1, kBlock)), dim3(kBlock), 0, s, blob_a, MA, query_box, w.flag_a);
+  hipLaunchKernelGGL(k_keep, dim3(grid_for(MB + 1, kBlock)), dim3(kBlock), 0, s, blob_b, MB, query_box, w.flag_b);
+  PR_HIP(hipcub::DeviceScan::ExclusiveSum(w.tmp, w.tmp_bytes, w.flag_a, w.pos_a, (int)(MA + 1), s));
+  PR_HIP(hipcub::DeviceScan::ExclusiveSum(w.tmp, w.tmp_bytes, w.flag_b, w.pos_b, (int)(MB + 1), s));
+  hipLaunchKernelGGL(k_list, dim3(grid_for(MA, kBlock)), dim3(kBlock), 0, s, (const int32_t*)w.flag_a,
+                     (const int32_t*)w.pos_a, MA, w.ids_a);
+  hipLaunchKernelGGL(k_list, dim3(grid_for(MB, kBlock)), dim3(kBlock), 0, s, (const int32_t*)w.flag_b,
+                     (const int32_t*)w.pos_b, MB, w.ids_b);
+  RowArgs ra{};
+  ra.blob_a = blob_a;
+  ra.blob_b = blob_b;
+  ra.query = query_box;
+  ra.ids_a = w.ids_a;
+  ra.ids_b = w.ids_b;
+  ra.na = w.pos_a + MA;
+  ra.nb = w.pos_b + MB;
+  ra.rows = MA;
+  ra.rowcnt = w.rowcnt;
+  ra.rowoff = w.rowoff;
+  ra.pairs = pairs;
+  ra.cap = cap;
+  const int rows_grid = (int)(MA < 65536 ? (MA > 0 ? MA : 1) : 65536);
+  hipLaunchKernelGGL(k_row_count, dim3(rows_grid), dim3(kBlock), 0, s, ra);
+  PR_HIP(hipcub::DeviceScan::ExclusiveSum(w.tmp, w.tmp_bytes, w.rowcnt, w.rowoff, (int)(MA + 1), s));
+  hipLaunchKernelGGL(k_row_write, dim3(rows_grid), dim3(kBlock), 0, s, ra);
+  hipLaunchKernelGGL(k_total, dim3(1), dim3(1), 0, s, (const int64_t*)w.rowoff, MA, dev_count);
+  PR_HIP(hipGetLastError());
+  return PR_OK;
+}
+
+extern "C" int compact_pairs_ws_bytes(int64_t n_pairs, size_t* ws_bytes) {
+  if (n_pairs < 0 || !ws_bytes) { set_error("bad argument"); return PR_E_ARG; }
+  if (n_pairs >= ((int64_t)1 << 30)) { set_error("n_pairs >= 2^30"); return PR_E_UNSUPPORTED; }
+  Carve cv{nullptr, 0};
+  CompactWs w{};
+  int r = carve_compact(cv, w, n_pairs);
+  if (r) return r;
+  *ws_bytes = cv.used + 256;
+  return PR_OK;
+}
+
+extern "C" int compact_pairs(const int32_t* pairs, const uint8_t* flags, int64_t n_pairs, int32_t* out, int64_t cap,
+                             int64_t* dev_count, void* ws, size_t ws_bytes, void* stream) {
+  if (n_pairs < 0 || cap < 0 || !dev_count || !ws || (n_pairs > 0 && (!pairs || !flags)) || (cap > 0 && !out)) {
+    set_error("bad argument");
+    return PR_E_ARG;
+  }
+  if (n_pairs >= ((int64_t)1 << 30)) { set_error("n_pairs >= 2^30"); return PR_E_UNSUPPORTED; }
+  hipStream_t s = (hipStream_t)stream;
+  Carve cv{(char*)ws, ws_bytes};
+  CompactWs w{};
+  int r = carve_compact(cv, w, n_pairs);
+  if (r) return r;
+  if (cv.used > ws_bytes || !w.tmp) { set_error("ws_bytes %zu < required %zu", ws_bytes, cv.used); return PR_E_CAPACITY; }
+  hipLaunchKernelGGL(k_flag_i32, dim3(grid_for(n_pairs + 1, kBlock)), dim3(kBlock), 0, s, flags, n_pairs, w.f);
+  PR_HIP(hipcub::DeviceScan::ExclusiveSum(w.tmp, w.tmp_bytes, w.f, w.pos, (int)(n_pairs + 1), s));
+  hipLaunchKernelGGL(k_compact, dim3(grid_for(n_pairs, kBlock)), dim3(kBlock), 0, s, pairs, (const int32_t*)w.f,
+                     (const int64_t*)w.pos, n_pairs, out, cap);
+  hipLaunchKernelGGL(k_total, dim3(1), dim3(1), 0, s, (const int64_t*)w.pos, n_pairs, dev_count);
+  PR_HIP(hipGetLastError());
+  return PR_OK;
+}

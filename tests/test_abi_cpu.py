@@ -1,0 +1,122 @@
+"""C-ABI checks that need no GPU: the library loads, exports every entry point
+declared in include/pierce.h, and rejects host-visible argument errors before
+touching the device."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_2609_24513_amd import _lib
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    src = open(os.path.join(ROOT, "include", "pierce.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    names = re.findall(r"^\s*(?:const\s+)?\w+\s*\*?\s*(\w+)\s*\(", src, flags=re.M)
+    return sorted(set(n for n in names if n not in ("if", "while")))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(_lib.LIB_PATH):
+        pytest.fail("libpierce_hip.so is not built; run __graft_entry__.build()")
+    return _lib.load()
+
+
+def test_exports_every_declared_symbol(lib):
+    declared = _declared()
+    assert len(declared) >= 12
+    for name in declared:
+        assert hasattr(lib, name), name
+    assert sorted(_lib.EXPORTS) == declared
+
+
+def test_abi_version(lib):
+    assert lib.pr_abi_version() == _lib.ABI_VERSION
+
+
+def test_struct_sizes():
+    assert ctypes.sizeof(_lib.BvhParams) == 16
+    assert ctypes.sizeof(_lib.RefineParams) == 32
+    assert ctypes.sizeof(_lib.RefineStats) == 64
+
+
+@pytest.mark.parametrize("w,l,b,r", [(3, 4, 0, 0), (4, 3, 0, 0), (4, 4, 1, 0), (4, 4, 0, 1), (16, 4, 0, 0)])
+def test_bvh_params_rejected(lib, w, l, b, r):
+    p = _lib.BvhParams(w, l, b, r)
+    bb, wb = ctypes.c_size_t(0), ctypes.c_size_t(0)
+    assert lib.build_mesh_bvh_sizes(1, 4, 4, ctypes.byref(p), ctypes.byref(bb), ctypes.byref(wb)) == _lib.PR_E_ARG
+    assert lib.pr_last_error().decode()
+
+
+def test_bvh_sizes_rejected(lib):
+    p = _lib.BvhParams(4, 4, 0, 0)
+    bb, wb = ctypes.c_size_t(0), ctypes.c_size_t(0)
+    assert lib.build_mesh_bvh_sizes(-1, 4, 4, ctypes.byref(p), ctypes.byref(bb), ctypes.byref(wb)) == _lib.PR_E_ARG
+    assert lib.build_mesh_bvh_sizes(1, 1 << 28, 4, ctypes.byref(p), ctypes.byref(bb),
+                                    ctypes.byref(wb)) == _lib.PR_E_UNSUPPORTED
+    assert lib.build_mesh_bvh_sizes(1, 4, 4, None, ctypes.byref(bb), ctypes.byref(wb)) == _lib.PR_E_ARG
+
+
+def test_build_null_pointers_rejected(lib):
+    p = _lib.BvhParams(4, 4, 0, 0)
+    assert lib.build_mesh_bvh(None, None, None, None, 1, 3, 1, ctypes.byref(p), None, 0, None, 0, None,
+                              None) == _lib.PR_E_ARG
+
+
+def _refine_params(**kw):
+    p = _lib.RefineParams()
+    p.bvh_width = kw.get("w", 4)
+    p.persistent = kw.get("persistent", 1)
+    p.precision = kw.get("precision", 0)
+    p.queue_cap = kw.get("queue_cap", 0)
+    p.grid_blocks = kw.get("grid_blocks", 0)
+    p.chunks_per_pop = kw.get("chunks_per_pop", 0)
+    return p
+
+
+@pytest.mark.parametrize("kw", [dict(w=3), dict(precision=3), dict(persistent=2), dict(queue_cap=-1),
+                                dict(grid_blocks=-5)])
+def test_refine_params_rejected(lib, kw):
+    p = _refine_params(**kw)
+    wb = ctypes.c_size_t(0)
+    assert lib.refine_workspace_bytes(10, ctypes.byref(p), ctypes.byref(wb)) == _lib.PR_E_ARG
+    assert lib.refine_intersects(None, 1, None, 1, None, 10, None, ctypes.byref(p), None, None, None, 0,
+                                 None) == _lib.PR_E_ARG
+
+
+def test_refine_reserved_and_sizes_rejected(lib):
+    p = _refine_params()
+    p.reserved[0] = 1
+    wb = ctypes.c_size_t(0)
+    assert lib.refine_workspace_bytes(10, ctypes.byref(p), ctypes.byref(wb)) == _lib.PR_E_ARG
+    p = _refine_params()
+    assert lib.refine_workspace_bytes(-1, ctypes.byref(p), ctypes.byref(wb)) == _lib.PR_E_ARG
+    assert lib.refine_workspace_bytes(1 << 30, ctypes.byref(p), ctypes.byref(wb)) == _lib.PR_E_UNSUPPORTED
+    # null blobs
+    assert lib.refine_intersects(None, 1, None, 1, None, 0, None, ctypes.byref(p), None, None, None, 0,
+                                 None) == _lib.PR_E_ARG
+
+
+def test_filter_and_compact_args_rejected(lib):
+    wb = ctypes.c_size_t(0)
+    assert lib.filter_aabb_pairs_ws_bytes(-1, 2, ctypes.byref(wb)) == _lib.PR_E_ARG
+    assert lib.filter_aabb_pairs(None, 1, None, 1, None, None, 0, None, None, 0, None) == _lib.PR_E_ARG
+    assert lib.compact_pairs_ws_bytes(-2, ctypes.byref(wb)) == _lib.PR_E_ARG
+    assert lib.compact_pairs(None, None, 5, None, 0, None, None, 0, None) == _lib.PR_E_ARG
+    assert lib.blob_mesh_boxes(None, 3, None, None) == _lib.PR_E_ARG
+    assert lib.blob_edge_counts(None, 3, None, None) == _lib.PR_E_ARG
+
+
+def test_product_path_has_no_oracle_dependency():
+    """The package must not import, load or call the CPU oracle."""
+    pkg = os.path.join(ROOT, "paper_2609_24513_amd")
+    for dirpath, _, files in os.walk(pkg):
+        for f in files:
+            if f.endswith((".py", ".hip", ".h", ".cpp")):
+                txt = open(os.path.join(dirpath, f)).read()
+                assert "import oracle" not in txt and "from oracle" not in txt, f
+                assert "_oracle.so" not in txt and "oracle.cpp" not in txt, f

@@ -1,0 +1,235 @@
+"""GPU parity: the HIP path (through the C ABI) against the exact CPU oracle.
+
+Flags are compared bit for bit (the predicate has exactly one correct answer
+per pair).  Cases: hand-built contact cases, the tiny config (all pairs), a
+precision-stress sample on a 2^-10 grid, a scaled pathology-shaped config,
+every BVH width / leaf size / launch form / precision mode, queue overflow,
+coordinates outside the FP32-safe range, and argument/geometry errors.
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+
+@pytest.fixture(scope="module")
+def env():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    import oracle
+    oracle.build(force=False)
+    import paper_2609_24513_amd as pa
+    from paper_2609_24513_amd import synth
+    return torch, pa, synth, oracle
+
+
+def _hand(synth):
+    cases = json.load(open(os.path.join(HERE, "golden", "hand_cases.json")))["cases"]
+    A = synth.concat_meshes([(np.asarray(c["A"]["verts"], np.float64), np.asarray(c["A"]["faces"])) for c in cases])
+    B = synth.concat_meshes([(np.asarray(c["B"]["verts"], np.float64), np.asarray(c["B"]["faces"])) for c in cases])
+    pairs = np.stack([np.arange(len(cases))] * 2, 1).astype(np.int32)
+    exp = np.array([c["expected"] for c in cases], np.uint8)
+    return A, B, pairs, exp
+
+
+def _run(env, A, B, pairs, width=4, leaf=4, **cfg):
+    torch, pa, synth, oracle = env
+    ga = pa.MeshBlob.build(A, width=width, leaf_size=leaf)
+    gb = pa.MeshBlob.build(B, width=width, leaf_size=leaf)
+    flags, stats, status = pa.refine(ga, gb, pairs, pa.RefineConfig(**cfg))
+    torch.cuda.synchronize()
+    assert int(status.item()) == 0
+    return flags.cpu().numpy(), pa.stats_dict(stats)
+
+
+CONFIGS = [dict(width=w, leaf=l, persistent=p, precision=q)
+           for w in (2, 4, 8) for l in (1, 4, 8) for p in (0, 1) for q in (0, 1, 2)
+           if not (l == 8 and q == 1)]
+
+
+@pytest.mark.parametrize("c", CONFIGS, ids=lambda c: "w%d_l%d_p%d_q%d" % (c["width"], c["leaf"], c["persistent"], c["precision"]))
+def test_hand_cases_all_configs(env, c):
+    torch, pa, synth, oracle = env
+    A, B, pairs, exp = _hand(synth)
+    got, st = _run(env, A, B, pairs, **c)
+    assert np.array_equal(got, exp), [i for i in np.nonzero(got != exp)[0]]
+    # roles swapped
+    got2, _ = _run(env, B, A, pairs, **c)
+    assert np.array_equal(got2, exp)
+
+
+def test_build_metadata_c1(env):
+    torch, pa, synth, oracle = env
+    A, B = synth.make_c1()
+    ga = pa.MeshBlob.build(A)
+    assert np.array_equal(ga.boxes().cpu().numpy(), A.aabbs())
+    ec = ga.edge_counts().cpu().numpy()
+    for m in range(A.n_meshes):
+        v, f = A.mesh(m)
+        assert ec[m] == synth.mesh_stats(v, f)["E"]
+
+
+def test_filter_matches_exact_boxes(env):
+    torch, pa, synth, oracle = env
+    for seed in (1, 2, 3):
+        A, B = synth.make_c1(seed=seed, n=20)
+        ga, gb = pa.MeshBlob.build(A), pa.MeshBlob.build(B)
+        got = pa.filter_pairs(ga, gb).cpu().numpy()
+        assert np.array_equal(got, synth.candidate_pairs(A.aabbs(), B.aabbs()))
+
+
+def test_filter_query_box_and_capacity(env):
+    torch, pa, synth, oracle = env
+    A, B = synth.make_c1(seed=4, n=40)
+    ga, gb = pa.MeshBlob.build(A), pa.MeshBlob.build(B)
+    rng = np.random.default_rng(0)
+    for _ in range(10):
+        c = rng.uniform(0, 4, size=3); h = rng.uniform(0.2, 2.0, size=3)
+        q = np.concatenate([c - h, c + h]).astype(np.float32)
+        got = pa.filter_pairs(ga, gb, query_box=q).cpu().numpy()
+        assert np.array_equal(got, synth.candidate_pairs(A.aabbs(), B.aabbs(), q))
+    full = synth.candidate_pairs(A.aabbs(), B.aabbs())
+    got = pa.filter_pairs(ga, gb, cap=3).cpu().numpy()  # relaunch path
+    assert np.array_equal(got, full)
+
+
+def test_c1_all_pairs_against_oracle(env):
+    torch, pa, synth, oracle = env
+    A, B = synth.make_c1()
+    pairs = np.array([(i, j) for i in range(8) for j in range(8)], np.int32)
+    want = oracle.join(A, B, pairs, mode=0)
+    for w, l in ((2, 1), (4, 4), (8, 8)):
+        for p in (0, 1):
+            got, st = _run(env, A, B, pairs, width=w, leaf=l, persistent=p, precision=0)
+            assert np.array_equal(got, want), (w, l, p)
+            assert st["pairs_true"] == int(want.sum())
+
+
+def test_c4_precision_stress_sample(env):
+    torch, pa, synth, oracle = env
+    A, B, pairs, cls = synth.make_c4(n_pairs=240)
+    want = oracle.join(A, B, pairs, mode=1)
+    results = {}
+    for q in (0, 1, 2):
+        for p in (0, 1):
+            got, st = _run(env, A, B, pairs, persistent=p, precision=q)
+            assert np.array_equal(got, want), (q, p, np.nonzero(got != want)[0][:10])
+            results[(q, p)] = st
+    assert results[(0, 1)]["fp32_ambiguous"] > 0
+    assert results[(0, 1)]["exact_decided"] > 0
+
+
+def test_c2_scaled_against_oracle(env):
+    torch, pa, synth, oracle = env
+    A, B = synth.make_c2(seed=2, n_nuclei=600, n_vessels=40, box=160.0)
+    ga, gb = pa.MeshBlob.build(A), pa.MeshBlob.build(B)
+    pairs = pa.filter_pairs(ga, gb)
+    hp = pairs.cpu().numpy()
+    assert np.array_equal(hp, synth.candidate_pairs(A.aabbs(), B.aabbs()))
+    assert hp.shape[0] > 100
+    want = oracle.join(A, B, hp, mode=1)
+    assert 0 < want.sum() < hp.shape[0]
+    for p in (0, 1):
+        flags, stats, status = pa.refine(ga, gb, pairs, pa.RefineConfig(persistent=p))
+        torch.cuda.synchronize()
+        assert np.array_equal(flags.cpu().numpy(), want), p
+    res = pa.compact(pairs, flags).cpu().numpy()
+    assert np.array_equal(res, hp[want == 1])
+
+
+def test_queue_overflow_decides_in_place(env):
+    torch, pa, synth, oracle = env
+    A, B, pairs, cls = synth.make_c4(n_pairs=60)
+    want = oracle.join(A, B, pairs, mode=1)
+    got, st = _run(env, A, B, pairs, persistent=1, precision=2, queue_cap=1)
+    assert np.array_equal(got, want)
+    assert st["queue_overflow"] > 0
+
+
+def test_coordinates_outside_fp32_safe_range(env):
+    """Scaling by 2^-45 is exact and keeps every answer, but puts coordinates
+    below 2^-40, which disables the FP32 bounds (all tests go exact)."""
+    torch, pa, synth, oracle = env
+    A, B = synth.make_c1()
+    pairs = np.array([(i, j) for i in range(8) for j in range(8)], np.int32)
+    want = oracle.join(A, B, pairs, mode=1)
+    s = np.float32(2.0 ** -45)
+    As = synth.MeshSet(A.verts * s, A.faces, A.vert_off, A.face_off)
+    Bs = synth.MeshSet(B.verts * s, B.faces, B.vert_off, B.face_off)
+    got, st = _run(env, As, Bs, pairs, persistent=1, precision=0)
+    assert np.array_equal(got, want)
+    assert st["fp32_ambiguous"] > 0
+
+
+def test_swap_gives_transposed_result(env):
+    torch, pa, synth, oracle = env
+    A, B = synth.make_c1(seed=9)
+    pairs = np.array([(i, j) for i in range(8) for j in range(8)], np.int32)
+    g1, _ = _run(env, A, B, pairs)
+    g2, _ = _run(env, B, A, pairs[:, ::-1].copy())
+    assert np.array_equal(g1, g2)
+
+
+def test_deterministic_reruns(env):
+    torch, pa, synth, oracle = env
+    A, B, pairs, cls = synth.make_c4(n_pairs=100)
+    r = [_run(env, A, B, pairs, persistent=1)[0] for _ in range(3)]
+    assert all(np.array_equal(r[0], x) for x in r[1:])
+
+
+def test_tiny_meshes_and_empty_pairs(env):
+    torch, pa, synth, oracle = env
+    tri = (np.array([[0, 0, 0], [1, 0, 0], [0, 1, 0]], np.float64), np.array([[0, 1, 2]]))
+    quad = (np.array([[0, 0, 0.5], [1, 0, 0.5], [0, 1, -0.5], [1, 1, -0.5]], np.float64), np.array([[0, 1, 2], [1, 3, 2]]))
+    far = (np.array([[5, 5, 5], [6, 5, 5], [5, 6, 5]], np.float64), np.array([[0, 1, 2]]))
+    A = synth.concat_meshes([tri, quad, far])
+    B = synth.concat_meshes([quad, tri, far, tri])
+    pairs = np.array([(i, j) for i in range(3) for j in range(4)], np.int32)
+    want = oracle.join(A, B, pairs, mode=0)
+    for w in (2, 4, 8):
+        got, _ = _run(env, A, B, pairs, width=w, leaf=1)
+        assert np.array_equal(got, want), w
+    ga, gb = pa.MeshBlob.build(A), pa.MeshBlob.build(B)
+    flags, stats, status = pa.refine(ga, gb, np.zeros((0, 2), np.int32))
+    torch.cuda.synchronize()
+    assert flags.numel() == 0 and int(status.item()) == 0
+
+
+def test_bad_pairs_and_width_mismatch_reported(env):
+    torch, pa, synth, oracle = env
+    A, B = synth.make_c1()
+    ga, gb = pa.MeshBlob.build(A), pa.MeshBlob.build(B)
+    pairs = np.array([[0, 0], [8, 0], [0, -1], [1, 1]], np.int32)
+    for p in (0, 1):
+        flags, stats, status = pa.refine(ga, gb, pairs, pa.RefineConfig(persistent=p))
+        torch.cuda.synchronize()
+        assert int(status.item()) == -1  # PR_E_ARG
+        f = flags.cpu().numpy()
+        assert f[1] == 0 and f[2] == 0
+        want = oracle.join(A, B, pairs[[0, 3]], mode=1)
+        assert f[0] == want[0] and f[3] == want[1]
+    g8 = pa.MeshBlob.build(B, width=8)
+    g8.width = 4  # lie about the width: the device check must catch it
+    flags, stats, status = pa.refine(ga, g8, np.array([[0, 0]], np.int32))
+    torch.cuda.synchronize()
+    assert int(status.item()) == -5  # PR_E_UNSUPPORTED
+    assert flags.cpu().numpy()[0] == 0
+
+
+def test_geometry_errors_reported(env):
+    torch, pa, synth, oracle = env
+    good = (np.array([[0, 0, 0], [1, 0, 0], [0, 1, 0], [0, 0, 1]], np.float64), np.array([[0, 1, 2], [0, 1, 3]]))
+    collinear = (np.array([[0, 0, 0], [1, 1, 1], [2, 2, 2]], np.float64), np.array([[0, 1, 2]]))
+    badid = (np.array([[0, 0, 0], [1, 0, 0], [0, 1, 0]], np.float64), np.array([[0, 1, 3]]))
+    nan = (np.array([[0, 0, 0], [np.nan, 0, 0], [0, 1, 0]], np.float64), np.array([[0, 1, 2]]))
+    for bad, face in ((collinear, 2), (badid, 2), (nan, 2)):
+        S = synth.concat_meshes([good, bad])
+        g = pa.MeshBlob.build(S, check_status=False)
+        assert g.status() == face
+    g = pa.MeshBlob.build(synth.concat_meshes([good, good]), check_status=False)
+    assert g.status() == -1
