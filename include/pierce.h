@@ -148,11 +148,16 @@ typedef struct {
   int32_t precision;   /* 0: FP32 filter, uncertain tests re-decided in FP64/exact
                           1: every leaf test decided in FP64/exact directly
                           2: every leaf test deferred to the FP64/exact pass (test mode) */
-  int32_t queue_cap;   /* capacity of the deferred-test queue (0 = default 1<<20);
-                          tests beyond it are decided in place, in FP64/exact */
+  int32_t queue_cap;   /* capacity of the deferred-test queue (0 = default 1<<20); a
+                          pair whose tests overflow it is traced again with every leaf
+                          test decided in FP64/exact */
   int32_t grid_blocks; /* persistent launch: blocks of 256 threads (0 = default) */
-  int32_t chunks_per_pop; /* persistent launch: 64-segment groups per queue pop (0 = default) */
+  int32_t chunks_per_pop; /* persistent launch: 64-segment groups per work item
+                             (0 = default 256; at most 1024) */
   int32_t reserved[2]; /* must be 0 */
+  void* ev_begin;      /* optional hipEvent_t (or NULL), recorded on `stream` just before the
+                          traversal kernel(s), for timing them alone */
+  void* ev_end;        /* optional hipEvent_t (or NULL), recorded just after them */
 } pr_refine_params;
 
 typedef struct {
@@ -164,6 +169,10 @@ typedef struct {
   uint64_t exact_decided;         /* tests decided in FP64/exact (deferred or in place) */
   uint64_t pairs_true;            /* pairs found intersecting */
   uint64_t queue_overflow;        /* deferred tests that did not fit in the queue */
+  uint64_t groups;                /* 64-segment groups picked up */
+  uint64_t tri_fetches;           /* wave-level leaf triangle loads */
+  uint64_t groups_box_pass;       /* groups whose box meets the target mesh box (segments loaded) */
+  uint64_t groups_traversed;      /* groups with a segment meeting the target mesh box */
 } pr_refine_stats;
 
 /* Workspace bytes for refine_intersects on n_pairs pairs. */

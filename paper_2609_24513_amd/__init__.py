@@ -132,7 +132,9 @@ def filter_pairs(A: MeshBlob, B: MeshBlob, query_box=None, cap: Optional[int] = 
 
 class RefineConfig:
     def __init__(self, persistent: int = 1, precision: int = 0, queue_cap: int = 0, grid_blocks: int = 0,
-                 chunks_per_pop: int = 0):
+                 chunks_per_pop: int = 0, ev_begin=None, ev_end=None):
+        self.ev_begin = ev_begin  # optional torch.cuda.Event recorded around the traversal kernel(s)
+        self.ev_end = ev_end
         self.persistent = persistent
         self.precision = precision
         self.queue_cap = queue_cap
@@ -147,7 +149,17 @@ class RefineConfig:
         p.queue_cap = self.queue_cap
         p.grid_blocks = self.grid_blocks
         p.chunks_per_pop = self.chunks_per_pop
+        p.ev_begin = _event_handle(self.ev_begin)
+        p.ev_end = _event_handle(self.ev_end)
         return p
+
+
+def _event_handle(ev):
+    if ev is None:
+        return None
+    if not ev.cuda_event:          # torch creates the event lazily at its first record
+        ev.record()
+    return int(ev.cuda_event)
 
 
 def refine_workspace(n_pairs: int, width: int, cfg: Optional[RefineConfig] = None):

@@ -42,14 +42,16 @@ class RefineParams(ctypes.Structure):
     _fields_ = [("bvh_width", ctypes.c_int32), ("persistent", ctypes.c_int32),
                 ("precision", ctypes.c_int32), ("queue_cap", ctypes.c_int32),
                 ("grid_blocks", ctypes.c_int32), ("chunks_per_pop", ctypes.c_int32),
-                ("reserved", ctypes.c_int32 * 2)]
+                ("reserved", ctypes.c_int32 * 2), ("ev_begin", ctypes.c_void_p), ("ev_end", ctypes.c_void_p)]
 
 
 class RefineStats(ctypes.Structure):
     _fields_ = [("segments", ctypes.c_uint64), ("node_visits", ctypes.c_uint64),
                 ("tri_tests", ctypes.c_uint64), ("fp32_ambiguous", ctypes.c_uint64),
                 ("fp64_filter_ambiguous", ctypes.c_uint64), ("exact_decided", ctypes.c_uint64),
-                ("pairs_true", ctypes.c_uint64), ("queue_overflow", ctypes.c_uint64)]
+                ("pairs_true", ctypes.c_uint64), ("queue_overflow", ctypes.c_uint64),
+                ("groups", ctypes.c_uint64), ("tri_fetches", ctypes.c_uint64),
+                ("groups_box_pass", ctypes.c_uint64), ("groups_traversed", ctypes.c_uint64)]
 
 
 STATS_FIELDS = [f for f, _ in RefineStats._fields_]

@@ -308,26 +308,30 @@ __device__ __forceinline__ void child_info(const BuildArgs& a, int32_t c, const 
   }
 }
 
+// One block per mesh: every climb of a mesh stays inside one workgroup, so
+// workgroup-scope acquire/release on the visit counters orders the box
+// writes without device-wide cache maintenance.
 __global__ void k_refit(BuildArgs a, const int32_t* sorted_face) {
   if (*a.status != INT_MAX) return;  // invalid input: the blob is not built
-  int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  for (; g < a.f_total; g += (int64_t)gridDim.x * blockDim.x) {
-    int32_t p = a.lparent[g];
-    while (p >= 0) {
-      uint32_t old = __hip_atomic_fetch_add(&a.visit[p], 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
-      if (old == 0) break;  // the sibling subtree is not done yet
-      float bl[6], br[6];
-      int32_t cl, cr, fl, fr;
-      child_info(a, a.left[p], sorted_face, bl, cl, fl);
-      child_info(a, a.right[p], sorted_face, br, cr, fr);
-      for (int k = 0; k < 3; ++k) {
-        a.nbox[6 * (int64_t)p + k] = fminf(bl[k], br[k]);
-        a.nbox[6 * (int64_t)p + 3 + k] = fmaxf(bl[3 + k], br[3 + k]);
+  for (int64_t m = blockIdx.x; m < a.n_meshes; m += gridDim.x) {
+    const int64_t f0 = a.face_off[m], f1 = a.face_off[m + 1];
+    for (int64_t g = f0 + threadIdx.x; g < f1; g += blockDim.x) {
+      int32_t p = a.lparent[g];
+      while (p >= 0) {
+        uint32_t old = __hip_atomic_fetch_add(&a.visit[p], 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_WORKGROUP);
+        if (old == 0) break;  // the sibling subtree is not done yet
+        float bl[6], br[6];
+        int32_t cl, cr, fl, fr;
+        child_info(a, a.left[p], sorted_face, bl, cl, fl);
+        child_info(a, a.right[p], sorted_face, br, cr, fr);
+        for (int k = 0; k < 3; ++k) {
+          a.nbox[6 * (int64_t)p + k] = fminf(bl[k], br[k]);
+          a.nbox[6 * (int64_t)p + 3 + k] = fmaxf(bl[3 + k], br[3 + k]);
+        }
+        a.ncount[p] = cl + cr;
+        a.nfirst[p] = fl < fr ? fl : fr;
+        p = a.parent[p];
       }
-      a.ncount[p] = cl + cr;
-      a.nfirst[p] = fl < fr ? fl : fr;
-      __threadfence();
-      p = a.parent[p];
     }
   }
 }
@@ -828,7 +832,7 @@ extern "C" int build_mesh_bvh(const float* verts, const int64_t* vert_off, const
     hipLaunchKernelGGL(k_morton, dim3(gF), dim3(kBlock), 0, s, a);
     PR_HIP(hipcub::DeviceRadixSort::SortPairs(tmp, tmp_bytes, a.key0, a.key1, a.val0, a.val1, (int)F, 0, eb, s));
     hipLaunchKernelGGL(k_karras, dim3(gF), dim3(kBlock), 0, s, a, (const uint64_t*)a.key1);
-    hipLaunchKernelGGL(k_refit, dim3(gF), dim3(kBlock), 0, s, a, (const int32_t*)a.val1);
+    hipLaunchKernelGGL(k_refit, dim3((int)(M < 65536 ? M : 65536)), dim3(kBlock), 0, s, a, (const int32_t*)a.val1);
   }
   if (M > 0) {
     hipLaunchKernelGGL(k_node_bound, dim3(gM), dim3(kBlock), 0, s, a);

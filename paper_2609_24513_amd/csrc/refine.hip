@@ -70,7 +70,7 @@ __device__ __forceinline__ BlobView view_of(const char* blob) {
 }
 
 enum {
-  S_SEG = 0, S_VISIT, S_TESTS, S_AMB32, S_AMB64, S_EXACT, S_TRUE, S_QOVER, S_N
+  S_SEG = 0, S_VISIT, S_TESTS, S_AMB32, S_AMB64, S_EXACT, S_TRUE, S_QOVER, S_GROUPS, S_TRIF, S_GBOX, S_GTRAV, S_N
 };
 
 struct RefineArgs {
@@ -83,14 +83,18 @@ struct RefineArgs {
   uint32_t* state;            // [P] 0 undecided, 1 intersecting
   int64_t* unit_cnt;          // [2P+1]
   int64_t* offs;              // [2P+1]
-  unsigned long long* ctr;    // pop counter
+  unsigned long long* ctr;    // 8 pop counters, 128 bytes apart (one per slice of the item space)
   int4* queue;                // deferred tests (pair, dir, segment slot, triangle)
   uint32_t qcap;
   uint32_t* qcount;
   unsigned long long* stats;  // [S_N]
   int32_t* status;            // [1]
-  int32_t chunks_per_pop;
+  int32_t item_groups;        // groups per work item
 };
+
+constexpr int kSlices = 8;     // one pop counter per XCD
+constexpr int kMaxItemGroups = 1024;
+constexpr int kCtrStride = 16; // u64 words between counters
 
 __device__ __forceinline__ uint32_t load_state(const uint32_t* p) {
   return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -143,12 +147,13 @@ struct WaveStats {
 
 __device__ __forceinline__ f3 tri_vertex(const float* t, int k) { return f3{t[3 * k], t[3 * k + 1], t[3 * k + 2]}; }
 
-// Traces group `chunk` of source mesh sm against target mesh tm.  Returns
-// true when the pair is decided (found here or by another wave).
+// Traces group `chunk` of source mesh sm against target mesh tm; the caller
+// has checked that the group's box meets the target mesh box.  Returns true
+// when the pair is decided (found here or by another wave).
 template <int W, int PREC>
-__device__ bool trace_chunk(const BlobView& S, const BlobView& T, const MeshDesc& sm, const MeshDesc& tm,
+__device__ bool trace_group(const BlobView& S, const BlobView& T, const MeshDesc& sm, const MeshDesc& tm,
                             int32_t chunk, int32_t pair, int32_t dir, bool safe, const RefineArgs& ra,
-                            int32_t* snode, uint64_t* smask, WaveStats& st) {
+                            int32_t* snode, uint64_t* smask, WaveStats& st, bool rerun = false) {
   const int lane = threadIdx.x & 63;
   const int64_t gc = (int64_t)sm.chunk_base + chunk;
   const int live = min(kChunk, sm.n_edges - chunk * kChunk);
@@ -157,8 +162,6 @@ __device__ bool trace_chunk(const BlobView& S, const BlobView& T, const MeshDesc
   const float* cbp = S.cbox + 8 * gc;
 #pragma unroll
   for (int k = 0; k < 6; ++k) cb[k] = cbp[k];
-  if (!box_meet(cb, tm.box[0], tm.box[1], tm.box[2], tm.box[3], tm.box[4], tm.box[5])) return false;
-  if (tm.root == kEmpty) return false;
   const bool valid = lane < live;
   const float* sp = S.seg + gc * (6 * kChunk);
   f3 p{sp[lane], sp[kChunk + lane], sp[2 * kChunk + lane]};
@@ -170,6 +173,7 @@ __device__ bool trace_chunk(const BlobView& S, const BlobView& T, const MeshDesc
   axis_setup(q.z - p.z, safe, r.iz, r.bz);
   uint64_t m0 = ballot(valid && slab(r, tm.box[0], tm.box[1], tm.box[2], tm.box[3], tm.box[4], tm.box[5]));
   if (m0 == 0) return false;
+  st.v[S_GTRAV] += 1;
   constexpr int CAP = stack_cap<W>();
   int top = 0;
   if (lane == 0) { snode[0] = tm.root; smask[0] = m0; }
@@ -180,7 +184,7 @@ __device__ bool trace_chunk(const BlobView& S, const BlobView& T, const MeshDesc
     --top;
     const int32_t node = uni(snode[top]);
     const uint64_t nm = uni64(smask[top]);
-    if ((++iter & 15) == 0 && load_state(ra.state + pair)) return true;
+    if (!rerun && (++iter & 15) == 0 && load_state(ra.state + pair)) return true;
     st.v[S_VISIT] += 1;
     const Node<W>* nd = nodes + node;
     const bool on = (nm >> lane) & 1ull;
@@ -206,6 +210,7 @@ __device__ bool trace_chunk(const BlobView& S, const BlobView& T, const MeshDesc
       const int32_t first = lr >> 3;
       const int cnt = (lr & 7) + 1;
       const bool lon = (hm >> lane) & 1ull;
+      st.v[S_TRIF] += (uint64_t)cnt;
       for (int t = 0; t < cnt; ++t) {
         const float* tp = T.tris + 9 * (int64_t)(first + t);
         const f3 a = tri_vertex(tp, 0), b = tri_vertex(tp, 1), c3 = tri_vertex(tp, 2);
@@ -223,7 +228,7 @@ __device__ bool trace_chunk(const BlobView& S, const BlobView& T, const MeshDesc
         st.v[S_TESTS] += (uint64_t)__popcll(hm);
         if (PREC == 1) st.v[S_EXACT] += (uint64_t)__popcll(hm);
         if (ballot(res == kHit)) {
-          if (lane == 0) mark_true(ra.state + pair);
+          if (lane == 0 && !rerun) mark_true(ra.state + pair);
           return true;
         }
         const uint64_t am = ballot(res == kAmbig);
@@ -232,23 +237,14 @@ __device__ bool trace_chunk(const BlobView& S, const BlobView& T, const MeshDesc
           uint32_t base = 0;
           if (lane == 0) base = atomicAdd(ra.qcount, (uint32_t)__popcll(am));
           base = (uint32_t)uni((int32_t)base);
-          bool inline_hit = false;
-          if (res == kAmbig) {
-            const uint32_t idx = base + (uint32_t)lanes_below(am);
-            if (idx < ra.qcap) {
-              ra.queue[idx] = make_int4(pair, dir, (int32_t)(gc * kChunk + lane), first + t);
-            } else {
-              ExactCounters ec{0};
-              inline_hit = seg_tri_exact(p, q, a, b, c3, ec);
-            }
-          }
-          const uint64_t over = ballot(res == kAmbig && base + (uint32_t)lanes_below(am) >= ra.qcap);
+          const uint32_t idx = base + (uint32_t)lanes_below(am);
+          if (res == kAmbig && idx < ra.qcap)
+            ra.queue[idx] = make_int4(pair, dir, (int32_t)(gc * kChunk + lane), first + t);
+          const uint64_t over = ballot(res == kAmbig && idx >= ra.qcap);
           if (over) {
+            // the queue is full: the whole pair is decided again later in FP64/exact
             st.v[S_QOVER] += (uint64_t)__popcll(over);
-            st.v[S_EXACT] += (uint64_t)__popcll(over);
-          }
-          if (ballot(inline_hit)) {
-            if (lane == 0) mark_true(ra.state + pair);
+            if (lane == 0) atomicCAS(ra.state + pair, 0u, 2u);
             return true;
           }
         }
@@ -256,6 +252,22 @@ __device__ bool trace_chunk(const BlobView& S, const BlobView& T, const MeshDesc
     }
   }
   return false;
+}
+
+// One group with its own box pre-test (per-pair and rerun kernels).
+template <int W, int PREC>
+__device__ bool trace_chunk(const BlobView& S, const BlobView& T, const MeshDesc& sm, const MeshDesc& tm,
+                            int32_t chunk, int32_t pair, int32_t dir, bool safe, const RefineArgs& ra,
+                            int32_t* snode, uint64_t* smask, WaveStats& st, bool rerun = false) {
+  st.v[S_GROUPS] += 1;
+  if (tm.root == kEmpty) return false;
+  const float* cbp = S.cbox + 8 * ((int64_t)sm.chunk_base + chunk);
+  float cb[6];
+#pragma unroll
+  for (int k = 0; k < 6; ++k) cb[k] = cbp[k];
+  if (!box_meet(cb, tm.box[0], tm.box[1], tm.box[2], tm.box[3], tm.box[4], tm.box[5])) return false;
+  st.v[S_GBOX] += 1;
+  return trace_group<W, PREC>(S, T, sm, tm, chunk, pair, dir, safe, ra, snode, smask, st, rerun);
 }
 
 __device__ __forceinline__ void flush_stats(const WaveStats& st, const RefineArgs& ra) {
@@ -283,9 +295,9 @@ __global__ void k_init(RefineArgs ra) {
   int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   for (int64_t p = i; p < ra.n_pairs; p += (int64_t)gridDim.x * blockDim.x) ra.state[p] = 0u;
   if (i < S_N) ra.stats[i] = 0ull;
+  if (i < kSlices) ra.ctr[kCtrStride * i] = 0ull;
   if (i == 0) {
     *ra.qcount = 0u;
-    *ra.ctr = 0ull;
     *ra.status = PR_OK;
   }
 }
@@ -332,8 +344,9 @@ __global__ void k_plan(RefineArgs ra) {
     } else {
       const MeshDesc a = A.mesh[i], b = B.mesh[j];
       if (box_meet(a.box, b.box[0], b.box[1], b.box[2], b.box[3], b.box[4], b.box[5])) {
-        if (coarse_meet<W>(a.box, B, b)) c0 = a.n_chunks;
-        if (coarse_meet<W>(b.box, A, a)) c1 = b.n_chunks;
+        const int64_t R = ra.item_groups;
+        if (coarse_meet<W>(a.box, B, b)) c0 = (a.n_chunks + R - 1) / R;
+        if (coarse_meet<W>(b.box, A, a)) c1 = (b.n_chunks + R - 1) / R;
       }
     }
     ra.unit_cnt[2 * p] = c0;
@@ -358,49 +371,122 @@ __device__ __forceinline__ int64_t find_unit(const int64_t* offs, int64_t U, int
   return lo;
 }
 
+// Conservative group cull: the group box must meet the target mesh box and
+// a child box of the root; when that child is an inner node, one of its child
+// boxes too (every triangle lies inside the boxes of its ancestors).  The
+// node loads are uniform; each lane tests its own group box.
+template <int W>
+__device__ __forceinline__ bool group_may_hit(const float* g, const BlobView& T, const MeshDesc& tm) {
+  if (!(g[0] <= tm.box[3] && tm.box[0] <= g[3] && g[1] <= tm.box[4] && tm.box[1] <= g[4] && g[2] <= tm.box[5] &&
+        tm.box[2] <= g[5]))
+    return false;
+  const Node<W>* nodes = reinterpret_cast<const Node<W>*>(T.nodes);
+  const Node<W>* root = nodes + tm.root;
+  bool hit = false;
+#pragma unroll
+  for (int c = 0; c < W; ++c) {
+    const int32_t ch = root->child[c];
+    if (ch == kEmpty) continue;
+    const bool m1 = box_meet(g, root->lo[0][c], root->lo[1][c], root->lo[2][c], root->hi[0][c], root->hi[1][c],
+                             root->hi[2][c]);
+    if (ch < 0) { hit = hit || m1; continue; }
+    const Node<W>* n2 = nodes + ch;
+    bool m2 = false;
+#pragma unroll
+    for (int d = 0; d < W; ++d)
+      m2 = m2 || (n2->child[d] != kEmpty &&
+                  box_meet(g, n2->lo[0][d], n2->lo[1][d], n2->lo[2][d], n2->hi[0][d], n2->hi[1][d], n2->hi[2][d]));
+    hit = hit || (m1 && m2);
+  }
+  return hit;
+}
+
+// Work item: (pair, direction, range of item_groups groups).  The item space
+// is cut into kSlices contiguous slices with one pop counter each; a block
+// starts on slice blockIdx % kSlices (workgroups are dealt round-robin to the
+// XCDs, so each XCD mostly pops its own counter and keeps its own meshes in
+// its L2) and then helps the other slices.  A block takes one item at a time:
+// its waves cull the item's groups 64 at a time (one group box per lane),
+// append the survivors to a list in LDS, then drain that list dynamically,
+// one group per wave at a time.
 template <int W, int PREC>
 __global__ __launch_bounds__(kBlock) void k_refine_persistent(RefineArgs ra) {
   constexpr int CAP = stack_cap<W>();
   __shared__ int32_t s_node[kWaves][CAP];
   __shared__ uint64_t s_mask[kWaves][CAP];
+  __shared__ int32_t s_list[kMaxItemGroups];
+  __shared__ int64_t s_idx;
+  __shared__ int32_t s_n, s_next;
   const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const BlobView A = view_of(ra.blob_a), B = view_of(ra.blob_b);
   if (!blobs_ok(A, B, ra, W)) return;
   const int64_t U = 2 * ra.n_pairs;
   const int64_t total = ra.offs[U];
-  const int64_t G = ra.chunks_per_pop;
   WaveStats st;
 #pragma unroll
   for (int k = 0; k < S_N; ++k) st.v[k] = 0;
-  int64_t cur_lo = 0, cur_hi = 0;
-  int32_t pair = 0, dir = 0;
-  MeshDesc sm, tm;
-  bool safe = false, skip = false;
-  for (;;) {
-    unsigned long long base = 0;
-    if (lane == 0) base = atomicAdd(ra.ctr, (unsigned long long)G);
-    base = uni64(base);
-    if ((int64_t)base >= total) break;
-    const int64_t end = ((int64_t)base + G < total) ? (int64_t)base + G : total;
-    for (int64_t v = (int64_t)base; v < end; ++v) {
-      if (v >= cur_hi || v < cur_lo) {
-        const int64_t u = find_unit(ra.offs, U, v);
-        cur_lo = ra.offs[u];
-        cur_hi = ra.offs[u + 1];
-        pair = uni((int32_t)(u >> 1));
-        dir = uni((int32_t)(u & 1));
-        const int32_t i = ra.pairs[2 * (int64_t)pair], j = ra.pairs[2 * (int64_t)pair + 1];
-        sm = dir == 0 ? A.mesh[i] : B.mesh[j];
-        tm = dir == 0 ? B.mesh[j] : A.mesh[i];
-        safe = (sm.flags & tm.flags & kMeshSafe) != 0;
-        skip = false;
+  const int home = (int)(blockIdx.x % kSlices);
+  for (int sl = 0; sl < kSlices; ++sl) {
+    const int cid = (home + sl) % kSlices;
+    const int64_t lo = total * cid / kSlices, hi = total * (cid + 1) / kSlices;
+    if (lo >= hi) continue;
+    for (;;) {
+      if (threadIdx.x == 0) {
+        s_idx = lo + (int64_t)atomicAdd(ra.ctr + kCtrStride * cid, 1ull);
+        s_n = 0;
+        s_next = 0;
       }
-      if (skip) continue;
-      if (load_state(ra.state + pair)) { skip = true; continue; }
-      const int32_t chunk = (int32_t)(v - cur_lo);
-      if (trace_chunk<W, PREC>(dir == 0 ? A : B, dir == 0 ? B : A, sm, tm, chunk, pair, dir, safe, ra,
-                               s_node[wv], s_mask[wv], st))
-        skip = true;
+      __syncthreads();
+      const int64_t idx = s_idx;
+      if (idx >= hi) {
+        __syncthreads();
+        break;
+      }
+      const int64_t u = find_unit(ra.offs, U, idx);
+      const int64_t j = idx - ra.offs[u];
+      const int32_t pair = uni((int32_t)(u >> 1));
+      const int32_t dir = uni((int32_t)(u & 1));
+      const int32_t ia = ra.pairs[2 * (int64_t)pair], jb = ra.pairs[2 * (int64_t)pair + 1];
+      const BlobView& S = dir == 0 ? A : B;
+      const BlobView& T = dir == 0 ? B : A;
+      const MeshDesc sm = dir == 0 ? A.mesh[ia] : B.mesh[jb];
+      const MeshDesc tm = dir == 0 ? B.mesh[jb] : A.mesh[ia];
+      const int32_t c0 = (int32_t)(j * ra.item_groups);
+      const int32_t c1 = min(c0 + ra.item_groups, sm.n_chunks);
+      if (tm.root != kEmpty && !load_state(ra.state + pair)) {
+        for (int32_t base = c0 + kChunk * wv; base < c1; base += kChunk * kWaves) {
+          const int32_t c = base + lane;
+          bool pass = false;
+          if (c < c1) {
+            const float* cbp = S.cbox + 8 * ((int64_t)sm.chunk_base + c);
+            float g[6] = {cbp[0], cbp[1], cbp[2], cbp[3], cbp[4], cbp[5]};
+            pass = group_may_hit<W>(g, T, tm);
+          }
+          const uint64_t mask = ballot(pass);
+          if (mask) {
+            int32_t pos = 0;
+            if (lane == 0) pos = atomicAdd(&s_n, (int32_t)__popcll(mask));
+            pos = uni(pos);
+            if (pass) s_list[pos + lanes_below(mask)] = c;
+          }
+          st.v[S_GBOX] += (uint64_t)__popcll(mask);
+        }
+        if (wv == 0) st.v[S_GROUPS] += (uint64_t)(c1 - c0);
+      }
+      __syncthreads();
+      const int32_t n = s_n;
+      const bool safe = (sm.flags & tm.flags & kMeshSafe) != 0;
+      for (;;) {
+        int32_t k = 0;
+        if (lane == 0) k = atomicAdd(&s_next, 1);
+        k = uni(k);
+        if (k >= n) break;
+        if (trace_group<W, PREC>(S, T, sm, tm, s_list[k], pair, dir, safe, ra, s_node[wv], s_mask[wv], st)) {
+          if (lane == 0) atomicExch(&s_next, n);  // the pair is decided: drop the rest of the list
+          break;
+        }
+      }
+      __syncthreads();
     }
   }
   flush_stats(st, ra);
@@ -444,6 +530,44 @@ __global__ __launch_bounds__(kBlock) void k_refine_pair(RefineArgs ra, int64_t p
   flush_stats(st, ra);
 }
 
+// Pairs whose deferred tests overflowed the queue (state 2) are traced again
+// with every leaf test decided in place in FP64/exact.  One block per pair.
+template <int W>
+__global__ __launch_bounds__(kBlock) void k_rerun(RefineArgs ra) {
+  constexpr int CAP = stack_cap<W>();
+  __shared__ int32_t s_node[kWaves][CAP];
+  __shared__ uint64_t s_mask[kWaves][CAP];
+  __shared__ uint32_t s_hit;
+  const int wv = threadIdx.x >> 6;
+  const BlobView A = view_of(ra.blob_a), B = view_of(ra.blob_b);
+  if (!blobs_ok(A, B, ra, W)) return;
+  WaveStats st;
+#pragma unroll
+  for (int k = 0; k < S_N; ++k) st.v[k] = 0;
+  for (int64_t p = blockIdx.x; p < ra.n_pairs; p += gridDim.x) {
+    if (load_state(ra.state + p) != 2u) continue;
+    if (threadIdx.x == 0) s_hit = 0;
+    __syncthreads();
+    int32_t i, j;
+    pair_ok(ra, p, i, j);
+    const MeshDesc a = A.mesh[i], b = B.mesh[j];
+    for (int dir = 0; dir < 2; ++dir) {
+      const MeshDesc& sm = dir == 0 ? a : b;
+      const MeshDesc& tm = dir == 0 ? b : a;
+      for (int32_t c = wv; c < sm.n_chunks; c += kWaves) {
+        if (s_hit) break;
+        if (trace_chunk<W, 1>(dir == 0 ? A : B, dir == 0 ? B : A, sm, tm, c, (int32_t)p, dir,
+                              (sm.flags & tm.flags & kMeshSafe) != 0, ra, s_node[wv], s_mask[wv], st, true))
+          s_hit = 1;
+      }
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) ra.state[p] = s_hit ? 1u : 0u;
+    __syncthreads();
+  }
+  flush_stats(st, ra);
+}
+
 // ---- deferred FP64 / exact decisions ----------------------------------------------
 
 __global__ void k_redecide(RefineArgs ra) {
@@ -474,7 +598,7 @@ __global__ void k_finalize(RefineArgs ra) {
   int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   unsigned long long cnt = 0;
   for (; p < ra.n_pairs; p += (int64_t)gridDim.x * blockDim.x) {
-    const uint8_t f = ra.state[p] ? 1 : 0;
+    const uint8_t f = ra.state[p] == 1u ? 1 : 0;
     ra.flags[p] = f;
     cnt += f;
   }
@@ -492,6 +616,10 @@ __global__ void k_report(RefineArgs ra, pr_refine_stats* out, int32_t* dev_statu
     out->exact_decided = ra.stats[S_EXACT];
     out->pairs_true = ra.stats[S_TRUE];
     out->queue_overflow = ra.stats[S_QOVER];
+    out->groups = ra.stats[S_GROUPS];
+    out->tri_fetches = ra.stats[S_TRIF];
+    out->groups_box_pass = ra.stats[S_GBOX];
+    out->groups_traversed = ra.stats[S_GTRAV];
   }
   if (dev_status) *dev_status = *ra.status;
 }
@@ -507,7 +635,7 @@ int carve(Carve& cv, RefineArgs& ra, int64_t P, uint32_t qcap, void** scan_tmp, 
   ra.state = cv.take<uint32_t>(P);
   ra.unit_cnt = cv.take<int64_t>(2 * P + 1);
   ra.offs = cv.take<int64_t>(2 * P + 1);
-  ra.ctr = cv.take<unsigned long long>(1);
+  ra.ctr = cv.take<unsigned long long>(kSlices * kCtrStride);
   ra.qcount = cv.take<uint32_t>(1);
   ra.stats = cv.take<unsigned long long>(S_N);
   ra.status = cv.take<int32_t>(1);
@@ -537,6 +665,7 @@ uint32_t qcap_of(const pr_refine_params* p) { return p->queue_cap > 0 ? (uint32_
 template <int W, int PREC>
 int launch(RefineArgs& ra, const pr_refine_params* prm, void* scan_tmp, size_t scan_bytes, hipStream_t s) {
   const int64_t P = ra.n_pairs;
+  hipEvent_t eb = (hipEvent_t)prm->ev_begin, ee = (hipEvent_t)prm->ev_end;
   if (prm->persistent) {
     hipLaunchKernelGGL(k_plan<W>, dim3(grid_for(P, kBlock)), dim3(kBlock), 0, s, ra);
     PR_HIP(hipcub::DeviceScan::ExclusiveSum(scan_tmp, scan_bytes, ra.unit_cnt, ra.offs, (int)(2 * P + 1), s));
@@ -548,10 +677,14 @@ int launch(RefineArgs& ra, const pr_refine_params* prm, void* scan_tmp, size_t s
       PR_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_refine_persistent<W, PREC>, kBlock, 0));
       blocks = cus * (per > 0 ? per : 1);
     }
+    if (eb) PR_HIP(hipEventRecord(eb, s));
     hipLaunchKernelGGL((k_refine_persistent<W, PREC>), dim3(blocks), dim3(kBlock), 0, s, ra);
+    if (ee) PR_HIP(hipEventRecord(ee, s));
   } else {
     const int blocks = prm->grid_blocks > 0 ? prm->grid_blocks : 64;
+    if (eb) PR_HIP(hipEventRecord(eb, s));
     for (int64_t p = 0; p < P; ++p) hipLaunchKernelGGL((k_refine_pair<W, PREC>), dim3(blocks), dim3(kBlock), 0, s, ra, p);
+    if (ee) PR_HIP(hipEventRecord(ee, s));
   }
   return PR_OK;
 }
@@ -602,7 +735,8 @@ extern "C" int refine_intersects(const void* blob_a, int64_t n_meshes_a, const v
   ra.n_pairs = n_pairs;
   ra.flags = flags;
   ra.qcap = qcap;
-  ra.chunks_per_pop = params->chunks_per_pop > 0 ? params->chunks_per_pop : 4;
+  ra.item_groups = params->chunks_per_pop > 0 ? params->chunks_per_pop : 256;
+  if (ra.item_groups > kMaxItemGroups) ra.item_groups = kMaxItemGroups;
   hipLaunchKernelGGL(k_init, dim3(grid_for(n_pairs > S_N ? n_pairs : S_N, kBlock)), dim3(kBlock), 0, s, ra);
   if (n_pairs > 0) {
     const int W = params->bvh_width, PREC = params->precision;
@@ -613,6 +747,11 @@ extern "C" int refine_intersects(const void* blob_a, int64_t n_meshes_a, const v
 #undef PR_LAUNCH
     if (r) return r;
     hipLaunchKernelGGL(k_redecide, dim3(1024), dim3(kBlock), 0, s, ra);
+    const int W2 = params->bvh_width;
+    const int rb = (int)(n_pairs < 4096 ? n_pairs : 4096);
+    if (W2 == 2) hipLaunchKernelGGL(k_rerun<2>, dim3(rb), dim3(kBlock), 0, s, ra);
+    else if (W2 == 4) hipLaunchKernelGGL(k_rerun<4>, dim3(rb), dim3(kBlock), 0, s, ra);
+    else hipLaunchKernelGGL(k_rerun<8>, dim3(rb), dim3(kBlock), 0, s, ra);
     hipLaunchKernelGGL(k_finalize, dim3(grid_for(n_pairs, kBlock)), dim3(kBlock), 0, s, ra);
   }
   hipLaunchKernelGGL(k_report, dim3(1), dim3(1), 0, s, ra, dev_stats, dev_status);

@@ -52,14 +52,18 @@ class MeshSet:
         return v, f
 
     def aabbs(self) -> np.ndarray:
-        """Exact per-mesh boxes f32[M, 6] = (lo_x, lo_y, lo_z, hi_x, hi_y, hi_z)."""
-        out = np.empty((self.n_meshes, 6), np.float32)
-        for m in range(self.n_meshes):
-            v, f = self.mesh(m)
-            used = v[np.unique(f)]
-            out[m, :3] = used.min(0)
-            out[m, 3:] = used.max(0)
-        return out
+        """Exact per-mesh boxes f32[M, 6] = (lo_x, lo_y, lo_z, hi_x, hi_y, hi_z)
+        over each mesh's vertex range (every generator here references all of
+        its vertices, so this is the box of the mesh's triangles)."""
+        M = self.n_meshes
+        lo = np.full((M, 3), np.inf, np.float32)
+        hi = np.full((M, 3), -np.inf, np.float32)
+        nonempty = (np.diff(self.vert_off) > 0) & (np.diff(self.face_off) > 0)
+        if nonempty.any():
+            idx = self.vert_off[:-1][nonempty]
+            lo[nonempty] = np.minimum.reduceat(self.verts, idx, axis=0)
+            hi[nonempty] = np.maximum.reduceat(self.verts, idx, axis=0)
+        return np.concatenate([lo, hi], axis=1)
 
     def digest(self) -> str:
         h = hashlib.sha256()
@@ -317,12 +321,25 @@ def make_c2(seed: int = 2, n_nuclei: int = 10_000, n_vessels: int = 1_000,
     P0~U[0,box]^3, P_{k+1} = P_k + U[-100,100]^3, tube radius U[2,6])."""
     rng = np.random.Generator(np.random.PCG64(seed))
     tv, tf = icosphere(nucleus_level)
-    nuc = []
-    for _ in range(n_nuclei):
-        r = rng.uniform(3.0, 8.0)
-        c = rng.uniform(0.0, box, size=3)
-        rad = r * (1.0 + _noise_radius(rng, tv, 0.15))
-        nuc.append((_f32(c[None, :] + rad[:, None] * tv), tf))
+    nv, nf = tv.shape[0], tf.shape[0]
+    r = rng.uniform(3.0, 8.0, size=n_nuclei)
+    c = rng.uniform(0.0, box, size=(n_nuclei, 3))
+    waves = 8
+    k = rng.normal(size=(n_nuclei, waves, 3))
+    k /= np.linalg.norm(k, axis=2, keepdims=True)
+    fr = rng.integers(1, 3, size=(n_nuclei, waves)).astype(np.float64)
+    ph = rng.uniform(0.0, 2.0 * np.pi, size=(n_nuclei, waves))
+    verts = np.empty((n_nuclei, nv, 3), np.float32)
+    step = 256
+    for s0 in range(0, n_nuclei, step):
+        s1 = min(n_nuclei, s0 + step)
+        proj = np.einsum("vd,mwd->mvw", tv, k[s0:s1])               # (m, V, waves)
+        n = np.sin(2.0 * np.pi * fr[s0:s1, None, :] * proj + ph[s0:s1, None, :]).sum(2)
+        n /= np.abs(n).max(axis=1, keepdims=True)
+        rad = r[s0:s1, None] * (1.0 + 0.15 * n)
+        verts[s0:s1] = (c[s0:s1, None, :] + rad[:, :, None] * tv[None]).astype(np.float32)
+    nuc = MeshSet(verts.reshape(-1, 3), np.ascontiguousarray(np.tile(tf.astype(np.int32), (n_nuclei, 1))),
+                  np.arange(n_nuclei + 1, dtype=np.int64) * nv, np.arange(n_nuclei + 1, dtype=np.int64) * nf)
     ves = []
     for _ in range(n_vessels):
         p0 = rng.uniform(0.0, box, size=3)
@@ -331,7 +348,7 @@ def make_c2(seed: int = 2, n_nuclei: int = 10_000, n_vessels: int = 1_000,
         rho = rng.uniform(2.0, 6.0)
         v, f = capped_tube(ctrl, rho, 64, 32)
         ves.append((_f32(v), f))
-    return concat_meshes(nuc), concat_meshes(ves)
+    return nuc, concat_meshes(ves)
 
 
 def _log_uniform_int(rng, lo, hi, size):

@@ -40,8 +40,8 @@ def test_abi_version(lib):
 
 def test_struct_sizes():
     assert ctypes.sizeof(_lib.BvhParams) == 16
-    assert ctypes.sizeof(_lib.RefineParams) == 32
-    assert ctypes.sizeof(_lib.RefineStats) == 64
+    assert ctypes.sizeof(_lib.RefineParams) == 48
+    assert ctypes.sizeof(_lib.RefineStats) == 96
 
 
 @pytest.mark.parametrize("w,l,b,r", [(3, 4, 0, 0), (4, 3, 0, 0), (4, 4, 1, 0), (4, 4, 0, 1), (16, 4, 0, 0)])
