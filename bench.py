@@ -109,6 +109,8 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--skip-cpu", action="store_true")
     ap.add_argument("--skip-plain", action="store_true")
+    ap.add_argument("--calibrate-copy-mib", type=int, default=0,
+                    help="also run one device-to-device copy of this many MiB (HBM counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: candidate pairs shard independently across GPUs, but no "
@@ -182,7 +184,12 @@ def main():
         args.steps, ms_step, kern_ms, refine_ms, filter_ms, n_true))
 
     W = args.width
-    alg_bytes = 24 * st["segments"] + 24 * st["groups"] + 28 * W * st["node_visits"] + 36 * st["tri_fetches"]
+    # algorithmic bytes of one traversal launch: every group box read by the cull,
+    # the box and the 64 segments of every traced group, one node per wave-level
+    # visit (28 W bytes of boxes and child references) and one triangle per
+    # wave-level leaf fetch
+    alg_bytes = (24 * st["groups"] + 24 * st["groups_box_pass"] + 24 * st["segments"]
+                 + 28 * W * st["node_visits"] + 36 * st["tri_fetches"])
     achieved = alg_bytes / (kern_ms * 1e-3) / 1e9
     traffic = None
     if os.path.exists(TRAFFIC_FILE):
@@ -195,6 +202,9 @@ def main():
 
     out_pairs = pairs.cpu().numpy()
     gflags = flags.cpu().numpy()
+    ea = ga.edge_counts().cpu().numpy().astype(np.int64)
+    eb = gb.edge_counts().cpu().numpy().astype(np.int64)
+    nominal_segments = int((ea[out_pairs[:, 0]] + eb[out_pairs[:, 1]]).sum()) if P else 0
     plain = None
     if not args.skip_plain:
         pe0, pe1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -230,12 +240,22 @@ def main():
                    "precision": ["fp32 filter + fp64/exact fallback", "fp64/exact", "forced deferral"][args.precision],
                    "refine": "one persistent launch (batched)", "step": "filter + refine + compact"},
         "segment_queries_per_s": st["segments"] / (refine_ms * 1e-3),
+        "nominal_segments": nominal_segments,
+        "nominal_segment_queries_per_s": nominal_segments / (refine_ms * 1e-3),
         "refine_pairs_per_s": P / (refine_ms * 1e-3),
         "refine_ms": refine_ms, "filter_ms": filter_ms, "build_ms": build_ms,
         "roofline": roofline, "cpu_baseline": cpu, "plain_per_pair": plain,
         "stats": st,
         "retest_fraction": (st["fp32_ambiguous"] / st["tri_tests"]) if st["tri_tests"] else 0.0,
     }
+    if args.calibrate_copy_mib > 0:
+        n = args.calibrate_copy_mib << 20
+        src = torch.ones(n // 4, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log("calibration copy of %d MiB done" % args.calibrate_copy_mib)
     print(json.dumps(line), flush=True)
 
 
