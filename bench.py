@@ -63,6 +63,10 @@ def make_workload(name: str):
     if name == "c4":
         A, B, pairs, _ = synth.make_c4()
         return A, B, pairs, "precision stress: 2,000 pairs of level-4 icospheres on a 2^-10 grid"
+    if name == "c3":
+        A, B, pairs = synth.make_c3()
+        return A, B, pairs, ("batching: 50,000 candidate pairs from a pool of 4,096 meshes (geodesic spheres and "
+                             "capped tubes) with face counts log-uniform in [500, 100,000], FP32")
     raise SystemExit("unknown workload " + name)
 
 
@@ -106,6 +110,10 @@ def main():
     ap.add_argument("--width", type=int, default=4)
     ap.add_argument("--leaf", type=int, default=4)
     ap.add_argument("--precision", type=int, default=0)
+    ap.add_argument("--schedule", type=int, default=1)
+    ap.add_argument("--autotune", action="store_true", help="pick width, leaf size and schedule first")
+    ap.add_argument("--compare-precision", action="store_true",
+                    help="also time the FP64/exact-only precision mode, batched and per pair")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--skip-cpu", action="store_true")
     ap.add_argument("--skip-plain", action="store_true")
@@ -126,6 +134,19 @@ def main():
     log("generated %s in %.1f s: %d+%d meshes, %d+%d triangles" % (
         args.workload, time.perf_counter() - t, A.n_meshes, B.n_meshes, A.faces.shape[0], B.faces.shape[0]))
 
+    tuned = None
+    if args.autotune:
+        from paper_2609_24513_amd import autotune
+        pairs_for_tune = given_pairs
+        if pairs_for_tune is None:
+            from paper_2609_24513_amd import synth
+            pairs_for_tune = synth.candidate_pairs(A.aabbs(), B.aabbs()).astype(np.int32)
+        tuned = autotune.tune(A, B, pairs_for_tune, log=log)
+        args.width, args.leaf, args.schedule = (tuned["best"]["width"], tuned["best"]["leaf_size"],
+                                                tuned["best"]["schedule"])
+        log("autotune picked W=%d L=%d schedule=%d (%.1f s, cached=%s)" % (
+            args.width, args.leaf, args.schedule, tuned["tune_seconds"], tuned["cached"]))
+
     ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     ev0.record()
     ga = pa.MeshBlob.build(A, width=args.width, leaf_size=args.leaf, check_status=False)
@@ -141,7 +162,7 @@ def main():
     P = int(first.shape[0])
     cfg_events = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
                   for _ in range(args.steps)]
-    base_cfg = dict(persistent=1, precision=args.precision)
+    base_cfg = dict(persistent=1, precision=args.precision, schedule=args.schedule)
     ws = pa.refine_workspace(P, args.width, pa.RefineConfig(**base_cfg))
     flags = torch.empty(P, dtype=torch.uint8, device="cuda")
     stats = torch.zeros(len(pa.STATS_FIELDS), dtype=torch.int64, device="cuda")
@@ -198,31 +219,46 @@ def main():
             traffic = tr.get("hbm_bytes_per_launch")
     roofline = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-                "kernel": "k_refine_persistent", "kernel_ms": kern_ms, "algorithmic_bytes": int(alg_bytes)}
+                "kernel": "k_refine_persistent" if args.schedule != 2 else "k_refine_wave",
+                "kernel_ms": kern_ms, "algorithmic_bytes": int(alg_bytes)}
 
     out_pairs = pairs.cpu().numpy()
     gflags = flags.cpu().numpy()
     ea = ga.edge_counts().cpu().numpy().astype(np.int64)
     eb = gb.edge_counts().cpu().numpy().astype(np.int64)
     nominal_segments = int((ea[out_pairs[:, 0]] + eb[out_pairs[:, 1]]).sum()) if P else 0
+    def one_run(persistent, precision):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        k0, k1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        fl = torch.empty(P, dtype=torch.uint8, device="cuda")
+        cfg = pa.RefineConfig(persistent=persistent, precision=precision, schedule=args.schedule,
+                              ev_begin=k0, ev_end=k1)
+        w_ = pa.refine_workspace(P, W, cfg)
+        pa.refine(ga, gb, pairs, cfg, ws=w_, flags=fl)  # warm
+        torch.cuda.synchronize()
+        e0.record()
+        _, pst, pstatus = pa.refine(ga, gb, pairs, cfg, ws=w_, flags=fl)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1)
+        return {"refine_ms": ms, "kernels_ms": k0.elapsed_time(k1), "pairs_per_s": P / (ms * 1e-3),
+                "same_flags": bool(np.array_equal(fl.cpu().numpy(), gflags)),
+                "stats": pa.stats_dict(pst)}
+
     plain = None
     if not args.skip_plain:
-        pe0, pe1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        ke0, ke1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        pflags = torch.empty(P, dtype=torch.uint8, device="cuda")
-        pcfg = pa.RefineConfig(persistent=0, precision=args.precision, ev_begin=ke0, ev_end=ke1)
-        pws = pa.refine_workspace(P, W, pcfg)
-        pa.refine(ga, gb, pairs, pcfg, ws=pws, flags=pflags)  # warm
-        torch.cuda.synchronize()
-        pe0.record()
-        _, pst, pstatus = pa.refine(ga, gb, pairs, pcfg, ws=pws, flags=pflags)
-        pe1.record()
-        torch.cuda.synchronize()
-        pms = pe0.elapsed_time(pe1)
-        same = bool(np.array_equal(pflags.cpu().numpy(), gflags))
-        plain = {"refine_ms": pms, "kernels_ms": ke0.elapsed_time(ke1), "pairs_per_s": P / (pms * 1e-3),
-                 "launches": P, "same_flags": same, "batched_speedup": pms / refine_ms}
-        log("plain per-pair launches: %.2f ms (%.1fx slower), same flags: %s" % (pms, pms / refine_ms, same))
+        plain = one_run(0, args.precision)
+        plain["launches"] = P
+        plain["batched_speedup"] = plain["refine_ms"] / refine_ms
+        log("plain per-pair launches: %.2f ms (%.1fx slower), same flags: %s" % (
+            plain["refine_ms"], plain["batched_speedup"], plain["same_flags"]))
+    precision_cmp = None
+    if args.compare_precision:
+        precision_cmp = {"batched_fp64_exact": one_run(1, 1)}
+        if not args.skip_plain:
+            precision_cmp["per_pair_fp64_exact"] = one_run(0, 1)
+        for k, v in precision_cmp.items():
+            log("%s: %.2f ms, same flags: %s" % (k, v["refine_ms"], v["same_flags"]))
 
     cpu = None
     if not args.skip_cpu:
@@ -238,13 +274,15 @@ def main():
         "config": {"workload": desc, "workload_id": args.workload, "candidate_pairs": P,
                    "intersecting_pairs": n_true, "bvh_width": W, "leaf_size": args.leaf,
                    "precision": ["fp32 filter + fp64/exact fallback", "fp64/exact", "forced deferral"][args.precision],
-                   "refine": "one persistent launch (batched)", "step": "filter + refine + compact"},
+                   "refine": "one persistent launch (batched)", "schedule": args.schedule,
+                   "step": ("filter + refine + compact" if given is None else "refine + compact (pairs given)")},
         "segment_queries_per_s": st["segments"] / (refine_ms * 1e-3),
         "nominal_segments": nominal_segments,
         "nominal_segment_queries_per_s": nominal_segments / (refine_ms * 1e-3),
         "refine_pairs_per_s": P / (refine_ms * 1e-3),
         "refine_ms": refine_ms, "filter_ms": filter_ms, "build_ms": build_ms,
         "roofline": roofline, "cpu_baseline": cpu, "plain_per_pair": plain,
+        "precision_comparison": precision_cmp, "autotune": tuned,
         "stats": st,
         "retest_fraction": (st["fp32_ambiguous"] / st["tri_tests"]) if st["tri_tests"] else 0.0,
     }

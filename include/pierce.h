@@ -154,7 +154,10 @@ typedef struct {
   int32_t grid_blocks; /* persistent launch: blocks of 256 threads (0 = default) */
   int32_t chunks_per_pop; /* persistent launch: 64-segment groups per work item
                              (0 = default 256; at most 1024) */
-  int32_t reserved[2]; /* must be 0 */
+  int32_t schedule;    /* persistent launch: 0 = default (1); 1 = the four waves of a
+                          block share one work item (they cull its groups and drain the
+                          survivors together); 2 = each wave owns one work item */
+  int32_t reserved;    /* must be 0 */
   void* ev_begin;      /* optional hipEvent_t (or NULL), recorded on `stream` just before the
                           traversal kernel(s), for timing them alone */
   void* ev_end;        /* optional hipEvent_t (or NULL), recorded just after them */

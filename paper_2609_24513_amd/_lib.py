@@ -42,7 +42,8 @@ class RefineParams(ctypes.Structure):
     _fields_ = [("bvh_width", ctypes.c_int32), ("persistent", ctypes.c_int32),
                 ("precision", ctypes.c_int32), ("queue_cap", ctypes.c_int32),
                 ("grid_blocks", ctypes.c_int32), ("chunks_per_pop", ctypes.c_int32),
-                ("reserved", ctypes.c_int32 * 2), ("ev_begin", ctypes.c_void_p), ("ev_end", ctypes.c_void_p)]
+                ("schedule", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("ev_begin", ctypes.c_void_p), ("ev_end", ctypes.c_void_p)]
 
 
 class RefineStats(ctypes.Structure):

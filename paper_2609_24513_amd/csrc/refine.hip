@@ -302,28 +302,26 @@ __global__ void k_init(RefineArgs ra) {
   }
 }
 
-// Coarse cull of a direction: does box `b` meet any leaf box of the target
-// tree within the first levels?  Conservative (true when unsure).
+// Coarse cull of a direction: does box `b` meet the target mesh box, a child
+// box of its root and, for an inner child, one of that child's child boxes?
+// Conservative: every triangle lies inside the boxes of its ancestors.
 template <int W>
 __device__ bool coarse_meet(const float* b, const BlobView& T, const MeshDesc& tm) {
   if (tm.root == kEmpty) return false;
+  if (!box_meet(b, tm.box[0], tm.box[1], tm.box[2], tm.box[3], tm.box[4], tm.box[5])) return false;
   const Node<W>* nodes = reinterpret_cast<const Node<W>*>(T.nodes);
-  int32_t stk[24];
-  int32_t dep[24];
-  int sp = 0, visits = 0;
-  stk[sp] = tm.root; dep[sp] = 1; ++sp;
-  while (sp > 0) {
-    --sp;
-    int32_t n = stk[sp], d = dep[sp];
-    if (++visits > 48) return true;
-    const Node<W>* nd = nodes + n;
-    for (int c = 0; c < W; ++c) {
-      int32_t ch = nd->child[c];
-      if (ch == kEmpty) continue;
-      if (!box_meet(b, nd->lo[0][c], nd->lo[1][c], nd->lo[2][c], nd->hi[0][c], nd->hi[1][c], nd->hi[2][c])) continue;
-      if (ch < 0 || d >= 4 || sp >= 24) return true;
-      stk[sp] = ch; dep[sp] = d + 1; ++sp;
-    }
+  const Node<W>* root = nodes + tm.root;
+  for (int c = 0; c < W; ++c) {
+    const int32_t ch = root->child[c];
+    if (ch == kEmpty) continue;
+    if (!box_meet(b, root->lo[0][c], root->lo[1][c], root->lo[2][c], root->hi[0][c], root->hi[1][c], root->hi[2][c]))
+      continue;
+    if (ch < 0) return true;
+    const Node<W>* n2 = nodes + ch;
+    for (int d = 0; d < W; ++d)
+      if (n2->child[d] != kEmpty &&
+          box_meet(b, n2->lo[0][d], n2->lo[1][d], n2->lo[2][d], n2->hi[0][d], n2->hi[1][d], n2->hi[2][d]))
+        return true;
   }
   return false;
 }
@@ -492,6 +490,71 @@ __global__ __launch_bounds__(kBlock) void k_refine_persistent(RefineArgs ra) {
   flush_stats(st, ra);
 }
 
+// Schedule 2: every wave pops and finishes its own work items (no block
+// synchronisation); the group cull is the same lane-parallel test.
+template <int W, int PREC>
+__global__ __launch_bounds__(kBlock) void k_refine_wave(RefineArgs ra) {
+  constexpr int CAP = stack_cap<W>();
+  __shared__ int32_t s_node[kWaves][CAP];
+  __shared__ uint64_t s_mask[kWaves][CAP];
+  const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const BlobView A = view_of(ra.blob_a), B = view_of(ra.blob_b);
+  if (!blobs_ok(A, B, ra, W)) return;
+  const int64_t U = 2 * ra.n_pairs;
+  const int64_t total = ra.offs[U];
+  WaveStats st;
+#pragma unroll
+  for (int k = 0; k < S_N; ++k) st.v[k] = 0;
+  const int home = (int)(blockIdx.x % kSlices);
+  for (int sl = 0; sl < kSlices; ++sl) {
+    const int cid = (home + sl) % kSlices;
+    const int64_t lo = total * cid / kSlices, hi = total * (cid + 1) / kSlices;
+    if (lo >= hi) continue;
+    for (;;) {
+      unsigned long long k = 0;
+      if (lane == 0) k = atomicAdd(ra.ctr + kCtrStride * cid, 1ull);
+      const int64_t idx = lo + (int64_t)uni64(k);
+      if (idx >= hi) break;
+      const int64_t u = find_unit(ra.offs, U, idx);
+      const int64_t j = idx - ra.offs[u];
+      const int32_t pair = uni((int32_t)(u >> 1));
+      const int32_t dir = uni((int32_t)(u & 1));
+      const int32_t ia = ra.pairs[2 * (int64_t)pair], jb = ra.pairs[2 * (int64_t)pair + 1];
+      const BlobView& S = dir == 0 ? A : B;
+      const BlobView& T = dir == 0 ? B : A;
+      const MeshDesc sm = dir == 0 ? A.mesh[ia] : B.mesh[jb];
+      const MeshDesc tm = dir == 0 ? B.mesh[jb] : A.mesh[ia];
+      if (tm.root == kEmpty) continue;
+      const bool safe = (sm.flags & tm.flags & kMeshSafe) != 0;
+      const int32_t c0 = (int32_t)(j * ra.item_groups);
+      const int32_t c1 = min(c0 + ra.item_groups, sm.n_chunks);
+      st.v[S_GROUPS] += (uint64_t)(c1 - c0);
+      bool done = false;
+      for (int32_t base = c0; base < c1 && !done; base += kChunk) {
+        if (load_state(ra.state + pair)) break;
+        const int32_t c = base + lane;
+        bool pass = false;
+        if (c < c1) {
+          const float* cbp = S.cbox + 8 * ((int64_t)sm.chunk_base + c);
+          float g[6] = {cbp[0], cbp[1], cbp[2], cbp[3], cbp[4], cbp[5]};
+          pass = group_may_hit<W>(g, T, tm);
+        }
+        uint64_t mask = ballot(pass);
+        st.v[S_GBOX] += (uint64_t)__popcll(mask);
+        while (mask) {
+          const int bit = __builtin_ctzll(mask);
+          mask &= mask - 1;
+          if (trace_group<W, PREC>(S, T, sm, tm, base + bit, pair, dir, safe, ra, s_node[wv], s_mask[wv], st)) {
+            done = true;
+            break;
+          }
+        }
+      }
+    }
+  }
+  flush_stats(st, ra);
+}
+
 template <int W, int PREC>
 __global__ __launch_bounds__(kBlock) void k_refine_pair(RefineArgs ra, int64_t p) {
   constexpr int CAP = stack_cap<W>();
@@ -654,7 +717,8 @@ int check(int64_t P, const pr_refine_params* p) {
   if (p->precision < 0 || p->precision > 2) { set_error("precision must be 0, 1 or 2"); return PR_E_ARG; }
   if (p->persistent < 0 || p->persistent > 1) { set_error("persistent must be 0 or 1"); return PR_E_ARG; }
   if (p->queue_cap < 0 || p->grid_blocks < 0 || p->chunks_per_pop < 0) { set_error("negative launch parameter"); return PR_E_ARG; }
-  if (p->reserved[0] || p->reserved[1]) { set_error("reserved fields must be 0"); return PR_E_ARG; }
+  if (p->schedule < 0 || p->schedule > 2) { set_error("schedule must be 0, 1 or 2"); return PR_E_ARG; }
+  if (p->reserved) { set_error("reserved field must be 0"); return PR_E_ARG; }
   if (P < 0) { set_error("n_pairs < 0"); return PR_E_ARG; }
   if (P >= ((int64_t)1 << 30)) { set_error("n_pairs >= 2^30"); return PR_E_UNSUPPORTED; }
   return PR_OK;
@@ -669,16 +733,21 @@ int launch(RefineArgs& ra, const pr_refine_params* prm, void* scan_tmp, size_t s
   if (prm->persistent) {
     hipLaunchKernelGGL(k_plan<W>, dim3(grid_for(P, kBlock)), dim3(kBlock), 0, s, ra);
     PR_HIP(hipcub::DeviceScan::ExclusiveSum(scan_tmp, scan_bytes, ra.unit_cnt, ra.offs, (int)(2 * P + 1), s));
+    const bool wave_sched = prm->schedule == 2;
     int blocks = prm->grid_blocks;
     if (blocks <= 0) {
       int dev = 0, cus = 0, per = 0;
       PR_HIP(hipGetDevice(&dev));
       PR_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
-      PR_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_refine_persistent<W, PREC>, kBlock, 0));
+      if (wave_sched)
+        PR_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_refine_wave<W, PREC>, kBlock, 0));
+      else
+        PR_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_refine_persistent<W, PREC>, kBlock, 0));
       blocks = cus * (per > 0 ? per : 1);
     }
     if (eb) PR_HIP(hipEventRecord(eb, s));
-    hipLaunchKernelGGL((k_refine_persistent<W, PREC>), dim3(blocks), dim3(kBlock), 0, s, ra);
+    if (wave_sched) hipLaunchKernelGGL((k_refine_wave<W, PREC>), dim3(blocks), dim3(kBlock), 0, s, ra);
+    else hipLaunchKernelGGL((k_refine_persistent<W, PREC>), dim3(blocks), dim3(kBlock), 0, s, ra);
     if (ee) PR_HIP(hipEventRecord(ee, s));
   } else {
     const int blocks = prm->grid_blocks > 0 ? prm->grid_blocks : 64;

@@ -150,35 +150,37 @@ _GEO_CACHE = {}
 
 def geodesic_sphere(nu: int) -> Tuple[np.ndarray, np.ndarray]:
     """Unit geodesic sphere of frequency nu: each icosahedron face is cut into
-    nu^2 triangles on a barycentric grid, then projected.  V=10nu^2+2, F=20nu^2."""
+    nu^2 triangles on a barycentric grid, then projected.  V=10nu^2+2, F=20nu^2.
+    Grid points shared by neighbouring faces are merged by exact equality of
+    their (pre-projection) coordinates, which are computed identically."""
     if nu in _GEO_CACHE:
         v, f = _GEO_CACHE[nu]
         return v.copy(), f.copy()
     iv, ifc = _icosahedron()
-    index = {}
-    verts: List[np.ndarray] = []
-
-    def vid(corners, weights):
-        key = tuple(sorted((c, w) for c, w in zip(corners, weights) if w))
-        if key not in index:
-            p = sum(w * iv[c] for c, w in zip(corners, weights)) / nu
-            index[key] = len(verts)
-            verts.append(p / np.linalg.norm(p))
-        return index[key]
-
-    faces = []
+    ii, jj = [], []
+    for i in range(nu + 1):
+        for j in range(nu + 1 - i):
+            ii.append(i); jj.append(j)
+    ii = np.array(ii); jj = np.array(jj); kk = nu - ii - jj
+    local = -np.ones((nu + 1, nu + 1), np.int64)
+    local[ii, jj] = np.arange(ii.shape[0])
+    tri = []
+    for i in range(nu):
+        for j in range(nu - i):
+            tri.append((local[i, j], local[i + 1, j], local[i, j + 1]))
+            if i + j < nu - 1:
+                tri.append((local[i + 1, j], local[i + 1, j + 1], local[i, j + 1]))
+    tri = np.array(tri, np.int64)
+    npts = ii.shape[0]
+    pts = []
     for a, b, c in ifc:
-        grid = {}
-        for i in range(nu + 1):
-            for j in range(nu + 1 - i):
-                k = nu - i - j
-                grid[(i, j)] = vid((a, b, c), (k, i, j))
-        for i in range(nu):
-            for j in range(nu - i):
-                faces.append((grid[(i, j)], grid[(i + 1, j)], grid[(i, j + 1)]))
-                if i + j < nu - 1:
-                    faces.append((grid[(i + 1, j)], grid[(i + 1, j + 1)], grid[(i, j + 1)]))
-    out = (np.array(verts, np.float64), np.array(faces, np.int64))
+        pts.append(kk[:, None] * iv[a][None] + ii[:, None] * iv[b][None] + jj[:, None] * iv[c][None])
+    pts = np.concatenate(pts) / nu
+    uniq, inv = np.unique(pts, axis=0, return_inverse=True)
+    inv = inv.reshape(-1)
+    faces = np.concatenate([inv[f * npts + tri] for f in range(ifc.shape[0])])
+    verts = uniq / np.linalg.norm(uniq, axis=1, keepdims=True)
+    out = (verts, faces.astype(np.int64))
     _GEO_CACHE[nu] = out
     return out[0].copy(), out[1].copy()
 
@@ -390,16 +392,20 @@ def make_c3(seed: int = 3, n_pairs: int = 50_000, n_pool: int = 4096,
     filter yields at least n_pairs A x B candidates; the first n_pairs in a
     seeded shuffled order are kept, sorted by (i, j).  Returns (A, B, pairs)."""
     meshes, fcount, rng = make_c3_pool(seed, n_pool, f_lo, f_hi)
-    nA = (len(meshes) + 1) // 2
     unit_c = rng.uniform(0.0, 1.0, size=(len(meshes), 3))
+    lo = np.array([v.min(0) for v, _ in meshes])
+    hi = np.array([v.max(0) for v, _ in meshes])
     side = 4096.0
     while True:
-        placed = [(_f32(v + side * unit_c[i][None, :]), f) for i, (v, f) in enumerate(meshes)]
-        A = concat_meshes(placed[0::2]); B = concat_meshes(placed[1::2])
-        cand = candidate_pairs(A.aabbs(), B.aabbs())
+        off = side * unit_c
+        # fl(x + o) is monotone in x, so the placed FP32 box is the rounded placed box
+        box = np.concatenate([lo + off, hi + off], axis=1).astype(np.float32)
+        cand = candidate_pairs(box[0::2], box[1::2])
         if cand.shape[0] >= n_pairs or side < 1.0:
             break
         side /= 2.0
+    placed = [(_f32(v + off[i][None, :]), f) for i, (v, f) in enumerate(meshes)]
+    A = concat_meshes(placed[0::2]); B = concat_meshes(placed[1::2])
     order = rng.permutation(cand.shape[0])[:n_pairs]
     pairs = cand[np.sort(order)]
     return A, B, np.ascontiguousarray(pairs.astype(np.int32))

@@ -75,11 +75,12 @@ def _refine_params(**kw):
     p.queue_cap = kw.get("queue_cap", 0)
     p.grid_blocks = kw.get("grid_blocks", 0)
     p.chunks_per_pop = kw.get("chunks_per_pop", 0)
+    p.schedule = kw.get("schedule", 0)
     return p
 
 
 @pytest.mark.parametrize("kw", [dict(w=3), dict(precision=3), dict(persistent=2), dict(queue_cap=-1),
-                                dict(grid_blocks=-5)])
+                                dict(grid_blocks=-5), dict(schedule=3), dict(schedule=-1)])
 def test_refine_params_rejected(lib, kw):
     p = _refine_params(**kw)
     wb = ctypes.c_size_t(0)
@@ -90,7 +91,7 @@ def test_refine_params_rejected(lib, kw):
 
 def test_refine_reserved_and_sizes_rejected(lib):
     p = _refine_params()
-    p.reserved[0] = 1
+    p.reserved = 1
     wb = ctypes.c_size_t(0)
     assert lib.refine_workspace_bytes(10, ctypes.byref(p), ctypes.byref(wb)) == _lib.PR_E_ARG
     p = _refine_params()

@@ -47,12 +47,13 @@ def _run(env, A, B, pairs, width=4, leaf=4, **cfg):
     return flags.cpu().numpy(), pa.stats_dict(stats)
 
 
-CONFIGS = [dict(width=w, leaf=l, persistent=p, precision=q)
-           for w in (2, 4, 8) for l in (1, 4, 8) for p in (0, 1) for q in (0, 1, 2)
-           if not (l == 8 and q == 1)]
+CONFIGS = [dict(width=w, leaf=l, persistent=p, precision=q, schedule=sc)
+           for w in (2, 4, 8) for l in (1, 4, 8) for p in (0, 1) for q in (0, 1, 2) for sc in (1, 2)
+           if not (l == 8 and q == 1) and not (p == 0 and sc == 2)]
 
 
-@pytest.mark.parametrize("c", CONFIGS, ids=lambda c: "w%d_l%d_p%d_q%d" % (c["width"], c["leaf"], c["persistent"], c["precision"]))
+@pytest.mark.parametrize("c", CONFIGS, ids=lambda c: "w%d_l%d_p%d_q%d_s%d" % (
+    c["width"], c["leaf"], c["persistent"], c["precision"], c["schedule"]))
 def test_hand_cases_all_configs(env, c):
     torch, pa, synth, oracle = env
     A, B, pairs, exp = _hand(synth)
@@ -122,6 +123,80 @@ def test_c4_precision_stress_sample(env):
             results[(q, p)] = st
     assert results[(0, 1)]["fp32_ambiguous"] > 0
     assert results[(0, 1)]["exact_decided"] > 0
+
+
+def test_c4_full_precision_stress_zero_mismatches(env):
+    """All 2,000 pairs of the precision-stress config, both launch forms."""
+    torch, pa, synth, oracle = env
+    A, B, pairs, cls = synth.make_c4()
+    want = oracle.join(A, B, pairs, mode=1)
+    for p in (1, 0):
+        got, st = _run(env, A, B, pairs, persistent=p, precision=0)
+        assert int((got != want).sum()) == 0, (p, np.nonzero(got != want)[0][:10])
+        assert st["fp32_ambiguous"] > 0 and st["exact_decided"] > 0
+    contact = np.array([c != "random" for c in cls])
+    assert want[contact].all()
+
+
+def test_c3_scaled_all_widths_and_schedules(env):
+    """Batching-shaped pairs (face counts log-uniform in [500, 20,000]) for every
+    width, leaf size and schedule; also a tiny work-item size."""
+    torch, pa, synth, oracle = env
+    A, B, pairs = synth.make_c3(n_pairs=3000, n_pool=256, f_hi=20000.0)
+    want = oracle.join(A, B, pairs, mode=1)
+    assert 0 < want.sum() < pairs.shape[0]
+    for w in (2, 4, 8):
+        for l in (1, 2, 4, 8):
+            ga = pa.MeshBlob.build(A, width=w, leaf_size=l)
+            gb = pa.MeshBlob.build(B, width=w, leaf_size=l)
+            for cfg in (dict(schedule=1), dict(schedule=2), dict(schedule=1, chunks_per_pop=1),
+                        dict(schedule=2, chunks_per_pop=64)):
+                flags, stats, status = pa.refine(ga, gb, pairs, pa.RefineConfig(persistent=1, **cfg))
+                torch.cuda.synchronize()
+                assert int(status.item()) == 0
+                assert np.array_equal(flags.cpu().numpy(), want), (w, l, cfg)
+
+
+def test_autotune_small(env):
+    torch, pa, synth, oracle = env
+    from paper_2609_24513_amd import autotune
+    A, B, pairs = synth.make_c3(n_pairs=1500, n_pool=128, f_hi=8000.0)
+    res = autotune.tune(A, B, pairs, widths=(2, 4), leaves=(1, 4), schedules=(1, 2), frac=0.2, reps=2,
+                        use_cache=False)
+    assert len(res["table"]) == 8
+    b = res["best"]
+    assert b["ms"] == min(r["ms"] for r in res["table"])
+    assert res["per_bucket"]
+    want = oracle.join(A, B, pairs, mode=1)
+    got, _ = _run(env, A, B, pairs, width=b["width"], leaf=b["leaf_size"], persistent=1, schedule=b["schedule"])
+    assert np.array_equal(got, want)
+
+
+def test_c2_full_size_against_oracle(env):
+    """The pathology-shaped workload at full size, in the launch configuration
+    the benchmark times (persistent, W=4, L=4): every candidate pair."""
+    torch, pa, synth, oracle = env
+    A, B = synth.make_c2()
+    ga, gb = pa.MeshBlob.build(A), pa.MeshBlob.build(B)
+    pairs = pa.filter_pairs(ga, gb)
+    hp = pairs.cpu().numpy()
+    assert np.array_equal(hp, synth.candidate_pairs(A.aabbs(), B.aabbs()))
+    want = oracle.join(A, B, hp, mode=1)
+    flags, stats, status = pa.refine(ga, gb, pairs, pa.RefineConfig(persistent=1))
+    torch.cuda.synchronize()
+    assert int(status.item()) == 0
+    assert int((flags.cpu().numpy() != want).sum()) == 0
+
+
+def test_c3_full_size_against_oracle(env):
+    """The batching workload at full size (50,000 pairs, faces up to 100,000
+    per mesh), one persistent launch: every pair checked."""
+    torch, pa, synth, oracle = env
+    A, B, pairs = synth.make_c3()
+    want = oracle.join(A, B, pairs, mode=1)
+    got, st = _run(env, A, B, pairs, persistent=1)
+    assert int((got != want).sum()) == 0
+    assert st["pairs_true"] == int(want.sum())
 
 
 def test_c2_scaled_against_oracle(env):
