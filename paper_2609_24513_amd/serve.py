@@ -1,0 +1,286 @@
+"""Serving loop: continuous batching of join queries over resident meshes.
+
+A request is a query box; its answer is every pair (r, s) of the two resident
+datasets whose closed mesh boxes meet each other and the query box and whose
+surfaces share a point.  The loop keeps both datasets' BVH blobs in HBM and
+runs without blocking the host:
+
+  * arrivals go to a FIFO;
+  * a batch is opened whenever a slot (a HIP stream with preallocated device
+    buffers) is free: it admits waiting requests in arrival order while the
+    HBM reserved by in-flight requests stays within the budget (a request
+    reserves room for `max_pairs` candidate pairs; when nothing is in flight
+    one request is always admitted, so nothing waits forever and nothing is
+    dropped);
+  * phase 1 runs each admitted request's candidate filter into its own region
+    of the slot and copies the counts to pinned host memory;
+  * phase 2, once the counts are on the host, gathers all the batch's pairs
+    into one list and refines them in ONE persistent launch, then copies the
+    flags to pinned host memory;
+  * a request completes when its flags are on the host; its latency is
+    completion time minus arrival time.
+
+Batches on different slots overlap on the device, and new requests are
+admitted while earlier ones are still running.  The per-request plain path
+(`run_plain`) serves the same trace first-in first-out, one request at a
+time, with one refinement launch per candidate pair.
+"""
+from __future__ import annotations
+
+import ctypes
+import dataclasses
+import time
+from collections import deque
+from typing import List, Optional, Sequence
+
+import numpy as np
+
+from . import _lib
+
+__all__ = ["Request", "JoinServer", "make_trace", "run_plain", "latency_summary"]
+
+
+@dataclasses.dataclass
+class Request:
+    rid: int
+    t_arrival: float            # seconds from the start of the trace
+    box: np.ndarray             # f32[6] query box
+    t_done: float = -1.0
+    pairs: Optional[np.ndarray] = None   # int32[n, 2]
+    flags: Optional[np.ndarray] = None   # uint8[n]
+
+    @property
+    def latency(self) -> float:
+        return self.t_done - self.t_arrival
+
+
+def make_trace(box_r: np.ndarray, box_s: np.ndarray, n: int, lam: float, seed: int = 5,
+               k_lo: float = 1.0, k_hi: float = 5000.0, space: float = 58.5, max_pairs: int = 5000):
+    """Poisson arrivals at rate lam; each request has a target size
+    k ~ LogUniform[k_lo, k_hi] and a cubic box of side k^(1/3) at a uniform
+    centre, redrawn until it selects between 1 and max_pairs candidate pairs
+    (counted on the host with exact closed-box comparisons)."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    t = 0.0
+    out = []
+    for rid in range(n):
+        t += rng.exponential(1.0 / lam)
+        while True:
+            k = float(np.exp(rng.uniform(np.log(k_lo), np.log(k_hi))))
+            side = k ** (1.0 / 3.0)
+            c = rng.uniform(0.0, space, size=3)
+            q = np.concatenate([c - side / 2, c + side / 2]).astype(np.float32)
+            cnt = count_candidates(box_r, box_s, q)
+            if 1 <= cnt <= max_pairs:
+                break
+        out.append(Request(rid, t, q))
+    return out
+
+
+def count_candidates(box_r, box_s, q) -> int:
+    sr = np.nonzero(np.all(box_r[:, :3] <= q[3:], 1) & np.all(box_r[:, 3:] >= q[:3], 1))[0]
+    ss = np.nonzero(np.all(box_s[:, :3] <= q[3:], 1) & np.all(box_s[:, 3:] >= q[:3], 1))[0]
+    if sr.size == 0 or ss.size == 0:
+        return 0
+    a, b = box_r[sr], box_s[ss]
+    lo = np.maximum(np.maximum(a[:, None, :3], b[None, :, :3]), q[None, None, :3])
+    hi = np.minimum(np.minimum(a[:, None, 3:], b[None, :, 3:]), q[None, None, 3:])
+    return int(np.all(lo <= hi, axis=2).sum())
+
+
+def latency_summary(reqs: Sequence[Request]) -> dict:
+    lat = np.array([r.latency for r in reqs]) * 1e3
+    pairs = int(sum(0 if r.pairs is None else r.pairs.shape[0] for r in reqs))
+    span = max(r.t_done for r in reqs) - min(r.t_arrival for r in reqs)
+    return {"requests": len(reqs), "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
+            "mean_ms": float(lat.mean()), "max_ms": float(lat.max()), "pairs": pairs,
+            "pairs_per_s": pairs / span if span > 0 else 0.0, "span_s": span}
+
+
+class _Slot:
+    def __init__(self, torch, pa, R, S, max_req: int, max_pairs: int, cfg):
+        self.torch = torch
+        self.stream = torch.cuda.Stream()
+        cap = max_req * max_pairs
+        self.region = torch.empty((cap, 2), dtype=torch.int32, device="cuda")
+        self.counts = torch.zeros(max_req, dtype=torch.int64, device="cuda")
+        self.counts_h = torch.zeros(max_req, dtype=torch.int64, pin_memory=True)
+        self.batch = torch.empty((cap, 2), dtype=torch.int32, device="cuda")
+        self.flags = torch.empty(cap, dtype=torch.uint8, device="cuda")
+        self.flags_h = torch.zeros(cap, dtype=torch.uint8, pin_memory=True)
+        self.status = torch.zeros(1, dtype=torch.int32, device="cuda")
+        self.status_h = torch.zeros(1, dtype=torch.int32, pin_memory=True)
+        lib = _lib.load()
+        wb = ctypes.c_size_t(0)
+        _lib.check(lib.filter_aabb_pairs_ws_bytes(R.n_meshes, S.n_meshes, ctypes.byref(wb)))
+        self.fws = torch.empty(max(256, wb.value), dtype=torch.uint8, device="cuda")
+        self.rws = pa.refine_workspace(cap, R.width, cfg)
+        self.reqs: List[Request] = []
+        self.phase = 0          # 0 free, 1 filtering, 2 refining
+        self.event = None
+        self.n_total = 0
+        self.offsets = []
+
+    def bytes(self) -> int:
+        t = [self.region, self.counts, self.batch, self.flags, self.fws, self.rws]
+        return int(sum(x.numel() * x.element_size() for x in t))
+
+
+class JoinServer:
+    """Continuous-batching server over two resident MeshBlobs (see module doc)."""
+
+    def __init__(self, R, S, max_req_per_batch: int = 32, max_pairs: int = 5000, slots: int = 3,
+                 hbm_budget: int = 1 << 30, cfg=None):
+        import torch
+        import paper_2609_24513_amd as pa
+        self.torch, self.pa = torch, pa
+        self.R, self.S = R, S
+        self.max_pairs = max_pairs
+        self.max_req = max_req_per_batch
+        self.cfg = cfg or pa.RefineConfig(persistent=1)
+        self.slots = [_Slot(torch, pa, R, S, max_req_per_batch, max_pairs, self.cfg) for _ in range(slots)]
+        self.hbm_budget = int(hbm_budget)
+        # device bytes a request holds while in flight: its pair region, gathered
+        # pairs, flags and refine workspace share
+        self.req_bytes = max_pairs * (8 + 8 + 1) + self.slots[0].rws.numel() // max(1, max_req_per_batch)
+        self.in_flight_bytes = 0
+        self.batches = 0
+        self.max_in_flight = 0
+
+    # --- phases ------------------------------------------------------------
+    def _start(self, slot: _Slot, reqs: List[Request]):
+        torch, lib = self.torch, _lib.load()
+        slot.reqs = reqs
+        slot.phase = 1
+        with torch.cuda.stream(slot.stream):
+            sp = int(slot.stream.cuda_stream)
+            for k, r in enumerate(reqs):
+                q = torch.as_tensor(r.box).to("cuda", non_blocking=False)
+                r._q = q  # keep alive until the stream has used it
+                _lib.check(lib.filter_aabb_pairs(
+                    self.R.ptr, self.R.n_meshes, self.S.ptr, self.S.n_meshes, q.data_ptr(),
+                    slot.region.data_ptr() + k * self.max_pairs * 8, self.max_pairs,
+                    slot.counts.data_ptr() + 8 * k, slot.fws.data_ptr(), slot.fws.numel(), sp))
+            slot.counts_h[:len(reqs)].copy_(slot.counts[:len(reqs)], non_blocking=True)
+            slot.event = torch.cuda.Event()
+            slot.event.record(slot.stream)
+
+    def _refine(self, slot: _Slot):
+        torch, pa = self.torch, self.pa
+        counts = slot.counts_h[:len(slot.reqs)].numpy().astype(np.int64)
+        counts = np.minimum(counts, self.max_pairs)
+        slot.offsets = np.concatenate([[0], np.cumsum(counts)])
+        n = int(slot.offsets[-1])
+        slot.n_total = n
+        slot.phase = 2
+        with torch.cuda.stream(slot.stream):
+            for k, c in enumerate(counts):
+                if c:
+                    o = int(slot.offsets[k])
+                    slot.batch[o:o + c].copy_(slot.region[k * self.max_pairs:k * self.max_pairs + c], non_blocking=True)
+            if n:
+                pa.refine(self.R, self.S, slot.batch[:n], self.cfg, ws=slot.rws, flags=slot.flags,
+                          status=slot.status, stream=slot.stream)
+                slot.flags_h[:n].copy_(slot.flags[:n], non_blocking=True)
+                slot.status_h.copy_(slot.status, non_blocking=True)
+            slot.event = torch.cuda.Event()
+            slot.event.record(slot.stream)
+        # the gathered pair list is kept for the results
+        slot._batch_view = slot.batch[:n]
+
+    def _finish(self, slot: _Slot, now: float):
+        n = slot.n_total
+        if n and int(slot.status_h.item()) != 0:
+            raise RuntimeError("refine status %d" % int(slot.status_h.item()))
+        flags = slot.flags_h[:n].numpy().copy()
+        pairs = slot._batch_view.cpu().numpy() if n else np.zeros((0, 2), np.int32)
+        for k, r in enumerate(slot.reqs):
+            a, b = int(slot.offsets[k]), int(slot.offsets[k + 1])
+            r.pairs = pairs[a:b]
+            r.flags = flags[a:b]
+            r.t_done = now
+        self.in_flight_bytes -= self.req_bytes * len(slot.reqs)
+        slot.reqs = []
+        slot.phase = 0
+        slot.event = None
+
+    # --- loop ----------------------------------------------------------------
+    def run(self, trace: Sequence[Request], realtime: bool = True) -> List[Request]:
+        """Serves `trace` (requests sorted by arrival).  With realtime=True the
+        requests are released at their arrival times on the host clock."""
+        pending = deque()
+        todo = deque(sorted(trace, key=lambda r: r.t_arrival))
+        t0 = time.perf_counter()
+        done = 0
+        n = len(todo)
+        while done < n:
+            now = time.perf_counter() - t0
+            while todo and (todo[0].t_arrival <= now or not realtime):
+                r = todo.popleft()
+                if not realtime:
+                    r.t_arrival = now
+                pending.append(r)
+            progressed = False
+            for slot in self.slots:
+                if slot.phase and slot.event.query():
+                    if slot.phase == 1:
+                        self._refine(slot)
+                    else:
+                        k = len(slot.reqs)
+                        self._finish(slot, time.perf_counter() - t0)
+                        done += k
+                    progressed = True
+            for slot in self.slots:
+                if slot.phase == 0 and pending:
+                    batch = []
+                    while pending and len(batch) < self.max_req:
+                        fits = self.in_flight_bytes + self.req_bytes <= self.hbm_budget
+                        if not fits and (self.in_flight_bytes > 0 or batch):
+                            break
+                        batch.append(pending.popleft())
+                        self.in_flight_bytes += self.req_bytes
+                    if batch:
+                        self._start(slot, batch)
+                        self.batches += 1
+                        progressed = True
+                    busy = sum(1 for s in self.slots if s.phase)
+                    self.max_in_flight = max(self.max_in_flight, busy)
+            if not progressed:
+                time.sleep(0.0001)
+        return list(trace)
+
+    def query_alone(self, box: np.ndarray):
+        """One request on its own (filter, then refine): (pairs, flags)."""
+        pa, torch = self.pa, self.torch
+        pairs = pa.filter_pairs(self.R, self.S, query_box=box, cap=self.max_pairs)
+        if pairs.shape[0] == 0:
+            return np.zeros((0, 2), np.int32), np.zeros(0, np.uint8)
+        flags, _, status = pa.refine(self.R, self.S, pairs, self.cfg)
+        torch.cuda.synchronize()
+        assert int(status.item()) == 0
+        return pairs.cpu().numpy(), flags.cpu().numpy()
+
+
+def run_plain(R, S, trace: Sequence[Request], realtime: bool = True, max_pairs: int = 5000) -> List[Request]:
+    """First-in first-out, one request at a time: filter, then one refinement
+    launch per candidate pair, then the flags back to the host."""
+    import torch
+    import paper_2609_24513_amd as pa
+    cfg = pa.RefineConfig(persistent=0)
+    ws = pa.refine_workspace(max_pairs, R.width, cfg)
+    reqs = sorted(trace, key=lambda r: r.t_arrival)
+    t0 = time.perf_counter()
+    for r in reqs:
+        now = time.perf_counter() - t0
+        if realtime and now < r.t_arrival:
+            time.sleep(r.t_arrival - now)
+        pairs = pa.filter_pairs(R, S, query_box=r.box, cap=max_pairs)
+        if pairs.shape[0]:
+            flags, _, status = pa.refine(R, S, pairs, cfg, ws=ws)
+            r.flags = flags.cpu().numpy()
+            r.pairs = pairs.cpu().numpy()
+        else:
+            r.flags = np.zeros(0, np.uint8)
+            r.pairs = np.zeros((0, 2), np.int32)
+        r.t_done = time.perf_counter() - t0
+    return list(trace)
