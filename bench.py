@@ -162,7 +162,7 @@ def main():
     ap.add_argument("--width", type=int, default=4)
     ap.add_argument("--leaf", type=int, default=4)
     ap.add_argument("--precision", type=int, default=0)
-    ap.add_argument("--schedule", type=int, default=1)
+    ap.add_argument("--schedule", type=int, default=3)
     ap.add_argument("--autotune", action="store_true", help="pick width, leaf size and schedule first")
     ap.add_argument("--serve-requests", type=int, default=2000, help="requests at the highest serving rate")
     ap.add_argument("--plain-requests", type=int, default=400, help="requests replayed on the plain path")
@@ -276,7 +276,7 @@ def main():
             traffic = tr.get("hbm_bytes_per_launch")
     roofline = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-                "kernel": "k_refine_persistent" if args.schedule != 2 else "k_refine_wave",
+                "kernel": {1: "k_refine_persistent", 2: "k_refine_wave", 3: "k_cull + k_trace"}[args.schedule],
                 "kernel_ms": kern_ms, "algorithmic_bytes": int(alg_bytes)}
 
     out_pairs = pairs.cpu().numpy()

@@ -154,10 +154,13 @@ typedef struct {
   int32_t grid_blocks; /* persistent launch: blocks of 256 threads (0 = default) */
   int32_t chunks_per_pop; /* persistent launch: 64-segment groups per work item
                              (0 = default 256; at most 1024) */
-  int32_t schedule;    /* persistent launch: 0 = default (1); 1 = the four waves of a
+  int32_t schedule;    /* persistent launch: 0 = default (3); 1 = the four waves of a
                           block share one work item (they cull its groups and drain the
-                          survivors together); 2 = each wave owns one work item */
-  int32_t reserved;    /* must be 0 */
+                          survivors together); 2 = each wave owns one work item;
+                          3 = two phases: every work item's groups are culled and the
+                          surviving groups queued, then waves pop single groups */
+  int32_t survivor_cap; /* schedule 3: capacity of the surviving-group queues (0 = default
+                          1<<22); groups beyond it are traced during the cull */
   void* ev_begin;      /* optional hipEvent_t (or NULL), recorded on `stream` just before the
                           traversal kernel(s), for timing them alone */
   void* ev_end;        /* optional hipEvent_t (or NULL), recorded just after them */
@@ -176,6 +179,8 @@ typedef struct {
   uint64_t tri_fetches;           /* wave-level leaf triangle loads */
   uint64_t groups_box_pass;       /* groups whose box meets the target mesh box (segments loaded) */
   uint64_t groups_traversed;      /* groups with a segment meeting the target mesh box */
+  uint64_t max_group_node_visits; /* most node visits of one traced group */
+  uint64_t max_group_leaf_fetches;/* most leaf triangle fetches of one traced group */
 } pr_refine_stats;
 
 /* Workspace bytes for refine_intersects on n_pairs pairs. */

@@ -132,7 +132,8 @@ def filter_pairs(A: MeshBlob, B: MeshBlob, query_box=None, cap: Optional[int] = 
 
 class RefineConfig:
     def __init__(self, persistent: int = 1, precision: int = 0, queue_cap: int = 0, grid_blocks: int = 0,
-                 chunks_per_pop: int = 0, schedule: int = 0, ev_begin=None, ev_end=None):
+                 chunks_per_pop: int = 0, schedule: int = 0, survivor_cap: int = 0, ev_begin=None,
+                 ev_end=None):
         self.ev_begin = ev_begin  # optional torch.cuda.Event recorded around the traversal kernel(s)
         self.ev_end = ev_end
         self.persistent = persistent
@@ -141,6 +142,7 @@ class RefineConfig:
         self.grid_blocks = grid_blocks
         self.chunks_per_pop = chunks_per_pop
         self.schedule = schedule
+        self.survivor_cap = survivor_cap
 
     def params(self, width: int) -> _lib.RefineParams:
         p = _lib.RefineParams()
@@ -151,6 +153,7 @@ class RefineConfig:
         p.grid_blocks = self.grid_blocks
         p.chunks_per_pop = self.chunks_per_pop
         p.schedule = self.schedule
+        p.survivor_cap = self.survivor_cap
         p.ev_begin = _event_handle(self.ev_begin)
         p.ev_end = _event_handle(self.ev_end)
         return p

@@ -42,7 +42,7 @@ class RefineParams(ctypes.Structure):
     _fields_ = [("bvh_width", ctypes.c_int32), ("persistent", ctypes.c_int32),
                 ("precision", ctypes.c_int32), ("queue_cap", ctypes.c_int32),
                 ("grid_blocks", ctypes.c_int32), ("chunks_per_pop", ctypes.c_int32),
-                ("schedule", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("schedule", ctypes.c_int32), ("survivor_cap", ctypes.c_int32),
                 ("ev_begin", ctypes.c_void_p), ("ev_end", ctypes.c_void_p)]
 
 
@@ -52,7 +52,8 @@ class RefineStats(ctypes.Structure):
                 ("fp64_filter_ambiguous", ctypes.c_uint64), ("exact_decided", ctypes.c_uint64),
                 ("pairs_true", ctypes.c_uint64), ("queue_overflow", ctypes.c_uint64),
                 ("groups", ctypes.c_uint64), ("tri_fetches", ctypes.c_uint64),
-                ("groups_box_pass", ctypes.c_uint64), ("groups_traversed", ctypes.c_uint64)]
+                ("groups_box_pass", ctypes.c_uint64), ("groups_traversed", ctypes.c_uint64),
+                ("max_group_node_visits", ctypes.c_uint64), ("max_group_leaf_fetches", ctypes.c_uint64)]
 
 
 STATS_FIELDS = [f for f, _ in RefineStats._fields_]

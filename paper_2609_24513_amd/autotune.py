@@ -66,7 +66,7 @@ def _time_refine(pa, torch, ga, gb, pairs_dev, cfg, reps: int) -> float:
 
 
 def tune(A, B, pairs, widths: Sequence[int] = (2, 4, 8), leaves: Sequence[int] = (1, 2, 4, 8),
-         schedules: Sequence[int] = (1, 2), frac: float = 0.02, n_buckets: int = 4, reps: int = 3,
+         schedules: Sequence[int] = (1, 2, 3), frac: float = 0.02, n_buckets: int = 4, reps: int = 3,
          seed: int = 0, use_cache: bool = True, log=None) -> Dict:
     """Returns {"best": {"width", "leaf_size", "schedule", "ms"}, "table": [...],
     "per_bucket": {bucket: best config}, "sample": n}."""

@@ -41,8 +41,10 @@ constexpr float kSlabS = 0x1p-120f;
 constexpr float kZeroInv = 0x1p100f;
 constexpr float kZeroBias = 0x1p16f;
 
+// Entries on a wave's stack: nodes and leaves; a node pops one entry and
+// pushes at most W, over at most kMaxDepth node levels plus the leaf level.
 template <int W>
-constexpr int stack_cap() { return (W - 1) * kMaxDepth + 1; }
+constexpr int stack_cap() { return (W - 1) * (kMaxDepth + 1) + 1; }
 
 struct BlobView {
   const MeshDesc* mesh;
@@ -70,7 +72,8 @@ __device__ __forceinline__ BlobView view_of(const char* blob) {
 }
 
 enum {
-  S_SEG = 0, S_VISIT, S_TESTS, S_AMB32, S_AMB64, S_EXACT, S_TRUE, S_QOVER, S_GROUPS, S_TRIF, S_GBOX, S_GTRAV, S_N
+  S_SEG = 0, S_VISIT, S_TESTS, S_AMB32, S_AMB64, S_EXACT, S_TRUE, S_QOVER, S_GROUPS, S_TRIF, S_GBOX, S_GTRAV,
+  S_MAXV, S_MAXL, S_N
 };
 
 struct RefineArgs {
@@ -90,6 +93,10 @@ struct RefineArgs {
   unsigned long long* stats;  // [S_N]
   int32_t* status;            // [1]
   int32_t item_groups;        // groups per work item
+  int2* surv;                 // kSlices queues of surviving groups (unit, group)
+  uint32_t surv_cap;          // entries per queue
+  unsigned long long* surv_cnt;  // kSlices fill counters (stride kCtrStride)
+  unsigned long long* surv_pop;  // kSlices pop counters (stride kCtrStride)
 };
 
 constexpr int kSlices = 8;     // one pop counter per XCD
@@ -174,6 +181,15 @@ __device__ bool trace_group(const BlobView& S, const BlobView& T, const MeshDesc
   uint64_t m0 = ballot(valid && slab(r, tm.box[0], tm.box[1], tm.box[2], tm.box[3], tm.box[4], tm.box[5]));
   if (m0 == 0) return false;
   st.v[S_GTRAV] += 1;
+  const uint64_t v0 = st.v[S_VISIT], l0 = st.v[S_TRIF];
+  struct MaxOnExit {
+    WaveStats& s; uint64_t v0, l0;
+    __device__ ~MaxOnExit() {
+      const uint64_t dv = s.v[S_VISIT] - v0, dl = s.v[S_TRIF] - l0;
+      if (dv > s.v[S_MAXV]) s.v[S_MAXV] = dv;
+      if (dl > s.v[S_MAXL]) s.v[S_MAXL] = dl;
+    }
+  } max_on_exit{st, v0, l0};
   constexpr int CAP = stack_cap<W>();
   int top = 0;
   if (lane == 0) { snode[0] = tm.root; smask[0] = m0; }
@@ -182,40 +198,22 @@ __device__ bool trace_group(const BlobView& S, const BlobView& T, const MeshDesc
   const Node<W>* nodes = reinterpret_cast<const Node<W>*>(T.nodes);
   while (top > 0) {
     --top;
-    const int32_t node = uni(snode[top]);
+    const int32_t ref = uni(snode[top]);
     const uint64_t nm = uni64(smask[top]);
     if (!rerun && (++iter & 15) == 0 && load_state(ra.state + pair)) return true;
-    st.v[S_VISIT] += 1;
-    const Node<W>* nd = nodes + node;
     const bool on = (nm >> lane) & 1ull;
-#pragma unroll
-    for (int c = 0; c < W; ++c) {
-      const int32_t ch = nd->child[c];
-      if (ch == kEmpty) continue;
-      const float lx = nd->lo[0][c], ly = nd->lo[1][c], lz = nd->lo[2][c];
-      const float hx = nd->hi[0][c], hy = nd->hi[1][c], hz = nd->hi[2][c];
-      if (!box_meet(cb, lx, ly, lz, hx, hy, hz)) continue;
-      const uint64_t hm = ballot(on && slab(r, lx, ly, lz, hx, hy, hz));
-      if (hm == 0) continue;
-      if (ch >= 0) {
-        if (top >= CAP) {  // cannot happen for a valid blob (depth <= kMaxDepth)
-          if (lane == 0) atomicMin(ra.status, (int32_t)PR_E_UNSUPPORTED);
-          return true;
-        }
-        if (lane == 0) { snode[top] = ch; smask[top] = hm; }
-        ++top;
-        continue;
-      }
-      const int32_t lr = ~ch;
+    if (ref < 0) {
+      // leaf: the lanes of the mask test their segment against its triangles
+      const int32_t lr = ~ref;
       const int32_t first = lr >> 3;
       const int cnt = (lr & 7) + 1;
-      const bool lon = (hm >> lane) & 1ull;
       st.v[S_TRIF] += (uint64_t)cnt;
+      const uint64_t lanes = (uint64_t)__popcll(nm);
       for (int t = 0; t < cnt; ++t) {
         const float* tp = T.tris + 9 * (int64_t)(first + t);
         const f3 a = tri_vertex(tp, 0), b = tri_vertex(tp, 1), c3 = tri_vertex(tp, 2);
         int res = kMiss;
-        if (lon) {
+        if (on) {
           if (PREC == 0) {
             res = safe ? seg_tri_f32(p, q, a, b, c3) : kAmbig;
           } else if (PREC == 1) {
@@ -225,8 +223,8 @@ __device__ bool trace_group(const BlobView& S, const BlobView& T, const MeshDesc
             res = kAmbig;
           }
         }
-        st.v[S_TESTS] += (uint64_t)__popcll(hm);
-        if (PREC == 1) st.v[S_EXACT] += (uint64_t)__popcll(hm);
+        st.v[S_TESTS] += lanes;
+        if (PREC == 1) st.v[S_EXACT] += lanes;
         if (ballot(res == kHit)) {
           if (lane == 0 && !rerun) mark_true(ra.state + pair);
           return true;
@@ -249,6 +247,25 @@ __device__ bool trace_group(const BlobView& S, const BlobView& T, const MeshDesc
           }
         }
       }
+      continue;
+    }
+    st.v[S_VISIT] += 1;
+    const Node<W>* nd = nodes + ref;
+#pragma unroll
+    for (int c = 0; c < W; ++c) {
+      const int32_t ch = nd->child[c];
+      if (ch == kEmpty) continue;
+      const float lx = nd->lo[0][c], ly = nd->lo[1][c], lz = nd->lo[2][c];
+      const float hx = nd->hi[0][c], hy = nd->hi[1][c], hz = nd->hi[2][c];
+      if (!box_meet(cb, lx, ly, lz, hx, hy, hz)) continue;
+      const uint64_t hm = ballot(on && slab(r, lx, ly, lz, hx, hy, hz));
+      if (hm == 0) continue;
+      if (top >= CAP) {  // cannot happen for a valid blob (depth <= kMaxDepth)
+        if (lane == 0) atomicMin(ra.status, (int32_t)PR_E_UNSUPPORTED);
+        return true;
+      }
+      if (lane == 0) { snode[top] = ch; smask[top] = hm; }
+      ++top;
     }
   }
   return false;
@@ -273,8 +290,11 @@ __device__ bool trace_chunk(const BlobView& S, const BlobView& T, const MeshDesc
 __device__ __forceinline__ void flush_stats(const WaveStats& st, const RefineArgs& ra) {
   if ((threadIdx.x & 63) == 0) {
 #pragma unroll
-    for (int k = 0; k < S_N; ++k)
-      if (st.v[k]) atomicAdd(ra.stats + k, (unsigned long long)st.v[k]);
+    for (int k = 0; k < S_N; ++k) {
+      if (!st.v[k]) continue;
+      if (k == S_MAXV || k == S_MAXL) atomicMax(ra.stats + k, (unsigned long long)st.v[k]);
+      else atomicAdd(ra.stats + k, (unsigned long long)st.v[k]);
+    }
   }
 }
 
@@ -295,7 +315,11 @@ __global__ void k_init(RefineArgs ra) {
   int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   for (int64_t p = i; p < ra.n_pairs; p += (int64_t)gridDim.x * blockDim.x) ra.state[p] = 0u;
   if (i < S_N) ra.stats[i] = 0ull;
-  if (i < kSlices) ra.ctr[kCtrStride * i] = 0ull;
+  if (i < kSlices) {
+    ra.ctr[kCtrStride * i] = 0ull;
+    ra.surv_cnt[kCtrStride * i] = 0ull;
+    ra.surv_pop[kCtrStride * i] = 0ull;
+  }
   if (i == 0) {
     *ra.qcount = 0u;
     *ra.status = PR_OK;
@@ -408,7 +432,7 @@ __device__ __forceinline__ bool group_may_hit(const float* g, const BlobView& T,
 // append the survivors to a list in LDS, then drain that list dynamically,
 // one group per wave at a time.
 template <int W, int PREC>
-__global__ __launch_bounds__(kBlock) void k_refine_persistent(RefineArgs ra) {
+__global__ __launch_bounds__(kBlock, 5) void k_refine_persistent(RefineArgs ra) {
   constexpr int CAP = stack_cap<W>();
   __shared__ int32_t s_node[kWaves][CAP];
   __shared__ uint64_t s_mask[kWaves][CAP];
@@ -555,6 +579,124 @@ __global__ __launch_bounds__(kBlock) void k_refine_wave(RefineArgs ra) {
   flush_stats(st, ra);
 }
 
+// Schedule 3, phase 1: every wave takes work items in a fixed stride, culls
+// their groups lane-parallel and appends the surviving (unit, group) entries to
+// the queue of its block's slice (blockIdx % kSlices, the XCD the block runs
+// on, so phase 2 mostly finds the pair's data in the same L2).  A group that
+// does not fit in the queue is traced here.
+template <int W, int PREC>
+__global__ __launch_bounds__(kBlock) void k_cull(RefineArgs ra) {
+  constexpr int CAP = stack_cap<W>();
+  __shared__ int32_t s_node[kWaves][CAP];
+  __shared__ uint64_t s_mask[kWaves][CAP];
+  const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const BlobView A = view_of(ra.blob_a), B = view_of(ra.blob_b);
+  if (!blobs_ok(A, B, ra, W)) return;
+  const int64_t U = 2 * ra.n_pairs;
+  const int64_t total = ra.offs[U];
+  const int slice = (int)(blockIdx.x % kSlices);
+  int2* q = ra.surv + (int64_t)slice * ra.surv_cap;
+  WaveStats st;
+#pragma unroll
+  for (int k = 0; k < S_N; ++k) st.v[k] = 0;
+  const int64_t nw = (int64_t)gridDim.x * kWaves;
+  for (int64_t idx = (int64_t)blockIdx.x * kWaves + wv; idx < total; idx += nw) {
+    const int64_t u = find_unit(ra.offs, U, idx);
+    const int64_t j = idx - ra.offs[u];
+    const int32_t pair = uni((int32_t)(u >> 1));
+    const int32_t dir = uni((int32_t)(u & 1));
+    const int32_t ia = ra.pairs[2 * (int64_t)pair], jb = ra.pairs[2 * (int64_t)pair + 1];
+    const BlobView& S = dir == 0 ? A : B;
+    const BlobView& T = dir == 0 ? B : A;
+    const MeshDesc sm = dir == 0 ? A.mesh[ia] : B.mesh[jb];
+    const MeshDesc tm = dir == 0 ? B.mesh[jb] : A.mesh[ia];
+    if (tm.root == kEmpty) continue;
+    const int32_t c0 = (int32_t)(j * ra.item_groups);
+    const int32_t c1 = min(c0 + ra.item_groups, sm.n_chunks);
+    st.v[S_GROUPS] += (uint64_t)(c1 - c0);
+    for (int32_t base = c0; base < c1; base += kChunk) {
+      const int32_t c = base + lane;
+      bool pass = false;
+      if (c < c1) {
+        const float* cbp = S.cbox + 8 * ((int64_t)sm.chunk_base + c);
+        float g[6] = {cbp[0], cbp[1], cbp[2], cbp[3], cbp[4], cbp[5]};
+        pass = group_may_hit<W>(g, T, tm);
+      }
+      const uint64_t mask = ballot(pass);
+      if (!mask) continue;
+      const int n = __popcll(mask);
+      st.v[S_GBOX] += (uint64_t)n;
+      unsigned long long b0 = 0;
+      if (lane == 0) b0 = atomicAdd(ra.surv_cnt + kCtrStride * slice, (unsigned long long)n);
+      const uint64_t b = uni64(b0);
+      const uint64_t pos = b + (uint64_t)lanes_below(mask);
+      if (pass && pos < ra.surv_cap) q[pos] = make_int2((int32_t)u, c);
+      uint64_t over = ballot(pass && pos >= ra.surv_cap);
+      if (over) {
+        const bool safe = (sm.flags & tm.flags & kMeshSafe) != 0;
+        while (over) {
+          const int bit = __builtin_ctzll(over);
+          over &= over - 1;
+          if (load_state(ra.state + pair)) break;
+          if (trace_group<W, PREC>(S, T, sm, tm, base + bit, pair, dir, safe, ra, s_node[wv], s_mask[wv], st)) break;
+        }
+      }
+    }
+  }
+  flush_stats(st, ra);
+}
+
+// Schedule 3, phase 2: waves pop surviving groups, two at a time, from their
+// block's slice first and then from the others, and trace them.
+template <int W, int PREC>
+__global__ __launch_bounds__(kBlock, 5) void k_trace(RefineArgs ra) {
+  constexpr int CAP = stack_cap<W>();
+  constexpr int kPop = 2;
+  __shared__ int32_t s_node[kWaves][CAP];
+  __shared__ uint64_t s_mask[kWaves][CAP];
+  const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const BlobView A = view_of(ra.blob_a), B = view_of(ra.blob_b);
+  if (!blobs_ok(A, B, ra, W)) return;
+  WaveStats st;
+#pragma unroll
+  for (int k = 0; k < S_N; ++k) st.v[k] = 0;
+  const int home = (int)(blockIdx.x % kSlices);
+  int32_t cur_unit = -1;
+  MeshDesc sm, tm;
+  int32_t pair = 0, dir = 0;
+  bool safe = false;
+  for (int sl = 0; sl < kSlices; ++sl) {
+    const int cid = (home + sl) % kSlices;
+    const uint64_t filled = ra.surv_cnt[kCtrStride * cid];
+    const uint64_t n = filled < ra.surv_cap ? filled : ra.surv_cap;
+    const int2* q = ra.surv + (int64_t)cid * ra.surv_cap;
+    for (;;) {
+      unsigned long long k0 = 0;
+      if (lane == 0) k0 = atomicAdd(ra.surv_pop + kCtrStride * cid, (unsigned long long)kPop);
+      const uint64_t k = uni64(k0);
+      if (k >= n) break;
+      const uint64_t kend = k + kPop < n ? k + kPop : n;
+      for (uint64_t e = k; e < kend; ++e) {
+        const int2 it = q[e];
+        const int32_t unit = uni(it.x), group = uni(it.y);
+        if (unit != cur_unit) {
+          cur_unit = unit;
+          pair = unit >> 1;
+          dir = unit & 1;
+          const int32_t ia = ra.pairs[2 * (int64_t)pair], jb = ra.pairs[2 * (int64_t)pair + 1];
+          sm = dir == 0 ? A.mesh[ia] : B.mesh[jb];
+          tm = dir == 0 ? B.mesh[jb] : A.mesh[ia];
+          safe = (sm.flags & tm.flags & kMeshSafe) != 0;
+        }
+        if (load_state(ra.state + pair)) continue;
+        trace_group<W, PREC>(dir == 0 ? A : B, dir == 0 ? B : A, sm, tm, group, pair, dir, safe, ra, s_node[wv],
+                             s_mask[wv], st);
+      }
+    }
+  }
+  flush_stats(st, ra);
+}
+
 template <int W, int PREC>
 __global__ __launch_bounds__(kBlock) void k_refine_pair(RefineArgs ra, int64_t p) {
   constexpr int CAP = stack_cap<W>();
@@ -683,6 +825,8 @@ __global__ void k_report(RefineArgs ra, pr_refine_stats* out, int32_t* dev_statu
     out->tri_fetches = ra.stats[S_TRIF];
     out->groups_box_pass = ra.stats[S_GBOX];
     out->groups_traversed = ra.stats[S_GTRAV];
+    out->max_group_node_visits = ra.stats[S_MAXV];
+    out->max_group_leaf_fetches = ra.stats[S_MAXL];
   }
   if (dev_status) *dev_status = *ra.status;
 }
@@ -694,7 +838,8 @@ struct WsLayout {
   size_t scan_bytes;
 };
 
-int carve(Carve& cv, RefineArgs& ra, int64_t P, uint32_t qcap, void** scan_tmp, size_t* scan_bytes) {
+int carve(Carve& cv, RefineArgs& ra, int64_t P, uint32_t qcap, uint32_t surv_cap, void** scan_tmp,
+          size_t* scan_bytes) {
   ra.state = cv.take<uint32_t>(P);
   ra.unit_cnt = cv.take<int64_t>(2 * P + 1);
   ra.offs = cv.take<int64_t>(2 * P + 1);
@@ -703,6 +848,9 @@ int carve(Carve& cv, RefineArgs& ra, int64_t P, uint32_t qcap, void** scan_tmp, 
   ra.stats = cv.take<unsigned long long>(S_N);
   ra.status = cv.take<int32_t>(1);
   ra.queue = cv.take<int4>(qcap);
+  ra.surv_cnt = cv.take<unsigned long long>(kSlices * kCtrStride);
+  ra.surv_pop = cv.take<unsigned long long>(kSlices * kCtrStride);
+  ra.surv = cv.take<int2>((int64_t)kSlices * surv_cap);
   size_t b = 0;
   hipError_t e = hipcub::DeviceScan::ExclusiveSum(nullptr, b, (int64_t*)nullptr, (int64_t*)nullptr, (int)(2 * P + 1));
   if (e != hipSuccess) return hip_fail(e, "hipcub scan size");
@@ -717,14 +865,18 @@ int check(int64_t P, const pr_refine_params* p) {
   if (p->precision < 0 || p->precision > 2) { set_error("precision must be 0, 1 or 2"); return PR_E_ARG; }
   if (p->persistent < 0 || p->persistent > 1) { set_error("persistent must be 0 or 1"); return PR_E_ARG; }
   if (p->queue_cap < 0 || p->grid_blocks < 0 || p->chunks_per_pop < 0) { set_error("negative launch parameter"); return PR_E_ARG; }
-  if (p->schedule < 0 || p->schedule > 2) { set_error("schedule must be 0, 1 or 2"); return PR_E_ARG; }
-  if (p->reserved) { set_error("reserved field must be 0"); return PR_E_ARG; }
+  if (p->schedule < 0 || p->schedule > 3) { set_error("schedule must be 0, 1, 2 or 3"); return PR_E_ARG; }
+  if (p->survivor_cap < 0) { set_error("survivor_cap < 0"); return PR_E_ARG; }
   if (P < 0) { set_error("n_pairs < 0"); return PR_E_ARG; }
   if (P >= ((int64_t)1 << 30)) { set_error("n_pairs >= 2^30"); return PR_E_UNSUPPORTED; }
   return PR_OK;
 }
 
 uint32_t qcap_of(const pr_refine_params* p) { return p->queue_cap > 0 ? (uint32_t)p->queue_cap : (1u << 20); }
+uint32_t scap_of(const pr_refine_params* p) {
+  const uint32_t total = p->survivor_cap > 0 ? (uint32_t)p->survivor_cap : (1u << 22);
+  return (total + kSlices - 1) / kSlices;
+}
 
 template <int W, int PREC>
 int launch(RefineArgs& ra, const pr_refine_params* prm, void* scan_tmp, size_t scan_bytes, hipStream_t s) {
@@ -733,21 +885,31 @@ int launch(RefineArgs& ra, const pr_refine_params* prm, void* scan_tmp, size_t s
   if (prm->persistent) {
     hipLaunchKernelGGL(k_plan<W>, dim3(grid_for(P, kBlock)), dim3(kBlock), 0, s, ra);
     PR_HIP(hipcub::DeviceScan::ExclusiveSum(scan_tmp, scan_bytes, ra.unit_cnt, ra.offs, (int)(2 * P + 1), s));
-    const bool wave_sched = prm->schedule == 2;
+    const int sched = prm->schedule == 0 ? 3 : prm->schedule;
     int blocks = prm->grid_blocks;
+    int dev = 0, cus = 0, per = 0;
+    PR_HIP(hipGetDevice(&dev));
+    PR_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
     if (blocks <= 0) {
-      int dev = 0, cus = 0, per = 0;
-      PR_HIP(hipGetDevice(&dev));
-      PR_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
-      if (wave_sched)
+      if (sched == 2)
         PR_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_refine_wave<W, PREC>, kBlock, 0));
+      else if (sched == 3)
+        PR_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_trace<W, PREC>, kBlock, 0));
       else
         PR_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_refine_persistent<W, PREC>, kBlock, 0));
       blocks = cus * (per > 0 ? per : 1);
     }
     if (eb) PR_HIP(hipEventRecord(eb, s));
-    if (wave_sched) hipLaunchKernelGGL((k_refine_wave<W, PREC>), dim3(blocks), dim3(kBlock), 0, s, ra);
-    else hipLaunchKernelGGL((k_refine_persistent<W, PREC>), dim3(blocks), dim3(kBlock), 0, s, ra);
+    if (sched == 2) {
+      hipLaunchKernelGGL((k_refine_wave<W, PREC>), dim3(blocks), dim3(kBlock), 0, s, ra);
+    } else if (sched == 3) {
+      int per_cull = 0;
+      PR_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cull, k_cull<W, PREC>, kBlock, 0));
+      hipLaunchKernelGGL((k_cull<W, PREC>), dim3(cus * (per_cull > 0 ? per_cull : 1)), dim3(kBlock), 0, s, ra);
+      hipLaunchKernelGGL((k_trace<W, PREC>), dim3(blocks), dim3(kBlock), 0, s, ra);
+    } else {
+      hipLaunchKernelGGL((k_refine_persistent<W, PREC>), dim3(blocks), dim3(kBlock), 0, s, ra);
+    }
     if (ee) PR_HIP(hipEventRecord(ee, s));
   } else {
     const int blocks = prm->grid_blocks > 0 ? prm->grid_blocks : 64;
@@ -771,7 +933,7 @@ extern "C" int refine_workspace_bytes(int64_t n_pairs, const pr_refine_params* p
   RefineArgs ra{};
   void* t;
   size_t b;
-  r = carve(cv, ra, n_pairs, qcap_of(params), &t, &b);
+  r = carve(cv, ra, n_pairs, qcap_of(params), scap_of(params), &t, &b);
   if (r) return r;
   *ws_bytes = cv.used + 256;
   return PR_OK;
@@ -793,7 +955,8 @@ extern "C" int refine_intersects(const void* blob_a, int64_t n_meshes_a, const v
   void* scan_tmp = nullptr;
   size_t scan_bytes = 0;
   const uint32_t qcap = qcap_of(params);
-  r = carve(cv, ra, n_pairs, qcap, &scan_tmp, &scan_bytes);
+  const uint32_t scap = scap_of(params);
+  r = carve(cv, ra, n_pairs, qcap, scap, &scan_tmp, &scan_bytes);
   if (r) return r;
   if (cv.used > ws_bytes || !scan_tmp) { set_error("ws_bytes %zu < required %zu", ws_bytes, cv.used); return PR_E_CAPACITY; }
   ra.blob_a = (const char*)blob_a;
@@ -804,6 +967,7 @@ extern "C" int refine_intersects(const void* blob_a, int64_t n_meshes_a, const v
   ra.n_pairs = n_pairs;
   ra.flags = flags;
   ra.qcap = qcap;
+  ra.surv_cap = scap;
   ra.item_groups = params->chunks_per_pop > 0 ? params->chunks_per_pop : 256;
   if (ra.item_groups > kMaxItemGroups) ra.item_groups = kMaxItemGroups;
   hipLaunchKernelGGL(k_init, dim3(grid_for(n_pairs > S_N ? n_pairs : S_N, kBlock)), dim3(kBlock), 0, s, ra);

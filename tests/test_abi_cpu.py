@@ -41,7 +41,7 @@ def test_abi_version(lib):
 def test_struct_sizes():
     assert ctypes.sizeof(_lib.BvhParams) == 16
     assert ctypes.sizeof(_lib.RefineParams) == 48
-    assert ctypes.sizeof(_lib.RefineStats) == 96
+    assert ctypes.sizeof(_lib.RefineStats) == 112
 
 
 @pytest.mark.parametrize("w,l,b,r", [(3, 4, 0, 0), (4, 3, 0, 0), (4, 4, 1, 0), (4, 4, 0, 1), (16, 4, 0, 0)])
@@ -80,7 +80,7 @@ def _refine_params(**kw):
 
 
 @pytest.mark.parametrize("kw", [dict(w=3), dict(precision=3), dict(persistent=2), dict(queue_cap=-1),
-                                dict(grid_blocks=-5), dict(schedule=3), dict(schedule=-1)])
+                                dict(grid_blocks=-5), dict(schedule=4), dict(schedule=-1)])
 def test_refine_params_rejected(lib, kw):
     p = _refine_params(**kw)
     wb = ctypes.c_size_t(0)
@@ -91,7 +91,7 @@ def test_refine_params_rejected(lib, kw):
 
 def test_refine_reserved_and_sizes_rejected(lib):
     p = _refine_params()
-    p.reserved = 1
+    p.survivor_cap = -1
     wb = ctypes.c_size_t(0)
     assert lib.refine_workspace_bytes(10, ctypes.byref(p), ctypes.byref(wb)) == _lib.PR_E_ARG
     p = _refine_params()

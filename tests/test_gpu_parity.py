@@ -48,8 +48,8 @@ def _run(env, A, B, pairs, width=4, leaf=4, **cfg):
 
 
 CONFIGS = [dict(width=w, leaf=l, persistent=p, precision=q, schedule=sc)
-           for w in (2, 4, 8) for l in (1, 4, 8) for p in (0, 1) for q in (0, 1, 2) for sc in (1, 2)
-           if not (l == 8 and q == 1) and not (p == 0 and sc == 2)]
+           for w in (2, 4, 8) for l in (1, 4, 8) for p in (0, 1) for q in (0, 1, 2) for sc in (1, 2, 3)
+           if not (l == 8 and q == 1) and not (p == 0 and sc != 1)]
 
 
 @pytest.mark.parametrize("c", CONFIGS, ids=lambda c: "w%d_l%d_p%d_q%d_s%d" % (
@@ -149,8 +149,9 @@ def test_c3_scaled_all_widths_and_schedules(env):
         for l in (1, 2, 4, 8):
             ga = pa.MeshBlob.build(A, width=w, leaf_size=l)
             gb = pa.MeshBlob.build(B, width=w, leaf_size=l)
-            for cfg in (dict(schedule=1), dict(schedule=2), dict(schedule=1, chunks_per_pop=1),
-                        dict(schedule=2, chunks_per_pop=64)):
+            for cfg in (dict(schedule=1), dict(schedule=2), dict(schedule=3), dict(schedule=1, chunks_per_pop=1),
+                        dict(schedule=2, chunks_per_pop=64), dict(schedule=3, survivor_cap=50),
+                        dict(schedule=3, chunks_per_pop=64, survivor_cap=8)):
                 flags, stats, status = pa.refine(ga, gb, pairs, pa.RefineConfig(persistent=1, **cfg))
                 torch.cuda.synchronize()
                 assert int(status.item()) == 0
@@ -161,9 +162,9 @@ def test_autotune_small(env):
     torch, pa, synth, oracle = env
     from paper_2609_24513_amd import autotune
     A, B, pairs = synth.make_c3(n_pairs=1500, n_pool=128, f_hi=8000.0)
-    res = autotune.tune(A, B, pairs, widths=(2, 4), leaves=(1, 4), schedules=(1, 2), frac=0.2, reps=2,
+    res = autotune.tune(A, B, pairs, widths=(2, 4), leaves=(1, 4), schedules=(1, 2, 3), frac=0.2, reps=2,
                         use_cache=False)
-    assert len(res["table"]) == 8
+    assert len(res["table"]) == 12
     b = res["best"]
     assert b["ms"] == min(r["ms"] for r in res["table"])
     assert res["per_bucket"]
@@ -194,9 +195,10 @@ def test_c3_full_size_against_oracle(env):
     torch, pa, synth, oracle = env
     A, B, pairs = synth.make_c3()
     want = oracle.join(A, B, pairs, mode=1)
-    got, st = _run(env, A, B, pairs, persistent=1)
-    assert int((got != want).sum()) == 0
-    assert st["pairs_true"] == int(want.sum())
+    for sc in (3, 1):
+        got, st = _run(env, A, B, pairs, persistent=1, schedule=sc)
+        assert int((got != want).sum()) == 0, sc
+        assert st["pairs_true"] == int(want.sum())
 
 
 def test_c2_scaled_against_oracle(env):
