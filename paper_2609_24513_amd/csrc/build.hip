@@ -98,7 +98,7 @@ struct BuildArgs {
   int32_t* parent;       // [F] parent of internal node g
   int32_t* lparent;      // [F] parent of leaf position g
   float* nbox;           // [F][6]
-  int32_t* ncount;       // [F]
+  int32_t* nleaf;        // [F] triangles under each binary node
   int32_t* nfirst;       // [F]
   uint32_t* visit;       // [F]
   int64_t* nbound;       // [M+1] scanned node bounds
@@ -117,6 +117,8 @@ struct BuildArgs {
   uint64_t* ekey2;       // [3F] sorted (mesh, Morton) keys of unique edges
   int64_t* nscan;        // [M+1] scanned node bounds
   int64_t* chunk_scan;   // [M+1] scanned group counts
+  char* tnodes;          // [node_cap] nodes at bound-sized offsets, before compaction
+  int64_t* ncount;       // [M+1] nodes used per mesh, then scanned
 };
 
 // ---- step 1 ---------------------------------------------------------------
@@ -303,7 +305,7 @@ __device__ __forceinline__ void child_info(const BuildArgs& a, int32_t c, const 
     first = pos;
   } else {
     for (int k = 0; k < 6; ++k) box[k] = a.nbox[6 * (int64_t)c + k];
-    count = a.ncount[c];
+    count = a.nleaf[c];
     first = a.nfirst[c];
   }
 }
@@ -328,7 +330,7 @@ __global__ void k_refit(BuildArgs a, const int32_t* sorted_face) {
           a.nbox[6 * (int64_t)p + k] = fminf(bl[k], br[k]);
           a.nbox[6 * (int64_t)p + 3 + k] = fmaxf(bl[3 + k], br[3 + k]);
         }
-        a.ncount[p] = cl + cr;
+        a.nleaf[p] = cl + cr;
         a.nfirst[p] = fl < fr ? fl : fr;
         p = a.parent[p];
       }
@@ -362,7 +364,7 @@ __global__ void k_collapse(BuildArgs a, const int64_t* node_base_scan) {
     int64_t fbase = a.face_off[m];
     int64_t nb = node_base_scan[m];
     int64_t bound = node_base_scan[m + 1] - nb;
-    Node<W>* nodes = reinterpret_cast<Node<W>*>(a.nodes);
+    Node<W>* nodes = reinterpret_cast<Node<W>*>(a.tnodes);
     if (n == 0) {
       a.mesh[m].root = kEmpty;
       a.mesh[m].n_nodes = 0;
@@ -448,6 +450,39 @@ __global__ void k_collapse(BuildArgs a, const int64_t* node_base_scan) {
     a.mesh[m].root = (int32_t)nb;
     a.mesh[m].n_nodes = used;
     a.mesh[m].depth = depth;
+  }
+}
+
+// Compaction: the collapse reserved nodes_bound() slots per mesh; the used
+// nodes are copied to consecutive positions of the blob (internal child
+// references shifted by the same amount), so a query touches a dense array.
+__global__ void k_node_count(BuildArgs a) {
+  int64_t m = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  for (; m < a.n_meshes; m += (int64_t)gridDim.x * blockDim.x) a.ncount[m] = a.mesh[m].n_nodes;
+  if (blockIdx.x == 0 && threadIdx.x == 0) a.ncount[a.n_meshes] = 0;
+}
+
+template <int W>
+__global__ void k_node_copy(BuildArgs a, const int64_t* new_base) {
+  if (*a.status != INT_MAX) return;  // invalid input: the blob is not built
+  const Node<W>* src = reinterpret_cast<const Node<W>*>(a.tnodes);
+  Node<W>* dst = reinterpret_cast<Node<W>*>(a.nodes);
+  for (int64_t m = blockIdx.x; m < a.n_meshes; m += gridDim.x) {
+    const int32_t old_base = a.mesh[m].node_base;
+    const int32_t n = a.mesh[m].n_nodes;
+    const int64_t nb = new_base[m];
+    const int32_t shift = (int32_t)(nb - old_base);
+    for (int32_t k = threadIdx.x; k < n; k += blockDim.x) {
+      Node<W> nd = src[old_base + k];
+      for (int c = 0; c < W; ++c)
+        if (nd.child[c] >= 0 && nd.child[c] != kEmpty) nd.child[c] += shift;
+      dst[nb + k] = nd;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      a.mesh[m].node_base = (int32_t)nb;
+      a.mesh[m].root = n > 0 ? (int32_t)nb : kEmpty;
+    }
   }
 }
 
@@ -678,7 +713,8 @@ int end_bit_for(int64_t M) {
 
 // Carves the workspace; with base == nullptr only measures.  Sort temp sizes
 // are queried from hipCUB.
-int carve_ws(Carve& cv, BuildArgs& a, int64_t M, int64_t F, void** sort_tmp, size_t* sort_bytes) {
+int carve_ws(Carve& cv, BuildArgs& a, int64_t M, int64_t F, int64_t node_cap, int W, void** sort_tmp,
+             size_t* sort_bytes) {
   int64_t E3 = 3 * F;
   a.status = cv.take<int32_t>(4);
   a.meshctr = cv.take<int32_t>(4);
@@ -694,7 +730,7 @@ int carve_ws(Carve& cv, BuildArgs& a, int64_t M, int64_t F, void** sort_tmp, siz
   a.parent = cv.take<int32_t>(F);
   a.lparent = cv.take<int32_t>(F);
   a.nbox = cv.take<float>(6 * F);
-  a.ncount = cv.take<int32_t>(F);
+  a.nleaf = cv.take<int32_t>(F);
   a.nfirst = cv.take<int32_t>(F);
   a.visit = cv.take<uint32_t>(F);
   a.nbound = cv.take<int64_t>(M + 1);
@@ -712,6 +748,8 @@ int carve_ws(Carve& cv, BuildArgs& a, int64_t M, int64_t F, void** sort_tmp, siz
   a.ekey2 = cv.take<uint64_t>(E3);
   a.nscan = cv.take<int64_t>(M + 1);
   a.chunk_scan = cv.take<int64_t>(M + 1);
+  a.ncount = cv.take<int64_t>(M + 1);
+  a.tnodes = cv.take<char>(node_cap * node_bytes(W));
   // temp storage for the library sorts and scans
   size_t need = 0, b = 0;
   int eb = end_bit_for(M);
@@ -771,7 +809,8 @@ extern "C" int build_mesh_bvh_sizes(int64_t n_meshes, int64_t f_total, int64_t v
   BuildArgs a{};
   void* tmp;
   size_t tb;
-  r = carve_ws(cv, a, n_meshes, f_total, &tmp, &tb);
+  Layout y0 = blob_layout(n_meshes, f_total, params->width, params->leaf_size);
+  r = carve_ws(cv, a, n_meshes, f_total, y0.node_cap, params->width, &tmp, &tb);
   if (r) return r;
   *ws_bytes = cv.used + 256;
   return PR_OK;
@@ -795,7 +834,7 @@ extern "C" int build_mesh_bvh(const float* verts, const int64_t* vert_off, const
   Carve cv{(char*)ws, ws_bytes};
   void* tmp = nullptr;
   size_t tmp_bytes = 0;
-  r = carve_ws(cv, a, n_meshes, f_total, &tmp, &tmp_bytes);
+  r = carve_ws(cv, a, n_meshes, f_total, y.node_cap, W, &tmp, &tmp_bytes);
   if (r) return r;
   if (cv.used > ws_bytes || !tmp) { set_error("ws_bytes %zu < required %zu", ws_bytes, cv.used); return PR_E_CAPACITY; }
   a.verts = verts; a.vert_off = vert_off; a.faces = faces; a.face_off = face_off;
@@ -840,6 +879,12 @@ extern "C" int build_mesh_bvh(const float* verts, const int64_t* vert_off, const
     if (W == 2) hipLaunchKernelGGL(k_collapse<2>, dim3(gM), dim3(kBlock), 0, s, a, (const int64_t*)a.nscan);
     else if (W == 4) hipLaunchKernelGGL(k_collapse<4>, dim3(gM), dim3(kBlock), 0, s, a, (const int64_t*)a.nscan);
     else hipLaunchKernelGGL(k_collapse<8>, dim3(gM), dim3(kBlock), 0, s, a, (const int64_t*)a.nscan);
+    hipLaunchKernelGGL(k_node_count, dim3(gM), dim3(kBlock), 0, s, a);
+    PR_HIP(hipcub::DeviceScan::ExclusiveSum(tmp, tmp_bytes, a.ncount, a.nbound, (int)(M + 1), s));
+    const int gMB = (int)(M < 65536 ? M : 65536);
+    if (W == 2) hipLaunchKernelGGL(k_node_copy<2>, dim3(gMB), dim3(kBlock), 0, s, a, (const int64_t*)a.nbound);
+    else if (W == 4) hipLaunchKernelGGL(k_node_copy<4>, dim3(gMB), dim3(kBlock), 0, s, a, (const int64_t*)a.nbound);
+    else hipLaunchKernelGGL(k_node_copy<8>, dim3(gMB), dim3(kBlock), 0, s, a, (const int64_t*)a.nbound);
   }
   if (F > 0) {
     hipLaunchKernelGGL(k_write_tris, dim3(gF), dim3(kBlock), 0, s, a);

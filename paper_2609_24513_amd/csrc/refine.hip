@@ -46,6 +46,17 @@ constexpr float kZeroBias = 0x1p16f;
 template <int W>
 constexpr int stack_cap() { return (W - 1) * (kMaxDepth + 1) + 1; }
 
+// Blob data is immutable during a query; reading it through the constant
+// address space lets uniform reads (nodes, triangles, group boxes,
+// descriptors) go through the scalar cache into SGPRs.
+template <class T>
+using cptr_t = const __attribute__((address_space(4))) T*;
+
+template <class T>
+__device__ __forceinline__ cptr_t<T> cview(const T* p) {
+  return (cptr_t<T>)(reinterpret_cast<uintptr_t>(p));
+}
+
 struct BlobView {
   const MeshDesc* mesh;
   const char* nodes;
@@ -153,6 +164,7 @@ struct WaveStats {
 };
 
 __device__ __forceinline__ f3 tri_vertex(const float* t, int k) { return f3{t[3 * k], t[3 * k + 1], t[3 * k + 2]}; }
+__device__ __forceinline__ f3 tri_vertex(cptr_t<float> t, int k) { return f3{t[3 * k], t[3 * k + 1], t[3 * k + 2]}; }
 
 // Traces group `chunk` of source mesh sm against target mesh tm; the caller
 // has checked that the group's box meets the target mesh box.  Returns true
@@ -166,7 +178,7 @@ __device__ bool trace_group(const BlobView& S, const BlobView& T, const MeshDesc
   const int live = min(kChunk, sm.n_edges - chunk * kChunk);
   st.v[S_SEG] += (uint64_t)live;
   float cb[6];
-  const float* cbp = S.cbox + 8 * gc;
+  const cptr_t<float> cbp = cview(S.cbox) + 8 * gc;
 #pragma unroll
   for (int k = 0; k < 6; ++k) cb[k] = cbp[k];
   const bool valid = lane < live;
@@ -203,42 +215,58 @@ __device__ bool trace_group(const BlobView& S, const BlobView& T, const MeshDesc
     if (!rerun && (++iter & 15) == 0 && load_state(ra.state + pair)) return true;
     const bool on = (nm >> lane) & 1ull;
     if (ref < 0) {
-      // leaf: the lanes of the mask test their segment against its triangles
+      // leaf: the lanes of the mask test their segment against its triangles,
+      // four at a time; the four triangles are loaded before any is tested
+      // (indices past the leaf are clamped to its last triangle and ignored)
       const int32_t lr = ~ref;
       const int32_t first = lr >> 3;
       const int cnt = (lr & 7) + 1;
       st.v[S_TRIF] += (uint64_t)cnt;
-      const uint64_t lanes = (uint64_t)__popcll(nm);
-      for (int t = 0; t < cnt; ++t) {
-        const float* tp = T.tris + 9 * (int64_t)(first + t);
-        const f3 a = tri_vertex(tp, 0), b = tri_vertex(tp, 1), c3 = tri_vertex(tp, 2);
-        int res = kMiss;
-        if (on) {
-          if (PREC == 0) {
-            res = safe ? seg_tri_f32(p, q, a, b, c3) : kAmbig;
-          } else if (PREC == 1) {
-            ExactCounters ec{0};
-            res = seg_tri_exact(p, q, a, b, c3, ec) ? kHit : kMiss;
-          } else {
-            res = kAmbig;
+      st.v[S_TESTS] += (uint64_t)__popcll(nm) * (uint64_t)cnt;
+      if (PREC == 1) st.v[S_EXACT] += (uint64_t)__popcll(nm) * (uint64_t)cnt;
+      uint32_t hitbits = 0, ambbits = 0;
+      for (int t0 = 0; t0 < cnt; t0 += 4) {
+        f3 ta[4], tb[4], tc[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+          const cptr_t<float> tp = cview(T.tris) + 9 * (int64_t)(first + min(t0 + k, cnt - 1));
+          ta[k] = tri_vertex(tp, 0); tb[k] = tri_vertex(tp, 1); tc[k] = tri_vertex(tp, 2);
+        }
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+          if (t0 + k >= cnt) break;
+          int res = kMiss;
+          if (on) {
+            if (PREC == 0) {
+              res = safe ? seg_tri_f32(p, q, ta[k], tb[k], tc[k]) : kAmbig;
+            } else if (PREC == 1) {
+              ExactCounters ec{0};
+              res = seg_tri_exact(p, q, ta[k], tb[k], tc[k], ec) ? kHit : kMiss;
+            } else {
+              res = kAmbig;
+            }
           }
+          hitbits |= (res == kHit ? 1u : 0u) << (t0 + k);
+          ambbits |= (res == kAmbig ? 1u : 0u) << (t0 + k);
         }
-        st.v[S_TESTS] += lanes;
-        if (PREC == 1) st.v[S_EXACT] += lanes;
-        if (ballot(res == kHit)) {
-          if (lane == 0 && !rerun) mark_true(ra.state + pair);
-          return true;
-        }
-        const uint64_t am = ballot(res == kAmbig);
-        if (am) {
+      }
+      if (ballot(hitbits != 0)) {
+        if (lane == 0 && !rerun) mark_true(ra.state + pair);
+        return true;
+      }
+      if (ballot(ambbits != 0)) {
+        for (int t = 0; t < cnt; ++t) {
+          const bool amb = (ambbits >> t) & 1u;
+          const uint64_t am = ballot(amb);
+          if (!am) continue;
           st.v[S_AMB32] += (uint64_t)__popcll(am);
           uint32_t base = 0;
           if (lane == 0) base = atomicAdd(ra.qcount, (uint32_t)__popcll(am));
           base = (uint32_t)uni((int32_t)base);
           const uint32_t idx = base + (uint32_t)lanes_below(am);
-          if (res == kAmbig && idx < ra.qcap)
+          if (amb && idx < ra.qcap)
             ra.queue[idx] = make_int4(pair, dir, (int32_t)(gc * kChunk + lane), first + t);
-          const uint64_t over = ballot(res == kAmbig && idx >= ra.qcap);
+          const uint64_t over = ballot(amb && idx >= ra.qcap);
           if (over) {
             // the queue is full: the whole pair is decided again later in FP64/exact
             st.v[S_QOVER] += (uint64_t)__popcll(over);
@@ -249,23 +277,43 @@ __device__ bool trace_group(const BlobView& S, const BlobView& T, const MeshDesc
       }
       continue;
     }
-    st.v[S_VISIT] += 1;
-    const Node<W>* nd = nodes + ref;
-#pragma unroll
-    for (int c = 0; c < W; ++c) {
-      const int32_t ch = nd->child[c];
-      if (ch == kEmpty) continue;
-      const float lx = nd->lo[0][c], ly = nd->lo[1][c], lz = nd->lo[2][c];
-      const float hx = nd->hi[0][c], hy = nd->hi[1][c], hz = nd->hi[2][c];
-      if (!box_meet(cb, lx, ly, lz, hx, hy, hz)) continue;
-      const uint64_t hm = ballot(on && slab(r, lx, ly, lz, hx, hy, hz));
-      if (hm == 0) continue;
-      if (top >= CAP) {  // cannot happen for a valid blob (depth <= kMaxDepth)
-        if (lane == 0) atomicMin(ra.status, (int32_t)PR_E_UNSUPPORTED);
-        return true;
+    // inner node; when the entry below is an inner node too, pop it as well so
+    // that both nodes' loads are in flight together
+    int32_t ref2 = -1;
+    uint64_t nm2 = 0;
+    if (top > 0) {
+      const int32_t r2 = uni(snode[top - 1]);
+      if (r2 >= 0) {
+        ref2 = r2;
+        nm2 = uni64(smask[top - 1]);
+        --top;
       }
-      if (lane == 0) { snode[top] = ch; smask[top] = hm; }
-      ++top;
+    }
+    const cptr_t<Node<W>> nd = cview(nodes) + ref;
+    const cptr_t<Node<W>> nd2 = cview(nodes) + (ref2 >= 0 ? ref2 : ref);
+    st.v[S_VISIT] += ref2 >= 0 ? 2 : 1;
+    const bool on2 = (nm2 >> lane) & 1ull;
+#pragma unroll
+    for (int pass = 0; pass < 2; ++pass) {
+      if (pass == 1 && ref2 < 0) break;
+      const cptr_t<Node<W>> n = pass == 0 ? nd : nd2;
+      const bool lon = pass == 0 ? on : on2;
+#pragma unroll
+      for (int c = 0; c < W; ++c) {
+        const int32_t ch = n->child[c];
+        if (ch == kEmpty) continue;
+        const float lx = n->lo[0][c], ly = n->lo[1][c], lz = n->lo[2][c];
+        const float hx = n->hi[0][c], hy = n->hi[1][c], hz = n->hi[2][c];
+        if (!box_meet(cb, lx, ly, lz, hx, hy, hz)) continue;
+        const uint64_t hm = ballot(lon && slab(r, lx, ly, lz, hx, hy, hz));
+        if (hm == 0) continue;
+        if (top >= CAP) {  // cannot happen for a valid blob (depth <= kMaxDepth)
+          if (lane == 0) atomicMin(ra.status, (int32_t)PR_E_UNSUPPORTED);
+          return true;
+        }
+        if (lane == 0) { snode[top] = ch; smask[top] = hm; }
+        ++top;
+      }
     }
   }
   return false;
@@ -402,8 +450,8 @@ __device__ __forceinline__ bool group_may_hit(const float* g, const BlobView& T,
   if (!(g[0] <= tm.box[3] && tm.box[0] <= g[3] && g[1] <= tm.box[4] && tm.box[1] <= g[4] && g[2] <= tm.box[5] &&
         tm.box[2] <= g[5]))
     return false;
-  const Node<W>* nodes = reinterpret_cast<const Node<W>*>(T.nodes);
-  const Node<W>* root = nodes + tm.root;
+  const cptr_t<Node<W>> nodes = cview(reinterpret_cast<const Node<W>*>(T.nodes));
+  const cptr_t<Node<W>> root = nodes + tm.root;
   bool hit = false;
 #pragma unroll
   for (int c = 0; c < W; ++c) {
@@ -412,7 +460,7 @@ __device__ __forceinline__ bool group_may_hit(const float* g, const BlobView& T,
     const bool m1 = box_meet(g, root->lo[0][c], root->lo[1][c], root->lo[2][c], root->hi[0][c], root->hi[1][c],
                              root->hi[2][c]);
     if (ch < 0) { hit = hit || m1; continue; }
-    const Node<W>* n2 = nodes + ch;
+    const cptr_t<Node<W>> n2 = nodes + ch;
     bool m2 = false;
 #pragma unroll
     for (int d = 0; d < W; ++d)
