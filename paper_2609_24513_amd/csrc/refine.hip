@@ -797,6 +797,7 @@ __global__ __launch_bounds__(kBlock) void k_rerun(RefineArgs ra) {
   WaveStats st;
 #pragma unroll
   for (int k = 0; k < S_N; ++k) st.v[k] = 0;
+  if (ra.stats[S_QOVER] == 0) return;  // no deferred test overflowed: nothing to rerun
   for (int64_t p = blockIdx.x; p < ra.n_pairs; p += gridDim.x) {
     if (load_state(ra.state + p) != 2u) continue;
     if (threadIdx.x == 0) s_hit = 0;
