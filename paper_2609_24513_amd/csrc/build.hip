@@ -695,7 +695,9 @@ Layout blob_layout(int64_t M, int64_t F, int W, int L) {
   int64_t o = align256(sizeof(BlobHeader));
   y.off_mesh = o; o = align256(o + M * (int64_t)sizeof(MeshDesc));
   y.off_node = o; o = align256(o + y.node_cap * node_bytes(W));
-  y.off_tri = o; o = align256(o + F * 36);
+  // three triangles of slack after the last one: a leaf's triangles are
+  // read four at a time as one contiguous block
+  y.off_tri = o; o = align256(o + (F + 3) * 36);
   y.off_triid = o; o = align256(o + F * 4);
   y.off_seg = o; o = align256(o + y.chunk_cap * 6 * kChunk * 4);
   y.off_edge = o; o = align256(o + y.chunk_cap * 2 * kChunk * 4);

@@ -104,7 +104,7 @@ struct RefineArgs {
   unsigned long long* stats;  // [S_N]
   int32_t* status;            // [1]
   int32_t item_groups;        // groups per work item
-  int2* surv;                 // kSlices queues of surviving groups (unit, group)
+  int4* surv;                 // kSlices queues of surviving groups (SurvEntry layout)
   uint32_t surv_cap;          // entries per queue
   unsigned long long* surv_cnt;  // kSlices fill counters (stride kCtrStride)
   unsigned long long* surv_pop;  // kSlices pop counters (stride kCtrStride)
@@ -112,7 +112,7 @@ struct RefineArgs {
 
 constexpr int kSlices = 8;     // one pop counter per XCD
 constexpr int kMaxItemGroups = 1024;
-constexpr int kCtrStride = 16; // u64 words between counters
+constexpr int kCtrStride = 512; // u64 words between counters (4 KiB: separate memory channels)
 
 __device__ __forceinline__ uint32_t load_state(const uint32_t* p) {
   return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -159,8 +159,14 @@ __device__ __forceinline__ bool slab(const Ray& r, float lx, float ly, float lz,
   return tn <= fmaf(tf, kSlabK, kSlabS);
 }
 
+// Per-wave statistics in one VGPR pair: lane k holds counter k (k < S_N), so
+// the counters cost no SGPRs in the traversal loops.
 struct WaveStats {
-  uint64_t v[S_N];
+  uint64_t acc = 0;
+  __device__ __forceinline__ void add(int k, uint64_t x) { acc += (threadIdx.x & 63) == k ? x : 0ull; }
+  __device__ __forceinline__ void max(int k, uint64_t x) {
+    if ((threadIdx.x & 63) == k && x > acc) acc = x;
+  }
 };
 
 __device__ __forceinline__ f3 tri_vertex(const float* t, int k) { return f3{t[3 * k], t[3 * k + 1], t[3 * k + 2]}; }
@@ -169,14 +175,97 @@ __device__ __forceinline__ f3 tri_vertex(cptr_t<float> t, int k) { return f3{t[3
 // Traces group `chunk` of source mesh sm against target mesh tm; the caller
 // has checked that the group's box meets the target mesh box.  Returns true
 // when the pair is decided (found here or by another wave).
+// Per-wave traversal stack of (entry, lane mask) pairs.  The stack top is
+// wave-uniform; the first kRegStack entries live in VGPR lanes (entry k in
+// lane k of three registers, written and read with lane-select instructions),
+// deeper entries in a per-wave LDS array written by lane 0.
+constexpr int kRegStack = 64;
+
+template <int W>
+constexpr int lds_stack_cap() { return stack_cap<W>() > kRegStack ? stack_cap<W>() - kRegStack : 1; }
+
+// v_writelane_b32: `old` with lane `lane` replaced by the uniform value v
+// (the LLVM intrinsic; this clang has no builtin spelling for it).
+__device__ int32_t lane_write(int32_t v, int32_t lane, int32_t old) __asm("llvm.amdgcn.writelane.i32");
+
+struct WaveStack {
+  int32_t ref;
+  int32_t mlo, mhi;
+  int32_t* lref;
+  uint64_t* lmask;
+  int32_t top;
+};
+
+__device__ __forceinline__ void stack_push(WaveStack& s, int32_t ref, uint64_t m) {
+  if (s.top < kRegStack) {
+    s.ref = lane_write(ref, s.top, s.ref);
+    s.mlo = lane_write((int32_t)(uint32_t)m, s.top, s.mlo);
+    s.mhi = lane_write((int32_t)(uint32_t)(m >> 32), s.top, s.mhi);
+  } else if ((threadIdx.x & 63) == 0) {
+    s.lref[s.top - kRegStack] = ref;
+    s.lmask[s.top - kRegStack] = m;
+  }
+  ++s.top;
+}
+
+__device__ __forceinline__ int32_t stack_ref(const WaveStack& s, int32_t i) {
+  return i < kRegStack ? __builtin_amdgcn_readlane(s.ref, i) : uni(s.lref[i - kRegStack]);
+}
+
+__device__ __forceinline__ uint64_t stack_mask(const WaveStack& s, int32_t i) {
+  if (i < kRegStack)
+    return ((uint64_t)(uint32_t)__builtin_amdgcn_readlane(s.mhi, i) << 32) |
+           (uint32_t)__builtin_amdgcn_readlane(s.mlo, i);
+  return uni64(s.lmask[i - kRegStack]);
+}
+
+// A wide node read in one burst through the scalar cache.
+template <int W>
+struct NodeRegs {
+  float lo[3][W], hi[3][W];
+  int32_t ch[W];
+};
+
+template <int W>
+__device__ __forceinline__ void load_node(NodeRegs<W>& d, cptr_t<Node<W>> n) {
+#pragma unroll
+  for (int c = 0; c < W; ++c) {
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      d.lo[a][c] = n->lo[a][c];
+      d.hi[a][c] = n->hi[a][c];
+    }
+    d.ch[c] = n->child[c];
+  }
+}
+
+// Lane masks of the children of a node hit by the segments of mask nm (no
+// branches: every child is tested by every lane and the result masked).  For
+// meshes outside the FP32-safe range the slab test accepts everything and the
+// exact uniform test against the group box does the pruning.
+template <int W>
+__device__ __forceinline__ void test_children(const NodeRegs<W>& d, const Ray& r, uint64_t nm, bool safe,
+                                              const float* cb, uint64_t* hm) {
+#pragma unroll
+  for (int c = 0; c < W; ++c) {
+    uint64_t m = ballot(slab(r, d.lo[0][c], d.lo[1][c], d.lo[2][c], d.hi[0][c], d.hi[1][c], d.hi[2][c])) & nm;
+    if (d.ch[c] == kEmpty) m = 0;
+    if (!safe && !box_meet(cb, d.lo[0][c], d.lo[1][c], d.lo[2][c], d.hi[0][c], d.hi[1][c], d.hi[2][c])) m = 0;
+    hm[c] = m;
+  }
+}
+
+// Traces segment group gc (global index in the source blob, `live` segments)
+// against the target mesh whose root node is `root` and box `tb`.  Returns
+// true when the pair is decided (found here or by another wave).
 template <int W, int PREC>
-__device__ bool trace_group(const BlobView& S, const BlobView& T, const MeshDesc& sm, const MeshDesc& tm,
-                            int32_t chunk, int32_t pair, int32_t dir, bool safe, const RefineArgs& ra,
-                            int32_t* snode, uint64_t* smask, WaveStats& st, bool rerun = false) {
+__device__ bool trace_core(const BlobView& S, const BlobView& T, int64_t gc, int live, int32_t root,
+                           const float* tb, int32_t pair, int32_t dir, bool safe, const RefineArgs& ra,
+                           int32_t* lref, uint64_t* lmask, WaveStats& st, bool rerun) {
   const int lane = threadIdx.x & 63;
-  const int64_t gc = (int64_t)sm.chunk_base + chunk;
-  const int live = min(kChunk, sm.n_edges - chunk * kChunk);
-  st.v[S_SEG] += (uint64_t)live;
+  // issue every load the group needs at once: its box, its segments and the
+  // pair's state
+  const uint32_t decided = rerun ? 0u : load_state(ra.state + pair);
   float cb[6];
   const cptr_t<float> cbp = cview(S.cbox) + 8 * gc;
 #pragma unroll
@@ -190,58 +279,72 @@ __device__ bool trace_group(const BlobView& S, const BlobView& T, const MeshDesc
   axis_setup(q.x - p.x, safe, r.ix, r.bx);
   axis_setup(q.y - p.y, safe, r.iy, r.by);
   axis_setup(q.z - p.z, safe, r.iz, r.bz);
-  uint64_t m0 = ballot(valid && slab(r, tm.box[0], tm.box[1], tm.box[2], tm.box[3], tm.box[4], tm.box[5]));
+  if (uni((int32_t)decided)) return true;
+  st.add(S_SEG, (uint64_t)live);
+  const uint64_t m0 = ballot(valid && slab(r, tb[0], tb[1], tb[2], tb[3], tb[4], tb[5]));
   if (m0 == 0) return false;
-  st.v[S_GTRAV] += 1;
-  const uint64_t v0 = st.v[S_VISIT], l0 = st.v[S_TRIF];
-  struct MaxOnExit {
-    WaveStats& s; uint64_t v0, l0;
-    __device__ ~MaxOnExit() {
-      const uint64_t dv = s.v[S_VISIT] - v0, dl = s.v[S_TRIF] - l0;
-      if (dv > s.v[S_MAXV]) s.v[S_MAXV] = dv;
-      if (dl > s.v[S_MAXL]) s.v[S_MAXL] = dl;
+  // per-group counters (uniform, 32 bits), folded into the wave's statistics
+  // when the group ends
+  struct GroupCount {
+    WaveStats& s;
+    uint32_t visits = 0, leaf_tris = 0, tests = 0;
+    __device__ ~GroupCount() {
+      s.add(S_GTRAV, 1);
+      s.add(S_VISIT, visits);
+      s.add(S_TRIF, leaf_tris);
+      s.add(S_TESTS, tests);
+      if (PREC == 1) s.add(S_EXACT, tests);
+      s.max(S_MAXV, visits);
+      s.max(S_MAXL, leaf_tris);
     }
-  } max_on_exit{st, v0, l0};
+  } gcount{st};
   constexpr int CAP = stack_cap<W>();
-  int top = 0;
-  if (lane == 0) { snode[0] = tm.root; smask[0] = m0; }
-  top = 1;
+  WaveStack stk;
+  stk.ref = 0; stk.mlo = 0; stk.mhi = 0;
+  stk.lref = lref; stk.lmask = lmask; stk.top = 0;
+  stack_push(stk, root, m0);
   int iter = 0;
-  const Node<W>* nodes = reinterpret_cast<const Node<W>*>(T.nodes);
-  while (top > 0) {
-    --top;
-    const int32_t ref = uni(snode[top]);
-    const uint64_t nm = uni64(smask[top]);
-    if (!rerun && (++iter & 15) == 0 && load_state(ra.state + pair)) return true;
-    const bool on = (nm >> lane) & 1ull;
+  const cptr_t<Node<W>> nodes = cview(reinterpret_cast<const Node<W>*>(T.nodes));
+  // the pair's state is polled every 16 pops; the load is issued one poll
+  // ahead so that the traversal never waits for it
+  uint32_t poll = 0;
+  while (stk.top > 0) {
+    --stk.top;
+    const int32_t ref = stack_ref(stk, stk.top);
+    const uint64_t nm = stack_mask(stk, stk.top);
+    if (!rerun && (++iter & 15) == 0) {
+      if (uni((int32_t)poll)) return true;
+      poll = load_state(ra.state + pair);
+    }
     if (ref < 0) {
-      // leaf: the lanes of the mask test their segment against its triangles,
-      // four at a time; the four triangles are loaded before any is tested
-      // (indices past the leaf are clamped to its last triangle and ignored)
+      // leaf: the lanes of the mask test their segment against its
+      // triangles, four at a time, read as one contiguous block (the
+      // triangle array has three triangles of slack at its end)
+      const bool on = (nm >> lane) & 1ull;
       const int32_t lr = ~ref;
       const int32_t first = lr >> 3;
       const int cnt = (lr & 7) + 1;
-      st.v[S_TRIF] += (uint64_t)cnt;
-      st.v[S_TESTS] += (uint64_t)__popcll(nm) * (uint64_t)cnt;
-      if (PREC == 1) st.v[S_EXACT] += (uint64_t)__popcll(nm) * (uint64_t)cnt;
+      gcount.leaf_tris += (uint32_t)cnt;
+      gcount.tests += (uint32_t)__popcll(nm) * (uint32_t)cnt;
       uint32_t hitbits = 0, ambbits = 0;
       for (int t0 = 0; t0 < cnt; t0 += 4) {
-        f3 ta[4], tb[4], tc[4];
+        const cptr_t<float> tp = cview(T.tris) + 9 * (int64_t)(first + t0);
+        float tv[36];
 #pragma unroll
-        for (int k = 0; k < 4; ++k) {
-          const cptr_t<float> tp = cview(T.tris) + 9 * (int64_t)(first + min(t0 + k, cnt - 1));
-          ta[k] = tri_vertex(tp, 0); tb[k] = tri_vertex(tp, 1); tc[k] = tri_vertex(tp, 2);
-        }
+        for (int k = 0; k < 36; ++k) tv[k] = tp[k];
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
           if (t0 + k >= cnt) break;
+          const f3 ta{tv[9 * k], tv[9 * k + 1], tv[9 * k + 2]};
+          const f3 tb3{tv[9 * k + 3], tv[9 * k + 4], tv[9 * k + 5]};
+          const f3 tc{tv[9 * k + 6], tv[9 * k + 7], tv[9 * k + 8]};
           int res = kMiss;
           if (on) {
             if (PREC == 0) {
-              res = safe ? seg_tri_f32(p, q, ta[k], tb[k], tc[k]) : kAmbig;
+              res = safe ? seg_tri_f32(p, q, ta, tb3, tc) : kAmbig;
             } else if (PREC == 1) {
               ExactCounters ec{0};
-              res = seg_tri_exact(p, q, ta[k], tb[k], tc[k], ec) ? kHit : kMiss;
+              res = seg_tri_exact(p, q, ta, tb3, tc, ec) ? kHit : kMiss;
             } else {
               res = kAmbig;
             }
@@ -259,7 +362,7 @@ __device__ bool trace_group(const BlobView& S, const BlobView& T, const MeshDesc
           const bool amb = (ambbits >> t) & 1u;
           const uint64_t am = ballot(amb);
           if (!am) continue;
-          st.v[S_AMB32] += (uint64_t)__popcll(am);
+          st.add(S_AMB32, (uint64_t)__popcll(am));
           uint32_t base = 0;
           if (lane == 0) base = atomicAdd(ra.qcount, (uint32_t)__popcll(am));
           base = (uint32_t)uni((int32_t)base);
@@ -269,7 +372,7 @@ __device__ bool trace_group(const BlobView& S, const BlobView& T, const MeshDesc
           const uint64_t over = ballot(amb && idx >= ra.qcap);
           if (over) {
             // the queue is full: the whole pair is decided again later in FP64/exact
-            st.v[S_QOVER] += (uint64_t)__popcll(over);
+            st.add(S_QOVER, (uint64_t)__popcll(over));
             if (lane == 0) atomicCAS(ra.state + pair, 0u, 2u);
             return true;
           }
@@ -277,46 +380,33 @@ __device__ bool trace_group(const BlobView& S, const BlobView& T, const MeshDesc
       }
       continue;
     }
-    // inner node; when the entry below is an inner node too, pop it as well so
-    // that both nodes' loads are in flight together
-    int32_t ref2 = -1;
-    uint64_t nm2 = 0;
-    if (top > 0) {
-      const int32_t r2 = uni(snode[top - 1]);
-      if (r2 >= 0) {
-        ref2 = r2;
-        nm2 = uni64(smask[top - 1]);
-        --top;
-      }
+    // inner node: all of it is loaded at once, every child is tested
+    NodeRegs<W> nd;
+    load_node<W>(nd, nodes + ref);
+    ++gcount.visits;
+    uint64_t hm[W];
+    test_children<W>(nd, r, nm, safe, cb, hm);
+    if (stk.top + W > CAP) {  // cannot happen for a valid blob (depth <= kMaxDepth)
+      if (lane == 0) atomicMin(ra.status, (int32_t)PR_E_UNSUPPORTED);
+      return true;
     }
-    const cptr_t<Node<W>> nd = cview(nodes) + ref;
-    const cptr_t<Node<W>> nd2 = cview(nodes) + (ref2 >= 0 ? ref2 : ref);
-    st.v[S_VISIT] += ref2 >= 0 ? 2 : 1;
-    const bool on2 = (nm2 >> lane) & 1ull;
 #pragma unroll
-    for (int pass = 0; pass < 2; ++pass) {
-      if (pass == 1 && ref2 < 0) break;
-      const cptr_t<Node<W>> n = pass == 0 ? nd : nd2;
-      const bool lon = pass == 0 ? on : on2;
-#pragma unroll
-      for (int c = 0; c < W; ++c) {
-        const int32_t ch = n->child[c];
-        if (ch == kEmpty) continue;
-        const float lx = n->lo[0][c], ly = n->lo[1][c], lz = n->lo[2][c];
-        const float hx = n->hi[0][c], hy = n->hi[1][c], hz = n->hi[2][c];
-        if (!box_meet(cb, lx, ly, lz, hx, hy, hz)) continue;
-        const uint64_t hm = ballot(lon && slab(r, lx, ly, lz, hx, hy, hz));
-        if (hm == 0) continue;
-        if (top >= CAP) {  // cannot happen for a valid blob (depth <= kMaxDepth)
-          if (lane == 0) atomicMin(ra.status, (int32_t)PR_E_UNSUPPORTED);
-          return true;
-        }
-        if (lane == 0) { snode[top] = ch; smask[top] = hm; }
-        ++top;
-      }
-    }
+    for (int c = 0; c < W; ++c)
+      if (hm[c]) stack_push(stk, nd.ch[c], hm[c]);
   }
   return false;
+}
+
+// Group `chunk` of source mesh sm against target mesh tm; the caller has
+// checked that the group's box meets the target mesh box.
+template <int W, int PREC>
+__device__ __forceinline__ bool trace_group(const BlobView& S, const BlobView& T, const MeshDesc& sm,
+                                            const MeshDesc& tm, int32_t chunk, int32_t pair, int32_t dir, bool safe,
+                                            const RefineArgs& ra, int32_t* lref, uint64_t* lmask, WaveStats& st,
+                                            bool rerun = false) {
+  const int64_t gc = (int64_t)sm.chunk_base + chunk;
+  const int live = min(kChunk, sm.n_edges - chunk * kChunk);
+  return trace_core<W, PREC>(S, T, gc, live, tm.root, tm.box, pair, dir, safe, ra, lref, lmask, st, rerun);
 }
 
 // One group with its own box pre-test (per-pair and rerun kernels).
@@ -324,25 +414,22 @@ template <int W, int PREC>
 __device__ bool trace_chunk(const BlobView& S, const BlobView& T, const MeshDesc& sm, const MeshDesc& tm,
                             int32_t chunk, int32_t pair, int32_t dir, bool safe, const RefineArgs& ra,
                             int32_t* snode, uint64_t* smask, WaveStats& st, bool rerun = false) {
-  st.v[S_GROUPS] += 1;
+  st.add(S_GROUPS, 1);
   if (tm.root == kEmpty) return false;
   const float* cbp = S.cbox + 8 * ((int64_t)sm.chunk_base + chunk);
   float cb[6];
 #pragma unroll
   for (int k = 0; k < 6; ++k) cb[k] = cbp[k];
   if (!box_meet(cb, tm.box[0], tm.box[1], tm.box[2], tm.box[3], tm.box[4], tm.box[5])) return false;
-  st.v[S_GBOX] += 1;
+  st.add(S_GBOX, 1);
   return trace_group<W, PREC>(S, T, sm, tm, chunk, pair, dir, safe, ra, snode, smask, st, rerun);
 }
 
 __device__ __forceinline__ void flush_stats(const WaveStats& st, const RefineArgs& ra) {
-  if ((threadIdx.x & 63) == 0) {
-#pragma unroll
-    for (int k = 0; k < S_N; ++k) {
-      if (!st.v[k]) continue;
-      if (k == S_MAXV || k == S_MAXL) atomicMax(ra.stats + k, (unsigned long long)st.v[k]);
-      else atomicAdd(ra.stats + k, (unsigned long long)st.v[k]);
-    }
+  const int k = threadIdx.x & 63;
+  if (k < S_N && st.acc) {
+    if (k == S_MAXV || k == S_MAXL) atomicMax(ra.stats + k, (unsigned long long)st.acc);
+    else atomicAdd(ra.stats + k, (unsigned long long)st.acc);
   }
 }
 
@@ -481,7 +568,7 @@ __device__ __forceinline__ bool group_may_hit(const float* g, const BlobView& T,
 // one group per wave at a time.
 template <int W, int PREC>
 __global__ __launch_bounds__(kBlock, 5) void k_refine_persistent(RefineArgs ra) {
-  constexpr int CAP = stack_cap<W>();
+  constexpr int CAP = lds_stack_cap<W>();
   __shared__ int32_t s_node[kWaves][CAP];
   __shared__ uint64_t s_mask[kWaves][CAP];
   __shared__ int32_t s_list[kMaxItemGroups];
@@ -493,8 +580,6 @@ __global__ __launch_bounds__(kBlock, 5) void k_refine_persistent(RefineArgs ra) 
   const int64_t U = 2 * ra.n_pairs;
   const int64_t total = ra.offs[U];
   WaveStats st;
-#pragma unroll
-  for (int k = 0; k < S_N; ++k) st.v[k] = 0;
   const int home = (int)(blockIdx.x % kSlices);
   for (int sl = 0; sl < kSlices; ++sl) {
     const int cid = (home + sl) % kSlices;
@@ -539,9 +624,9 @@ __global__ __launch_bounds__(kBlock, 5) void k_refine_persistent(RefineArgs ra) 
             pos = uni(pos);
             if (pass) s_list[pos + lanes_below(mask)] = c;
           }
-          st.v[S_GBOX] += (uint64_t)__popcll(mask);
+          st.add(S_GBOX, (uint64_t)__popcll(mask));
         }
-        if (wv == 0) st.v[S_GROUPS] += (uint64_t)(c1 - c0);
+        if (wv == 0) st.add(S_GROUPS, (uint64_t)(c1 - c0));
       }
       __syncthreads();
       const int32_t n = s_n;
@@ -566,7 +651,7 @@ __global__ __launch_bounds__(kBlock, 5) void k_refine_persistent(RefineArgs ra) 
 // synchronisation); the group cull is the same lane-parallel test.
 template <int W, int PREC>
 __global__ __launch_bounds__(kBlock) void k_refine_wave(RefineArgs ra) {
-  constexpr int CAP = stack_cap<W>();
+  constexpr int CAP = lds_stack_cap<W>();
   __shared__ int32_t s_node[kWaves][CAP];
   __shared__ uint64_t s_mask[kWaves][CAP];
   const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -575,8 +660,6 @@ __global__ __launch_bounds__(kBlock) void k_refine_wave(RefineArgs ra) {
   const int64_t U = 2 * ra.n_pairs;
   const int64_t total = ra.offs[U];
   WaveStats st;
-#pragma unroll
-  for (int k = 0; k < S_N; ++k) st.v[k] = 0;
   const int home = (int)(blockIdx.x % kSlices);
   for (int sl = 0; sl < kSlices; ++sl) {
     const int cid = (home + sl) % kSlices;
@@ -600,7 +683,7 @@ __global__ __launch_bounds__(kBlock) void k_refine_wave(RefineArgs ra) {
       const bool safe = (sm.flags & tm.flags & kMeshSafe) != 0;
       const int32_t c0 = (int32_t)(j * ra.item_groups);
       const int32_t c1 = min(c0 + ra.item_groups, sm.n_chunks);
-      st.v[S_GROUPS] += (uint64_t)(c1 - c0);
+      st.add(S_GROUPS, (uint64_t)(c1 - c0));
       bool done = false;
       for (int32_t base = c0; base < c1 && !done; base += kChunk) {
         if (load_state(ra.state + pair)) break;
@@ -612,7 +695,7 @@ __global__ __launch_bounds__(kBlock) void k_refine_wave(RefineArgs ra) {
           pass = group_may_hit<W>(g, T, tm);
         }
         uint64_t mask = ballot(pass);
-        st.v[S_GBOX] += (uint64_t)__popcll(mask);
+        st.add(S_GBOX, (uint64_t)__popcll(mask));
         while (mask) {
           const int bit = __builtin_ctzll(mask);
           mask &= mask - 1;
@@ -627,119 +710,200 @@ __global__ __launch_bounds__(kBlock) void k_refine_wave(RefineArgs ra) {
   flush_stats(st, ra);
 }
 
-// Schedule 3, phase 1: every wave takes work items in a fixed stride, culls
-// their groups lane-parallel and appends the surviving (unit, group) entries to
-// the queue of its block's slice (blockIdx % kSlices, the XCD the block runs
-// on, so phase 2 mostly finds the pair's data in the same L2).  A group that
-// does not fit in the queue is traced here.
-template <int W, int PREC>
-__global__ __launch_bounds__(kBlock) void k_cull(RefineArgs ra) {
-  constexpr int CAP = stack_cap<W>();
-  __shared__ int32_t s_node[kWaves][CAP];
-  __shared__ uint64_t s_mask[kWaves][CAP];
-  const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const BlobView A = view_of(ra.blob_a), B = view_of(ra.blob_b);
-  if (!blobs_ok(A, B, ra, W)) return;
-  const int64_t U = 2 * ra.n_pairs;
-  const int64_t total = ra.offs[U];
-  const int slice = (int)(blockIdx.x % kSlices);
-  int2* q = ra.surv + (int64_t)slice * ra.surv_cap;
-  WaveStats st;
+// Per-lane two-level cull of group box g against a target mesh whose root
+// node is loaded in `root`: g must meet a child box of the root and, for an
+// inner child, one of that child's child boxes (every triangle lies inside
+// the boxes of its ancestors).  A child node is loaded (in one burst) only
+// when some lane meets its box.
+template <int W>
+__device__ __forceinline__ bool cull2(const float* g, const NodeRegs<W>& root, cptr_t<Node<W>> nodes) {
+  bool hit = false;
 #pragma unroll
-  for (int k = 0; k < S_N; ++k) st.v[k] = 0;
-  const int64_t nw = (int64_t)gridDim.x * kWaves;
-  for (int64_t idx = (int64_t)blockIdx.x * kWaves + wv; idx < total; idx += nw) {
-    const int64_t u = find_unit(ra.offs, U, idx);
-    const int64_t j = idx - ra.offs[u];
-    const int32_t pair = uni((int32_t)(u >> 1));
-    const int32_t dir = uni((int32_t)(u & 1));
-    const int32_t ia = ra.pairs[2 * (int64_t)pair], jb = ra.pairs[2 * (int64_t)pair + 1];
-    const BlobView& S = dir == 0 ? A : B;
-    const BlobView& T = dir == 0 ? B : A;
-    const MeshDesc sm = dir == 0 ? A.mesh[ia] : B.mesh[jb];
-    const MeshDesc tm = dir == 0 ? B.mesh[jb] : A.mesh[ia];
-    if (tm.root == kEmpty) continue;
-    const int32_t c0 = (int32_t)(j * ra.item_groups);
-    const int32_t c1 = min(c0 + ra.item_groups, sm.n_chunks);
-    st.v[S_GROUPS] += (uint64_t)(c1 - c0);
-    for (int32_t base = c0; base < c1; base += kChunk) {
-      const int32_t c = base + lane;
-      bool pass = false;
-      if (c < c1) {
-        const float* cbp = S.cbox + 8 * ((int64_t)sm.chunk_base + c);
-        float g[6] = {cbp[0], cbp[1], cbp[2], cbp[3], cbp[4], cbp[5]};
-        pass = group_may_hit<W>(g, T, tm);
-      }
-      const uint64_t mask = ballot(pass);
-      if (!mask) continue;
-      const int n = __popcll(mask);
-      st.v[S_GBOX] += (uint64_t)n;
-      unsigned long long b0 = 0;
-      if (lane == 0) b0 = atomicAdd(ra.surv_cnt + kCtrStride * slice, (unsigned long long)n);
-      const uint64_t b = uni64(b0);
-      const uint64_t pos = b + (uint64_t)lanes_below(mask);
-      if (pass && pos < ra.surv_cap) q[pos] = make_int2((int32_t)u, c);
-      uint64_t over = ballot(pass && pos >= ra.surv_cap);
-      if (over) {
-        const bool safe = (sm.flags & tm.flags & kMeshSafe) != 0;
-        while (over) {
-          const int bit = __builtin_ctzll(over);
-          over &= over - 1;
-          if (load_state(ra.state + pair)) break;
-          if (trace_group<W, PREC>(S, T, sm, tm, base + bit, pair, dir, safe, ra, s_node[wv], s_mask[wv], st)) break;
-        }
-      }
+  for (int c = 0; c < W; ++c) {
+    const int32_t ch = root.ch[c];
+    const bool m1 = ch != kEmpty && box_meet(g, root.lo[0][c], root.lo[1][c], root.lo[2][c], root.hi[0][c],
+                                             root.hi[1][c], root.hi[2][c]);
+    if (ch < 0 || ch == kEmpty) {  // leaf child (or none): its box decides
+      hit = hit || m1;
+      continue;
+    }
+    if (!ballot(m1)) continue;
+    NodeRegs<W> n2;
+    load_node<W>(n2, nodes + ch);
+    bool m2 = false;
+#pragma unroll
+    for (int d = 0; d < W; ++d)
+      m2 = m2 || (n2.ch[d] != kEmpty &&
+                  box_meet(g, n2.lo[0][d], n2.lo[1][d], n2.lo[2][d], n2.hi[0][d], n2.hi[1][d], n2.hi[2][d]));
+    hit = hit || (m1 && m2);
+  }
+  return hit;
+}
+
+constexpr int kCullBuf = 256;  // survivor entries buffered per wave in LDS
+// Multiplier of the pop-order permutation of a survivor queue; a prime above
+// any queue length, so coprime with it.
+constexpr uint64_t kSpread = 2654435761ull;
+
+// Appends a wave's buffered survivors to its slice queue with one atomic.
+// A survivor that does not fit marks its pair for the rerun pass (state 2:
+// every group of the pair traced again, exactly), as an overflow of the
+// deferred-test queue does.
+__device__ void flush_survivors(const int4* buf, int n, int slice, const RefineArgs& ra, WaveStats& st) {
+  const int lane = threadIdx.x & 63;
+  unsigned long long b0 = 0;
+  if (lane == 0) b0 = atomicAdd(ra.surv_cnt + kCtrStride * slice, (unsigned long long)n);
+  const uint64_t base = uni64(b0);
+  int4* q = ra.surv + (int64_t)slice * ra.surv_cap;
+  uint32_t over = 0;
+  for (int i = lane; i < n; i += 64) {
+    const int4 e = buf[i];
+    if (base + i < ra.surv_cap) {
+      q[base + i] = e;
+    } else {
+      atomicCAS(ra.state + (e.y >> 1), 0u, 2u);
+      ++over;
     }
   }
+  if (base + n > ra.surv_cap) {
+    for (int o = 32; o > 0; o >>= 1) over += __shfl_xor(over, o);
+    st.add(S_QOVER, (uint64_t)over);
+  }
+}
+
+// Schedule 3, phase 1: one wave per unit (pair, direction), units dealt to the
+// waves in a fixed stride.  The wave validates the pair, tests the source
+// mesh box against the target mesh box and its top two levels, then culls
+// the source groups 64 at a time (one group box per lane, the next 64 boxes
+// loading while the current ones are tested) and buffers the survivors in
+// LDS; full buffers go to the queue of the block's slice (blockIdx % kSlices,
+// the XCD the block runs on, so phase 2 mostly finds the pair's data in the
+// same L2).  Survivor entry: global group index, unit, target mesh, live
+// segments | FP32-safe flag << 8.
+template <int W, int PREC>
+__global__ __launch_bounds__(kBlock) void k_cull(RefineArgs ra) {
+  __shared__ int4 s_buf[kWaves][kCullBuf];
+  const int wv = uni((int32_t)(threadIdx.x >> 6)), lane = threadIdx.x & 63;
+  const BlobView A = view_of(ra.blob_a), B = view_of(ra.blob_b);
+  if (!blobs_ok(A, B, ra, W)) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) atomicMin(ra.status, (int32_t)PR_E_UNSUPPORTED);
+    return;
+  }
+  const int slice = (int)(blockIdx.x % kSlices);
+  int4* buf = s_buf[wv];
+  int nbuf = 0;
+  WaveStats st;
+  const int64_t U = 2 * ra.n_pairs;
+  const int64_t nw = (int64_t)gridDim.x * kWaves;
+  const cptr_t<int32_t> pairs = cview(ra.pairs);
+  for (int64_t u = (int64_t)blockIdx.x * kWaves + wv; u < U; u += nw) {
+    const int32_t pair = (int32_t)(u >> 1), dir = (int32_t)(u & 1);
+    const int32_t ia = pairs[2 * (int64_t)pair], jb = pairs[2 * (int64_t)pair + 1];
+    if (ia < 0 || ia >= ra.n_meshes_a || jb < 0 || jb >= ra.n_meshes_b) {
+      if (lane == 0) atomicMin(ra.status, (int32_t)PR_E_ARG);
+      continue;
+    }
+    const BlobView& S = dir == 0 ? A : B;
+    const BlobView& T = dir == 0 ? B : A;
+    const int32_t sid = dir == 0 ? ia : jb, tid = dir == 0 ? jb : ia;
+    const cptr_t<MeshDesc> smd = cview(S.mesh) + sid;
+    const cptr_t<MeshDesc> tmd = cview(T.mesh) + tid;
+    float sb[6], tb[6];
+#pragma unroll
+    for (int k = 0; k < 6; ++k) { sb[k] = smd->box[k]; tb[k] = tmd->box[k]; }
+    const int32_t troot = tmd->root;
+    const int32_t n_chunks = smd->n_chunks, n_edges = smd->n_edges, chunk_base = smd->chunk_base;
+    const bool safe = (smd->flags & tmd->flags & kMeshSafe) != 0;
+    if (troot == kEmpty || n_chunks <= 0 || !box_meet(sb, tb[0], tb[1], tb[2], tb[3], tb[4], tb[5])) continue;
+    const cptr_t<Node<W>> nodes = cview(reinterpret_cast<const Node<W>*>(T.nodes));
+    NodeRegs<W> root;
+    load_node<W>(root, nodes + troot);
+    // the whole source mesh against the top two levels (uniform)
+    if (!cull2<W>(sb, root, nodes)) continue;
+    st.add(S_GROUPS, (uint64_t)n_chunks);
+    const float* cbox = S.cbox + 8 * (int64_t)chunk_base;
+    float g[6], gn[6];
+    {
+      const float* cp = cbox + 8 * (int64_t)min(lane, n_chunks - 1);
+#pragma unroll
+      for (int k = 0; k < 6; ++k) g[k] = cp[k];
+    }
+    for (int32_t base = 0; base < n_chunks; base += kChunk) {
+      const int32_t c = base + lane;
+      if (base + kChunk < n_chunks) {  // prefetch the next 64 group boxes
+        const float* cp = cbox + 8 * (int64_t)min(c + kChunk, n_chunks - 1);
+#pragma unroll
+        for (int k = 0; k < 6; ++k) gn[k] = cp[k];
+      }
+      const bool pass = c < n_chunks && box_meet(g, tb[0], tb[1], tb[2], tb[3], tb[4], tb[5]) &&
+                        cull2<W>(g, root, nodes);
+      const uint64_t mask = ballot(pass);
+      if (mask) {
+        const int n = __popcll(mask);
+        st.add(S_GBOX, (uint64_t)n);
+        if (nbuf + n > kCullBuf) {
+          flush_survivors(buf, nbuf, slice, ra, st);
+          nbuf = 0;
+        }
+        if (pass) {
+          const int live = min(kChunk, n_edges - c * kChunk);
+          buf[nbuf + lanes_below(mask)] = make_int4(chunk_base + c, (int32_t)u, tid, live | (safe ? 256 : 0));
+        }
+        nbuf += n;
+      }
+#pragma unroll
+      for (int k = 0; k < 6; ++k) g[k] = gn[k];
+    }
+  }
+  if (nbuf) flush_survivors(buf, nbuf, slice, ra, st);
   flush_stats(st, ra);
 }
 
-// Schedule 3, phase 2: waves pop surviving groups, two at a time, from their
-// block's slice first and then from the others, and trace them.
+// Schedule 3, phase 2: waves pop surviving groups kPop at a time from the
+// queue of their block's slice (blockIdx % kSlices: the XCD the block runs
+// on, which is the XCD whose phase-1 blocks filled that queue) and trace
+// them; a wave ends after its first empty pop.  Phase 1 deals the units to
+// the slices round-robin, so the queues are about equally long, and no wave
+// ever touches another slice's counter (every cross-slice atomic or flag
+// word is a memory-side hot spot).  Pop slot j maps to queue slot j * kSpread mod (slots):
+// the queue holds each pair's groups side by side, and spreading them over
+// the run lets a hit found in one group cancel the pair's later groups.
 template <int W, int PREC>
 __global__ __launch_bounds__(kBlock, 5) void k_trace(RefineArgs ra) {
-  constexpr int CAP = stack_cap<W>();
-  constexpr int kPop = 2;
+  constexpr int CAP = lds_stack_cap<W>();
+  constexpr int kPop = 4;
   __shared__ int32_t s_node[kWaves][CAP];
   __shared__ uint64_t s_mask[kWaves][CAP];
   const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const BlobView A = view_of(ra.blob_a), B = view_of(ra.blob_b);
   if (!blobs_ok(A, B, ra, W)) return;
   WaveStats st;
+  const int cid = (int)(blockIdx.x % kSlices);
+  const uint64_t filled = ra.surv_cnt[kCtrStride * cid];
+  const uint64_t n = filled < ra.surv_cap ? filled : ra.surv_cap;
+  const uint64_t slots = (n + kPop - 1) / kPop;
+  const cptr_t<int32_t> q = cview(reinterpret_cast<const int32_t*>(ra.surv + (int64_t)cid * ra.surv_cap));
+  auto pop = [&]() -> uint64_t {
+    unsigned long long k0 = 0;
+    if (lane == 0) k0 = atomicAdd(ra.surv_pop + kCtrStride * cid, (unsigned long long)kPop);
+    return uni64(k0);
+  };
+  for (;;) {
+    const uint64_t k = pop();
+    if (k >= n) break;
+    const uint64_t e0 = ((k / kPop) * kSpread % slots) * kPop;
+    const uint64_t kend = e0 + kPop < n ? e0 + kPop : n;
+    for (uint64_t e = e0; e < kend; ++e) {
+      const int4 it = make_int4(q[4 * e], q[4 * e + 1], q[4 * e + 2], q[4 * e + 3]);
+      const int32_t pair = it.y >> 1, dir = it.y & 1;
+      const BlobView& S = dir == 0 ? A : B;
+      const BlobView& T = dir == 0 ? B : A;
+      const cptr_t<MeshDesc> tmd = cview(T.mesh) + it.z;
+      float tb[6];
 #pragma unroll
-  for (int k = 0; k < S_N; ++k) st.v[k] = 0;
-  const int home = (int)(blockIdx.x % kSlices);
-  int32_t cur_unit = -1;
-  MeshDesc sm, tm;
-  int32_t pair = 0, dir = 0;
-  bool safe = false;
-  for (int sl = 0; sl < kSlices; ++sl) {
-    const int cid = (home + sl) % kSlices;
-    const uint64_t filled = ra.surv_cnt[kCtrStride * cid];
-    const uint64_t n = filled < ra.surv_cap ? filled : ra.surv_cap;
-    const int2* q = ra.surv + (int64_t)cid * ra.surv_cap;
-    for (;;) {
-      unsigned long long k0 = 0;
-      if (lane == 0) k0 = atomicAdd(ra.surv_pop + kCtrStride * cid, (unsigned long long)kPop);
-      const uint64_t k = uni64(k0);
-      if (k >= n) break;
-      const uint64_t kend = k + kPop < n ? k + kPop : n;
-      for (uint64_t e = k; e < kend; ++e) {
-        const int2 it = q[e];
-        const int32_t unit = uni(it.x), group = uni(it.y);
-        if (unit != cur_unit) {
-          cur_unit = unit;
-          pair = unit >> 1;
-          dir = unit & 1;
-          const int32_t ia = ra.pairs[2 * (int64_t)pair], jb = ra.pairs[2 * (int64_t)pair + 1];
-          sm = dir == 0 ? A.mesh[ia] : B.mesh[jb];
-          tm = dir == 0 ? B.mesh[jb] : A.mesh[ia];
-          safe = (sm.flags & tm.flags & kMeshSafe) != 0;
-        }
-        if (load_state(ra.state + pair)) continue;
-        trace_group<W, PREC>(dir == 0 ? A : B, dir == 0 ? B : A, sm, tm, group, pair, dir, safe, ra, s_node[wv],
-                             s_mask[wv], st);
-      }
+      for (int c = 0; c < 6; ++c) tb[c] = tmd->box[c];
+      trace_core<W, PREC>(S, T, it.x, it.w & 0xff, tmd->root, tb, pair, dir, (it.w & 256) != 0, ra, s_node[wv],
+                          s_mask[wv], st, false);
     }
   }
   flush_stats(st, ra);
@@ -747,7 +911,7 @@ __global__ __launch_bounds__(kBlock, 5) void k_trace(RefineArgs ra) {
 
 template <int W, int PREC>
 __global__ __launch_bounds__(kBlock) void k_refine_pair(RefineArgs ra, int64_t p) {
-  constexpr int CAP = stack_cap<W>();
+  constexpr int CAP = lds_stack_cap<W>();
   __shared__ int32_t s_node[kWaves][CAP];
   __shared__ uint64_t s_mask[kWaves][CAP];
   const int wv = threadIdx.x >> 6;
@@ -764,8 +928,6 @@ __global__ __launch_bounds__(kBlock) void k_refine_pair(RefineArgs ra, int64_t p
   const MeshDesc a = A.mesh[i], b = B.mesh[j];
   if (!box_meet(a.box, b.box[0], b.box[1], b.box[2], b.box[3], b.box[4], b.box[5])) return;
   WaveStats st;
-#pragma unroll
-  for (int k = 0; k < S_N; ++k) st.v[k] = 0;
   const int32_t gw = (int32_t)(blockIdx.x * kWaves + wv), nw = (int32_t)(gridDim.x * kWaves);
   const bool safe = (a.flags & b.flags & kMeshSafe) != 0;
   const int32_t pr32 = (int32_t)p;
@@ -787,7 +949,7 @@ __global__ __launch_bounds__(kBlock) void k_refine_pair(RefineArgs ra, int64_t p
 // with every leaf test decided in place in FP64/exact.  One block per pair.
 template <int W>
 __global__ __launch_bounds__(kBlock) void k_rerun(RefineArgs ra) {
-  constexpr int CAP = stack_cap<W>();
+  constexpr int CAP = lds_stack_cap<W>();
   __shared__ int32_t s_node[kWaves][CAP];
   __shared__ uint64_t s_mask[kWaves][CAP];
   __shared__ uint32_t s_hit;
@@ -795,8 +957,6 @@ __global__ __launch_bounds__(kBlock) void k_rerun(RefineArgs ra) {
   const BlobView A = view_of(ra.blob_a), B = view_of(ra.blob_b);
   if (!blobs_ok(A, B, ra, W)) return;
   WaveStats st;
-#pragma unroll
-  for (int k = 0; k < S_N; ++k) st.v[k] = 0;
   if (ra.stats[S_QOVER] == 0) return;  // no deferred test overflowed: nothing to rerun
   for (int64_t p = blockIdx.x; p < ra.n_pairs; p += gridDim.x) {
     if (load_state(ra.state + p) != 2u) continue;
@@ -899,7 +1059,7 @@ int carve(Carve& cv, RefineArgs& ra, int64_t P, uint32_t qcap, uint32_t surv_cap
   ra.queue = cv.take<int4>(qcap);
   ra.surv_cnt = cv.take<unsigned long long>(kSlices * kCtrStride);
   ra.surv_pop = cv.take<unsigned long long>(kSlices * kCtrStride);
-  ra.surv = cv.take<int2>((int64_t)kSlices * surv_cap);
+  ra.surv = cv.take<int4>((int64_t)kSlices * surv_cap);
   size_t b = 0;
   hipError_t e = hipcub::DeviceScan::ExclusiveSum(nullptr, b, (int64_t*)nullptr, (int64_t*)nullptr, (int)(2 * P + 1));
   if (e != hipSuccess) return hip_fail(e, "hipcub scan size");
@@ -932,9 +1092,11 @@ int launch(RefineArgs& ra, const pr_refine_params* prm, void* scan_tmp, size_t s
   const int64_t P = ra.n_pairs;
   hipEvent_t eb = (hipEvent_t)prm->ev_begin, ee = (hipEvent_t)prm->ev_end;
   if (prm->persistent) {
-    hipLaunchKernelGGL(k_plan<W>, dim3(grid_for(P, kBlock)), dim3(kBlock), 0, s, ra);
-    PR_HIP(hipcub::DeviceScan::ExclusiveSum(scan_tmp, scan_bytes, ra.unit_cnt, ra.offs, (int)(2 * P + 1), s));
     const int sched = prm->schedule == 0 ? 3 : prm->schedule;
+    if (sched != 3) {  // work items: per-unit group counts and their offsets
+      hipLaunchKernelGGL(k_plan<W>, dim3(grid_for(P, kBlock)), dim3(kBlock), 0, s, ra);
+      PR_HIP(hipcub::DeviceScan::ExclusiveSum(scan_tmp, scan_bytes, ra.unit_cnt, ra.offs, (int)(2 * P + 1), s));
+    }
     int blocks = prm->grid_blocks;
     int dev = 0, cus = 0, per = 0;
     PR_HIP(hipGetDevice(&dev));
