@@ -2,17 +2,19 @@
 //
 // Filter: all (i, j) whose closed mesh boxes overlap (touching boxes count),
 // optionally restricted to pairs whose common box part meets a closed query
-// box.  Meshes are first reduced to those meeting the query box (one flag
-// pass and a scan per dataset), then every kept row i of A is matched against
-// the kept meshes of B by one block; counts are scanned and a second pass
-// writes each row's pairs in ascending j with a block-wide ordered
+// box.  Meshes are first reduced to those meeting the query box (an ordered
+// compaction per dataset: one block per dataset up to kSmallScan meshes, a
+// flag pass and a device scan beyond), then every kept row i of A is matched
+// against the kept meshes of B by one block; counts are scanned and a second
+// pass writes each row's pairs in ascending j with a block-wide ordered
 // compaction, so the output is sorted by (i, j) and identical run to run.
 // The exact total is always written; output beyond `cap` is dropped (the
 // caller relaunches with a larger buffer, as the paper does for its result
 // structure, Section 3.5).
 //
 // Compaction (Section 3.5 result materialisation): pairs whose flag is 1,
-// in input order, by the same count/scan/write scheme.
+// in input order: one block up to kSmallScan pairs, else a flag pass, a
+// device scan and a scatter.
 #include <hip/hip_runtime.h>
 #include <hipcub/hipcub.hpp>
 
@@ -22,6 +24,10 @@ namespace pr {
 namespace {
 
 constexpr int kBlock = 256;
+constexpr int kScanBlock = 1024;        // threads of the single-block scans
+constexpr int kScanItems = 4;           // consecutive items per thread per tile
+constexpr int64_t kSmallScan = 65536;   // single-block scans up to this many items
+constexpr int kUnroll = 4;              // box tests in flight per thread in the row kernels
 
 __device__ __forceinline__ const MeshDesc* meshes_of(const void* blob) {
   const BlobHeader* h = reinterpret_cast<const BlobHeader*>(blob);
@@ -67,6 +73,118 @@ __global__ void k_list(const void* blob, const int32_t* flag, const int32_t* pos
     }
 }
 
+// Without a query box every mesh is a row (A) or a column (B): boxes copied
+// in index order, an empty mesh given an inverted box (+inf lows, -inf
+// highs) that meets nothing; ids are the identity.
+__global__ void k_boxes_all(const void* blob_a, int64_t MA, int32_t* ids_a, float* box_a, int32_t* cnt_a,
+                            const void* blob_b, int64_t MB, int32_t* ids_b, float* box_b, int32_t* cnt_b) {
+  const int64_t n = MA + MB;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    const bool a = i < MA;
+    const int64_t m = a ? i : i - MA;
+    const MeshDesc& d = meshes_of(a ? blob_a : blob_b)[m];
+    float* bx = (a ? box_a : box_b) + 6 * m;
+    const bool ok = d.n_tris > 0;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      bx[c] = ok ? d.box[c] : INFINITY;
+      bx[3 + c] = ok ? d.box[3 + c] : -INFINITY;
+    }
+    (a ? ids_a : ids_b)[m] = (int32_t)m;
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    *cnt_a = (int32_t)MA;
+    *cnt_b = (int32_t)MB;
+  }
+}
+
+// With a query box: ordered compaction of the meshes that meet it, one
+// dataset per block (block 0: A, block 1: B), for datasets of at most
+// kSmallScan meshes: tiles of kScanBlock * kScanItems meshes (each thread
+// reads its meshes' box and size once), a block scan of the per-thread
+// counts, ids and boxes written in index order; the count goes to cnt.
+__global__ __launch_bounds__(kScanBlock) void k_keep_small(const void* blob_a, int64_t MA, int32_t* ids_a,
+                                                           float* box_a, int32_t* cnt_a, const void* blob_b,
+                                                           int64_t MB, int32_t* ids_b, float* box_b, int32_t* cnt_b,
+                                                           const float* query) {
+  using BlockScan = hipcub::BlockScan<int32_t, kScanBlock>;
+  __shared__ typename BlockScan::TempStorage tmp;
+  const bool first = blockIdx.x == 0;
+  const MeshDesc* md = meshes_of(first ? blob_a : blob_b);
+  const int64_t M = first ? MA : MB;
+  int32_t* ids = first ? ids_a : ids_b;
+  float* boxes = first ? box_a : box_b;
+  float q[6];
+#pragma unroll
+  for (int c = 0; c < 6; ++c) q[c] = query[c];
+  int32_t running = 0;
+  for (int64_t base = 0; base < M; base += kScanBlock * kScanItems) {
+    const int64_t m0 = base + (int64_t)threadIdx.x * kScanItems;
+    float bx[kScanItems][6];
+    uint32_t keep = 0;
+#pragma unroll
+    for (int i = 0; i < kScanItems; ++i) {
+      const int64_t m = m0 + i;
+      bool ok = false;
+      if (m < M) {
+        const float4* p4 = reinterpret_cast<const float4*>(md + m);
+        const float4 u = p4[0], v = p4[1], w = p4[2];  // box, node base/count, tri base/count
+        bx[i][0] = u.x; bx[i][1] = u.y; bx[i][2] = u.z; bx[i][3] = u.w; bx[i][4] = v.x; bx[i][5] = v.y;
+        ok = __float_as_int(w.y) > 0 && meet(bx[i], q);
+      }
+      keep |= (ok ? 1u : 0u) << i;
+    }
+    int32_t pre = 0, total = 0;
+    BlockScan(tmp).ExclusiveSum((int32_t)__popc(keep), pre, total);
+    int32_t pos = running + pre;
+#pragma unroll
+    for (int i = 0; i < kScanItems; ++i)
+      if ((keep >> i) & 1u) {
+        ids[pos] = (int32_t)(m0 + i);
+#pragma unroll
+        for (int c = 0; c < 6; ++c) boxes[6 * (int64_t)pos + c] = bx[i][c];
+        ++pos;
+      }
+    running += total;
+    __syncthreads();  // tmp is reused by the next tile
+  }
+  if (threadIdx.x == 0) *(first ? cnt_a : cnt_b) = running;
+}
+
+// Exclusive scan of the row counts (at most kSmallScan rows) in one block;
+// the total goes to rowoff[rows] and to the caller's count.
+__global__ __launch_bounds__(kScanBlock) void k_rowscan_small(const int64_t* cnt, int64_t rows, int64_t* off,
+                                                              int64_t* total_out) {
+  using BlockScan = hipcub::BlockScan<int64_t, kScanBlock>;
+  __shared__ typename BlockScan::TempStorage tmp;
+  int64_t running = 0;
+  for (int64_t base = 0; base < rows; base += kScanBlock * kScanItems) {
+    const int64_t r0 = base + (int64_t)threadIdx.x * kScanItems;
+    int64_t v[kScanItems];
+    int64_t sum = 0;
+#pragma unroll
+    for (int i = 0; i < kScanItems; ++i) {
+      v[i] = r0 + i < rows ? cnt[r0 + i] : 0;
+      sum += v[i];
+    }
+    int64_t pre = 0, total = 0;
+    BlockScan(tmp).ExclusiveSum(sum, pre, total);
+    int64_t o = running + pre;
+#pragma unroll
+    for (int i = 0; i < kScanItems; ++i)
+      if (r0 + i < rows) {
+        off[r0 + i] = o;
+        o += v[i];
+      }
+    running += total;
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    off[rows] = running;
+    *total_out = running;
+  }
+}
+
 struct RowArgs {
   const float* box_a;  // compact boxes of the kept meshes
   const float* box_b;
@@ -95,7 +213,13 @@ __global__ void k_row_count(RowArgs r) {
     if (row < na) {
       float a[6];
       for (int q = 0; q < 6; ++q) a[q] = r.box_a[6 * row + q];
-      for (int32_t k = threadIdx.x; k < nb; k += blockDim.x) c += test_pair(r, a, k) ? 1 : 0;
+      for (int32_t base = 0; base < nb; base += kUnroll * kBlock) {
+#pragma unroll
+        for (int u = 0; u < kUnroll; ++u) {
+          const int32_t k = base + u * kBlock + (int32_t)threadIdx.x;
+          c += (k < nb && test_pair(r, a, k)) ? 1 : 0;
+        }
+      }
     }
     for (int o = 32; o > 0; o >>= 1) c += __shfl_xor(c, o);
     if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = c;
@@ -119,9 +243,19 @@ __global__ void k_row_write(RowArgs r) {
     float a[6];
     for (int q = 0; q < 6; ++q) a[q] = r.box_a[6 * row + q];
     int64_t out = r.rowoff[row];
-    for (int32_t base = 0; base < nb; base += kBlock) {
+    for (int32_t base0 = 0; base0 < nb; base0 += kUnroll * kBlock) {
+      bool oks[kUnroll];
+#pragma unroll
+      for (int u = 0; u < kUnroll; ++u) {
+        const int32_t k = base0 + u * kBlock + (int32_t)threadIdx.x;
+        oks[u] = k < nb && test_pair(r, a, k);
+      }
+#pragma unroll
+      for (int u = 0; u < kUnroll; ++u) {
+      const int32_t base = base0 + u * kBlock;
+      if (base >= nb) break;
       const int32_t k = base + threadIdx.x;
-      const bool ok = k < nb && test_pair(r, a, k);
+      const bool ok = oks[u];
       const int32_t jb = ok ? r.ids_b[k] : 0;
       const uint64_t m = __ballot(ok);
       const int below = __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
@@ -141,6 +275,7 @@ __global__ void k_row_write(RowArgs r) {
         }
       }
       out += tot;
+      }
     }
   }
 }
@@ -161,6 +296,36 @@ __global__ void k_compact(const int32_t* pairs, const int32_t* f, const int64_t*
       out[2 * pos[i]] = pairs[2 * i];
       out[2 * pos[i] + 1] = pairs[2 * i + 1];
     }
+}
+
+// Ordered compaction of the flagged pairs in one block (at most kSmallScan
+// pairs): the count goes to *count, output beyond cap is dropped.
+__global__ __launch_bounds__(kScanBlock) void k_compact_small(const int32_t* pairs, const uint8_t* flags, int64_t n,
+                                                              int32_t* out, int64_t cap, int64_t* count) {
+  using BlockScan = hipcub::BlockScan<int32_t, kScanBlock>;
+  __shared__ typename BlockScan::TempStorage tmp;
+  int64_t running = 0;
+  for (int64_t base = 0; base < n; base += kScanBlock * kScanItems) {
+    const int64_t i0 = base + (int64_t)threadIdx.x * kScanItems;
+    uint32_t f = 0;
+#pragma unroll
+    for (int i = 0; i < kScanItems; ++i) f |= (i0 + i < n && flags[i0 + i] ? 1u : 0u) << i;
+    int32_t pre = 0, total = 0;
+    BlockScan(tmp).ExclusiveSum((int32_t)__popc(f), pre, total);
+    int64_t pos = running + pre;
+#pragma unroll
+    for (int i = 0; i < kScanItems; ++i)
+      if ((f >> i) & 1u) {
+        if (pos < cap) {
+          out[2 * pos] = pairs[2 * (i0 + i)];
+          out[2 * pos + 1] = pairs[2 * (i0 + i) + 1];
+        }
+        ++pos;
+      }
+    running += total;
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) *count = running;
 }
 
 struct FilterWs {
@@ -242,14 +407,22 @@ extern "C" int filter_aabb_pairs(const void* blob_a, int64_t n_meshes_a, const v
   if (r) return r;
   if (cv.used > ws_bytes || !w.tmp) { set_error("ws_bytes %zu < required %zu", ws_bytes, cv.used); return PR_E_CAPACITY; }
   const int64_t MA = n_meshes_a, MB = n_meshes_b;
-  hipLaunchKernelGGL(k_keep, dim3(grid_for(MA + 1, kBlock)), dim3(kBlock), 0, s, blob_a, MA, query_box, w.flag_a);
-  hipLaunchKernelGGL(k_keep, dim3(grid_for(MB + 1, kBlock)), dim3(kBlock), 0, s, blob_b, MB, query_box, w.flag_b);
-  PR_HIP(hipcub::DeviceScan::ExclusiveSum(w.tmp, w.tmp_bytes, w.flag_a, w.pos_a, (int)(MA + 1), s));
-  PR_HIP(hipcub::DeviceScan::ExclusiveSum(w.tmp, w.tmp_bytes, w.flag_b, w.pos_b, (int)(MB + 1), s));
-  hipLaunchKernelGGL(k_list, dim3(grid_for(MA, kBlock)), dim3(kBlock), 0, s, blob_a, (const int32_t*)w.flag_a,
-                     (const int32_t*)w.pos_a, MA, w.ids_a, w.box_a);
-  hipLaunchKernelGGL(k_list, dim3(grid_for(MB, kBlock)), dim3(kBlock), 0, s, blob_b, (const int32_t*)w.flag_b,
-                     (const int32_t*)w.pos_b, MB, w.ids_b, w.box_b);
+  if (!query_box) {
+    hipLaunchKernelGGL(k_boxes_all, dim3(grid_for(MA + MB, kBlock)), dim3(kBlock), 0, s, blob_a, MA, w.ids_a,
+                       w.box_a, w.pos_a + MA, blob_b, MB, w.ids_b, w.box_b, w.pos_b + MB);
+  } else if (MA <= kSmallScan && MB <= kSmallScan) {
+    hipLaunchKernelGGL(k_keep_small, dim3(2), dim3(kScanBlock), 0, s, blob_a, MA, w.ids_a, w.box_a, w.pos_a + MA,
+                       blob_b, MB, w.ids_b, w.box_b, w.pos_b + MB, query_box);
+  } else {
+    hipLaunchKernelGGL(k_keep, dim3(grid_for(MA + 1, kBlock)), dim3(kBlock), 0, s, blob_a, MA, query_box, w.flag_a);
+    hipLaunchKernelGGL(k_keep, dim3(grid_for(MB + 1, kBlock)), dim3(kBlock), 0, s, blob_b, MB, query_box, w.flag_b);
+    PR_HIP(hipcub::DeviceScan::ExclusiveSum(w.tmp, w.tmp_bytes, w.flag_a, w.pos_a, (int)(MA + 1), s));
+    PR_HIP(hipcub::DeviceScan::ExclusiveSum(w.tmp, w.tmp_bytes, w.flag_b, w.pos_b, (int)(MB + 1), s));
+    hipLaunchKernelGGL(k_list, dim3(grid_for(MA, kBlock)), dim3(kBlock), 0, s, blob_a, (const int32_t*)w.flag_a,
+                       (const int32_t*)w.pos_a, MA, w.ids_a, w.box_a);
+    hipLaunchKernelGGL(k_list, dim3(grid_for(MB, kBlock)), dim3(kBlock), 0, s, blob_b, (const int32_t*)w.flag_b,
+                       (const int32_t*)w.pos_b, MB, w.ids_b, w.box_b);
+  }
   RowArgs ra{};
   ra.box_a = w.box_a;
   ra.box_b = w.box_b;
@@ -265,9 +438,15 @@ extern "C" int filter_aabb_pairs(const void* blob_a, int64_t n_meshes_a, const v
   ra.cap = cap;
   const int rows_grid = (int)(MA < 2048 ? (MA > 0 ? MA : 1) : 2048);
   hipLaunchKernelGGL(k_row_count, dim3(rows_grid), dim3(kBlock), 0, s, ra);
-  PR_HIP(hipcub::DeviceScan::ExclusiveSum(w.tmp, w.tmp_bytes, w.rowcnt, w.rowoff, (int)(MA + 1), s));
-  hipLaunchKernelGGL(k_row_write, dim3(rows_grid), dim3(kBlock), 0, s, ra);
-  hipLaunchKernelGGL(k_total, dim3(1), dim3(1), 0, s, (const int64_t*)w.rowoff, MA, dev_count);
+  if (MA <= kSmallScan) {
+    hipLaunchKernelGGL(k_rowscan_small, dim3(1), dim3(kScanBlock), 0, s, (const int64_t*)w.rowcnt, MA, w.rowoff,
+                       dev_count);
+    hipLaunchKernelGGL(k_row_write, dim3(rows_grid), dim3(kBlock), 0, s, ra);
+  } else {
+    PR_HIP(hipcub::DeviceScan::ExclusiveSum(w.tmp, w.tmp_bytes, w.rowcnt, w.rowoff, (int)(MA + 1), s));
+    hipLaunchKernelGGL(k_row_write, dim3(rows_grid), dim3(kBlock), 0, s, ra);
+    hipLaunchKernelGGL(k_total, dim3(1), dim3(1), 0, s, (const int64_t*)w.rowoff, MA, dev_count);
+  }
   PR_HIP(hipGetLastError());
   return PR_OK;
 }
@@ -296,6 +475,11 @@ extern "C" int compact_pairs(const int32_t* pairs, const uint8_t* flags, int64_t
   int r = carve_compact(cv, w, n_pairs);
   if (r) return r;
   if (cv.used > ws_bytes || !w.tmp) { set_error("ws_bytes %zu < required %zu", ws_bytes, cv.used); return PR_E_CAPACITY; }
+  if (n_pairs <= kSmallScan) {
+    hipLaunchKernelGGL(k_compact_small, dim3(1), dim3(kScanBlock), 0, s, pairs, flags, n_pairs, out, cap, dev_count);
+    PR_HIP(hipGetLastError());
+    return PR_OK;
+  }
   hipLaunchKernelGGL(k_flag_i32, dim3(grid_for(n_pairs + 1, kBlock)), dim3(kBlock), 0, s, flags, n_pairs, w.f);
   PR_HIP(hipcub::DeviceScan::ExclusiveSum(w.tmp, w.tmp_bytes, w.f, w.pos, (int)(n_pairs + 1), s));
   hipLaunchKernelGGL(k_compact, dim3(grid_for(n_pairs, kBlock)), dim3(kBlock), 0, s, pairs, (const int32_t*)w.f,

@@ -84,6 +84,39 @@ def test_filter_matches_exact_boxes(env):
         assert np.array_equal(got, synth.candidate_pairs(A.aabbs(), B.aabbs()))
 
 
+def _tetra_set(synth, n, seed, side):
+    """n small random tetrahedra (4 faces each) scattered in [0, side]^3."""
+    rng = np.random.default_rng(seed)
+    tf = np.array([[0, 2, 1], [0, 1, 3], [1, 2, 3], [0, 3, 2]], np.int32)
+    c = rng.uniform(0, side, size=(n, 1, 3))
+    v = (c + rng.uniform(-0.5, 0.5, size=(n, 4, 3))).astype(np.float32).reshape(-1, 3)
+    f = np.tile(tf, (n, 1))
+    off4 = np.arange(n + 1, dtype=np.int64) * 4
+    return synth.MeshSet(v, f, off4, off4.copy())
+
+
+@pytest.mark.parametrize("na,nb", [(300, 70_000), (70_000, 50)])
+def test_filter_large_mesh_counts(env, na, nb):
+    """Datasets above the single-block scan limit take the device-scan path
+    for the kept lists and the row offsets."""
+    torch, pa, synth, oracle = env
+    A, B = _tetra_set(synth, na, 11, 30.0), _tetra_set(synth, nb, 12, 30.0)
+    ga, gb = pa.MeshBlob.build(A), pa.MeshBlob.build(B)
+    got = pa.filter_pairs(ga, gb).cpu().numpy()
+    assert np.array_equal(got, synth.candidate_pairs(A.aabbs(), B.aabbs()))
+
+
+@pytest.mark.parametrize("n", [1, 4096, 65_536, 100_003])
+def test_compact_matches_numpy(env, n):
+    """Ordered compaction on both sides of the single-block limit."""
+    torch, pa, synth, oracle = env
+    rng = np.random.default_rng(n)
+    pairs = rng.integers(0, 1 << 20, size=(n, 2)).astype(np.int32)
+    flags = (rng.random(n) < 0.3).astype(np.uint8)
+    got = pa.compact(torch.as_tensor(pairs).cuda(), torch.as_tensor(flags).cuda()).cpu().numpy()
+    assert np.array_equal(got, pairs[flags == 1])
+
+
 def test_filter_query_box_and_capacity(env):
     torch, pa, synth, oracle = env
     A, B = synth.make_c1(seed=4, n=40)
