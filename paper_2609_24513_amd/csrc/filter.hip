@@ -27,7 +27,6 @@ constexpr int kBlock = 256;
 constexpr int kScanBlock = 1024;        // threads of the single-block scans
 constexpr int kScanItems = 4;           // consecutive items per thread per tile
 constexpr int64_t kSmallScan = 65536;   // single-block scans up to this many items
-constexpr int kUnroll = 4;              // box tests in flight per thread in the row kernels
 
 __device__ __forceinline__ const MeshDesc* meshes_of(const void* blob) {
   const BlobHeader* h = reinterpret_cast<const BlobHeader*>(blob);
@@ -36,16 +35,6 @@ __device__ __forceinline__ const MeshDesc* meshes_of(const void* blob) {
 
 __device__ __forceinline__ bool meet(const float* a, const float* b) {
   return a[0] <= b[3] && b[0] <= a[3] && a[1] <= b[4] && b[1] <= a[4] && a[2] <= b[5] && b[2] <= a[5];
-}
-
-// triple overlap of closed boxes a, b, q
-__device__ __forceinline__ bool meet3(const float* a, const float* b, const float* q) {
-  for (int k = 0; k < 3; ++k) {
-    float lo = fmaxf(fmaxf(a[k], b[k]), q[k]);
-    float hi = fminf(fminf(a[3 + k], b[3 + k]), q[3 + k]);
-    if (!(lo <= hi)) return false;
-  }
-  return true;
 }
 
 __global__ void k_keep(const void* blob, int64_t M, const float* query, int32_t* flag) {
@@ -200,81 +189,97 @@ struct RowArgs {
   int64_t cap;
 };
 
-__device__ __forceinline__ bool test_pair(const RowArgs& r, const float* a, int32_t k) {
-  const float* b = r.box_b + 6 * (int64_t)k;
-  return r.query ? meet3(a, b, r.query) : meet(a, b);
+// Row kernels: a block takes kRowsPerBlock kept rows of A (one per wave) and
+// walks the kept boxes of B in tiles of kTile staged in LDS (one copy per
+// tile for the block's rows instead of one L2 read per row); each wave tests
+// its row against the tile, 64 columns at a time.
+constexpr int kRowsPerBlock = kBlock / 64;
+constexpr int kTile = 1024;
+
+__device__ __forceinline__ bool test_box(const float* a, const float* q, float l0, float l1, float l2, float h0,
+                                         float h1, float h2) {
+  if (q) {
+    return fmaxf(fmaxf(a[0], l0), q[0]) <= fminf(fminf(a[3], h0), q[3]) &&
+           fmaxf(fmaxf(a[1], l1), q[1]) <= fminf(fminf(a[4], h1), q[4]) &&
+           fmaxf(fmaxf(a[2], l2), q[2]) <= fminf(fminf(a[5], h2), q[5]);
+  }
+  return a[0] <= h0 && l0 <= a[3] && a[1] <= h1 && l1 <= a[4] && a[2] <= h2 && l2 <= a[5];
 }
 
-__global__ void k_row_count(RowArgs r) {
-  __shared__ unsigned long long sh[kBlock / 64];
-  const int32_t na = *r.na, nb = *r.nb;
-  for (int64_t row = blockIdx.x; row < r.rows; row += gridDim.x) {
-    unsigned long long c = 0;
-    if (row < na) {
-      float a[6];
-      for (int q = 0; q < 6; ++q) a[q] = r.box_a[6 * row + q];
-      for (int32_t base = 0; base < nb; base += kUnroll * kBlock) {
+__device__ __forceinline__ void load_tile(float (*t)[kTile], const float* box_b, int32_t t0, int32_t nb) {
+  for (int i = threadIdx.x; i < kTile; i += kBlock) {
+    const int32_t k = t0 + i;
+    if (k < nb) {
 #pragma unroll
-        for (int u = 0; u < kUnroll; ++u) {
-          const int32_t k = base + u * kBlock + (int32_t)threadIdx.x;
-          c += (k < nb && test_pair(r, a, k)) ? 1 : 0;
+      for (int c = 0; c < 6; ++c) t[c][i] = box_b[6 * (int64_t)k + c];
+    }
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void k_row_count(RowArgs r) {
+  __shared__ float tile[6][kTile];
+  const int32_t na = *r.na, nb = *r.nb;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int64_t groups = (r.rows + kRowsPerBlock - 1) / kRowsPerBlock;
+  for (int64_t g = blockIdx.x; g < groups; g += gridDim.x) {
+    const int64_t row = g * kRowsPerBlock + wv;
+    const bool live = row < na;
+    float a[6];
+#pragma unroll
+    for (int c = 0; c < 6; ++c) a[c] = live ? r.box_a[6 * row + c] : 0.f;
+    unsigned long long cnt = 0;
+    if (g * kRowsPerBlock < na) {  // uniform over the block
+      for (int32_t t0 = 0; t0 < nb; t0 += kTile) {
+        __syncthreads();
+        load_tile(tile, r.box_b, t0, nb);
+        __syncthreads();
+        if (live) {
+          const int32_t n = min(kTile, nb - t0);
+          for (int32_t i = lane; i < n; i += 64)
+            cnt += test_box(a, r.query, tile[0][i], tile[1][i], tile[2][i], tile[3][i], tile[4][i], tile[5][i]) ? 1
+                                                                                                             : 0;
         }
       }
     }
-    for (int o = 32; o > 0; o >>= 1) c += __shfl_xor(c, o);
-    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = c;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-      unsigned long long t = 0;
-      for (int w = 0; w < kBlock / 64; ++w) t += sh[w];
-      r.rowcnt[row] = (int64_t)t;
-    }
-    __syncthreads();
+    for (int o = 32; o > 0; o >>= 1) cnt += __shfl_xor(cnt, o);
+    if (lane == 0 && row < r.rows) r.rowcnt[row] = (int64_t)cnt;
   }
   if (blockIdx.x == 0 && threadIdx.x == 0) r.rowcnt[r.rows] = 0;
 }
 
-__global__ void k_row_write(RowArgs r) {
-  __shared__ int32_t wsum[kBlock / 64];
+__global__ __launch_bounds__(kBlock) void k_row_write(RowArgs r) {
+  __shared__ float tile[6][kTile];
   const int32_t na = *r.na, nb = *r.nb;
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  for (int64_t row = blockIdx.x; row < na; row += gridDim.x) {
-    const int32_t ia = r.ids_a[row];
+  const int64_t groups = ((int64_t)na + kRowsPerBlock - 1) / kRowsPerBlock;
+  for (int64_t g = blockIdx.x; g < groups; g += gridDim.x) {
+    const int64_t row = g * kRowsPerBlock + wv;
+    const bool live = row < na;
     float a[6];
-    for (int q = 0; q < 6; ++q) a[q] = r.box_a[6 * row + q];
-    int64_t out = r.rowoff[row];
-    for (int32_t base0 = 0; base0 < nb; base0 += kUnroll * kBlock) {
-      bool oks[kUnroll];
 #pragma unroll
-      for (int u = 0; u < kUnroll; ++u) {
-        const int32_t k = base0 + u * kBlock + (int32_t)threadIdx.x;
-        oks[u] = k < nb && test_pair(r, a, k);
-      }
-#pragma unroll
-      for (int u = 0; u < kUnroll; ++u) {
-      const int32_t base = base0 + u * kBlock;
-      if (base >= nb) break;
-      const int32_t k = base + threadIdx.x;
-      const bool ok = oks[u];
-      const int32_t jb = ok ? r.ids_b[k] : 0;
-      const uint64_t m = __ballot(ok);
-      const int below = __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+    for (int c = 0; c < 6; ++c) a[c] = live ? r.box_a[6 * row + c] : 0.f;
+    const int32_t ia = live ? r.ids_a[row] : 0;
+    int64_t out = live ? r.rowoff[row] : 0;
+    for (int32_t t0 = 0; t0 < nb; t0 += kTile) {
       __syncthreads();
-      if (lane == 0) wsum[wv] = __popcll(m);
+      load_tile(tile, r.box_b, t0, nb);
       __syncthreads();
-      int32_t before = 0, tot = 0;
-      for (int w = 0; w < kBlock / 64; ++w) {
-        if (w < wv) before += wsum[w];
-        tot += wsum[w];
-      }
-      if (ok) {
-        const int64_t pos = out + before + below;
-        if (pos < r.cap) {
-          r.pairs[2 * pos] = ia;
-          r.pairs[2 * pos + 1] = jb;
+      if (!live) continue;
+      const int32_t n = min(kTile, nb - t0);
+      for (int32_t i0 = 0; i0 < n; i0 += 64) {
+        const int32_t i = i0 + lane;
+        const bool ok =
+            i < n && test_box(a, r.query, tile[0][i], tile[1][i], tile[2][i], tile[3][i], tile[4][i], tile[5][i]);
+        const uint64_t m = __ballot(ok);
+        if (ok) {
+          const int64_t pos = out + __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32),
+                                                              __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+          if (pos < r.cap) {
+            r.pairs[2 * pos] = ia;
+            r.pairs[2 * pos + 1] = r.ids_b[t0 + i];
+          }
         }
-      }
-      out += tot;
+        out += __popcll(m);
       }
     }
   }
@@ -436,7 +441,8 @@ extern "C" int filter_aabb_pairs(const void* blob_a, int64_t n_meshes_a, const v
   ra.rowoff = w.rowoff;
   ra.pairs = pairs;
   ra.cap = cap;
-  const int rows_grid = (int)(MA < 2048 ? (MA > 0 ? MA : 1) : 2048);
+  const int64_t row_groups = (MA + kRowsPerBlock - 1) / kRowsPerBlock;
+  const int rows_grid = (int)(row_groups < 2048 ? (row_groups > 0 ? row_groups : 1) : 2048);
   hipLaunchKernelGGL(k_row_count, dim3(rows_grid), dim3(kBlock), 0, s, ra);
   if (MA <= kSmallScan) {
     hipLaunchKernelGGL(k_rowscan_small, dim3(1), dim3(kScanBlock), 0, s, (const int64_t*)w.rowcnt, MA, w.rowoff,

@@ -113,6 +113,15 @@ struct RefineArgs {
 constexpr int kSlices = 8;     // one pop counter per XCD
 constexpr int kMaxItemGroups = 1024;
 constexpr int kCtrStride = 512; // u64 words between counters (4 KiB: separate memory channels)
+// Statistics: kStatCopies copies of the S_N counters (blockIdx % kStatCopies),
+// kCtrStride words apart, summed when reported: atomics on one address
+// serialise at the memory side (about 11 ns each), and every wave adds its
+// counters when it ends.  The overflow counter lives in copy 0 only, so that
+// one load tells whether a rerun is needed.
+constexpr int kStatCopies = 64;
+__device__ __forceinline__ unsigned long long* stat_copy(unsigned long long* stats) {
+  return stats + kCtrStride * (blockIdx.x % kStatCopies);
+}
 
 __device__ __forceinline__ uint32_t load_state(const uint32_t* p) {
   return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -428,8 +437,9 @@ __device__ bool trace_chunk(const BlobView& S, const BlobView& T, const MeshDesc
 __device__ __forceinline__ void flush_stats(const WaveStats& st, const RefineArgs& ra) {
   const int k = threadIdx.x & 63;
   if (k < S_N && st.acc) {
-    if (k == S_MAXV || k == S_MAXL) atomicMax(ra.stats + k, (unsigned long long)st.acc);
-    else atomicAdd(ra.stats + k, (unsigned long long)st.acc);
+    unsigned long long* c = k == S_QOVER ? ra.stats : stat_copy(ra.stats);
+    if (k == S_MAXV || k == S_MAXL) atomicMax(c + k, (unsigned long long)st.acc);
+    else atomicAdd(c + k, (unsigned long long)st.acc);
   }
 }
 
@@ -449,7 +459,7 @@ __device__ __forceinline__ bool blobs_ok(const BlobView& A, const BlobView& B, c
 __global__ void k_init(RefineArgs ra) {
   int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   for (int64_t p = i; p < ra.n_pairs; p += (int64_t)gridDim.x * blockDim.x) ra.state[p] = 0u;
-  if (i < S_N) ra.stats[i] = 0ull;
+  if (i < kStatCopies * S_N) ra.stats[kCtrStride * (i / S_N) + i % S_N] = 0ull;
   if (i < kSlices) {
     ra.ctr[kCtrStride * i] = 0ull;
     ra.surv_cnt[kCtrStride * i] = 0ull;
@@ -796,9 +806,20 @@ __global__ __launch_bounds__(kBlock) void k_cull(RefineArgs ra) {
   const int64_t U = 2 * ra.n_pairs;
   const int64_t nw = (int64_t)gridDim.x * kWaves;
   const cptr_t<int32_t> pairs = cview(ra.pairs);
-  for (int64_t u = (int64_t)blockIdx.x * kWaves + wv; u < U; u += nw) {
+  const int64_t u0 = (int64_t)blockIdx.x * kWaves + wv;
+  // the pair of the wave's next unit is read while the current one is culled
+  int32_t next_a = 0, next_b = 0;
+  if (u0 < U) {
+    next_a = pairs[2 * (u0 >> 1)];
+    next_b = pairs[2 * (u0 >> 1) + 1];
+  }
+  for (int64_t u = u0; u < U; u += nw) {
     const int32_t pair = (int32_t)(u >> 1), dir = (int32_t)(u & 1);
-    const int32_t ia = pairs[2 * (int64_t)pair], jb = pairs[2 * (int64_t)pair + 1];
+    const int32_t ia = next_a, jb = next_b;
+    if (u + nw < U) {
+      next_a = pairs[2 * ((u + nw) >> 1)];
+      next_b = pairs[2 * ((u + nw) >> 1) + 1];
+    }
     if (ia < 0 || ia >= ra.n_meshes_a || jb < 0 || jb >= ra.n_meshes_b) {
       if (lane == 0) atomicMin(ra.status, (int32_t)PR_E_ARG);
       continue;
@@ -815,12 +836,7 @@ __global__ __launch_bounds__(kBlock) void k_cull(RefineArgs ra) {
     const int32_t n_chunks = smd->n_chunks, n_edges = smd->n_edges, chunk_base = smd->chunk_base;
     const bool safe = (smd->flags & tmd->flags & kMeshSafe) != 0;
     if (troot == kEmpty || n_chunks <= 0 || !box_meet(sb, tb[0], tb[1], tb[2], tb[3], tb[4], tb[5])) continue;
-    const cptr_t<Node<W>> nodes = cview(reinterpret_cast<const Node<W>*>(T.nodes));
-    NodeRegs<W> root;
-    load_node<W>(root, nodes + troot);
-    // the whole source mesh against the top two levels (uniform)
-    if (!cull2<W>(sb, root, nodes)) continue;
-    st.add(S_GROUPS, (uint64_t)n_chunks);
+    // the first 64 group boxes load while the top of the target tree is read
     const float* cbox = S.cbox + 8 * (int64_t)chunk_base;
     float g[6], gn[6];
     {
@@ -828,6 +844,12 @@ __global__ __launch_bounds__(kBlock) void k_cull(RefineArgs ra) {
 #pragma unroll
       for (int k = 0; k < 6; ++k) g[k] = cp[k];
     }
+    const cptr_t<Node<W>> nodes = cview(reinterpret_cast<const Node<W>*>(T.nodes));
+    NodeRegs<W> root;
+    load_node<W>(root, nodes + troot);
+    // the whole source mesh against the top two levels (uniform)
+    if (!cull2<W>(sb, root, nodes)) continue;
+    st.add(S_GROUPS, (uint64_t)n_chunks);
     for (int32_t base = 0; base < n_chunks; base += kChunk) {
       const int32_t c = base + lane;
       if (base + kChunk < n_chunks) {  // prefetch the next 64 group boxes
@@ -957,7 +979,7 @@ __global__ __launch_bounds__(kBlock) void k_rerun(RefineArgs ra) {
   const BlobView A = view_of(ra.blob_a), B = view_of(ra.blob_b);
   if (!blobs_ok(A, B, ra, W)) return;
   WaveStats st;
-  if (ra.stats[S_QOVER] == 0) return;  // no deferred test overflowed: nothing to rerun
+  if (ra.stats[S_QOVER] == 0) return;  // nothing overflowed: nothing to rerun
   for (int64_t p = blockIdx.x; p < ra.n_pairs; p += gridDim.x) {
     if (load_state(ra.state + p) != 2u) continue;
     if (threadIdx.x == 0) s_hit = 0;
@@ -1004,8 +1026,8 @@ __global__ void k_redecide(RefineArgs ra) {
     if (ec.exact_signs) ++namb;
     if (h) mark_true(ra.state + e.x);
   }
-  if (nexact) atomicAdd(ra.stats + S_EXACT, (unsigned long long)nexact);
-  if (namb) atomicAdd(ra.stats + S_AMB64, (unsigned long long)namb);
+  if (nexact) atomicAdd(stat_copy(ra.stats) + S_EXACT, (unsigned long long)nexact);
+  if (namb) atomicAdd(stat_copy(ra.stats) + S_AMB64, (unsigned long long)namb);
 }
 
 __global__ void k_finalize(RefineArgs ra) {
@@ -1017,27 +1039,42 @@ __global__ void k_finalize(RefineArgs ra) {
     cnt += f;
   }
   for (int o = 32; o > 0; o >>= 1) cnt += __shfl_xor(cnt, o);
-  if ((threadIdx.x & 63) == 0 && cnt) atomicAdd(ra.stats + S_TRUE, cnt);
+  if ((threadIdx.x & 63) == 0 && cnt) atomicAdd(stat_copy(ra.stats) + S_TRUE, cnt);
 }
 
+// One wave: lane c reads copy c of the statistics, then sums (maxima) across
+// the lanes.
 __global__ void k_report(RefineArgs ra, pr_refine_stats* out, int32_t* dev_status) {
+  static_assert(kStatCopies == 64, "one lane per copy");
+  const int lane = threadIdx.x & 63;
   if (out) {
-    out->segments = ra.stats[S_SEG];
-    out->node_visits = ra.stats[S_VISIT];
-    out->tri_tests = ra.stats[S_TESTS];
-    out->fp32_ambiguous = ra.stats[S_AMB32];
-    out->fp64_filter_ambiguous = ra.stats[S_AMB64];
-    out->exact_decided = ra.stats[S_EXACT];
-    out->pairs_true = ra.stats[S_TRUE];
-    out->queue_overflow = ra.stats[S_QOVER];
-    out->groups = ra.stats[S_GROUPS];
-    out->tri_fetches = ra.stats[S_TRIF];
-    out->groups_box_pass = ra.stats[S_GBOX];
-    out->groups_traversed = ra.stats[S_GTRAV];
-    out->max_group_node_visits = ra.stats[S_MAXV];
-    out->max_group_leaf_fetches = ra.stats[S_MAXL];
+    unsigned long long v[S_N];
+#pragma unroll
+    for (int k = 0; k < S_N; ++k) {
+      unsigned long long x = ra.stats[kCtrStride * lane + k];
+      for (int o = 32; o > 0; o >>= 1) {
+        const unsigned long long y = __shfl_xor(x, o);
+        x = (k == S_MAXV || k == S_MAXL) ? (y > x ? y : x) : x + y;
+      }
+      v[k] = x;
+    }
+    if (lane != 0) return;
+    out->segments = v[S_SEG];
+    out->node_visits = v[S_VISIT];
+    out->tri_tests = v[S_TESTS];
+    out->fp32_ambiguous = v[S_AMB32];
+    out->fp64_filter_ambiguous = v[S_AMB64];
+    out->exact_decided = v[S_EXACT];
+    out->pairs_true = v[S_TRUE];
+    out->queue_overflow = v[S_QOVER];
+    out->groups = v[S_GROUPS];
+    out->tri_fetches = v[S_TRIF];
+    out->groups_box_pass = v[S_GBOX];
+    out->groups_traversed = v[S_GTRAV];
+    out->max_group_node_visits = v[S_MAXV];
+    out->max_group_leaf_fetches = v[S_MAXL];
   }
-  if (dev_status) *dev_status = *ra.status;
+  if (dev_status && lane == 0) *dev_status = *ra.status;
 }
 
 // ---- host side ---------------------------------------------------------------------
@@ -1054,7 +1091,7 @@ int carve(Carve& cv, RefineArgs& ra, int64_t P, uint32_t qcap, uint32_t surv_cap
   ra.offs = cv.take<int64_t>(2 * P + 1);
   ra.ctr = cv.take<unsigned long long>(kSlices * kCtrStride);
   ra.qcount = cv.take<uint32_t>(1);
-  ra.stats = cv.take<unsigned long long>(S_N);
+  ra.stats = cv.take<unsigned long long>(kStatCopies * kCtrStride);
   ra.status = cv.take<int32_t>(1);
   ra.queue = cv.take<int4>(qcap);
   ra.surv_cnt = cv.take<unsigned long long>(kSlices * kCtrStride);
@@ -1181,7 +1218,8 @@ extern "C" int refine_intersects(const void* blob_a, int64_t n_meshes_a, const v
   ra.surv_cap = scap;
   ra.item_groups = params->chunks_per_pop > 0 ? params->chunks_per_pop : 256;
   if (ra.item_groups > kMaxItemGroups) ra.item_groups = kMaxItemGroups;
-  hipLaunchKernelGGL(k_init, dim3(grid_for(n_pairs > S_N ? n_pairs : S_N, kBlock)), dim3(kBlock), 0, s, ra);
+  hipLaunchKernelGGL(k_init, dim3(grid_for(n_pairs > kStatCopies * S_N ? n_pairs : kStatCopies * S_N, kBlock)),
+                     dim3(kBlock), 0, s, ra);
   if (n_pairs > 0) {
     const int W = params->bvh_width, PREC = params->precision;
 #define PR_LAUNCH(w, q) if (W == w && PREC == q) r = launch<w, q>(ra, params, scan_tmp, scan_bytes, s)
@@ -1198,7 +1236,7 @@ extern "C" int refine_intersects(const void* blob_a, int64_t n_meshes_a, const v
     else hipLaunchKernelGGL(k_rerun<8>, dim3(rb), dim3(kBlock), 0, s, ra);
     hipLaunchKernelGGL(k_finalize, dim3(grid_for(n_pairs, kBlock)), dim3(kBlock), 0, s, ra);
   }
-  hipLaunchKernelGGL(k_report, dim3(1), dim3(1), 0, s, ra, dev_stats, dev_status);
+  hipLaunchKernelGGL(k_report, dim3(1), dim3(64), 0, s, ra, dev_stats, dev_status);
   PR_HIP(hipGetLastError());
   return PR_OK;
 }
