@@ -104,13 +104,18 @@ struct RefineArgs {
   unsigned long long* stats;  // [S_N]
   int32_t* status;            // [1]
   int32_t item_groups;        // groups per work item
-  int4* surv;                 // kSlices queues of surviving groups (SurvEntry layout)
+  int4* surv;                 // kQueues queues of surviving groups (survivor entry layout)
   uint32_t surv_cap;          // entries per queue
-  unsigned long long* surv_cnt;  // kSlices fill counters (stride kCtrStride)
-  unsigned long long* surv_pop;  // kSlices pop counters (stride kCtrStride)
+  unsigned long long* surv_cnt;  // kQueues fill counters (stride kCtrStride)
+  unsigned long long* surv_pop;  // kQueues pop counters (stride kCtrStride)
 };
 
 constexpr int kSlices = 8;     // one pop counter per XCD
+// Survivor queues of schedule 3: queue blockIdx % kQueues, so every queue is
+// filled and drained by the blocks of one XCD (blocks are dealt round-robin
+// to the 8 XCDs); 8 queues per XCD keep the atomics on each queue's counters
+// below the memory-side serialisation rate.
+constexpr int kQueues = 64;
 constexpr int kMaxItemGroups = 1024;
 constexpr int kCtrStride = 512; // u64 words between counters (4 KiB: separate memory channels)
 // Statistics: kStatCopies copies of the S_N counters (blockIdx % kStatCopies),
@@ -460,8 +465,8 @@ __global__ void k_init(RefineArgs ra) {
   int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   for (int64_t p = i; p < ra.n_pairs; p += (int64_t)gridDim.x * blockDim.x) ra.state[p] = 0u;
   if (i < kStatCopies * S_N) ra.stats[kCtrStride * (i / S_N) + i % S_N] = 0ull;
-  if (i < kSlices) {
-    ra.ctr[kCtrStride * i] = 0ull;
+  if (i < kSlices) ra.ctr[kCtrStride * i] = 0ull;
+  if (i < kQueues) {
     ra.surv_cnt[kCtrStride * i] = 0ull;
     ra.surv_pop[kCtrStride * i] = 0ull;
   }
@@ -786,7 +791,7 @@ __device__ void flush_survivors(const int4* buf, int n, int slice, const RefineA
 // mesh box against the target mesh box and its top two levels, then culls
 // the source groups 64 at a time (one group box per lane, the next 64 boxes
 // loading while the current ones are tested) and buffers the survivors in
-// LDS; full buffers go to the queue of the block's slice (blockIdx % kSlices,
+// LDS; full buffers go to the block's queue (blockIdx % kQueues, on
 // the XCD the block runs on, so phase 2 mostly finds the pair's data in the
 // same L2).  Survivor entry: global group index, unit, target mesh, live
 // segments | FP32-safe flag << 8.
@@ -799,7 +804,7 @@ __global__ __launch_bounds__(kBlock) void k_cull(RefineArgs ra) {
     if (blockIdx.x == 0 && threadIdx.x == 0) atomicMin(ra.status, (int32_t)PR_E_UNSUPPORTED);
     return;
   }
-  const int slice = (int)(blockIdx.x % kSlices);
+  const int slice = (int)(blockIdx.x % kQueues);
   int4* buf = s_buf[wv];
   int nbuf = 0;
   WaveStats st;
@@ -882,14 +887,15 @@ __global__ __launch_bounds__(kBlock) void k_cull(RefineArgs ra) {
 }
 
 // Schedule 3, phase 2: waves pop surviving groups kPop at a time from the
-// queue of their block's slice (blockIdx % kSlices: the XCD the block runs
-// on, which is the XCD whose phase-1 blocks filled that queue) and trace
-// them; a wave ends after its first empty pop.  Phase 1 deals the units to
-// the slices round-robin, so the queues are about equally long, and no wave
-// ever touches another slice's counter (every cross-slice atomic or flag
-// word is a memory-side hot spot).  Pop slot j maps to queue slot j * kSpread mod (slots):
-// the queue holds each pair's groups side by side, and spreading them over
-// the run lets a hit found in one group cancel the pair's later groups.
+// queue of their block (blockIdx % kQueues, on the XCD whose phase-1 blocks
+// filled it) and trace them; a wave leaves a queue after its first empty pop.
+// Phase 1 deals the units to the queues round-robin, so the queues are about
+// equally long, and no wave touches another queue's counter (a counter that
+// many waves hit is a memory-side hot spot).  With fewer blocks than queues a
+// block drains queues blockIdx, blockIdx + gridDim, ...  Pop slot j maps to
+// queue slot j * kSpread mod (slots): the queue holds each pair's groups side
+// by side, and spreading them over the run lets a hit found in one group
+// cancel the pair's later groups.
 template <int W, int PREC>
 __global__ __launch_bounds__(kBlock, 5) void k_trace(RefineArgs ra) {
   constexpr int CAP = lds_stack_cap<W>();
@@ -900,32 +906,31 @@ __global__ __launch_bounds__(kBlock, 5) void k_trace(RefineArgs ra) {
   const BlobView A = view_of(ra.blob_a), B = view_of(ra.blob_b);
   if (!blobs_ok(A, B, ra, W)) return;
   WaveStats st;
-  const int cid = (int)(blockIdx.x % kSlices);
-  const uint64_t filled = ra.surv_cnt[kCtrStride * cid];
-  const uint64_t n = filled < ra.surv_cap ? filled : ra.surv_cap;
-  const uint64_t slots = (n + kPop - 1) / kPop;
-  const cptr_t<int32_t> q = cview(reinterpret_cast<const int32_t*>(ra.surv + (int64_t)cid * ra.surv_cap));
-  auto pop = [&]() -> uint64_t {
-    unsigned long long k0 = 0;
-    if (lane == 0) k0 = atomicAdd(ra.surv_pop + kCtrStride * cid, (unsigned long long)kPop);
-    return uni64(k0);
-  };
-  for (;;) {
-    const uint64_t k = pop();
-    if (k >= n) break;
-    const uint64_t e0 = ((k / kPop) * kSpread % slots) * kPop;
-    const uint64_t kend = e0 + kPop < n ? e0 + kPop : n;
-    for (uint64_t e = e0; e < kend; ++e) {
-      const int4 it = make_int4(q[4 * e], q[4 * e + 1], q[4 * e + 2], q[4 * e + 3]);
-      const int32_t pair = it.y >> 1, dir = it.y & 1;
-      const BlobView& S = dir == 0 ? A : B;
-      const BlobView& T = dir == 0 ? B : A;
-      const cptr_t<MeshDesc> tmd = cview(T.mesh) + it.z;
-      float tb[6];
+  const int qstep = (int)(gridDim.x < (unsigned)kQueues ? gridDim.x : kQueues);
+  for (int cid = (int)(blockIdx.x % kQueues); cid < kQueues; cid += qstep) {
+    const uint64_t filled = ra.surv_cnt[kCtrStride * cid];
+    const uint64_t n = filled < ra.surv_cap ? filled : ra.surv_cap;
+    const uint64_t slots = (n + kPop - 1) / kPop;
+    const cptr_t<int32_t> q = cview(reinterpret_cast<const int32_t*>(ra.surv + (int64_t)cid * ra.surv_cap));
+    for (;;) {
+      unsigned long long k0 = 0;
+      if (lane == 0) k0 = atomicAdd(ra.surv_pop + kCtrStride * cid, (unsigned long long)kPop);
+      const uint64_t k = uni64(k0);
+      if (k >= n) break;
+      const uint64_t e0 = ((k / kPop) * kSpread % slots) * kPop;
+      const uint64_t kend = e0 + kPop < n ? e0 + kPop : n;
+      for (uint64_t e = e0; e < kend; ++e) {
+        const int4 it = make_int4(q[4 * e], q[4 * e + 1], q[4 * e + 2], q[4 * e + 3]);
+        const int32_t pair = it.y >> 1, dir = it.y & 1;
+        const BlobView& S = dir == 0 ? A : B;
+        const BlobView& T = dir == 0 ? B : A;
+        const cptr_t<MeshDesc> tmd = cview(T.mesh) + it.z;
+        float tb[6];
 #pragma unroll
-      for (int c = 0; c < 6; ++c) tb[c] = tmd->box[c];
-      trace_core<W, PREC>(S, T, it.x, it.w & 0xff, tmd->root, tb, pair, dir, (it.w & 256) != 0, ra, s_node[wv],
-                          s_mask[wv], st, false);
+        for (int c = 0; c < 6; ++c) tb[c] = tmd->box[c];
+        trace_core<W, PREC>(S, T, it.x, it.w & 0xff, tmd->root, tb, pair, dir, (it.w & 256) != 0, ra, s_node[wv],
+                            s_mask[wv], st, false);
+      }
     }
   }
   flush_stats(st, ra);
@@ -1094,9 +1099,9 @@ int carve(Carve& cv, RefineArgs& ra, int64_t P, uint32_t qcap, uint32_t surv_cap
   ra.stats = cv.take<unsigned long long>(kStatCopies * kCtrStride);
   ra.status = cv.take<int32_t>(1);
   ra.queue = cv.take<int4>(qcap);
-  ra.surv_cnt = cv.take<unsigned long long>(kSlices * kCtrStride);
-  ra.surv_pop = cv.take<unsigned long long>(kSlices * kCtrStride);
-  ra.surv = cv.take<int4>((int64_t)kSlices * surv_cap);
+  ra.surv_cnt = cv.take<unsigned long long>(kQueues * kCtrStride);
+  ra.surv_pop = cv.take<unsigned long long>(kQueues * kCtrStride);
+  ra.surv = cv.take<int4>((int64_t)kQueues * surv_cap);
   size_t b = 0;
   hipError_t e = hipcub::DeviceScan::ExclusiveSum(nullptr, b, (int64_t*)nullptr, (int64_t*)nullptr, (int)(2 * P + 1));
   if (e != hipSuccess) return hip_fail(e, "hipcub scan size");
@@ -1121,7 +1126,7 @@ int check(int64_t P, const pr_refine_params* p) {
 uint32_t qcap_of(const pr_refine_params* p) { return p->queue_cap > 0 ? (uint32_t)p->queue_cap : (1u << 20); }
 uint32_t scap_of(const pr_refine_params* p) {
   const uint32_t total = p->survivor_cap > 0 ? (uint32_t)p->survivor_cap : (1u << 22);
-  return (total + kSlices - 1) / kSlices;
+  return (total + kQueues - 1) / kQueues;
 }
 
 template <int W, int PREC>
