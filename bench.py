@@ -228,19 +228,24 @@ def main():
     ref_ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
 
     def step(k=None):
+        # one pass on the device: filter -> refine -> compaction, the pair count
+        # handed from stage to stage on the device (no host round trip)
         if k is not None:
             filt_ev[k][0].record()
-        pairs = pa.filter_pairs(ga, gb, cap=P) if given is None else given
+        if given is None:
+            pairs, cnt = pa.filter_pairs(ga, gb, cap=P, sync=False)
+        else:
+            pairs, cnt = given, None
         if k is not None:
             filt_ev[k][1].record()
             ref_ev[k][0].record()
         cfg = pa.RefineConfig(**base_cfg, ev_begin=None if k is None else cfg_events[k][0],
-                              ev_end=None if k is None else cfg_events[k][1])
+                              ev_end=None if k is None else cfg_events[k][1], n_dev=cnt)
         pa.refine(ga, gb, pairs, cfg, ws=ws, flags=flags, stats=stats, status=status)
         if k is not None:
             ref_ev[k][1].record()
-        res = pa.compact(pairs, flags)
-        return pairs, res
+        res, rcnt = pa.compact(pairs, flags, n_dev=cnt, sync=False)
+        return pairs, cnt, res, rcnt
 
     for _ in range(args.warmup):
         step()
@@ -248,9 +253,12 @@ def main():
     log("warmup done (%d steps), %d candidate pairs" % (args.warmup, P))
     t0 = time.perf_counter()
     for k in range(args.steps):
-        pairs, res = step(k)
+        pairs, cnt, res, rcnt = step(k)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
+    if cnt is not None and int(cnt.item()) != P:
+        raise RuntimeError("filter count %d != %d" % (int(cnt.item()), P))
+    res = res[:int(rcnt.item())]
     ms_step = (t1 - t0) * 1e3 / args.steps
     kern_ms = float(np.mean([a.elapsed_time(b) for a, b in cfg_events]))
     refine_ms = float(np.mean([a.elapsed_time(b) for a, b in ref_ev]))

@@ -38,7 +38,7 @@
 extern "C" {
 #endif
 
-#define PR_ABI_VERSION 1
+#define PR_ABI_VERSION 2
 
 enum {
   PR_OK = 0,
@@ -159,11 +159,18 @@ typedef struct {
                           survivors together); 2 = each wave owns one work item;
                           3 = two phases: every work item's groups are culled and the
                           surviving groups queued, then waves pop single groups */
-  int32_t survivor_cap; /* schedule 3: capacity of the surviving-group queues (0 = default
-                          1<<22); groups beyond it are traced during the cull */
+  int32_t survivor_cap; /* schedule 3: total capacity of the surviving-group queues (0 =
+                          default 1<<22); a group beyond it sends its pair to the rerun
+                          pass (every group of the pair traced again, leaf tests in
+                          FP64/exact) */
   void* ev_begin;      /* optional hipEvent_t (or NULL), recorded on `stream` just before the
                           traversal kernel(s), for timing them alone */
   void* ev_end;        /* optional hipEvent_t (or NULL), recorded just after them */
+  const int64_t* dev_n_pairs; /* optional device i64[1] (or NULL): the pairs processed are the
+                          first min(*dev_n_pairs, n_pairs), so a count left on the device
+                          by filter_aabb_pairs feeds the refinement without a host round
+                          trip; n_pairs is then the capacity of pairs[] and flags[] (it
+                          sizes the workspace), and flags past the count are not written */
 } pr_refine_params;
 
 typedef struct {
@@ -205,11 +212,15 @@ int refine_intersects(const void* blob_a, int64_t n_meshes_a, const void* blob_b
 
 /* ------------------------------------------------------------------------ */
 /* Result materialisation (Section 3.5): keeps the pairs whose flag is 1, in
- * input order.  out dev i32[cap][2]; dev_count dev i64[1] gets the exact
- * total even if it exceeds cap.  ws of at least compact_pairs_ws_bytes. */
+ * input order.  pairs dev i32[n_pairs][2], flags dev u8[n_pairs]; dev_n_pairs
+ * dev i64[1] or NULL: when given, only the first min(*dev_n_pairs, n_pairs)
+ * pairs are considered (n_pairs is then the capacity); out dev i32[cap][2];
+ * dev_count dev i64[1] gets the exact total even if it exceeds cap.  ws of
+ * at least compact_pairs_ws_bytes. */
 int compact_pairs_ws_bytes(int64_t n_pairs, size_t* ws_bytes);
-int compact_pairs(const int32_t* pairs, const uint8_t* flags, int64_t n_pairs, int32_t* out,
-                  int64_t cap, int64_t* dev_count, void* ws, size_t ws_bytes, void* stream);
+int compact_pairs(const int32_t* pairs, const uint8_t* flags, int64_t n_pairs,
+                  const int64_t* dev_n_pairs, int32_t* out, int64_t cap, int64_t* dev_count, void* ws,
+                  size_t ws_bytes, void* stream);
 
 #ifdef __cplusplus
 }

@@ -107,17 +107,27 @@ class MeshBlob:
         return out
 
 
-def filter_pairs(A: MeshBlob, B: MeshBlob, query_box=None, cap: Optional[int] = None, stream=None):
+def filter_pairs(A: MeshBlob, B: MeshBlob, query_box=None, cap: Optional[int] = None, stream=None,
+                 sync: bool = True):
     """Closed-box candidate pairs (i in A, j in B), sorted; int32 [P, 2] on the device.
-    Synchronises to read the count; relaunches once if `cap` was too small."""
+    With sync=True: synchronises to read the count, relaunches once if `cap` was too
+    small, returns the pairs.  With sync=False: returns (buffer int32[cap, 2], count
+    int64[1]) on the device without synchronising; the first min(count, cap) rows are
+    the pairs (the caller checks count <= cap once it reads it)."""
     torch = _torch()
     lib = _lib.load()
     wb = ctypes.c_size_t(0)
     _lib.check(lib.filter_aabb_pairs_ws_bytes(A.n_meshes, B.n_meshes, ctypes.byref(wb)))
     ws = _ws(wb.value)
     q = None if query_box is None else _dev(np.asarray(query_box, np.float32).reshape(6), torch.float32)
-    cnt = torch.zeros(1, dtype=torch.int64, device="cuda")
+    cnt = torch.empty(1, dtype=torch.int64, device="cuda")  # always written by the filter
     cap = int(cap) if cap is not None else max(1024, 4 * (A.n_meshes + B.n_meshes))
+    if not sync:
+        out = torch.empty((max(cap, 1), 2), dtype=torch.int32, device="cuda")
+        _lib.check(lib.filter_aabb_pairs(A.ptr, A.n_meshes, B.ptr, B.n_meshes,
+                                         None if q is None else q.data_ptr(), out.data_ptr(), cap,
+                                         cnt.data_ptr(), ws.data_ptr(), wb.value, _stream_ptr(stream)))
+        return out[:cap], cnt
     for _ in range(2):
         out = torch.empty((max(cap, 1), 2), dtype=torch.int32, device="cuda")
         _lib.check(lib.filter_aabb_pairs(A.ptr, A.n_meshes, B.ptr, B.n_meshes,
@@ -133,7 +143,8 @@ def filter_pairs(A: MeshBlob, B: MeshBlob, query_box=None, cap: Optional[int] = 
 class RefineConfig:
     def __init__(self, persistent: int = 1, precision: int = 0, queue_cap: int = 0, grid_blocks: int = 0,
                  chunks_per_pop: int = 0, schedule: int = 0, survivor_cap: int = 0, ev_begin=None,
-                 ev_end=None):
+                 ev_end=None, n_dev=None):
+        self.n_dev = n_dev        # optional device int64[1]: number of pairs to process
         self.ev_begin = ev_begin  # optional torch.cuda.Event recorded around the traversal kernel(s)
         self.ev_end = ev_end
         self.persistent = persistent
@@ -156,6 +167,7 @@ class RefineConfig:
         p.survivor_cap = self.survivor_cap
         p.ev_begin = _event_handle(self.ev_begin)
         p.ev_end = _event_handle(self.ev_end)
+        p.dev_n_pairs = None if self.n_dev is None else int(self.n_dev.data_ptr())
         return p
 
 
@@ -206,8 +218,10 @@ def stats_dict(stats) -> dict:
     return {k: int(v) for k, v in zip(STATS_FIELDS, vals)}
 
 
-def compact(pairs, flags, stream=None):
-    """Pairs whose flag is 1, in input order (synchronises to read the count)."""
+def compact(pairs, flags, stream=None, n_dev=None, sync: bool = True):
+    """Pairs whose flag is 1, in input order.  n_dev: optional device int64[1], the
+    number of leading pairs to consider.  sync=True synchronises to read the count and
+    returns the pairs; sync=False returns (buffer int32[P, 2], count int64[1])."""
     torch = _torch()
     lib = _lib.load()
     pairs = _dev(pairs, torch.int32).reshape(-1, 2)
@@ -216,7 +230,10 @@ def compact(pairs, flags, stream=None):
     _lib.check(lib.compact_pairs_ws_bytes(P, ctypes.byref(wb)))
     ws = _ws(wb.value)
     out = torch.empty((max(P, 1), 2), dtype=torch.int32, device="cuda")
-    cnt = torch.zeros(1, dtype=torch.int64, device="cuda")
-    _lib.check(lib.compact_pairs(pairs.data_ptr(), flags.data_ptr(), P, out.data_ptr(), P, cnt.data_ptr(),
-                                 ws.data_ptr(), wb.value, _stream_ptr(stream)))
+    cnt = torch.empty(1, dtype=torch.int64, device="cuda")  # always written by the compaction
+    _lib.check(lib.compact_pairs(pairs.data_ptr(), flags.data_ptr(), P,
+                                 None if n_dev is None else n_dev.data_ptr(), out.data_ptr(), P,
+                                 cnt.data_ptr(), ws.data_ptr(), wb.value, _stream_ptr(stream)))
+    if not sync:
+        return out, cnt
     return out[:int(cnt.item())]

@@ -18,7 +18,7 @@ PR_E_CAPACITY = -2
 PR_E_GEOMETRY = -3
 PR_E_DEVICE = -4
 PR_E_UNSUPPORTED = -5
-ABI_VERSION = 1
+ABI_VERSION = 2
 
 EXPORTS = [
     "pr_last_error", "pr_abi_version", "build_mesh_bvh_sizes", "build_mesh_bvh", "blob_mesh_boxes",
@@ -43,7 +43,8 @@ class RefineParams(ctypes.Structure):
                 ("precision", ctypes.c_int32), ("queue_cap", ctypes.c_int32),
                 ("grid_blocks", ctypes.c_int32), ("chunks_per_pop", ctypes.c_int32),
                 ("schedule", ctypes.c_int32), ("survivor_cap", ctypes.c_int32),
-                ("ev_begin", ctypes.c_void_p), ("ev_end", ctypes.c_void_p)]
+                ("ev_begin", ctypes.c_void_p), ("ev_end", ctypes.c_void_p),
+                ("dev_n_pairs", ctypes.c_void_p)]
 
 
 class RefineStats(ctypes.Structure):
@@ -91,7 +92,7 @@ def load():
         lib.refine_intersects.argtypes = [vp, i64, vp, i64, vp, i64, vp, ctypes.POINTER(RefineParams),
                                           vp, vp, vp, ctypes.c_size_t, vp]
         lib.compact_pairs_ws_bytes.argtypes = [i64, szp]
-        lib.compact_pairs.argtypes = [vp, vp, i64, vp, i64, vp, vp, ctypes.c_size_t, vp]
+        lib.compact_pairs.argtypes = [vp, vp, i64, vp, vp, i64, vp, vp, ctypes.c_size_t, vp]
         for name in EXPORTS[2:]:
             getattr(lib, name).restype = ctypes.c_int
         if lib.pr_abi_version() != ABI_VERSION:

@@ -287,9 +287,10 @@ __global__ __launch_bounds__(kBlock) void k_row_write(RowArgs r) {
 
 __global__ void k_total(const int64_t* scan, int64_t n, int64_t* out) { *out = scan[n]; }
 
-__global__ void k_flag_i32(const uint8_t* flags, int64_t n, int32_t* f) {
+__global__ void k_flag_i32(const uint8_t* flags, int64_t n, const int64_t* n_dev, int32_t* f) {
+  const int64_t m = n_dev ? (*n_dev < 0 ? 0 : (*n_dev < n ? *n_dev : n)) : n;
   int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  for (; i < n; i += (int64_t)gridDim.x * blockDim.x) f[i] = flags[i] ? 1 : 0;
+  for (; i < n; i += (int64_t)gridDim.x * blockDim.x) f[i] = i < m && flags[i] ? 1 : 0;
   if (blockIdx.x == 0 && threadIdx.x == 0) f[n] = 0;
 }
 
@@ -306,9 +307,11 @@ __global__ void k_compact(const int32_t* pairs, const int32_t* f, const int64_t*
 // Ordered compaction of the flagged pairs in one block (at most kSmallScan
 // pairs): the count goes to *count, output beyond cap is dropped.
 __global__ __launch_bounds__(kScanBlock) void k_compact_small(const int32_t* pairs, const uint8_t* flags, int64_t n,
-                                                              int32_t* out, int64_t cap, int64_t* count) {
+                                                              const int64_t* n_dev, int32_t* out, int64_t cap,
+                                                              int64_t* count) {
   using BlockScan = hipcub::BlockScan<int32_t, kScanBlock>;
   __shared__ typename BlockScan::TempStorage tmp;
+  if (n_dev) n = *n_dev < 0 ? 0 : (*n_dev < n ? *n_dev : n);
   int64_t running = 0;
   for (int64_t base = 0; base < n; base += kScanBlock * kScanItems) {
     const int64_t i0 = base + (int64_t)threadIdx.x * kScanItems;
@@ -468,8 +471,8 @@ extern "C" int compact_pairs_ws_bytes(int64_t n_pairs, size_t* ws_bytes) {
   return PR_OK;
 }
 
-extern "C" int compact_pairs(const int32_t* pairs, const uint8_t* flags, int64_t n_pairs, int32_t* out, int64_t cap,
-                             int64_t* dev_count, void* ws, size_t ws_bytes, void* stream) {
+extern "C" int compact_pairs(const int32_t* pairs, const uint8_t* flags, int64_t n_pairs, const int64_t* dev_n_pairs,
+                             int32_t* out, int64_t cap, int64_t* dev_count, void* ws, size_t ws_bytes, void* stream) {
   if (n_pairs < 0 || cap < 0 || !dev_count || !ws || (n_pairs > 0 && (!pairs || !flags)) || (cap > 0 && !out)) {
     set_error("bad argument");
     return PR_E_ARG;
@@ -482,11 +485,13 @@ extern "C" int compact_pairs(const int32_t* pairs, const uint8_t* flags, int64_t
   if (r) return r;
   if (cv.used > ws_bytes || !w.tmp) { set_error("ws_bytes %zu < required %zu", ws_bytes, cv.used); return PR_E_CAPACITY; }
   if (n_pairs <= kSmallScan) {
-    hipLaunchKernelGGL(k_compact_small, dim3(1), dim3(kScanBlock), 0, s, pairs, flags, n_pairs, out, cap, dev_count);
+    hipLaunchKernelGGL(k_compact_small, dim3(1), dim3(kScanBlock), 0, s, pairs, flags, n_pairs, dev_n_pairs, out, cap,
+                       dev_count);
     PR_HIP(hipGetLastError());
     return PR_OK;
   }
-  hipLaunchKernelGGL(k_flag_i32, dim3(grid_for(n_pairs + 1, kBlock)), dim3(kBlock), 0, s, flags, n_pairs, w.f);
+  hipLaunchKernelGGL(k_flag_i32, dim3(grid_for(n_pairs + 1, kBlock)), dim3(kBlock), 0, s, flags, n_pairs, dev_n_pairs,
+                     w.f);
   PR_HIP(hipcub::DeviceScan::ExclusiveSum(w.tmp, w.tmp_bytes, w.f, w.pos, (int)(n_pairs + 1), s));
   hipLaunchKernelGGL(k_compact, dim3(grid_for(n_pairs, kBlock)), dim3(kBlock), 0, s, pairs, (const int32_t*)w.f,
                      (const int64_t*)w.pos, n_pairs, out, cap);

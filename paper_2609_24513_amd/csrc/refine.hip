@@ -92,7 +92,8 @@ struct RefineArgs {
   const char* blob_b;
   int64_t n_meshes_a, n_meshes_b;
   const int32_t* pairs;
-  int64_t n_pairs;
+  int64_t n_pairs;            // capacity: pairs[] holds at least this many entries
+  const int64_t* np_dev;      // optional device count of the pairs to process
   uint8_t* flags;
   uint32_t* state;            // [P] 0 undecided, 1 intersecting
   int64_t* unit_cnt;          // [2P+1]
@@ -454,6 +455,14 @@ __device__ __forceinline__ bool pair_ok(const RefineArgs& ra, int64_t p, int32_t
   return i >= 0 && i < ra.n_meshes_a && j >= 0 && j < ra.n_meshes_b;
 }
 
+// Pairs processed: n_pairs, or the device count when one is given (clamped
+// to [0, n_pairs]).
+__device__ __forceinline__ int64_t npairs(const RefineArgs& ra) {
+  if (!ra.np_dev) return ra.n_pairs;
+  const int64_t v = *ra.np_dev;
+  return v < 0 ? 0 : (v < ra.n_pairs ? v : ra.n_pairs);
+}
+
 __device__ __forceinline__ bool blobs_ok(const BlobView& A, const BlobView& B, const RefineArgs& ra, int W) {
   return A.magic == kMagic && B.magic == kMagic && A.width == W && B.width == W && A.n_meshes == ra.n_meshes_a &&
          B.n_meshes == ra.n_meshes_b;
@@ -505,11 +514,14 @@ __global__ void k_plan(RefineArgs ra) {
   const BlobView A = view_of(ra.blob_a), B = view_of(ra.blob_b);
   const bool bok = blobs_ok(A, B, ra, W);
   int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  const int64_t np = npairs(ra);
   if (p == 0) ra.unit_cnt[2 * ra.n_pairs] = 0;
   for (; p < ra.n_pairs; p += (int64_t)gridDim.x * blockDim.x) {
     int32_t i, j;
     int64_t c0 = 0, c1 = 0;
-    if (!bok) {
+    if (p >= np) {
+      // beyond the device count: no work
+    } else if (!bok) {
       if (p == 0) atomicMin(ra.status, (int32_t)PR_E_UNSUPPORTED);
     } else if (!pair_ok(ra, p, i, j)) {
       atomicMin(ra.status, (int32_t)PR_E_ARG);
@@ -808,7 +820,7 @@ __global__ __launch_bounds__(kBlock) void k_cull(RefineArgs ra) {
   int4* buf = s_buf[wv];
   int nbuf = 0;
   WaveStats st;
-  const int64_t U = 2 * ra.n_pairs;
+  const int64_t U = 2 * npairs(ra);
   const int64_t nw = (int64_t)gridDim.x * kWaves;
   const cptr_t<int32_t> pairs = cview(ra.pairs);
   const int64_t u0 = (int64_t)blockIdx.x * kWaves + wv;
@@ -888,11 +900,12 @@ __global__ __launch_bounds__(kBlock) void k_cull(RefineArgs ra) {
 
 // Schedule 3, phase 2: waves pop surviving groups kPop at a time from the
 // queue of their block (blockIdx % kQueues, on the XCD whose phase-1 blocks
-// filled it) and trace them; a wave leaves a queue after its first empty pop.
-// Phase 1 deals the units to the queues round-robin, so the queues are about
-// equally long, and no wave touches another queue's counter (a counter that
-// many waves hit is a memory-side hot spot).  With fewer blocks than queues a
-// block drains queues blockIdx, blockIdx + gridDim, ...  Pop slot j maps to
+// filled it) and trace them; a wave leaves a queue after its first empty pop
+// and then helps with the other queues of its XCD (q + 8, q + 16, ...), so
+// the queues of one XCD finish together.  No wave touches another XCD's
+// counters (a counter that many waves hit is a memory-side hot spot).  With
+// fewer blocks than queues a block drains queues blockIdx, blockIdx +
+// gridDim, ...  Pop slot j maps to
 // queue slot j * kSpread mod (slots): the queue holds each pair's groups side
 // by side, and spreading them over the run lets a hit found in one group
 // cancel the pair's later groups.
@@ -906,8 +919,13 @@ __global__ __launch_bounds__(kBlock, 5) void k_trace(RefineArgs ra) {
   const BlobView A = view_of(ra.blob_a), B = view_of(ra.blob_b);
   if (!blobs_ok(A, B, ra, W)) return;
   WaveStats st;
-  const int qstep = (int)(gridDim.x < (unsigned)kQueues ? gridDim.x : kQueues);
-  for (int cid = (int)(blockIdx.x % kQueues); cid < kQueues; cid += qstep) {
+  const int home = (int)(blockIdx.x % kQueues);
+  const bool few = gridDim.x < (unsigned)kQueues;
+  // with a full grid: home, then the XCD's other queues; with a small one:
+  // home, home + gridDim, ... (every queue has a block)
+  const int nq = few ? (kQueues - 1 - home) / (int)gridDim.x + 1 : kQueues / kSlices;
+  for (int j = 0; j < nq; ++j) {
+    const int cid = few ? home + j * (int)gridDim.x : (home + j * kSlices) % kQueues;
     const uint64_t filled = ra.surv_cnt[kCtrStride * cid];
     const uint64_t n = filled < ra.surv_cap ? filled : ra.surv_cap;
     const uint64_t slots = (n + kPop - 1) / kPop;
@@ -944,6 +962,7 @@ __global__ __launch_bounds__(kBlock) void k_refine_pair(RefineArgs ra, int64_t p
   const int wv = threadIdx.x >> 6;
   const BlobView A = view_of(ra.blob_a), B = view_of(ra.blob_b);
   int32_t i, j;
+  if (p >= npairs(ra)) return;  // beyond the device count
   if (!blobs_ok(A, B, ra, W)) {
     if (blockIdx.x == 0 && threadIdx.x == 0) atomicMin(ra.status, (int32_t)PR_E_UNSUPPORTED);
     return;
@@ -985,7 +1004,8 @@ __global__ __launch_bounds__(kBlock) void k_rerun(RefineArgs ra) {
   if (!blobs_ok(A, B, ra, W)) return;
   WaveStats st;
   if (ra.stats[S_QOVER] == 0) return;  // nothing overflowed: nothing to rerun
-  for (int64_t p = blockIdx.x; p < ra.n_pairs; p += gridDim.x) {
+  const int64_t np = npairs(ra);
+  for (int64_t p = blockIdx.x; p < np; p += gridDim.x) {
     if (load_state(ra.state + p) != 2u) continue;
     if (threadIdx.x == 0) s_hit = 0;
     __syncthreads();
@@ -1038,7 +1058,8 @@ __global__ void k_redecide(RefineArgs ra) {
 __global__ void k_finalize(RefineArgs ra) {
   int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   unsigned long long cnt = 0;
-  for (; p < ra.n_pairs; p += (int64_t)gridDim.x * blockDim.x) {
+  const int64_t np = npairs(ra);
+  for (; p < np; p += (int64_t)gridDim.x * blockDim.x) {
     const uint8_t f = ra.state[p] == 1u ? 1 : 0;
     ra.flags[p] = f;
     cnt += f;
@@ -1218,6 +1239,7 @@ extern "C" int refine_intersects(const void* blob_a, int64_t n_meshes_a, const v
   ra.n_meshes_b = n_meshes_b;
   ra.pairs = pairs;
   ra.n_pairs = n_pairs;
+  ra.np_dev = params->dev_n_pairs;
   ra.flags = flags;
   ra.qcap = qcap;
   ra.surv_cap = scap;

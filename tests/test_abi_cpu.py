@@ -40,7 +40,7 @@ def test_abi_version(lib):
 
 def test_struct_sizes():
     assert ctypes.sizeof(_lib.BvhParams) == 16
-    assert ctypes.sizeof(_lib.RefineParams) == 48
+    assert ctypes.sizeof(_lib.RefineParams) == 56
     assert ctypes.sizeof(_lib.RefineStats) == 112
 
 
@@ -107,7 +107,7 @@ def test_filter_and_compact_args_rejected(lib):
     assert lib.filter_aabb_pairs_ws_bytes(-1, 2, ctypes.byref(wb)) == _lib.PR_E_ARG
     assert lib.filter_aabb_pairs(None, 1, None, 1, None, None, 0, None, None, 0, None) == _lib.PR_E_ARG
     assert lib.compact_pairs_ws_bytes(-2, ctypes.byref(wb)) == _lib.PR_E_ARG
-    assert lib.compact_pairs(None, None, 5, None, 0, None, None, 0, None) == _lib.PR_E_ARG
+    assert lib.compact_pairs(None, None, 5, None, None, 0, None, None, 0, None) == _lib.PR_E_ARG
     assert lib.blob_mesh_boxes(None, 3, None, None) == _lib.PR_E_ARG
     assert lib.blob_edge_counts(None, 3, None, None) == _lib.PR_E_ARG
 

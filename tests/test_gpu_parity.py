@@ -192,6 +192,30 @@ def test_c3_scaled_all_widths_and_schedules(env):
                 assert np.array_equal(flags.cpu().numpy(), want), (w, l, cfg)
 
 
+@pytest.mark.parametrize("schedule", [1, 2, 3])
+def test_device_pair_count(env, schedule):
+    """Filter -> refine -> compaction with the pair count left on the device:
+    rows past the count are invalid padding that must be ignored, and the
+    result equals the host-count run and the oracle."""
+    torch, pa, synth, oracle = env
+    A, B = synth.make_c1(seed=5, n=24)
+    ga, gb = pa.MeshBlob.build(A), pa.MeshBlob.build(B)
+    ref = pa.filter_pairs(ga, gb)
+    n = int(ref.shape[0])
+    buf, cnt = pa.filter_pairs(ga, gb, cap=n + 37, sync=False)
+    buf[n:] = -7  # out-of-range ids: processing them would raise PR_E_ARG
+    flags, _, status = pa.refine(ga, gb, buf, pa.RefineConfig(schedule=schedule, n_dev=cnt))
+    torch.cuda.synchronize()
+    assert int(cnt.item()) == n and int(status.item()) == 0
+    want, _ = _run(env, A, B, ref.cpu().numpy(), schedule=schedule)
+    assert np.array_equal(flags[:n].cpu().numpy(), want)
+    exp = oracle.join(A, B, ref.cpu().numpy().astype(np.int64))
+    assert np.array_equal(want, np.asarray(exp, np.uint8))
+    res, rcnt = pa.compact(buf, flags, n_dev=cnt, sync=False)
+    got = res[:int(rcnt.item())].cpu().numpy()
+    assert np.array_equal(got, ref.cpu().numpy()[want == 1])
+
+
 def test_autotune_small(env):
     torch, pa, synth, oracle = env
     from paper_2609_24513_amd import autotune
