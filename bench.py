@@ -30,7 +30,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "refine_persistent_c2_traffic.json")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "refine_cull_trace_%s_traffic.json")  # % workload
 KERNEL_SOURCES = ["paper_2609_24513_amd/csrc/refine.hip", "paper_2609_24513_amd/csrc/predicates.h",
                   "paper_2609_24513_amd/csrc/common.h"]
 METRIC = "refined mesh pairs/s + segment queries/s on 1 MI355X; p50/p99 join latency"
@@ -278,8 +278,8 @@ def main():
                  + 28 * W * st["node_visits"] + 36 * st["tri_fetches"])
     achieved = alg_bytes / (kern_ms * 1e-3) / 1e9
     traffic = None
-    if os.path.exists(TRAFFIC_FILE):
-        tr = json.load(open(TRAFFIC_FILE))
+    if os.path.exists(TRAFFIC_FILE % args.workload):
+        tr = json.load(open(TRAFFIC_FILE % args.workload))
         if tr.get("kernel_source_sha") == kernel_source_sha() and tr.get("workload") == args.workload:
             traffic = tr.get("hbm_bytes_per_launch")
     roofline = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",

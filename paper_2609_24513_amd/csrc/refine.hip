@@ -937,9 +937,14 @@ __global__ __launch_bounds__(kBlock, 5) void k_trace(RefineArgs ra) {
       if (k >= n) break;
       const uint64_t e0 = ((k / kPop) * kSpread % slots) * kPop;
       const uint64_t kend = e0 + kPop < n ? e0 + kPop : n;
+      // the batch's groups mostly belong to one pair: when its first pair is
+      // already decided, those groups are dropped before their segments load
+      const int32_t first_pair = q[4 * e0 + 1] >> 1;
+      const bool first_decided = load_state(ra.state + first_pair) != 0u;
       for (uint64_t e = e0; e < kend; ++e) {
         const int4 it = make_int4(q[4 * e], q[4 * e + 1], q[4 * e + 2], q[4 * e + 3]);
         const int32_t pair = it.y >> 1, dir = it.y & 1;
+        if (first_decided && pair == first_pair) continue;
         const BlobView& S = dir == 0 ? A : B;
         const BlobView& T = dir == 0 ? B : A;
         const cptr_t<MeshDesc> tmd = cview(T.mesh) + it.z;
