@@ -159,8 +159,8 @@ typedef struct {
                           survivors together); 2 = each wave owns one work item;
                           3 = two phases: every work item's groups are culled and the
                           surviving groups queued, then waves pop single groups */
-  int32_t survivor_cap; /* schedule 3: total capacity of the surviving-group queues (0 =
-                          default 1<<22); a group beyond it sends its pair to the rerun
+  int32_t survivor_cap; /* schedule 3: total capacity of the surviving-group queues, 16 bytes
+                          per entry (0 = default 1<<24); a group beyond it sends its pair to the rerun
                           pass (every group of the pair traced again, leaf tests in
                           FP64/exact) */
   void* ev_begin;      /* optional hipEvent_t (or NULL), recorded on `stream` just before the

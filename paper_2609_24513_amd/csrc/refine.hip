@@ -1151,7 +1151,7 @@ int check(int64_t P, const pr_refine_params* p) {
 
 uint32_t qcap_of(const pr_refine_params* p) { return p->queue_cap > 0 ? (uint32_t)p->queue_cap : (1u << 20); }
 uint32_t scap_of(const pr_refine_params* p) {
-  const uint32_t total = p->survivor_cap > 0 ? (uint32_t)p->survivor_cap : (1u << 22);
+  const uint32_t total = p->survivor_cap > 0 ? (uint32_t)p->survivor_cap : (1u << 24);
   return (total + kQueues - 1) / kQueues;
 }
 

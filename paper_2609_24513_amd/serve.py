@@ -29,6 +29,7 @@ from __future__ import annotations
 
 import ctypes
 import dataclasses
+import copy
 import time
 from collections import deque
 from typing import List, Optional, Sequence
@@ -138,6 +139,12 @@ class JoinServer:
         self.max_pairs = max_pairs
         self.max_req = max_req_per_batch
         self.cfg = cfg or pa.RefineConfig(persistent=1)
+        if self.cfg.survivor_cap == 0:
+            # a batch queues at most (groups of the largest mesh of R + of S) per pair
+            gmax = int((R.edge_counts().max().item() + 63) // 64 + (S.edge_counts().max().item() + 63) // 64)
+            cfg2 = copy.copy(self.cfg)
+            cfg2.survivor_cap = int(min(1 << 24, max(1 << 16, gmax * max_req_per_batch * max_pairs)))
+            self.cfg = cfg2
         self.slots = [_Slot(torch, pa, R, S, max_req_per_batch, max_pairs, self.cfg) for _ in range(slots)]
         self.hbm_budget = int(hbm_budget)
         # device bytes a request holds while in flight: its pair region, gathered
