@@ -163,6 +163,9 @@ def main():
     ap.add_argument("--leaf", type=int, default=4)
     ap.add_argument("--precision", type=int, default=0)
     ap.add_argument("--schedule", type=int, default=3)
+    ap.add_argument("--trace-budget", type=int, default=0,
+                    help="schedule 3: steps before a long group hands its stack to the continuation pass "
+                         "(0 = library default, -1 = never)")
     ap.add_argument("--autotune", action="store_true", help="pick width, leaf size and schedule first")
     ap.add_argument("--serve-requests", type=int, default=2000, help="requests at the highest serving rate")
     ap.add_argument("--plain-requests", type=int, default=400, help="requests replayed on the plain path")
@@ -219,7 +222,7 @@ def main():
     P = int(first.shape[0])
     cfg_events = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
                   for _ in range(args.steps)]
-    base_cfg = dict(persistent=1, precision=args.precision, schedule=args.schedule)
+    base_cfg = dict(persistent=1, precision=args.precision, schedule=args.schedule, trace_budget=args.trace_budget)
     ws = pa.refine_workspace(P, args.width, pa.RefineConfig(**base_cfg))
     flags = torch.empty(P, dtype=torch.uint8, device="cuda")
     stats = torch.zeros(len(pa.STATS_FIELDS), dtype=torch.int64, device="cuda")

@@ -38,7 +38,7 @@
 extern "C" {
 #endif
 
-#define PR_ABI_VERSION 2
+#define PR_ABI_VERSION 3
 
 enum {
   PR_OK = 0,
@@ -171,6 +171,10 @@ typedef struct {
                           by filter_aabb_pairs feeds the refinement without a host round
                           trip; n_pairs is then the capacity of pairs[] and flags[] (it
                           sizes the workspace), and flags past the count are not written */
+  int32_t trace_budget; /* schedule 3: traversal steps after which a group hands its pending
+                          stack entries to a continuation pass spread over all waves (> 0);
+                          0 = default (no hand-over), -1 = never */
+  int32_t reserved;
 } pr_refine_params;
 
 typedef struct {

@@ -143,8 +143,9 @@ def filter_pairs(A: MeshBlob, B: MeshBlob, query_box=None, cap: Optional[int] = 
 class RefineConfig:
     def __init__(self, persistent: int = 1, precision: int = 0, queue_cap: int = 0, grid_blocks: int = 0,
                  chunks_per_pop: int = 0, schedule: int = 0, survivor_cap: int = 0, ev_begin=None,
-                 ev_end=None, n_dev=None):
+                 ev_end=None, n_dev=None, trace_budget: int = 0):
         self.n_dev = n_dev        # optional device int64[1]: number of pairs to process
+        self.trace_budget = trace_budget
         self.ev_begin = ev_begin  # optional torch.cuda.Event recorded around the traversal kernel(s)
         self.ev_end = ev_end
         self.persistent = persistent
@@ -168,6 +169,7 @@ class RefineConfig:
         p.ev_begin = _event_handle(self.ev_begin)
         p.ev_end = _event_handle(self.ev_end)
         p.dev_n_pairs = None if self.n_dev is None else int(self.n_dev.data_ptr())
+        p.trace_budget = self.trace_budget
         return p
 
 

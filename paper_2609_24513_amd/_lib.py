@@ -18,7 +18,7 @@ PR_E_CAPACITY = -2
 PR_E_GEOMETRY = -3
 PR_E_DEVICE = -4
 PR_E_UNSUPPORTED = -5
-ABI_VERSION = 2
+ABI_VERSION = 3
 
 EXPORTS = [
     "pr_last_error", "pr_abi_version", "build_mesh_bvh_sizes", "build_mesh_bvh", "blob_mesh_boxes",
@@ -44,7 +44,7 @@ class RefineParams(ctypes.Structure):
                 ("grid_blocks", ctypes.c_int32), ("chunks_per_pop", ctypes.c_int32),
                 ("schedule", ctypes.c_int32), ("survivor_cap", ctypes.c_int32),
                 ("ev_begin", ctypes.c_void_p), ("ev_end", ctypes.c_void_p),
-                ("dev_n_pairs", ctypes.c_void_p)]
+                ("dev_n_pairs", ctypes.c_void_p), ("trace_budget", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 class RefineStats(ctypes.Structure):

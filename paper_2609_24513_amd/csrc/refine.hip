@@ -109,6 +109,12 @@ struct RefineArgs {
   uint32_t surv_cap;          // entries per queue
   unsigned long long* surv_cnt;  // kQueues fill counters (stride kCtrStride)
   unsigned long long* surv_pop;  // kQueues pop counters (stride kCtrStride)
+  int4* tasks;                // kQueues lists of continuation tasks (group, unit, node ref, live | safe << 8)
+  uint64_t* tmask;            // lane mask of each task
+  uint32_t task_cap;          // tasks per list
+  unsigned long long* task_cnt;  // kQueues fill counters (stride kCtrStride)
+  unsigned long long* task_pop;  // kQueues pop counters (stride kCtrStride)
+  int32_t budget;             // schedule 3: traversal steps before a group hands its stack over (0 = none)
 };
 
 constexpr int kSlices = 8;     // one pop counter per XCD
@@ -117,6 +123,12 @@ constexpr int kSlices = 8;     // one pop counter per XCD
 // to the 8 XCDs); 8 queues per XCD keep the atomics on each queue's counters
 // below the memory-side serialisation rate.
 constexpr int kQueues = 64;
+// Continuation tasks (schedule 3): a group still running after kBudget
+// traversal steps hands its pending stack entries over to a third kernel, so
+// that the few long groups are spread over many waves instead of ending the
+// run alone.  kTaskCap tasks per list.
+constexpr int kBudget = 0;  // off by default: measured slower on the pathology-shaped workload
+constexpr uint32_t kTaskCap = 1u << 14;
 constexpr int kMaxItemGroups = 1024;
 constexpr int kCtrStride = 512; // u64 words between counters (4 KiB: separate memory channels)
 // Statistics: kStatCopies copies of the S_N counters (blockIdx % kStatCopies),
@@ -165,10 +177,15 @@ __device__ __forceinline__ void axis_setup(float d, bool safe, float& inv, float
   else { inv = kZeroInv; bias = kZeroBias; }
 }
 
+// t = (plane - p) * inv -+ bias as one fused multiply-add: with bias 0 (a
+// non-zero direction component) the value is the rounded product, as two
+// separate operations would give; with a zero component the sign of
+// (plane - p) is kept exactly and the bias opens the slab to all t, or
+// pushes it away from [0, 1].
 __device__ __forceinline__ bool slab(const Ray& r, float lx, float ly, float lz, float hx, float hy, float hz) {
-  float t0x = (lx - r.px) * r.ix - r.bx, t1x = (hx - r.px) * r.ix + r.bx;
-  float t0y = (ly - r.py) * r.iy - r.by, t1y = (hy - r.py) * r.iy + r.by;
-  float t0z = (lz - r.pz) * r.iz - r.bz, t1z = (hz - r.pz) * r.iz + r.bz;
+  float t0x = fmaf(lx - r.px, r.ix, -r.bx), t1x = fmaf(hx - r.px, r.ix, r.bx);
+  float t0y = fmaf(ly - r.py, r.iy, -r.by), t1y = fmaf(hy - r.py, r.iy, r.by);
+  float t0z = fmaf(lz - r.pz, r.iz, -r.bz), t1z = fmaf(hz - r.pz, r.iz, r.bz);
   float tn = fmaxf(fmaxf(fminf(t0x, t1x), fminf(t0y, t1y)), fmaxf(fminf(t0z, t1z), 0.f));
   float tf = fminf(fminf(fmaxf(t0x, t1x), fmaxf(t0y, t1y)), fminf(fmaxf(t0z, t1z), 1.f));
   return tn <= fmaf(tf, kSlabK, kSlabS);
@@ -270,13 +287,39 @@ __device__ __forceinline__ void test_children(const NodeRegs<W>& d, const Ray& r
   }
 }
 
+// Hands the pending entries of a wave's stack over as continuation tasks of
+// list tq: entry k sits in lane k of the register stack, so the lanes write
+// their own entries; as many as fit are taken from the top.  Returns true
+// when the whole stack was handed over.
+__device__ bool hand_over(WaveStack& stk, const RefineArgs& ra, int tq, int64_t gc, int32_t unit, int32_t live_safe) {
+  const int lane = threadIdx.x & 63;
+  const int n = stk.top;
+  if (n > kRegStack) return false;  // deeper stacks are finished in place
+  unsigned long long b0 = 0;
+  if (lane == 0) b0 = atomicAdd(ra.task_cnt + kCtrStride * tq, (unsigned long long)n);
+  const uint64_t base = uni64(b0);
+  const int fit = base >= ra.task_cap ? 0 : (int)min((uint64_t)n, ra.task_cap - base);
+  if (lane < n && lane >= n - fit) {
+    const int64_t at = (int64_t)tq * ra.task_cap + (int64_t)(base + (uint64_t)(lane - (n - fit)));
+    ra.tasks[at] = make_int4((int32_t)gc, unit, stk.ref, live_safe);
+    ra.tmask[at] = ((uint64_t)(uint32_t)stk.mhi << 32) | (uint32_t)stk.mlo;
+  }
+  stk.top = n - fit;
+  return fit == n;
+}
+
 // Traces segment group gc (global index in the source blob, `live` segments)
 // against the target mesh whose root node is `root` and box `tb`.  Returns
-// true when the pair is decided (found here or by another wave).
+// true when the pair is decided (found here or by another wave).  With a
+// non-zero start_mask the trace continues a handed-over task instead: the
+// stack starts as (root, start_mask) and the group's segments are not counted
+// again.  With a budget, a group still running after that many steps hands its
+// stack over to task list tq and returns.
 template <int W, int PREC>
 __device__ bool trace_core(const BlobView& S, const BlobView& T, int64_t gc, int live, int32_t root,
                            const float* tb, int32_t pair, int32_t dir, bool safe, const RefineArgs& ra,
-                           int32_t* lref, uint64_t* lmask, WaveStats& st, bool rerun) {
+                           int32_t* lref, uint64_t* lmask, WaveStats& st, bool rerun, uint64_t start_mask = 0,
+                           int budget = 0, int tq = 0) {
   const int lane = threadIdx.x & 63;
   // issue every load the group needs at once: its box, its segments and the
   // pair's state
@@ -295,16 +338,20 @@ __device__ bool trace_core(const BlobView& S, const BlobView& T, int64_t gc, int
   axis_setup(q.y - p.y, safe, r.iy, r.by);
   axis_setup(q.z - p.z, safe, r.iz, r.bz);
   if (uni((int32_t)decided)) return true;
-  st.add(S_SEG, (uint64_t)live);
-  const uint64_t m0 = ballot(valid && slab(r, tb[0], tb[1], tb[2], tb[3], tb[4], tb[5]));
-  if (m0 == 0) return false;
+  uint64_t m0 = start_mask;
+  if (m0 == 0) {
+    st.add(S_SEG, (uint64_t)live);
+    m0 = ballot(valid && slab(r, tb[0], tb[1], tb[2], tb[3], tb[4], tb[5]));
+    if (m0 == 0) return false;
+  }
   // per-group counters (uniform, 32 bits), folded into the wave's statistics
   // when the group ends
   struct GroupCount {
     WaveStats& s;
+    bool cont;
     uint32_t visits = 0, leaf_tris = 0, tests = 0;
     __device__ ~GroupCount() {
-      s.add(S_GTRAV, 1);
+      if (!cont) s.add(S_GTRAV, 1);
       s.add(S_VISIT, visits);
       s.add(S_TRIF, leaf_tris);
       s.add(S_TESTS, tests);
@@ -312,7 +359,7 @@ __device__ bool trace_core(const BlobView& S, const BlobView& T, int64_t gc, int
       s.max(S_MAXV, visits);
       s.max(S_MAXL, leaf_tris);
     }
-  } gcount{st};
+  } gcount{st, start_mask != 0};
   constexpr int CAP = stack_cap<W>();
   WaveStack stk;
   stk.ref = 0; stk.mlo = 0; stk.mhi = 0;
@@ -324,6 +371,11 @@ __device__ bool trace_core(const BlobView& S, const BlobView& T, int64_t gc, int
   // ahead so that the traversal never waits for it
   uint32_t poll = 0;
   while (stk.top > 0) {
+    if (budget && iter >= budget) {
+      if (hand_over(stk, ra, tq, gc, (pair << 1) | dir, live | (safe ? 256 : 0))) return false;
+      budget = 0;  // the rest did not fit: finish here
+      if (stk.top == 0) return false;
+    }
     --stk.top;
     const int32_t ref = stack_ref(stk, stk.top);
     const uint64_t nm = stack_mask(stk, stk.top);
@@ -478,6 +530,8 @@ __global__ void k_init(RefineArgs ra) {
   if (i < kQueues) {
     ra.surv_cnt[kCtrStride * i] = 0ull;
     ra.surv_pop[kCtrStride * i] = 0ull;
+    ra.task_cnt[kCtrStride * i] = 0ull;
+    ra.task_pop[kCtrStride * i] = 0ull;
   }
   if (i == 0) {
     *ra.qcount = 0u;
@@ -952,8 +1006,48 @@ __global__ __launch_bounds__(kBlock, 5) void k_trace(RefineArgs ra) {
 #pragma unroll
         for (int c = 0; c < 6; ++c) tb[c] = tmd->box[c];
         trace_core<W, PREC>(S, T, it.x, it.w & 0xff, tmd->root, tb, pair, dir, (it.w & 256) != 0, ra, s_node[wv],
-                            s_mask[wv], st, false);
+                            s_mask[wv], st, false, 0, ra.budget, cid);
       }
+    }
+  }
+  flush_stats(st, ra);
+}
+
+// Schedule 3, phase 3: the stacks that phase 2 handed over, one task (node,
+// lane mask of its group) at a time, popped like the survivors: task list of
+// the block first, then the other lists of its XCD.
+template <int W, int PREC>
+__global__ __launch_bounds__(kBlock, 5) void k_trace2(RefineArgs ra) {
+  constexpr int CAP = lds_stack_cap<W>();
+  __shared__ int32_t s_node[kWaves][CAP];
+  __shared__ uint64_t s_mask[kWaves][CAP];
+  const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const BlobView A = view_of(ra.blob_a), B = view_of(ra.blob_b);
+  if (!blobs_ok(A, B, ra, W)) return;
+  WaveStats st;
+  const int home = (int)(blockIdx.x % kQueues);
+  const bool few = gridDim.x < (unsigned)kQueues;
+  const int nq = few ? (kQueues - 1 - home) / (int)gridDim.x + 1 : kQueues / kSlices;
+  for (int j = 0; j < nq; ++j) {
+    const int cid = few ? home + j * (int)gridDim.x : (home + j * kSlices) % kQueues;
+    const uint64_t filled = ra.task_cnt[kCtrStride * cid];
+    const uint64_t n = filled < ra.task_cap ? filled : ra.task_cap;
+    if (n == 0) continue;
+    const cptr_t<int32_t> q = cview(reinterpret_cast<const int32_t*>(ra.tasks + (int64_t)cid * ra.task_cap));
+    const cptr_t<uint64_t> qm = cview(ra.tmask + (int64_t)cid * ra.task_cap);
+    for (;;) {
+      unsigned long long k0 = 0;
+      if (lane == 0) k0 = atomicAdd(ra.task_pop + kCtrStride * cid, 1ull);
+      const uint64_t e = uni64(k0);
+      if (e >= n) break;
+      const int4 it = make_int4(q[4 * e], q[4 * e + 1], q[4 * e + 2], q[4 * e + 3]);
+      const uint64_t m = qm[e];
+      const int32_t pair = it.y >> 1, dir = it.y & 1;
+      const BlobView& S = dir == 0 ? A : B;
+      const BlobView& T = dir == 0 ? B : A;
+      const float tb_unused[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};  // the root test was done in phase 2
+      trace_core<W, PREC>(S, T, it.x, it.w & 0xff, it.z, tb_unused, pair, dir, (it.w & 256) != 0, ra, s_node[wv],
+                          s_mask[wv], st, false, m);
     }
   }
   flush_stats(st, ra);
@@ -1128,6 +1222,11 @@ int carve(Carve& cv, RefineArgs& ra, int64_t P, uint32_t qcap, uint32_t surv_cap
   ra.surv_cnt = cv.take<unsigned long long>(kQueues * kCtrStride);
   ra.surv_pop = cv.take<unsigned long long>(kQueues * kCtrStride);
   ra.surv = cv.take<int4>((int64_t)kQueues * surv_cap);
+  ra.task_cap = kTaskCap;
+  ra.tasks = cv.take<int4>((int64_t)kQueues * kTaskCap);
+  ra.tmask = cv.take<uint64_t>((int64_t)kQueues * kTaskCap);
+  ra.task_cnt = cv.take<unsigned long long>(kQueues * kCtrStride);
+  ra.task_pop = cv.take<unsigned long long>(kQueues * kCtrStride);
   size_t b = 0;
   hipError_t e = hipcub::DeviceScan::ExclusiveSum(nullptr, b, (int64_t*)nullptr, (int64_t*)nullptr, (int)(2 * P + 1));
   if (e != hipSuccess) return hip_fail(e, "hipcub scan size");
@@ -1144,6 +1243,7 @@ int check(int64_t P, const pr_refine_params* p) {
   if (p->queue_cap < 0 || p->grid_blocks < 0 || p->chunks_per_pop < 0) { set_error("negative launch parameter"); return PR_E_ARG; }
   if (p->schedule < 0 || p->schedule > 3) { set_error("schedule must be 0, 1, 2 or 3"); return PR_E_ARG; }
   if (p->survivor_cap < 0) { set_error("survivor_cap < 0"); return PR_E_ARG; }
+  if (p->trace_budget < -1) { set_error("trace_budget < -1"); return PR_E_ARG; }
   if (P < 0) { set_error("n_pairs < 0"); return PR_E_ARG; }
   if (P >= ((int64_t)1 << 30)) { set_error("n_pairs >= 2^30"); return PR_E_UNSUPPORTED; }
   return PR_OK;
@@ -1186,6 +1286,7 @@ int launch(RefineArgs& ra, const pr_refine_params* prm, void* scan_tmp, size_t s
       PR_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cull, k_cull<W, PREC>, kBlock, 0));
       hipLaunchKernelGGL((k_cull<W, PREC>), dim3(cus * (per_cull > 0 ? per_cull : 1)), dim3(kBlock), 0, s, ra);
       hipLaunchKernelGGL((k_trace<W, PREC>), dim3(blocks), dim3(kBlock), 0, s, ra);
+      if (ra.budget > 0) hipLaunchKernelGGL((k_trace2<W, PREC>), dim3(blocks), dim3(kBlock), 0, s, ra);
     } else {
       hipLaunchKernelGGL((k_refine_persistent<W, PREC>), dim3(blocks), dim3(kBlock), 0, s, ra);
     }
@@ -1249,6 +1350,7 @@ extern "C" int refine_intersects(const void* blob_a, int64_t n_meshes_a, const v
   ra.qcap = qcap;
   ra.surv_cap = scap;
   ra.item_groups = params->chunks_per_pop > 0 ? params->chunks_per_pop : 256;
+  ra.budget = params->trace_budget == 0 ? kBudget : (params->trace_budget < 0 ? 0 : params->trace_budget);
   if (ra.item_groups > kMaxItemGroups) ra.item_groups = kMaxItemGroups;
   hipLaunchKernelGGL(k_init, dim3(grid_for(n_pairs > kStatCopies * S_N ? n_pairs : kStatCopies * S_N, kBlock)),
                      dim3(kBlock), 0, s, ra);

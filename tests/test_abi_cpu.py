@@ -40,7 +40,7 @@ def test_abi_version(lib):
 
 def test_struct_sizes():
     assert ctypes.sizeof(_lib.BvhParams) == 16
-    assert ctypes.sizeof(_lib.RefineParams) == 56
+    assert ctypes.sizeof(_lib.RefineParams) == 64
     assert ctypes.sizeof(_lib.RefineStats) == 112
 
 
@@ -76,11 +76,13 @@ def _refine_params(**kw):
     p.grid_blocks = kw.get("grid_blocks", 0)
     p.chunks_per_pop = kw.get("chunks_per_pop", 0)
     p.schedule = kw.get("schedule", 0)
+    p.trace_budget = kw.get("trace_budget", 0)
     return p
 
 
 @pytest.mark.parametrize("kw", [dict(w=3), dict(precision=3), dict(persistent=2), dict(queue_cap=-1),
-                                dict(grid_blocks=-5), dict(schedule=4), dict(schedule=-1)])
+                                dict(grid_blocks=-5), dict(schedule=4), dict(schedule=-1),
+                                dict(trace_budget=-2)])
 def test_refine_params_rejected(lib, kw):
     p = _refine_params(**kw)
     wb = ctypes.c_size_t(0)

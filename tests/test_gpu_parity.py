@@ -185,7 +185,8 @@ def test_c3_scaled_all_widths_and_schedules(env):
             for cfg in (dict(schedule=1), dict(schedule=2), dict(schedule=3), dict(schedule=1, chunks_per_pop=1),
                         dict(schedule=2, chunks_per_pop=64), dict(schedule=3, survivor_cap=50),
                         dict(schedule=3, chunks_per_pop=64, survivor_cap=8), dict(schedule=3, grid_blocks=5),
-                        dict(schedule=3, grid_blocks=100)):
+                        dict(schedule=3, grid_blocks=100), dict(schedule=3, trace_budget=1),
+                        dict(schedule=3, trace_budget=3, grid_blocks=7), dict(schedule=3, trace_budget=-1)):
                 flags, stats, status = pa.refine(ga, gb, pairs, pa.RefineConfig(persistent=1, **cfg))
                 torch.cuda.synchronize()
                 assert int(status.item()) == 0
