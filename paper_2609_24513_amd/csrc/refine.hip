@@ -115,6 +115,7 @@ struct RefineArgs {
   unsigned long long* task_cnt;  // kQueues fill counters (stride kCtrStride)
   unsigned long long* task_pop;  // kQueues pop counters (stride kCtrStride)
   int32_t budget;             // schedule 3: traversal steps before a group hands its stack over (0 = none)
+  unsigned int* fin_done;     // blocks of k_finalize that have finished
 };
 
 constexpr int kSlices = 8;     // one pop counter per XCD
@@ -534,6 +535,7 @@ __global__ void k_init(RefineArgs ra) {
     ra.task_pop[kCtrStride * i] = 0ull;
   }
   if (i == 0) {
+    *ra.fin_done = 0u;
     *ra.qcount = 0u;
     *ra.status = PR_OK;
   }
@@ -1090,14 +1092,20 @@ __global__ __launch_bounds__(kBlock) void k_refine_pair(RefineArgs ra, int64_t p
   flush_stats(st, ra);
 }
 
-// Pairs whose deferred tests overflowed the queue (state 2) are traced again
-// with every leaf test decided in place in FP64/exact.  One block per pair.
+__device__ void redecide(const RefineArgs& ra);
+
+// After the traversal: (1) the deferred tests of undecided pairs (state 0) are
+// decided in FP64/exact, one thread per test; (2) pairs whose deferred tests
+// or survivors overflowed a queue (state 2) are traced again with every leaf
+// test decided in place in FP64/exact, one block per pair.  The two parts
+// touch disjoint pairs.
 template <int W>
-__global__ __launch_bounds__(kBlock) void k_rerun(RefineArgs ra) {
+__global__ __launch_bounds__(kBlock) void k_fix(RefineArgs ra) {
   constexpr int CAP = lds_stack_cap<W>();
   __shared__ int32_t s_node[kWaves][CAP];
   __shared__ uint64_t s_mask[kWaves][CAP];
   __shared__ uint32_t s_hit;
+  redecide(ra);
   const int wv = threadIdx.x >> 6;
   const BlobView A = view_of(ra.blob_a), B = view_of(ra.blob_b);
   if (!blobs_ok(A, B, ra, W)) return;
@@ -1130,7 +1138,7 @@ __global__ __launch_bounds__(kBlock) void k_rerun(RefineArgs ra) {
 
 // ---- deferred FP64 / exact decisions ----------------------------------------------
 
-__global__ void k_redecide(RefineArgs ra) {
+__device__ void redecide(const RefineArgs& ra) {
   const BlobView A = view_of(ra.blob_a), B = view_of(ra.blob_b);
   const uint32_t qn = *ra.qcount;
   const uint32_t n = qn < ra.qcap ? qn : ra.qcap;
@@ -1154,7 +1162,48 @@ __global__ void k_redecide(RefineArgs ra) {
   if (namb) atomicAdd(stat_copy(ra.stats) + S_AMB64, (unsigned long long)namb);
 }
 
-__global__ void k_finalize(RefineArgs ra) {
+// Statistics and status out: one wave, lane c reads copy c of the counters
+// (agent-scope loads: other XCDs wrote them), then sums (maxima) across lanes.
+__device__ void report(const RefineArgs& ra, pr_refine_stats* out, int32_t* dev_status) {
+  static_assert(kStatCopies == 64, "one lane per copy");
+  const int lane = threadIdx.x & 63;
+  if (out) {
+    unsigned long long v[S_N];
+#pragma unroll
+    for (int k = 0; k < S_N; ++k) {
+      unsigned long long x = __hip_atomic_load(ra.stats + kCtrStride * lane + k, __ATOMIC_RELAXED,
+                                               __HIP_MEMORY_SCOPE_AGENT);
+      for (int o = 32; o > 0; o >>= 1) {
+        const unsigned long long y = __shfl_xor(x, o);
+        x = (k == S_MAXV || k == S_MAXL) ? (y > x ? y : x) : x + y;
+      }
+      v[k] = x;
+    }
+    if (lane == 0) {
+      out->segments = v[S_SEG];
+      out->node_visits = v[S_VISIT];
+      out->tri_tests = v[S_TESTS];
+      out->fp32_ambiguous = v[S_AMB32];
+      out->fp64_filter_ambiguous = v[S_AMB64];
+      out->exact_decided = v[S_EXACT];
+      out->pairs_true = v[S_TRUE];
+      out->queue_overflow = v[S_QOVER];
+      out->groups = v[S_GROUPS];
+      out->tri_fetches = v[S_TRIF];
+      out->groups_box_pass = v[S_GBOX];
+      out->groups_traversed = v[S_GTRAV];
+      out->max_group_node_visits = v[S_MAXV];
+      out->max_group_leaf_fetches = v[S_MAXL];
+    }
+  }
+  if (dev_status && lane == 0)
+    *dev_status = __hip_atomic_load(ra.status, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Flags from the pair states; the block that finishes last (every block
+// fences its updates, then counts itself done) writes the report.
+__global__ __launch_bounds__(kBlock) void k_finalize(RefineArgs ra, pr_refine_stats* out, int32_t* dev_status) {
+  __shared__ uint32_t s_last;
   int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   unsigned long long cnt = 0;
   const int64_t np = npairs(ra);
@@ -1165,42 +1214,18 @@ __global__ void k_finalize(RefineArgs ra) {
   }
   for (int o = 32; o > 0; o >>= 1) cnt += __shfl_xor(cnt, o);
   if ((threadIdx.x & 63) == 0 && cnt) atomicAdd(stat_copy(ra.stats) + S_TRUE, cnt);
+  __threadfence();
+  __syncthreads();
+  if (threadIdx.x == 0) s_last = atomicAdd(ra.fin_done, 1u) == gridDim.x - 1 ? 1u : 0u;
+  __syncthreads();
+  if (s_last && threadIdx.x < 64) {
+    __threadfence();
+    report(ra, out, dev_status);
+  }
 }
 
-// One wave: lane c reads copy c of the statistics, then sums (maxima) across
-// the lanes.
-__global__ void k_report(RefineArgs ra, pr_refine_stats* out, int32_t* dev_status) {
-  static_assert(kStatCopies == 64, "one lane per copy");
-  const int lane = threadIdx.x & 63;
-  if (out) {
-    unsigned long long v[S_N];
-#pragma unroll
-    for (int k = 0; k < S_N; ++k) {
-      unsigned long long x = ra.stats[kCtrStride * lane + k];
-      for (int o = 32; o > 0; o >>= 1) {
-        const unsigned long long y = __shfl_xor(x, o);
-        x = (k == S_MAXV || k == S_MAXL) ? (y > x ? y : x) : x + y;
-      }
-      v[k] = x;
-    }
-    if (lane != 0) return;
-    out->segments = v[S_SEG];
-    out->node_visits = v[S_VISIT];
-    out->tri_tests = v[S_TESTS];
-    out->fp32_ambiguous = v[S_AMB32];
-    out->fp64_filter_ambiguous = v[S_AMB64];
-    out->exact_decided = v[S_EXACT];
-    out->pairs_true = v[S_TRUE];
-    out->queue_overflow = v[S_QOVER];
-    out->groups = v[S_GROUPS];
-    out->tri_fetches = v[S_TRIF];
-    out->groups_box_pass = v[S_GBOX];
-    out->groups_traversed = v[S_GTRAV];
-    out->max_group_node_visits = v[S_MAXV];
-    out->max_group_leaf_fetches = v[S_MAXL];
-  }
-  if (dev_status && lane == 0) *dev_status = *ra.status;
-}
+// The report alone (no pairs).
+__global__ void k_report(RefineArgs ra, pr_refine_stats* out, int32_t* dev_status) { report(ra, out, dev_status); }
 
 // ---- host side ---------------------------------------------------------------------
 
@@ -1218,6 +1243,7 @@ int carve(Carve& cv, RefineArgs& ra, int64_t P, uint32_t qcap, uint32_t surv_cap
   ra.qcount = cv.take<uint32_t>(1);
   ra.stats = cv.take<unsigned long long>(kStatCopies * kCtrStride);
   ra.status = cv.take<int32_t>(1);
+  ra.fin_done = cv.take<unsigned int>(64);
   ra.queue = cv.take<int4>(qcap);
   ra.surv_cnt = cv.take<unsigned long long>(kQueues * kCtrStride);
   ra.surv_pop = cv.take<unsigned long long>(kQueues * kCtrStride);
@@ -1362,15 +1388,15 @@ extern "C" int refine_intersects(const void* blob_a, int64_t n_meshes_a, const v
     PR_LAUNCH(8, 0); PR_LAUNCH(8, 1); PR_LAUNCH(8, 2);
 #undef PR_LAUNCH
     if (r) return r;
-    hipLaunchKernelGGL(k_redecide, dim3(1024), dim3(kBlock), 0, s, ra);
     const int W2 = params->bvh_width;
-    const int rb = (int)(n_pairs < 4096 ? n_pairs : 4096);
-    if (W2 == 2) hipLaunchKernelGGL(k_rerun<2>, dim3(rb), dim3(kBlock), 0, s, ra);
-    else if (W2 == 4) hipLaunchKernelGGL(k_rerun<4>, dim3(rb), dim3(kBlock), 0, s, ra);
-    else hipLaunchKernelGGL(k_rerun<8>, dim3(rb), dim3(kBlock), 0, s, ra);
-    hipLaunchKernelGGL(k_finalize, dim3(grid_for(n_pairs, kBlock)), dim3(kBlock), 0, s, ra);
+    const int fb = 1024;  // enough threads for the deferred tests, blocks for the reruns
+    if (W2 == 2) hipLaunchKernelGGL(k_fix<2>, dim3(fb), dim3(kBlock), 0, s, ra);
+    else if (W2 == 4) hipLaunchKernelGGL(k_fix<4>, dim3(fb), dim3(kBlock), 0, s, ra);
+    else hipLaunchKernelGGL(k_fix<8>, dim3(fb), dim3(kBlock), 0, s, ra);
+    hipLaunchKernelGGL(k_finalize, dim3(grid_for(n_pairs, kBlock)), dim3(kBlock), 0, s, ra, dev_stats, dev_status);
+  } else {
+    hipLaunchKernelGGL(k_report, dim3(1), dim3(64), 0, s, ra, dev_stats, dev_status);
   }
-  hipLaunchKernelGGL(k_report, dim3(1), dim3(64), 0, s, ra, dev_stats, dev_status);
   PR_HIP(hipGetLastError());
   return PR_OK;
 }
