@@ -70,6 +70,26 @@ def make_workload(name: str):
     raise SystemExit("unknown workload " + name)
 
 
+def achievable_hbm_gbs(torch, mib: int = 2048, reps: int = 5) -> float:
+    """Streaming device-to-device copy of `mib` MiB on the same GPU: bytes read plus
+    bytes written over the best of `reps` timed copies."""
+    n = (mib << 20) // 4
+    src = torch.ones(n, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    best = float("inf")
+    for _ in range(reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        dst.copy_(src)
+        e1.record()
+        torch.cuda.synchronize()
+        best = min(best, e0.elapsed_time(e1) * 1e-3)
+    del src, dst
+    torch.cuda.empty_cache()
+    return 2.0 * (mib << 20) / best / 1e9
+
+
 def cpu_baseline(A, B, pairs_np, gpu_flags, budget_s: float, seed: int = 0):
     """The exact CPU oracle on a bounded random sample of the same candidates."""
     import oracle
@@ -95,7 +115,14 @@ def cpu_baseline(A, B, pairs_np, gpu_flags, budget_s: float, seed: int = 0):
     else:
         ntests = None
     agree = bool(np.array_equal(f, gpu_flags[idx]))
+    # single-thread rate on a sub-sample of about a quarter of the budget
+    n1 = int(min(len(idx), max(16, len(idx) * (0.25 * budget_s) / max(dt * threads, 1e-3))))
+    t = time.perf_counter()
+    f1 = oracle.join(A, B, pairs_np[idx[:n1]], mode=1, threads=1)
+    dt1 = time.perf_counter() - t
+    agree = agree and bool(np.array_equal(f1, gpu_flags[idx[:n1]]))
     return {"value": len(idx) / dt, "unit": "pairs/s", "cores": threads, "kind": "oracle",
+            "single_thread_pairs_per_s": n1 / dt1, "single_thread_sample": n1,
             "sample": "%d of %d candidate pairs (seeded random), exact SAT triangle tests with exact box "
                       "sweep-and-prune, %.1f s" % (len(idx), P, dt),
             "tri_tests_per_s": (ntests / dt) if ntests else None, "gpu_agrees_on_sample": agree}
@@ -295,6 +322,11 @@ def main():
     ea = ga.edge_counts().cpu().numpy().astype(np.int64)
     eb = gb.edge_counts().cpu().numpy().astype(np.int64)
     nominal_segments = int((ea[out_pairs[:, 0]] + eb[out_pairs[:, 1]]).sum()) if P else 0
+    # compulsory floor: every unique edge of every candidate's two meshes read once
+    # (8 B vertex ids + 24 B endpoints)
+    roofline["compulsory_floor_bytes"] = 32 * nominal_segments
+    roofline["achievable_gbs"] = achievable_hbm_gbs(torch)
+    roofline["frac_of_achievable"] = roofline["achieved"] / roofline["achievable_gbs"]
     def one_run(persistent, precision):
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         k0, k1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
