@@ -101,6 +101,17 @@ __host__ __device__ inline int64_t align256(int64_t x) { return (x + 255) & ~(in
 void set_error(const char* fmt, ...);
 int hip_fail(hipError_t e, const char* what);
 
+// Data that no kernel writes while it is read (blob contents, filter
+// inputs) is read through the constant address space, so that uniform reads
+// go through the scalar cache into SGPRs.
+template <class T>
+using cptr_t = const __attribute__((address_space(4))) T*;
+
+template <class T>
+__device__ __forceinline__ cptr_t<T> cview(const T* p) {
+  return (cptr_t<T>)(reinterpret_cast<uintptr_t>(p));
+}
+
 #define PR_HIP(call)                                   \
   do {                                                 \
     hipError_t e_ = (call);                            \

@@ -2,15 +2,17 @@
 //
 // Filter: all (i, j) whose closed mesh boxes overlap (touching boxes count),
 // optionally restricted to pairs whose common box part meets a closed query
-// box.  Meshes are first reduced to those meeting the query box (an ordered
-// compaction per dataset: one block per dataset up to kSmallScan meshes, a
-// flag pass and a device scan beyond), then every kept row i of A is matched
-// against the kept meshes of B by one block; counts are scanned and a second
-// pass writes each row's pairs in ascending j with a block-wide ordered
-// compaction, so the output is sorted by (i, j) and identical run to run.
-// The exact total is always written; output beyond `cap` is dropped (the
-// caller relaunches with a larger buffer, as the paper does for its result
-// structure, Section 3.5).
+// box.  With a query box the meshes are first reduced to those meeting it
+// (an ordered compaction per dataset: one block per dataset up to kSmallScan
+// meshes, a flag pass and a device scan beyond).  Up to kFastCols columns
+// and kFastRows rows, two kernels produce the pairs (a count pass and a
+// write pass over blocks of 64 rows, the block totals summed in front of
+// each block); larger datasets take the general path: one wave per kept row
+// of A against LDS tiles of the kept boxes of B, a scan of the row counts
+// and a second pass that writes each row's pairs.  Either way the output is
+// sorted by (i, j) and identical run to run.  The exact total is always
+// written; output beyond `cap` is dropped (the caller relaunches with a
+// larger buffer, as the paper does for its result structure, Section 3.5).
 //
 // Compaction (Section 3.5 result materialisation): pairs whose flag is 1,
 // in input order: one block up to kSmallScan pairs, else a flag pass, a
@@ -285,6 +287,171 @@ __global__ __launch_bounds__(kBlock) void k_row_write(RowArgs r) {
   }
 }
 
+// Pair kernels for the common shape (at most kFastCols columns, at most
+// kFastRows rows).  A block owns kRT = 64 consecutive rows, one per lane;
+// each of its kPairWaves waves holds the rows' boxes and walks a contiguous
+// slice of the columns, 64 at a time: one vector load per lane stages the
+// chunk in the wave's LDS area, then every column is read back as an LDS
+// broadcast and tested by all 64 rows at once (six compares per 64 tests),
+// each lane counting its row's hits in a register.  The count pass stores
+// the (row, slice) counts and the block's total; the write pass scans the
+// block's counts in row-major order, adds the totals of the blocks before
+// it and walks the slices again, each lane writing its row's pairs in
+// ascending column order: the same sorted list as the general path's.
+// Without a query box the kernels read the mesh descriptors directly (an
+// empty mesh pairs with nothing); with one they read the kept lists.
+constexpr int kRT = 64;
+constexpr int kPairBlock = 1024;
+constexpr int kPairWaves = kPairBlock / 64;
+constexpr int64_t kFastCols = 8192;
+constexpr int64_t kFastGrid = 2048;
+constexpr int64_t kFastRows = kRT * kFastGrid;
+
+struct PairArgs {
+  const void* blob_a;  // descriptors (no query box)
+  const void* blob_b;
+  const float* box_a;  // kept lists (query box)
+  const float* box_b;
+  const int32_t* ids_a;
+  const int32_t* ids_b;
+  const int32_t* na;  // kept counts (query box)
+  const int32_t* nb;
+  int64_t MA, MB;
+  int32_t* cnt;       // [grid * kRT * kPairWaves]: (row, slice) counts
+  int32_t* blocksum;  // [grid]
+  int32_t* pairs;
+  int64_t cap;
+  int64_t* count;
+};
+
+template <bool Q>
+__device__ __forceinline__ int64_t rows_of(const PairArgs& a) { return Q ? (int64_t)*a.na : a.MA; }
+template <bool Q>
+__device__ __forceinline__ int64_t cols_of(const PairArgs& a) { return Q ? (int64_t)*a.nb : a.MB; }
+
+// Box and id of row i of A or column i of B; an empty mesh gets an
+// inverted box (+inf lows, -inf highs), which meets nothing.
+template <bool Q>
+__device__ __forceinline__ int32_t mesh_box(const void* blob, const float* boxes, const int32_t* ids, int64_t i,
+                                            float* b) {
+  if (Q) {
+    const cptr_t<float> p = cview(boxes) + 6 * i;
+#pragma unroll
+    for (int c = 0; c < 6; ++c) b[c] = p[c];
+    return cview(ids)[i];
+  }
+  const cptr_t<MeshDesc> d = cview(meshes_of(blob)) + i;
+  const bool ok = d->n_tris > 0;
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    b[c] = ok ? d->box[c] : INFINITY;
+    b[3 + c] = ok ? d->box[3 + c] : -INFINITY;
+  }
+  return (int32_t)i;
+}
+
+// Column slice of wave w: [lo, hi).
+__device__ __forceinline__ void slice_of(int64_t nb, int w, int64_t& lo, int64_t& hi) {
+  const int64_t per = (nb + kPairWaves - 1) / kPairWaves;
+  lo = per * w < nb ? per * w : nb;
+  hi = lo + per < nb ? lo + per : nb;
+}
+
+// Closed overlap of row box a and a column box, without branches.  With a
+// query box the rows and columns are the kept meshes, which each meet the
+// query box; two such boxes that overlap share a point with it on every
+// axis (three pairwise-meeting intervals have a common point), so the same
+// test serves both cases.
+__device__ __forceinline__ bool overlap(const float* a, float l0, float l1, float l2, float h0, float h1, float h2) {
+  return (a[0] <= h0) & (l0 <= a[3]) & (a[1] <= h1) & (l1 <= a[4]) & (a[2] <= h2) & (l2 <= a[5]);
+}
+
+// A staged column: box (lo xyz, hi xyz) and id.
+struct alignas(16) ColBox {
+  float lo[3];
+  float hi0;
+  float hi1, hi2;
+  int32_t id, pad;
+};
+
+// Walks the wave's slice [lo, hi) in chunks of 64 staged in `st` (the
+// wave's 64-entry LDS area) for the lane's row box rb; with WRITE, each hit
+// (row id ia, column id) goes to pairs[out++] while out < cap.  Returns the
+// number of hits.
+template <bool Q, bool WRITE>
+__device__ __forceinline__ int32_t walk(const PairArgs& a, ColBox* st, int64_t lo, int64_t hi, const float* rb,
+                                        int32_t ia, int64_t out) {
+  const int lane = threadIdx.x & 63;
+  int32_t n = 0;
+  for (int64_t c0 = lo; c0 < hi; c0 += 64) {
+    const int m = (int)(hi - c0 < 64 ? hi - c0 : 64);
+    if (lane < m) {
+      float b[6];
+      const int32_t id = mesh_box<Q>(a.blob_b, a.box_b, a.ids_b, c0 + lane, b);
+      st[lane] = ColBox{{b[0], b[1], b[2]}, b[3], b[4], b[5], id, 0};
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    for (int u = 0; u < m; ++u) {
+      const ColBox c = st[u];
+      const bool ok = overlap(rb, c.lo[0], c.lo[1], c.lo[2], c.hi0, c.hi1, c.hi2);
+      if (WRITE && ok) {
+        if (out < a.cap) {
+          a.pairs[2 * out] = ia;
+          a.pairs[2 * out + 1] = c.id;
+        }
+        ++out;
+      }
+      n += ok ? 1 : 0;
+    }
+    __builtin_amdgcn_wave_barrier();  // the chunk is read before the next one is staged
+  }
+  return n;
+}
+
+template <bool Q, bool WRITE>
+__global__ __launch_bounds__(kPairBlock) void k_pairs(PairArgs a) {
+  using BlockScan = hipcub::BlockScan<int32_t, kPairBlock>;
+  using BlockReduce = hipcub::BlockReduce<int64_t, kPairBlock>;
+  __shared__ typename BlockScan::TempStorage scan_tmp;
+  __shared__ typename BlockReduce::TempStorage red_tmp;
+  __shared__ ColBox s_col[kPairWaves][64];
+  __shared__ int64_t s_base;
+  const int lane = threadIdx.x & 63;
+  const int w = __builtin_amdgcn_readfirstlane((int32_t)(threadIdx.x >> 6));
+  const int64_t r0 = (int64_t)blockIdx.x * kRT;
+  const int64_t na = rows_of<Q>(a), nb = cols_of<Q>(a);
+  const int64_t row = r0 + lane;
+  float rb[6] = {INFINITY, INFINITY, INFINITY, -INFINITY, -INFINITY, -INFINITY};
+  int32_t ia = 0;
+  if (row < na) ia = mesh_box<Q>(a.blob_a, a.box_a, a.ids_a, row, rb);
+  int64_t lo, hi;
+  slice_of(nb, w, lo, hi);
+  const bool any = r0 < na;  // uniform over the block
+  int32_t* cnt = a.cnt + (int64_t)blockIdx.x * kPairBlock;
+  if (!WRITE) {
+    const int32_t n = any ? walk<Q, false>(a, s_col[w], lo, hi, rb, ia, 0) : 0;
+    cnt[lane * kPairWaves + w] = n;  // row-major (row, slice)
+    const int32_t t = BlockReduce(red_tmp).Sum((int64_t)n);
+    if (threadIdx.x == 0) a.blocksum[blockIdx.x] = t;
+    return;
+  }
+  int32_t pre = 0, total = 0;
+  BlockScan(scan_tmp).ExclusiveSum(cnt[threadIdx.x], pre, total);
+  int64_t before = 0;
+  for (int64_t b = threadIdx.x; b < (int64_t)blockIdx.x; b += kPairBlock) before += a.blocksum[b];
+  before = BlockReduce(red_tmp).Sum(before);
+  if (threadIdx.x == 0) s_base = before;
+  __syncthreads();
+  // the offset of (row = lane, slice = w) sits with thread lane * kPairWaves + w
+  __shared__ int32_t s_off[kPairBlock];
+  s_off[threadIdx.x] = pre;
+  __syncthreads();
+  if (any) walk<Q, true>(a, s_col[w], lo, hi, rb, ia, s_base + s_off[lane * kPairWaves + w]);
+  if (blockIdx.x == gridDim.x - 1 && threadIdx.x == 0) *a.count = s_base + total;
+}
+
 __global__ void k_total(const int64_t* scan, int64_t n, int64_t* out) { *out = scan[n]; }
 
 __global__ void k_flag_i32(const uint8_t* flags, int64_t n, const int64_t* n_dev, int32_t* f) {
@@ -305,7 +472,11 @@ __global__ void k_compact(const int32_t* pairs, const int32_t* f, const int64_t*
 }
 
 // Ordered compaction of the flagged pairs in one block (at most kSmallScan
-// pairs): the count goes to *count, output beyond cap is dropped.
+// pairs), kCompactItems consecutive flags per thread so that up to 16 K pairs
+// take a single block scan: the count goes to *count, output beyond cap is
+// dropped.
+constexpr int kCompactItems = 16;
+
 __global__ __launch_bounds__(kScanBlock) void k_compact_small(const int32_t* pairs, const uint8_t* flags, int64_t n,
                                                               const int64_t* n_dev, int32_t* out, int64_t cap,
                                                               int64_t* count) {
@@ -313,20 +484,28 @@ __global__ __launch_bounds__(kScanBlock) void k_compact_small(const int32_t* pai
   __shared__ typename BlockScan::TempStorage tmp;
   if (n_dev) n = *n_dev < 0 ? 0 : (*n_dev < n ? *n_dev : n);
   int64_t running = 0;
-  for (int64_t base = 0; base < n; base += kScanBlock * kScanItems) {
-    const int64_t i0 = base + (int64_t)threadIdx.x * kScanItems;
+  for (int64_t base = 0; base < n; base += kScanBlock * kCompactItems) {
+    const int64_t i0 = base + (int64_t)threadIdx.x * kCompactItems;
     uint32_t f = 0;
 #pragma unroll
-    for (int i = 0; i < kScanItems; ++i) f |= (i0 + i < n && flags[i0 + i] ? 1u : 0u) << i;
+    for (int i = 0; i < kCompactItems; ++i) f |= (i0 + i < n && flags[i0 + i] ? 1u : 0u) << i;
+    // the flagged pairs are read before the scan (all loads in flight at once)
+    int32_t pv[kCompactItems][2];
+#pragma unroll
+    for (int i = 0; i < kCompactItems; ++i)
+      if ((f >> i) & 1u) {
+        pv[i][0] = pairs[2 * (i0 + i)];
+        pv[i][1] = pairs[2 * (i0 + i) + 1];
+      }
     int32_t pre = 0, total = 0;
     BlockScan(tmp).ExclusiveSum((int32_t)__popc(f), pre, total);
     int64_t pos = running + pre;
 #pragma unroll
-    for (int i = 0; i < kScanItems; ++i)
+    for (int i = 0; i < kCompactItems; ++i)
       if ((f >> i) & 1u) {
         if (pos < cap) {
-          out[2 * pos] = pairs[2 * (i0 + i)];
-          out[2 * pos + 1] = pairs[2 * (i0 + i) + 1];
+          out[2 * pos] = pv[i][0];
+          out[2 * pos + 1] = pv[i][1];
         }
         ++pos;
       }
@@ -340,6 +519,7 @@ struct FilterWs {
   int32_t *flag_a, *flag_b, *pos_a, *pos_b, *ids_a, *ids_b;
   float *box_a, *box_b;
   int64_t *rowcnt, *rowoff;
+  int32_t *blocksum, *paircnt;
   void* tmp;
   size_t tmp_bytes;
 };
@@ -355,6 +535,9 @@ int carve_filter(Carve& cv, FilterWs& w, int64_t MA, int64_t MB) {
   w.box_b = cv.take<float>(6 * (MB + 1));
   w.rowcnt = cv.take<int64_t>(MA + 1);
   w.rowoff = cv.take<int64_t>(MA + 1);
+  w.blocksum = cv.take<int32_t>(kFastGrid);
+  const int64_t fast_rows = MA <= kFastRows ? MA : 0;
+  w.paircnt = cv.take<int32_t>((fast_rows + kRT - 1) / kRT * kPairBlock);
   size_t b1 = 0, b2 = 0;
   int64_t mx = MA > MB ? MA : MB;
   hipError_t e = hipcub::DeviceScan::ExclusiveSum(nullptr, b1, (int32_t*)nullptr, (int32_t*)nullptr, (int)(mx + 1));
@@ -415,6 +598,36 @@ extern "C" int filter_aabb_pairs(const void* blob_a, int64_t n_meshes_a, const v
   if (r) return r;
   if (cv.used > ws_bytes || !w.tmp) { set_error("ws_bytes %zu < required %zu", ws_bytes, cv.used); return PR_E_CAPACITY; }
   const int64_t MA = n_meshes_a, MB = n_meshes_b;
+  if (MA > 0 && MB > 0 && MA <= kFastRows && MB <= kFastCols && (!query_box || MA <= kSmallScan)) {
+    PairArgs pa{};
+    pa.MA = MA;
+    pa.MB = MB;
+    pa.blocksum = w.blocksum;
+    pa.cnt = w.paircnt;
+    pa.pairs = pairs;
+    pa.cap = cap;
+    pa.count = dev_count;
+    const int grid = (int)((MA + kRT - 1) / kRT);
+    if (!query_box) {
+      pa.blob_a = blob_a;
+      pa.blob_b = blob_b;
+      hipLaunchKernelGGL((k_pairs<false, false>), dim3(grid), dim3(kPairBlock), 0, s, pa);
+      hipLaunchKernelGGL((k_pairs<false, true>), dim3(grid), dim3(kPairBlock), 0, s, pa);
+    } else {
+      hipLaunchKernelGGL(k_keep_small, dim3(2), dim3(kScanBlock), 0, s, blob_a, MA, w.ids_a, w.box_a, w.pos_a + MA,
+                         blob_b, MB, w.ids_b, w.box_b, w.pos_b + MB, query_box);
+      pa.box_a = w.box_a;
+      pa.box_b = w.box_b;
+      pa.ids_a = w.ids_a;
+      pa.ids_b = w.ids_b;
+      pa.na = w.pos_a + MA;
+      pa.nb = w.pos_b + MB;
+      hipLaunchKernelGGL((k_pairs<true, false>), dim3(grid), dim3(kPairBlock), 0, s, pa);
+      hipLaunchKernelGGL((k_pairs<true, true>), dim3(grid), dim3(kPairBlock), 0, s, pa);
+    }
+    PR_HIP(hipGetLastError());
+    return PR_OK;
+  }
   if (!query_box) {
     hipLaunchKernelGGL(k_boxes_all, dim3(grid_for(MA + MB, kBlock)), dim3(kBlock), 0, s, blob_a, MA, w.ids_a,
                        w.box_a, w.pos_a + MA, blob_b, MB, w.ids_b, w.box_b, w.pos_b + MB);

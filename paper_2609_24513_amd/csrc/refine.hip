@@ -26,6 +26,7 @@
 #include <hip/hip_runtime.h>
 #include <hipcub/hipcub.hpp>
 
+#include <atomic>
 #include <climits>
 
 #include "common.h"
@@ -45,17 +46,6 @@ constexpr float kZeroBias = 0x1p16f;
 // pushes at most W, over at most kMaxDepth node levels plus the leaf level.
 template <int W>
 constexpr int stack_cap() { return (W - 1) * (kMaxDepth + 1) + 1; }
-
-// Blob data is immutable during a query; reading it through the constant
-// address space lets uniform reads (nodes, triangles, group boxes,
-// descriptors) go through the scalar cache into SGPRs.
-template <class T>
-using cptr_t = const __attribute__((address_space(4))) T*;
-
-template <class T>
-__device__ __forceinline__ cptr_t<T> cview(const T* p) {
-  return (cptr_t<T>)(reinterpret_cast<uintptr_t>(p));
-}
 
 struct BlobView {
   const MeshDesc* mesh;
@@ -1281,6 +1271,40 @@ uint32_t scap_of(const pr_refine_params* p) {
   return (total + kQueues - 1) / kQueues;
 }
 
+// Launches a kernel whose one argument is the RefineArgs.  The optional
+// events take the dispatch's own start and end time stamps, so that timing
+// puts no marker packets (and no idle gaps) into the stream.
+template <typename K>
+int launch_ra(K kernel, int blocks, hipStream_t s, RefineArgs& ra, hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr) {
+  void* args[] = {&ra};
+  PR_HIP(hipExtLaunchKernel(reinterpret_cast<const void*>(kernel), dim3(blocks), dim3(kBlock), args, 0, s, e0, e1, 0));
+  return PR_OK;
+}
+
+// Resident blocks per compute unit for a kernel, computed once per device.
+template <typename K>
+int blocks_per_cu(K kernel, int dev) {
+  static std::atomic<int> cache[64];
+  if (dev < 0 || dev >= 64) return -1;
+  int v = cache[dev].load(std::memory_order_relaxed);
+  if (v > 0) return v;
+  int per = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, kernel, kBlock, 0) != hipSuccess) return -1;
+  v = per > 0 ? per : 1;
+  cache[dev].store(v, std::memory_order_relaxed);
+  return v;
+}
+
+int cu_count(int dev) {
+  static std::atomic<int> cache[64];
+  if (dev < 0 || dev >= 64) return -1;
+  int v = cache[dev].load(std::memory_order_relaxed);
+  if (v > 0) return v;
+  if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || v <= 0) return -1;
+  cache[dev].store(v, std::memory_order_relaxed);
+  return v;
+}
+
 template <int W, int PREC>
 int launch(RefineArgs& ra, const pr_refine_params* prm, void* scan_tmp, size_t scan_bytes, hipStream_t s) {
   const int64_t P = ra.n_pairs;
@@ -1291,32 +1315,27 @@ int launch(RefineArgs& ra, const pr_refine_params* prm, void* scan_tmp, size_t s
       hipLaunchKernelGGL(k_plan<W>, dim3(grid_for(P, kBlock)), dim3(kBlock), 0, s, ra);
       PR_HIP(hipcub::DeviceScan::ExclusiveSum(scan_tmp, scan_bytes, ra.unit_cnt, ra.offs, (int)(2 * P + 1), s));
     }
-    int blocks = prm->grid_blocks;
-    int dev = 0, cus = 0, per = 0;
+    int dev = 0;
     PR_HIP(hipGetDevice(&dev));
-    PR_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
-    if (blocks <= 0) {
-      if (sched == 2)
-        PR_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_refine_wave<W, PREC>, kBlock, 0));
-      else if (sched == 3)
-        PR_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_trace<W, PREC>, kBlock, 0));
-      else
-        PR_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_refine_persistent<W, PREC>, kBlock, 0));
-      blocks = cus * (per > 0 ? per : 1);
-    }
-    if (eb) PR_HIP(hipEventRecord(eb, s));
+    const int cus = cu_count(dev);
+    const int per = sched == 2   ? blocks_per_cu(k_refine_wave<W, PREC>, dev)
+                    : sched == 3 ? blocks_per_cu(k_trace<W, PREC>, dev)
+                                 : blocks_per_cu(k_refine_persistent<W, PREC>, dev);
+    if (cus <= 0 || per <= 0) { set_error("device attribute query failed"); return PR_E_DEVICE; }
+    const int blocks = prm->grid_blocks > 0 ? prm->grid_blocks : cus * per;
+    int r = PR_OK;
     if (sched == 2) {
-      hipLaunchKernelGGL((k_refine_wave<W, PREC>), dim3(blocks), dim3(kBlock), 0, s, ra);
+      r = launch_ra(k_refine_wave<W, PREC>, blocks, s, ra, eb, ee);
     } else if (sched == 3) {
-      int per_cull = 0;
-      PR_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cull, k_cull<W, PREC>, kBlock, 0));
-      hipLaunchKernelGGL((k_cull<W, PREC>), dim3(cus * (per_cull > 0 ? per_cull : 1)), dim3(kBlock), 0, s, ra);
-      hipLaunchKernelGGL((k_trace<W, PREC>), dim3(blocks), dim3(kBlock), 0, s, ra);
-      if (ra.budget > 0) hipLaunchKernelGGL((k_trace2<W, PREC>), dim3(blocks), dim3(kBlock), 0, s, ra);
+      const int per_cull = blocks_per_cu(k_cull<W, PREC>, dev);
+      if (per_cull <= 0) { set_error("occupancy query failed"); return PR_E_DEVICE; }
+      r = launch_ra(k_cull<W, PREC>, cus * per_cull, s, ra, eb, nullptr);
+      if (r == PR_OK) r = launch_ra(k_trace<W, PREC>, blocks, s, ra, nullptr, ra.budget > 0 ? nullptr : ee);
+      if (r == PR_OK && ra.budget > 0) r = launch_ra(k_trace2<W, PREC>, blocks, s, ra, nullptr, ee);
     } else {
-      hipLaunchKernelGGL((k_refine_persistent<W, PREC>), dim3(blocks), dim3(kBlock), 0, s, ra);
+      r = launch_ra(k_refine_persistent<W, PREC>, blocks, s, ra, eb, ee);
     }
-    if (ee) PR_HIP(hipEventRecord(ee, s));
+    if (r != PR_OK) return r;
   } else {
     const int blocks = prm->grid_blocks > 0 ? prm->grid_blocks : 64;
     if (eb) PR_HIP(hipEventRecord(eb, s));

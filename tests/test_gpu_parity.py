@@ -106,6 +106,40 @@ def test_filter_large_mesh_counts(env, na, nb):
     assert np.array_equal(got, synth.candidate_pairs(A.aabbs(), B.aabbs()))
 
 
+def _tetra_set_with_empties(synth, n, seed, side, every=7):
+    """Like _tetra_set, with every `every`-th mesh empty (no vertices, no faces)."""
+    full = _tetra_set(synth, n, seed, side)
+    keep = np.arange(n) % every != 3
+    v = full.verts.reshape(n, 4, 3)[keep].reshape(-1, 3)
+    f = full.faces.reshape(n, 4, 3)[keep].reshape(-1, 3)
+    sizes = np.where(keep, 4, 0)
+    off = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int64)
+    return synth.MeshSet(v, f, off, off.copy())
+
+
+@pytest.mark.parametrize("na,nb", [(1, 1), (17, 4096), (65_537, 300), (131_072, 40), (131_073, 30), (500, 4_097)])
+def test_filter_row_block_path_limits(env, na, nb):
+    """Row and column counts on both sides of the limits of the 64-rows-per-block
+    path (4,096 columns, 131,072 rows; with a query box 65,536 rows), with empty
+    meshes mixed in, with and without a query box, and a capacity below the count."""
+    torch, pa, synth, oracle = env
+    A = _tetra_set_with_empties(synth, na, 21, 30.0)
+    B = _tetra_set_with_empties(synth, nb, 22, 30.0)
+    ga, gb = pa.MeshBlob.build(A), pa.MeshBlob.build(B)
+    ba, bb = A.aabbs(), B.aabbs()
+    want = synth.candidate_pairs(ba, bb)
+    got = pa.filter_pairs(ga, gb).cpu().numpy()
+    assert np.array_equal(got, want)
+    q = np.array([5, 2, 4, 22, 25, 19], np.float32)
+    got = pa.filter_pairs(ga, gb, query_box=q).cpu().numpy()
+    assert np.array_equal(got, synth.candidate_pairs(ba, bb, q))
+    if want.shape[0] > 1:
+        cap = want.shape[0] // 2
+        buf, cnt = pa.filter_pairs(ga, gb, cap=cap, sync=False)
+        assert int(cnt.item()) == want.shape[0]
+        assert np.array_equal(buf[:cap].cpu().numpy(), want[:cap])
+
+
 @pytest.mark.parametrize("n", [1, 4096, 65_536, 100_003])
 def test_compact_matches_numpy(env, n):
     """Ordered compaction on both sides of the single-block limit."""
