@@ -163,17 +163,25 @@ typedef struct {
                           per entry (0 = default 1<<24); a group beyond it sends its pair to the rerun
                           pass (every group of the pair traced again, leaf tests in
                           FP64/exact) */
-  void* ev_begin;      /* optional hipEvent_t (or NULL), recorded on `stream` just before the
-                          traversal kernel(s), for timing them alone */
-  void* ev_end;        /* optional hipEvent_t (or NULL), recorded just after them */
+  void* ev_begin;      /* optional hipEvent_t (or NULL) for timing the traversal kernel(s)
+                          alone: with persistent = 1 it takes the start time stamp of the
+                          first traversal dispatch on `stream` (attached to the dispatch,
+                          no extra packet); with persistent = 0 it is recorded on `stream`
+                          just before the per-pair launches */
+  void* ev_end;        /* optional hipEvent_t (or NULL): the end time stamp of the last
+                          traversal dispatch (persistent = 1), or recorded just after the
+                          launches (persistent = 0) */
   const int64_t* dev_n_pairs; /* optional device i64[1] (or NULL): the pairs processed are the
                           first min(*dev_n_pairs, n_pairs), so a count left on the device
                           by filter_aabb_pairs feeds the refinement without a host round
                           trip; n_pairs is then the capacity of pairs[] and flags[] (it
                           sizes the workspace), and flags past the count are not written */
-  int32_t trace_budget; /* schedule 3: traversal steps after which a group hands its pending
-                          stack entries to a continuation pass spread over all waves (> 0);
-                          0 = default (no hand-over), -1 = never */
+  int32_t trace_budget; /* schedule 3: 0 = default: a wave whose queues are drained takes
+                          pending stack entries (subtrees) that the other waves of its
+                          block hand over on seeing it wait; > 0: instead, a group still
+                          running after that many traversal steps hands its pending
+                          entries to a continuation pass spread over all waves; -1 = no
+                          hand-over of either kind */
   int32_t reserved;
 } pr_refine_params;
 

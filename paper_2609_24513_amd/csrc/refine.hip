@@ -106,6 +106,7 @@ struct RefineArgs {
   unsigned long long* task_pop;  // kQueues pop counters (stride kCtrStride)
   int32_t budget;             // schedule 3: traversal steps before a group hands its stack over (0 = none)
   unsigned int* fin_done;     // blocks of k_finalize that have finished
+  int32_t share;              // schedule 3: waves of a block share pending stack entries (1 = on)
 };
 
 constexpr int kSlices = 8;     // one pop counter per XCD
@@ -299,6 +300,52 @@ __device__ bool hand_over(WaveStack& stk, const RefineArgs& ra, int tq, int64_t 
   return fit == n;
 }
 
+// Work sharing inside a block (schedule 3): a wave whose queues are drained
+// waits for pending stack entries that its block's tracing waves move into a
+// small LDS task list when they see it waiting.  Every counter is monotonic
+// within one launch; slots beyond kBlkTasks are never used.
+constexpr uint32_t kBlkTasks = 128;
+
+struct BlockShare {
+  int4 task[kBlkTasks];       // group, unit, node ref, live | safe << 8
+  uint64_t mask[kBlkTasks];   // lane mask of the entry
+  uint32_t ready[kBlkTasks];  // 1 once the slot is written
+  uint32_t tail;              // slots reserved
+  uint32_t head;              // slots taken
+  uint32_t idle;              // waves waiting for a task
+  uint32_t active;            // waves still on their queues
+  uint32_t busy;              // waves tracing a task they took (or about to)
+};
+
+__device__ __forceinline__ uint32_t lds_load(const uint32_t* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+
+// Moves the `h` oldest pending entries of a wave's stack (entries 0..h-1,
+// the subtrees nearest the root; h <= top) to the block's task list: each lane below
+// h writes its entry and then marks the slot ready; the rest of the stack
+// moves down.  Returns the number of entries moved (fewer when the list is
+// full).
+__device__ int share_out(WaveStack& stk, BlockShare* sh, int64_t gc, int32_t unit, int32_t live_safe, int h) {
+  const int lane = threadIdx.x & 63;
+  uint32_t b0 = 0;
+  if (lane == 0) b0 = __hip_atomic_fetch_add(&sh->tail, (uint32_t)h, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+  const uint32_t base = (uint32_t)uni((int32_t)b0);
+  const int fit = base >= kBlkTasks ? 0 : (int)min((uint32_t)h, kBlkTasks - base);
+  if (fit == 0) return 0;
+  if (lane < fit) {
+    sh->task[base + lane] = make_int4((int32_t)gc, unit, stk.ref, live_safe);
+    sh->mask[base + lane] = ((uint64_t)(uint32_t)stk.mhi << 32) | (uint32_t)stk.mlo;
+    __hip_atomic_store(&sh->ready[base + lane], 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
+  }
+  const int src = lane + fit < 64 ? lane + fit : 63;
+  stk.ref = __shfl(stk.ref, src);
+  stk.mlo = __shfl(stk.mlo, src);
+  stk.mhi = __shfl(stk.mhi, src);
+  stk.top -= fit;
+  return fit;
+}
+
 // Traces segment group gc (global index in the source blob, `live` segments)
 // against the target mesh whose root node is `root` and box `tb`.  Returns
 // true when the pair is decided (found here or by another wave).  With a
@@ -310,7 +357,7 @@ template <int W, int PREC>
 __device__ bool trace_core(const BlobView& S, const BlobView& T, int64_t gc, int live, int32_t root,
                            const float* tb, int32_t pair, int32_t dir, bool safe, const RefineArgs& ra,
                            int32_t* lref, uint64_t* lmask, WaveStats& st, bool rerun, uint64_t start_mask = 0,
-                           int budget = 0, int tq = 0) {
+                           int budget = 0, int tq = 0, BlockShare* sh = nullptr) {
   const int lane = threadIdx.x & 63;
   // issue every load the group needs at once: its box, its segments and the
   // pair's state
@@ -373,6 +420,15 @@ __device__ bool trace_core(const BlobView& S, const BlobView& T, int64_t gc, int
     if (!rerun && (++iter & 15) == 0) {
       if (uni((int32_t)poll)) return true;
       poll = load_state(ra.state + pair);
+    }
+    if (sh && stk.top >= 1 && stk.top <= kRegStack) {
+      // waves of the block waiting for work, beyond the tasks already waiting
+      const uint32_t idle = lds_load(&sh->idle), tail = lds_load(&sh->tail), head = lds_load(&sh->head);
+      const uint32_t n = tail < kBlkTasks ? tail : kBlkTasks;
+      const uint32_t waiting = n > head ? n - head : 0u;
+      const int want = uni((int32_t)(idle > waiting ? idle - waiting : 0u));
+      if (want > 0 && tail < kBlkTasks)
+        share_out(stk, sh, gc, (pair << 1) | dir, live | (safe ? 256 : 0), want < stk.top ? want : stk.top);
     }
     if (ref < 0) {
       // leaf: the lanes of the mask test their segment against its
@@ -944,6 +1000,95 @@ __global__ __launch_bounds__(kBlock) void k_cull(RefineArgs ra) {
   flush_stats(st, ra);
 }
 
+// After its queues are drained a wave takes tasks from its block's list
+// (pending stack entries that the block's tracing waves moved out on seeing
+// it wait) until no wave of the block is still on its queues or tracing a
+// task and the list is drained.  A wave that moves entries out comes back
+// here afterwards and leaves only after seeing the list drained, so no task
+// is left behind.  All waiting is on LDS; a wait longer than kHelpSpinLimit
+// looks (far beyond any traversal) reports PR_E_DEVICE and leaves.
+constexpr uint32_t kHelpSpinLimit = 1u << 22;
+
+template <int W, int PREC>
+__device__ void block_help(const BlobView& A, const BlobView& B, const RefineArgs& ra, BlockShare* sh, int32_t* lref,
+                           uint64_t* lmask, WaveStats& st) {
+  const int lane = threadIdx.x & 63;
+  if (lane == 0) {
+    __hip_atomic_fetch_add(&sh->idle, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    __hip_atomic_fetch_add(&sh->active, ~0u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
+  }
+  for (uint32_t spin = 0;; ++spin) {
+    if (spin >= kHelpSpinLimit) {
+      if (lane == 0) atomicMin(ra.status, (int32_t)PR_E_DEVICE);
+      break;
+    }
+    const uint32_t tail = lds_load(&sh->tail), head = lds_load(&sh->head);
+    const uint32_t n = tail < kBlkTasks ? tail : kBlkTasks;
+    if (uni((int32_t)(head < n))) {
+      // announce the attempt before claiming: a wave deciding whether to
+      // leave reads the busy count before the list
+      if (lane == 0) __hip_atomic_fetch_add(&sh->busy, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_WORKGROUP);
+      uint32_t got = ~0u;
+      if (lane == 0) {
+        uint32_t h = lds_load(&sh->head);
+        for (int t = 0; t < 64; ++t) {
+          const uint32_t tl = lds_load(&sh->tail);
+          if (h >= (tl < kBlkTasks ? tl : kBlkTasks)) break;
+          uint32_t e = h;
+          if (__hip_atomic_compare_exchange_strong(&sh->head, &e, h + 1, __ATOMIC_ACQ_REL, __ATOMIC_RELAXED,
+                                                   __HIP_MEMORY_SCOPE_WORKGROUP)) {
+            got = h;
+            break;
+          }
+          h = e;
+        }
+      }
+      got = (uint32_t)uni((int32_t)got);
+      if (got == ~0u) {
+        if (lane == 0) __hip_atomic_fetch_add(&sh->busy, ~0u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
+        continue;
+      }
+      if (lane == 0) __hip_atomic_fetch_add(&sh->idle, ~0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+      // the slot was reserved by a wave of this block that writes it next
+      uint32_t ok = 0;
+      for (uint32_t w = 0; w < kHelpSpinLimit && !ok; ++w) {
+        ok = (uint32_t)uni((int32_t)__hip_atomic_load(&sh->ready[got], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP));
+        if (!ok) __builtin_amdgcn_s_sleep(1);
+      }
+      if (!ok) {
+        if (lane == 0) {
+          atomicMin(ra.status, (int32_t)PR_E_DEVICE);
+          __hip_atomic_fetch_add(&sh->busy, ~0u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
+        }
+        break;
+      }
+      const int4 t = sh->task[got];
+      const uint64_t m = sh->mask[got];
+      const int32_t pair = t.y >> 1, dir = t.y & 1;
+      const BlobView& S = dir == 0 ? A : B;
+      const BlobView& T = dir == 0 ? B : A;
+      const float tb_unused[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};  // the root was tested when the group started
+      trace_core<W, PREC>(S, T, uni(t.x), uni(t.w) & 0xff, uni(t.z), tb_unused, pair, dir, (uni(t.w) & 256) != 0, ra,
+                          lref, lmask, st, false, uni64(m), 0, 0, sh);
+      if (lane == 0) {
+        __hip_atomic_fetch_add(&sh->idle, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        __hip_atomic_fetch_add(&sh->busy, ~0u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
+      }
+      spin = 0;
+      continue;
+    }
+    // nothing to take: leave once no wave of the block is on its queues or
+    // tracing a task (read first) and the list is drained (read after)
+    if (uni((int32_t)(__hip_atomic_load(&sh->active, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP) == 0u &&
+                      __hip_atomic_load(&sh->busy, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP) == 0u))) {
+      const uint32_t tl = lds_load(&sh->tail);
+      if (uni((int32_t)(lds_load(&sh->head) >= (tl < kBlkTasks ? tl : kBlkTasks)))) break;
+    }
+    __builtin_amdgcn_s_sleep(2);
+  }
+}
+
+
 // Schedule 3, phase 2: waves pop surviving groups kPop at a time from the
 // queue of their block (blockIdx % kQueues, on the XCD whose phase-1 blocks
 // filled it) and trace them; a wave leaves a queue after its first empty pop
@@ -961,7 +1106,18 @@ __global__ __launch_bounds__(kBlock, 5) void k_trace(RefineArgs ra) {
   constexpr int kPop = 4;
   __shared__ int32_t s_node[kWaves][CAP];
   __shared__ uint64_t s_mask[kWaves][CAP];
+  __shared__ BlockShare s_share;
   const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  if (threadIdx.x < kBlkTasks) s_share.ready[threadIdx.x] = 0u;
+  if (threadIdx.x == 0) {
+    s_share.tail = 0u;
+    s_share.head = 0u;
+    s_share.idle = 0u;
+    s_share.active = kWaves;
+    s_share.busy = 0u;
+  }
+  __syncthreads();
+  BlockShare* const sh = ra.share ? &s_share : nullptr;
   const BlobView A = view_of(ra.blob_a), B = view_of(ra.blob_b);
   if (!blobs_ok(A, B, ra, W)) return;
   WaveStats st;
@@ -998,10 +1154,11 @@ __global__ __launch_bounds__(kBlock, 5) void k_trace(RefineArgs ra) {
 #pragma unroll
         for (int c = 0; c < 6; ++c) tb[c] = tmd->box[c];
         trace_core<W, PREC>(S, T, it.x, it.w & 0xff, tmd->root, tb, pair, dir, (it.w & 256) != 0, ra, s_node[wv],
-                            s_mask[wv], st, false, 0, ra.budget, cid);
+                            s_mask[wv], st, false, 0, ra.budget, cid, sh);
       }
     }
   }
+  if (sh) block_help<W, PREC>(A, B, ra, sh, s_node[wv], s_mask[wv], st);
   flush_stats(st, ra);
 }
 
@@ -1396,6 +1553,7 @@ extern "C" int refine_intersects(const void* blob_a, int64_t n_meshes_a, const v
   ra.surv_cap = scap;
   ra.item_groups = params->chunks_per_pop > 0 ? params->chunks_per_pop : 256;
   ra.budget = params->trace_budget == 0 ? kBudget : (params->trace_budget < 0 ? 0 : params->trace_budget);
+  ra.share = params->trace_budget == 0 && ra.budget == 0 ? 1 : 0;
   if (ra.item_groups > kMaxItemGroups) ra.item_groups = kMaxItemGroups;
   hipLaunchKernelGGL(k_init, dim3(grid_for(n_pairs > kStatCopies * S_N ? n_pairs : kStatCopies * S_N, kBlock)),
                      dim3(kBlock), 0, s, ra);

@@ -220,11 +220,30 @@ def test_c3_scaled_all_widths_and_schedules(env):
                         dict(schedule=2, chunks_per_pop=64), dict(schedule=3, survivor_cap=50),
                         dict(schedule=3, chunks_per_pop=64, survivor_cap=8), dict(schedule=3, grid_blocks=5),
                         dict(schedule=3, grid_blocks=100), dict(schedule=3, trace_budget=1),
-                        dict(schedule=3, trace_budget=3, grid_blocks=7), dict(schedule=3, trace_budget=-1)):
+                        dict(schedule=3, trace_budget=3, grid_blocks=7), dict(schedule=3, trace_budget=-1),
+                        dict(schedule=3, grid_blocks=1), dict(schedule=3, grid_blocks=2, survivor_cap=50)):
                 flags, stats, status = pa.refine(ga, gb, pairs, pa.RefineConfig(persistent=1, **cfg))
                 torch.cuda.synchronize()
                 assert int(status.item()) == 0
                 assert np.array_equal(flags.cpu().numpy(), want), (w, l, cfg)
+
+
+def test_block_sharing_matches_unshared(env):
+    """Schedule 3 with the waves of a block sharing pending stack entries (the
+    default) against sharing off (trace_budget=-1) and the oracle, on the
+    precision-stress pairs (long exact traversals) with one and two blocks,
+    where three of every four waves spend most of the run helping."""
+    torch, pa, synth, oracle = env
+    A, B, pairs, _ = synth.make_c4(n_pairs=300)
+    want = oracle.join(A, B, pairs, mode=1)
+    ga, gb = pa.MeshBlob.build(A), pa.MeshBlob.build(B)
+    for cfg in (dict(grid_blocks=1), dict(grid_blocks=2), dict(), dict(trace_budget=-1, grid_blocks=1)):
+        for prec in (0, 1):
+            flags, stats, status = pa.refine(ga, gb, pairs, pa.RefineConfig(persistent=1, schedule=3, precision=prec,
+                                                                            **cfg))
+            torch.cuda.synchronize()
+            assert int(status.item()) == 0, (cfg, prec)
+            assert np.array_equal(flags.cpu().numpy(), want), (cfg, prec)
 
 
 @pytest.mark.parametrize("schedule", [1, 2, 3])
