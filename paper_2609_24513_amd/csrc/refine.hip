@@ -842,10 +842,11 @@ __global__ __launch_bounds__(kBlock) void k_refine_wave(RefineArgs ra) {
 // Per-lane two-level cull of group box g against a target mesh whose root
 // node is loaded in `root`: g must meet a child box of the root and, for an
 // inner child, one of that child's child boxes (every triangle lies inside
-// the boxes of its ancestors).  A child node is loaded (in one burst) only
-// when some lane meets its box.
+// the boxes of its ancestors).  The second level is read from the wave's LDS
+// copy (`stage_level2`); a child is looked at only when some lane meets its
+// box.
 template <int W>
-__device__ __forceinline__ bool cull2(const float* g, const NodeRegs<W>& root, cptr_t<Node<W>> nodes) {
+__device__ __forceinline__ bool cull2(const float* g, const NodeRegs<W>& root, const Node<W>* l2) {
   bool hit = false;
 #pragma unroll
   for (int c = 0; c < W; ++c) {
@@ -857,16 +858,38 @@ __device__ __forceinline__ bool cull2(const float* g, const NodeRegs<W>& root, c
       continue;
     }
     if (!ballot(m1)) continue;
-    NodeRegs<W> n2;
-    load_node<W>(n2, nodes + ch);
+    const Node<W>& n2 = l2[c];
     bool m2 = false;
 #pragma unroll
     for (int d = 0; d < W; ++d)
-      m2 = m2 || (n2.ch[d] != kEmpty &&
+      m2 = m2 || (n2.child[d] != kEmpty &&
                   box_meet(g, n2.lo[0][d], n2.lo[1][d], n2.lo[2][d], n2.hi[0][d], n2.hi[1][d], n2.hi[2][d]));
     hit = hit || (m1 && m2);
   }
   return hit;
+}
+
+// Copies the root's internal children (the second level) into the wave's LDS
+// area: one vector load per child, lane k reading dword k, all issued
+// together, so the culling of a unit waits for one round of loads here
+// instead of one per child.
+template <int W>
+__device__ __forceinline__ void stage_level2(const NodeRegs<W>& root, const char* nodes, Node<W>* l2) {
+  const int lane = threadIdx.x & 63;
+  constexpr int kDw = (int)(sizeof(Node<W>) / 4);
+  int32_t v[W];
+#pragma unroll
+  for (int c = 0; c < W; ++c) {
+    const int32_t ch = root.ch[c];
+    v[c] = 0;
+    if (ch >= 0 && ch != kEmpty && lane < kDw) v[c] = reinterpret_cast<const int32_t*>(nodes)[(int64_t)ch * kDw + lane];
+  }
+#pragma unroll
+  for (int c = 0; c < W; ++c)
+    if (lane < kDw) reinterpret_cast<int32_t*>(l2 + c)[lane] = v[c];
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
 constexpr int kCullBuf = 256;  // survivor entries buffered per wave in LDS
@@ -912,6 +935,7 @@ __device__ void flush_survivors(const int4* buf, int n, int slice, const RefineA
 template <int W, int PREC>
 __global__ __launch_bounds__(kBlock) void k_cull(RefineArgs ra) {
   __shared__ int4 s_buf[kWaves][kCullBuf];
+  __shared__ Node<W> s_l2[kWaves][W];
   const int wv = uni((int32_t)(threadIdx.x >> 6)), lane = threadIdx.x & 63;
   const BlobView A = view_of(ra.blob_a), B = view_of(ra.blob_b);
   if (!blobs_ok(A, B, ra, W)) {
@@ -966,8 +990,11 @@ __global__ __launch_bounds__(kBlock) void k_cull(RefineArgs ra) {
     const cptr_t<Node<W>> nodes = cview(reinterpret_cast<const Node<W>*>(T.nodes));
     NodeRegs<W> root;
     load_node<W>(root, nodes + troot);
+    // the loop below reads the previous unit's copy until here
+    __builtin_amdgcn_wave_barrier();
+    stage_level2<W>(root, T.nodes, s_l2[wv]);
     // the whole source mesh against the top two levels (uniform)
-    if (!cull2<W>(sb, root, nodes)) continue;
+    if (!cull2<W>(sb, root, s_l2[wv])) continue;
     st.add(S_GROUPS, (uint64_t)n_chunks);
     for (int32_t base = 0; base < n_chunks; base += kChunk) {
       const int32_t c = base + lane;
@@ -977,7 +1004,7 @@ __global__ __launch_bounds__(kBlock) void k_cull(RefineArgs ra) {
         for (int k = 0; k < 6; ++k) gn[k] = cp[k];
       }
       const bool pass = c < n_chunks && box_meet(g, tb[0], tb[1], tb[2], tb[3], tb[4], tb[5]) &&
-                        cull2<W>(g, root, nodes);
+                        cull2<W>(g, root, s_l2[wv]);
       const uint64_t mask = ballot(pass);
       if (mask) {
         const int n = __popcll(mask);
