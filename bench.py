@@ -191,8 +191,9 @@ def main():
     ap.add_argument("--precision", type=int, default=0)
     ap.add_argument("--schedule", type=int, default=3)
     ap.add_argument("--trace-budget", type=int, default=0,
-                    help="schedule 3: steps before a long group hands its stack to the continuation pass "
-                         "(0 = library default, -1 = never)")
+                    help="schedule 3: 0 = library default (waves of a block share pending subtrees), "
+                         "> 0 = steps before a long group hands its stack to a continuation pass, "
+                         "-1 = no hand-over")
     ap.add_argument("--autotune", action="store_true", help="pick width, leaf size and schedule first")
     ap.add_argument("--serve-requests", type=int, default=2000, help="requests at the highest serving rate")
     ap.add_argument("--plain-requests", type=int, default=400, help="requests replayed on the plain path")

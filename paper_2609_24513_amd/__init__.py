@@ -145,7 +145,7 @@ class RefineConfig:
                  chunks_per_pop: int = 0, schedule: int = 0, survivor_cap: int = 0, ev_begin=None,
                  ev_end=None, n_dev=None, trace_budget: int = 0):
         self.n_dev = n_dev        # optional device int64[1]: number of pairs to process
-        self.trace_budget = trace_budget
+        self.trace_budget = trace_budget  # 0: block work sharing; > 0: continuation pass; -1: neither
         self.ev_begin = ev_begin  # optional torch.cuda.Event recorded around the traversal kernel(s)
         self.ev_end = ev_end
         self.persistent = persistent
