@@ -1126,7 +1126,9 @@ __device__ void block_help(const BlobView& A, const BlobView& B, const RefineArg
 // gridDim, ...  Pop slot j maps to
 // queue slot j * kSpread mod (slots): the queue holds each pair's groups side
 // by side, and spreading them over the run lets a hit found in one group
-// cancel the pair's later groups.
+// cancel the pair's later groups.  A wave whose queues are drained then
+// takes the pending subtrees that the other waves of its block hand over
+// (`block_help`), so the block's long traversals end together.
 template <int W, int PREC>
 __global__ __launch_bounds__(kBlock, 5) void k_trace(RefineArgs ra) {
   constexpr int CAP = lds_stack_cap<W>();
