@@ -13,8 +13,10 @@
  * Conventions shared by every entry point:
  *  - Pointers documented "dev" are device pointers (HIP global memory) owned
  *    by the caller; "host" pointers are ordinary host memory.  The library
- *    never allocates or frees memory in these calls and keeps no state
- *    between calls; scratch space comes from the caller's workspace `ws`.
+ *    never allocates or frees memory in these calls; scratch space comes
+ *    from the caller's workspace `ws`.  The only state kept between calls is
+ *    a per-device cache of launch figures (compute-unit count, resident
+ *    blocks per compute unit of each persistent kernel), filled on first use.
  *  - Work is enqueued on `stream` (a hipStream_t passed as void*); nothing
  *    synchronises the host.  Results are valid once the stream has reached
  *    the end of the call.
