@@ -1467,15 +1467,16 @@ int launch_ra(K kernel, int blocks, hipStream_t s, RefineArgs& ra, hipEvent_t e0
   return PR_OK;
 }
 
-// Resident blocks per compute unit for a kernel, computed once per device.
-template <typename K>
-int blocks_per_cu(K kernel, int dev) {
+// Resident blocks per compute unit of kernel K, computed once per device
+// (one cache per kernel instantiation).
+template <auto K>
+int blocks_per_cu(int dev) {
   static std::atomic<int> cache[64];
   if (dev < 0 || dev >= 64) return -1;
   int v = cache[dev].load(std::memory_order_relaxed);
   if (v > 0) return v;
   int per = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, kernel, kBlock, 0) != hipSuccess) return -1;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, K, kBlock, 0) != hipSuccess) return -1;
   v = per > 0 ? per : 1;
   cache[dev].store(v, std::memory_order_relaxed);
   return v;
@@ -1504,16 +1505,16 @@ int launch(RefineArgs& ra, const pr_refine_params* prm, void* scan_tmp, size_t s
     int dev = 0;
     PR_HIP(hipGetDevice(&dev));
     const int cus = cu_count(dev);
-    const int per = sched == 2   ? blocks_per_cu(k_refine_wave<W, PREC>, dev)
-                    : sched == 3 ? blocks_per_cu(k_trace<W, PREC>, dev)
-                                 : blocks_per_cu(k_refine_persistent<W, PREC>, dev);
+    const int per = sched == 2   ? blocks_per_cu<k_refine_wave<W, PREC>>(dev)
+                    : sched == 3 ? blocks_per_cu<k_trace<W, PREC>>(dev)
+                                 : blocks_per_cu<k_refine_persistent<W, PREC>>(dev);
     if (cus <= 0 || per <= 0) { set_error("device attribute query failed"); return PR_E_DEVICE; }
     const int blocks = prm->grid_blocks > 0 ? prm->grid_blocks : cus * per;
     int r = PR_OK;
     if (sched == 2) {
       r = launch_ra(k_refine_wave<W, PREC>, blocks, s, ra, eb, ee);
     } else if (sched == 3) {
-      const int per_cull = blocks_per_cu(k_cull<W, PREC>, dev);
+      const int per_cull = blocks_per_cu<k_cull<W, PREC>>(dev);
       if (per_cull <= 0) { set_error("occupancy query failed"); return PR_E_DEVICE; }
       r = launch_ra(k_cull<W, PREC>, cus * per_cull, s, ra, eb, nullptr);
       if (r == PR_OK) r = launch_ra(k_trace<W, PREC>, blocks, s, ra, nullptr, ra.budget > 0 ? nullptr : ee);
