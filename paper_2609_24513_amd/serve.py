@@ -111,6 +111,9 @@ class _Slot:
         self.flags_h = torch.zeros(cap, dtype=torch.uint8, pin_memory=True)
         self.status = torch.zeros(1, dtype=torch.int32, device="cuda")
         self.status_h = torch.zeros(1, dtype=torch.int32, pin_memory=True)
+        # query boxes of a batch: filled on the host, one asynchronous copy
+        self.boxes_h = torch.zeros((max_req, 6), dtype=torch.float32, pin_memory=True)
+        self.boxes = torch.empty((max_req, 6), dtype=torch.float32, device="cuda")
         lib = _lib.load()
         wb = ctypes.c_size_t(0)
         _lib.check(lib.filter_aabb_pairs_ws_bytes(R.n_meshes, S.n_meshes, ctypes.byref(wb)))
@@ -159,13 +162,16 @@ class JoinServer:
         torch, lib = self.torch, _lib.load()
         slot.reqs = reqs
         slot.phase = 1
+        # the slot is free, so its previous box copy has completed
+        bh = slot.boxes_h.numpy()
+        for k, r in enumerate(reqs):
+            bh[k] = r.box
         with torch.cuda.stream(slot.stream):
             sp = int(slot.stream.cuda_stream)
+            slot.boxes[:len(reqs)].copy_(slot.boxes_h[:len(reqs)], non_blocking=True)
             for k, r in enumerate(reqs):
-                q = torch.as_tensor(r.box).to("cuda", non_blocking=False)
-                r._q = q  # keep alive until the stream has used it
                 _lib.check(lib.filter_aabb_pairs(
-                    self.R.ptr, self.R.n_meshes, self.S.ptr, self.S.n_meshes, q.data_ptr(),
+                    self.R.ptr, self.R.n_meshes, self.S.ptr, self.S.n_meshes, slot.boxes.data_ptr() + 24 * k,
                     slot.region.data_ptr() + k * self.max_pairs * 8, self.max_pairs,
                     slot.counts.data_ptr() + 8 * k, slot.fws.data_ptr(), slot.fws.numel(), sp))
             slot.counts_h[:len(reqs)].copy_(slot.counts[:len(reqs)], non_blocking=True)
@@ -253,7 +259,9 @@ class JoinServer:
                     busy = sum(1 for s in self.slots if s.phase)
                     self.max_in_flight = max(self.max_in_flight, busy)
             if not progressed:
-                time.sleep(0.0001)
+                # spin while a batch is on the device (its completion is
+                # picked up at once); sleep only while waiting for arrivals
+                time.sleep(0 if any(s.phase for s in self.slots) else 0.0001)
         return list(trace)
 
     def query_alone(self, box: np.ndarray):
