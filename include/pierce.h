@@ -40,7 +40,7 @@
 extern "C" {
 #endif
 
-#define PR_ABI_VERSION 3
+#define PR_ABI_VERSION 4
 
 enum {
   PR_OK = 0,
@@ -235,6 +235,18 @@ int compact_pairs_ws_bytes(int64_t n_pairs, size_t* ws_bytes);
 int compact_pairs(const int32_t* pairs, const uint8_t* flags, int64_t n_pairs,
                   const int64_t* dev_n_pairs, int32_t* out, int64_t cap, int64_t* dev_count, void* ws,
                   size_t ws_bytes, void* stream);
+
+/* Batch assembly for serving (Section 3.5 query pipeline): concatenates the
+ * leading pairs of n_regions regions, in region order, without a host round
+ * trip.  regions dev i32[n_regions * region_cap][2] (region k starts at pair
+ * k * region_cap, as left by one filter_aabb_pairs call per query with cap =
+ * region_cap); dev_counts dev i64[n_regions], the filter's counts (each
+ * clamped to [0, region_cap]); out dev i32[cap][2] receives the
+ * concatenation (rows past cap are dropped); dev_total dev i64[1] gets the
+ * exact concatenated length, so it can feed refine_intersects as
+ * dev_n_pairs.  n_regions <= 2^20 (PR_E_UNSUPPORTED beyond). */
+int gather_pair_regions(const int32_t* regions, int64_t region_cap, const int64_t* dev_counts,
+                        int64_t n_regions, int32_t* out, int64_t cap, int64_t* dev_total, void* stream);
 
 #ifdef __cplusplus
 }

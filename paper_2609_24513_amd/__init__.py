@@ -20,7 +20,7 @@ import numpy as np
 from . import _lib
 from ._lib import PierceError, RefineStats, STATS_FIELDS  # noqa: F401
 
-__all__ = ["MeshBlob", "filter_pairs", "refine", "compact", "refine_workspace", "PierceError",
+__all__ = ["MeshBlob", "filter_pairs", "refine", "compact", "gather_regions", "refine_workspace", "PierceError",
            "RefineConfig"]
 
 
@@ -218,6 +218,16 @@ def refine(A: MeshBlob, B: MeshBlob, pairs, cfg: Optional[RefineConfig] = None, 
 def stats_dict(stats) -> dict:
     vals = stats.cpu().numpy().astype(np.uint64)
     return {k: int(v) for k, v in zip(STATS_FIELDS, vals)}
+
+
+def gather_regions(regions, region_cap: int, counts, n_regions: int, out, total, stream=None):
+    """gather_pair_regions: the leading pairs of n_regions regions of `region_cap`
+    pairs each (counts: device int64[n_regions]) concatenated into `out` (device
+    int32[cap, 2]); the length goes to `total` (device int64[1]).  No sync."""
+    _lib.check(_lib.load().gather_pair_regions(regions.data_ptr(), int(region_cap), counts.data_ptr(),
+                                                int(n_regions), out.data_ptr(), int(out.shape[0]),
+                                                total.data_ptr(), _stream_ptr(stream)))
+    return out, total
 
 
 def compact(pairs, flags, stream=None, n_dev=None, sync: bool = True):

@@ -18,12 +18,12 @@ PR_E_CAPACITY = -2
 PR_E_GEOMETRY = -3
 PR_E_DEVICE = -4
 PR_E_UNSUPPORTED = -5
-ABI_VERSION = 3
+ABI_VERSION = 4
 
 EXPORTS = [
     "pr_last_error", "pr_abi_version", "build_mesh_bvh_sizes", "build_mesh_bvh", "blob_mesh_boxes",
     "blob_edge_counts", "filter_aabb_pairs_ws_bytes", "filter_aabb_pairs", "refine_workspace_bytes",
-    "refine_intersects", "compact_pairs_ws_bytes", "compact_pairs",
+    "refine_intersects", "compact_pairs_ws_bytes", "compact_pairs", "gather_pair_regions",
 ]
 
 
@@ -93,6 +93,7 @@ def load():
                                           vp, vp, vp, ctypes.c_size_t, vp]
         lib.compact_pairs_ws_bytes.argtypes = [i64, szp]
         lib.compact_pairs.argtypes = [vp, vp, i64, vp, vp, i64, vp, vp, ctypes.c_size_t, vp]
+        lib.gather_pair_regions.argtypes = [vp, i64, vp, i64, vp, i64, vp, vp]
         for name in EXPORTS[2:]:
             getattr(lib, name).restype = ctypes.c_int
         if lib.pr_abi_version() != ABI_VERSION:

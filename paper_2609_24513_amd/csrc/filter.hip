@@ -515,6 +515,39 @@ __global__ __launch_bounds__(kScanBlock) void k_compact_small(const int32_t* pai
   if (threadIdx.x == 0) *count = running;
 }
 
+// Concatenation of the leading pairs of n fixed-size regions (the candidate
+// lists that one filter call per query leaves in its own region), in region
+// order, with the counts read on the device: one block per region sums the
+// clamped counts of the regions before it, then copies its rows.
+__global__ __launch_bounds__(kBlock) void k_gather(const int32_t* regions, int64_t region_cap, const int64_t* counts,
+                                                  int64_t n, int32_t* out, int64_t cap, int64_t* total) {
+  using BlockReduce = hipcub::BlockReduce<int64_t, kBlock>;
+  __shared__ typename BlockReduce::TempStorage tmp;
+  __shared__ int64_t s_off;
+  const int64_t k = blockIdx.x;
+  if (n == 0) {
+    if (threadIdx.x == 0) *total = 0;
+    return;
+  }
+  auto clamped = [&](int64_t j) {
+    const int64_t c = counts[j];
+    return c < 0 ? (int64_t)0 : (c < region_cap ? c : region_cap);
+  };
+  int64_t part = 0;
+  for (int64_t j = threadIdx.x; j < k; j += kBlock) part += clamped(j);
+  part = BlockReduce(tmp).Sum(part);
+  if (threadIdx.x == 0) s_off = part;
+  __syncthreads();
+  const int64_t off = s_off, c = clamped(k);
+  const int32_t* src = regions + 2 * k * region_cap;
+  for (int64_t i = threadIdx.x; i < c; i += kBlock)
+    if (off + i < cap) {
+      out[2 * (off + i)] = src[2 * i];
+      out[2 * (off + i) + 1] = src[2 * i + 1];
+    }
+  if (k == n - 1 && threadIdx.x == 0) *total = off + c;
+}
+
 struct FilterWs {
   int32_t *flag_a, *flag_b, *pos_a, *pos_b, *ids_a, *ids_b;
   float *box_a, *box_b;
@@ -709,6 +742,20 @@ extern "C" int compact_pairs(const int32_t* pairs, const uint8_t* flags, int64_t
   hipLaunchKernelGGL(k_compact, dim3(grid_for(n_pairs, kBlock)), dim3(kBlock), 0, s, pairs, (const int32_t*)w.f,
                      (const int64_t*)w.pos, n_pairs, out, cap);
   hipLaunchKernelGGL(k_total, dim3(1), dim3(1), 0, s, (const int64_t*)w.pos, n_pairs, dev_count);
+  PR_HIP(hipGetLastError());
+  return PR_OK;
+}
+
+extern "C" int gather_pair_regions(const int32_t* regions, int64_t region_cap, const int64_t* dev_counts,
+                                   int64_t n_regions, int32_t* out, int64_t cap, int64_t* dev_total, void* stream) {
+  if (region_cap < 0 || n_regions < 0 || cap < 0 || !dev_total ||
+      (n_regions > 0 && (!regions || !dev_counts)) || (cap > 0 && !out)) {
+    set_error("bad argument");
+    return PR_E_ARG;
+  }
+  if (n_regions > ((int64_t)1 << 20)) { set_error("n_regions > 2^20"); return PR_E_UNSUPPORTED; }
+  hipLaunchKernelGGL(k_gather, dim3(n_regions > 0 ? (unsigned)n_regions : 1u), dim3(kBlock), 0, (hipStream_t)stream,
+                     regions, region_cap, dev_counts, n_regions, out, cap, dev_total);
   PR_HIP(hipGetLastError());
   return PR_OK;
 }

@@ -12,13 +12,15 @@ runs without blocking the host:
     reserves room for `max_pairs` candidate pairs; when nothing is in flight
     one request is always admitted, so nothing waits forever and nothing is
     dropped);
-  * phase 1 runs each admitted request's candidate filter into its own region
-    of the slot and copies the counts to pinned host memory;
-  * phase 2, once the counts are on the host, gathers all the batch's pairs
-    into one list and refines them in ONE persistent launch, then copies the
-    flags to pinned host memory;
-  * a request completes when its flags are on the host; its latency is
-    completion time minus arrival time.
+  * the batch's query boxes go to the device in one asynchronous copy; each
+    admitted request's candidate filter writes its own region of the slot,
+    the regions are concatenated on the device with the counts left there
+    (gather_pair_regions), and the concatenation is refined in ONE persistent
+    launch that reads the count on the device: the whole batch is enqueued at
+    once, with no host round trip;
+  * when the slot's stream has finished, the counts, flags and pairs are read
+    back; a request completes then, and its latency is completion time minus
+    arrival time.
 
 Batches on different slots overlap on the device, and new requests are
 admitted while earlier ones are still running.  The per-request plain path
@@ -111,6 +113,7 @@ class _Slot:
         self.flags_h = torch.zeros(cap, dtype=torch.uint8, pin_memory=True)
         self.status = torch.zeros(1, dtype=torch.int32, device="cuda")
         self.status_h = torch.zeros(1, dtype=torch.int32, pin_memory=True)
+        self.total = torch.zeros(1, dtype=torch.int64, device="cuda")
         # query boxes of a batch: filled on the host, one asynchronous copy
         self.boxes_h = torch.zeros((max_req, 6), dtype=torch.float32, pin_memory=True)
         self.boxes = torch.empty((max_req, 6), dtype=torch.float32, device="cuda")
@@ -120,10 +123,8 @@ class _Slot:
         self.fws = torch.empty(max(256, wb.value), dtype=torch.uint8, device="cuda")
         self.rws = pa.refine_workspace(cap, R.width, cfg)
         self.reqs: List[Request] = []
-        self.phase = 0          # 0 free, 1 filtering, 2 refining
+        self.phase = 0          # 0 free, 1 on the device
         self.event = None
-        self.n_total = 0
-        self.offsets = []
 
     def bytes(self) -> int:
         t = [self.region, self.counts, self.batch, self.flags, self.fws, self.rws]
@@ -159,13 +160,19 @@ class JoinServer:
 
     # --- phases ------------------------------------------------------------
     def _start(self, slot: _Slot, reqs: List[Request]):
-        torch, lib = self.torch, _lib.load()
+        """Enqueues the whole batch on the slot's stream with no host round
+        trip: one filter per query into its region, the regions concatenated
+        on the device (gather_pair_regions), one refinement of the
+        concatenation with the device count, then the counts and status
+        copied back."""
+        torch, pa, lib = self.torch, self.pa, _lib.load()
         slot.reqs = reqs
         slot.phase = 1
         # the slot is free, so its previous box copy has completed
         bh = slot.boxes_h.numpy()
         for k, r in enumerate(reqs):
             bh[k] = r.box
+        cap = slot.batch.shape[0]
         with torch.cuda.stream(slot.stream):
             sp = int(slot.stream.cuda_stream)
             slot.boxes[:len(reqs)].copy_(slot.boxes_h[:len(reqs)], non_blocking=True)
@@ -174,41 +181,27 @@ class JoinServer:
                     self.R.ptr, self.R.n_meshes, self.S.ptr, self.S.n_meshes, slot.boxes.data_ptr() + 24 * k,
                     slot.region.data_ptr() + k * self.max_pairs * 8, self.max_pairs,
                     slot.counts.data_ptr() + 8 * k, slot.fws.data_ptr(), slot.fws.numel(), sp))
+            _lib.check(lib.gather_pair_regions(slot.region.data_ptr(), self.max_pairs, slot.counts.data_ptr(),
+                                               len(reqs), slot.batch.data_ptr(), cap, slot.total.data_ptr(), sp))
+            cfg = copy.copy(self.cfg)
+            cfg.n_dev = slot.total
+            pa.refine(self.R, self.S, slot.batch, cfg, ws=slot.rws, flags=slot.flags, status=slot.status,
+                      stream=slot.stream)
             slot.counts_h[:len(reqs)].copy_(slot.counts[:len(reqs)], non_blocking=True)
+            slot.status_h.copy_(slot.status, non_blocking=True)
             slot.event = torch.cuda.Event()
             slot.event.record(slot.stream)
-
-    def _refine(self, slot: _Slot):
-        torch, pa = self.torch, self.pa
-        counts = slot.counts_h[:len(slot.reqs)].numpy().astype(np.int64)
-        counts = np.minimum(counts, self.max_pairs)
-        slot.offsets = np.concatenate([[0], np.cumsum(counts)])
-        n = int(slot.offsets[-1])
-        slot.n_total = n
-        slot.phase = 2
-        with torch.cuda.stream(slot.stream):
-            for k, c in enumerate(counts):
-                if c:
-                    o = int(slot.offsets[k])
-                    slot.batch[o:o + c].copy_(slot.region[k * self.max_pairs:k * self.max_pairs + c], non_blocking=True)
-            if n:
-                pa.refine(self.R, self.S, slot.batch[:n], self.cfg, ws=slot.rws, flags=slot.flags,
-                          status=slot.status, stream=slot.stream)
-                slot.flags_h[:n].copy_(slot.flags[:n], non_blocking=True)
-                slot.status_h.copy_(slot.status, non_blocking=True)
-            slot.event = torch.cuda.Event()
-            slot.event.record(slot.stream)
-        # the gathered pair list is kept for the results
-        slot._batch_view = slot.batch[:n]
 
     def _finish(self, slot: _Slot, now: float):
-        n = slot.n_total
+        counts = np.minimum(np.maximum(slot.counts_h[:len(slot.reqs)].numpy().astype(np.int64), 0), self.max_pairs)
+        offsets = np.concatenate([[0], np.cumsum(counts)])
+        n = int(offsets[-1])
         if n and int(slot.status_h.item()) != 0:
             raise RuntimeError("refine status %d" % int(slot.status_h.item()))
-        flags = slot.flags_h[:n].numpy().copy()
-        pairs = slot._batch_view.cpu().numpy() if n else np.zeros((0, 2), np.int32)
+        flags = slot.flags[:n].cpu().numpy() if n else np.zeros(0, np.uint8)
+        pairs = slot.batch[:n].cpu().numpy() if n else np.zeros((0, 2), np.int32)
         for k, r in enumerate(slot.reqs):
-            a, b = int(slot.offsets[k]), int(slot.offsets[k + 1])
+            a, b = int(offsets[k]), int(offsets[k + 1])
             r.pairs = pairs[a:b]
             r.flags = flags[a:b]
             r.t_done = now
@@ -236,12 +229,9 @@ class JoinServer:
             progressed = False
             for slot in self.slots:
                 if slot.phase and slot.event.query():
-                    if slot.phase == 1:
-                        self._refine(slot)
-                    else:
-                        k = len(slot.reqs)
-                        self._finish(slot, time.perf_counter() - t0)
-                        done += k
+                    k = len(slot.reqs)
+                    self._finish(slot, time.perf_counter() - t0)
+                    done += k
                     progressed = True
             for slot in self.slots:
                 if slot.phase == 0 and pending:

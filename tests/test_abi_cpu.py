@@ -104,7 +104,7 @@ def test_refine_reserved_and_sizes_rejected(lib):
                                  None) == _lib.PR_E_ARG
 
 
-def test_filter_and_compact_args_rejected(lib):
+def test_filter_compact_and_gather_args_rejected(lib):
     wb = ctypes.c_size_t(0)
     assert lib.filter_aabb_pairs_ws_bytes(-1, 2, ctypes.byref(wb)) == _lib.PR_E_ARG
     assert lib.filter_aabb_pairs(None, 1, None, 1, None, None, 0, None, None, 0, None) == _lib.PR_E_ARG
@@ -112,6 +112,14 @@ def test_filter_and_compact_args_rejected(lib):
     assert lib.compact_pairs(None, None, 5, None, None, 0, None, None, 0, None) == _lib.PR_E_ARG
     assert lib.blob_mesh_boxes(None, 3, None, None) == _lib.PR_E_ARG
     assert lib.blob_edge_counts(None, 3, None, None) == _lib.PR_E_ARG
+    # gather: null total, negative sizes, null inputs with regions, too many regions
+    assert lib.gather_pair_regions(None, 4, None, 0, None, 0, None, None) == _lib.PR_E_ARG
+    dummy = ctypes.c_int64(0)
+    assert lib.gather_pair_regions(None, -1, None, 0, None, 0, ctypes.byref(dummy), None) == _lib.PR_E_ARG
+    assert lib.gather_pair_regions(None, 4, None, 2, None, 0, ctypes.byref(dummy), None) == _lib.PR_E_ARG
+    assert lib.gather_pair_regions(None, 4, None, 0, None, 5, ctypes.byref(dummy), None) == _lib.PR_E_ARG
+    assert lib.gather_pair_regions(ctypes.byref(dummy), 4, ctypes.byref(dummy), (1 << 20) + 1, None, 0,
+                                   ctypes.byref(dummy), None) == _lib.PR_E_UNSUPPORTED
 
 
 def test_product_path_has_no_oracle_dependency():

@@ -140,6 +140,30 @@ def test_filter_row_block_path_limits(env, na, nb):
         assert np.array_equal(buf[:cap].cpu().numpy(), want[:cap])
 
 
+@pytest.mark.parametrize("n_regions,region_cap,cap", [(0, 10, 5), (1, 7, 7), (5, 100, 1000), (32, 5000, 40_000),
+                                                        (300, 3, 2000)])
+def test_gather_regions_matches_numpy(env, n_regions, region_cap, cap):
+    """Region concatenation with counts on the device: counts below, at and
+    above the region size (clamped), negative counts (none), and an output
+    smaller than the total (rows dropped, exact total still reported)."""
+    torch, pa, synth, oracle = env
+    rng = np.random.default_rng(n_regions * 7 + region_cap)
+    regions = rng.integers(-5, 1 << 20, size=(max(n_regions, 1) * region_cap, 2)).astype(np.int32)
+    counts = rng.integers(-2, region_cap + 3, size=max(n_regions, 1)).astype(np.int64)[:n_regions]
+    keep = [regions[k * region_cap:k * region_cap + min(max(c, 0), region_cap)] for k, c in enumerate(counts)]
+    want = np.concatenate(keep) if keep else np.zeros((0, 2), np.int32)
+    out = torch.full((cap, 2), -7, dtype=torch.int32, device="cuda")
+    total = torch.full((1,), -1, dtype=torch.int64, device="cuda")
+    pa.gather_regions(torch.as_tensor(regions).cuda(), region_cap,
+                      torch.as_tensor(counts if n_regions else np.zeros(1, np.int64)).cuda(), n_regions, out, total)
+    torch.cuda.synchronize()
+    assert int(total.item()) == want.shape[0]
+    m = min(cap, want.shape[0])
+    got = out.cpu().numpy()
+    assert np.array_equal(got[:m], want[:m])
+    assert (got[m:] == -7).all()
+
+
 @pytest.mark.parametrize("n", [1, 4096, 65_536, 100_003])
 def test_compact_matches_numpy(env, n):
     """Ordered compaction on both sides of the single-block limit."""
