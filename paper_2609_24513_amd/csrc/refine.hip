@@ -896,6 +896,10 @@ constexpr int kCullBuf = 256;  // survivor entries buffered per wave in LDS
 // Multiplier of the pop-order permutation of a survivor queue; a prime above
 // any queue length, so coprime with it.
 constexpr uint64_t kSpread = 2654435761ull;
+// k_cull: up to kCullStatic units per wave are dealt in a fixed stride;
+// beyond, waves take kCullGrab units at a time from their XCD's share.
+constexpr int kCullStatic = 8;
+constexpr int kCullGrab = 4;
 
 // Appends a wave's buffered survivors to its slice queue with one atomic.
 // A survivor that does not fit marks its pair for the rerun pass (state 2:
@@ -924,7 +928,8 @@ __device__ void flush_survivors(const int4* buf, int n, int slice, const RefineA
 }
 
 // Schedule 3, phase 1: one wave per unit (pair, direction), units dealt to the
-// waves in a fixed stride.  The wave validates the pair, tests the source
+// waves in a fixed stride or, with many units per wave, taken from per-XCD
+// shares a few at a time.  The wave validates the pair, tests the source
 // mesh box against the target mesh box and its top two levels, then culls
 // the source groups 64 at a time (one group box per lane, the next 64 boxes
 // loading while the current ones are tested) and buffers the survivors in
@@ -947,25 +952,13 @@ __global__ __launch_bounds__(kBlock) void k_cull(RefineArgs ra) {
   int nbuf = 0;
   WaveStats st;
   const int64_t U = 2 * npairs(ra);
-  const int64_t nw = (int64_t)gridDim.x * kWaves;
   const cptr_t<int32_t> pairs = cview(ra.pairs);
-  const int64_t u0 = (int64_t)blockIdx.x * kWaves + wv;
-  // the pair of the wave's next unit is read while the current one is culled
-  int32_t next_a = 0, next_b = 0;
-  if (u0 < U) {
-    next_a = pairs[2 * (u0 >> 1)];
-    next_b = pairs[2 * (u0 >> 1) + 1];
-  }
-  for (int64_t u = u0; u < U; u += nw) {
+  // Culls unit u (pair ids ia, jb).
+  auto cull_unit = [&](int64_t u, int32_t ia, int32_t jb) {
     const int32_t pair = (int32_t)(u >> 1), dir = (int32_t)(u & 1);
-    const int32_t ia = next_a, jb = next_b;
-    if (u + nw < U) {
-      next_a = pairs[2 * ((u + nw) >> 1)];
-      next_b = pairs[2 * ((u + nw) >> 1) + 1];
-    }
     if (ia < 0 || ia >= ra.n_meshes_a || jb < 0 || jb >= ra.n_meshes_b) {
       if (lane == 0) atomicMin(ra.status, (int32_t)PR_E_ARG);
-      continue;
+      return;
     }
     const BlobView& S = dir == 0 ? A : B;
     const BlobView& T = dir == 0 ? B : A;
@@ -978,7 +971,7 @@ __global__ __launch_bounds__(kBlock) void k_cull(RefineArgs ra) {
     const int32_t troot = tmd->root;
     const int32_t n_chunks = smd->n_chunks, n_edges = smd->n_edges, chunk_base = smd->chunk_base;
     const bool safe = (smd->flags & tmd->flags & kMeshSafe) != 0;
-    if (troot == kEmpty || n_chunks <= 0 || !box_meet(sb, tb[0], tb[1], tb[2], tb[3], tb[4], tb[5])) continue;
+    if (troot == kEmpty || n_chunks <= 0 || !box_meet(sb, tb[0], tb[1], tb[2], tb[3], tb[4], tb[5])) return;
     // the first 64 group boxes load while the top of the target tree is read
     const float* cbox = S.cbox + 8 * (int64_t)chunk_base;
     float g[6], gn[6];
@@ -994,7 +987,7 @@ __global__ __launch_bounds__(kBlock) void k_cull(RefineArgs ra) {
     __builtin_amdgcn_wave_barrier();
     stage_level2<W>(root, T.nodes, s_l2[wv]);
     // the whole source mesh against the top two levels (uniform)
-    if (!cull2<W>(sb, root, s_l2[wv])) continue;
+    if (!cull2<W>(sb, root, s_l2[wv])) return;
     st.add(S_GROUPS, (uint64_t)n_chunks);
     for (int32_t base = 0; base < n_chunks; base += kChunk) {
       const int32_t c = base + lane;
@@ -1021,6 +1014,53 @@ __global__ __launch_bounds__(kBlock) void k_cull(RefineArgs ra) {
       }
 #pragma unroll
       for (int k = 0; k < 6; ++k) g[k] = gn[k];
+    }
+  };
+  const int64_t nw = (int64_t)gridDim.x * kWaves;
+  if (U <= kCullStatic * nw) {
+    // few units per wave: dealt in a fixed stride, the pair of the wave's
+    // next unit read while the current one is culled
+    const int64_t u0 = (int64_t)blockIdx.x * kWaves + wv;
+    int32_t next_a = 0, next_b = 0;
+    if (u0 < U) {
+      next_a = pairs[2 * (u0 >> 1)];
+      next_b = pairs[2 * (u0 >> 1) + 1];
+    }
+    for (int64_t u = u0; u < U; u += nw) {
+      const int32_t ia = next_a, jb = next_b;
+      if (u + nw < U) {
+        next_a = pairs[2 * ((u + nw) >> 1)];
+        next_b = pairs[2 * ((u + nw) >> 1) + 1];
+      }
+      cull_unit(u, ia, jb);
+    }
+  } else {
+    // many units per wave, of uneven cost: cut into one contiguous share per
+    // XCD, from which the waves of that XCD take kCullGrab units at a time
+    // (the next grab in flight while the current units are culled), so a
+    // block that starts late or draws large meshes takes fewer
+    const int nsl = gridDim.x < (unsigned)kSlices ? 1 : kSlices;
+    const int xs = (int)(blockIdx.x % nsl);
+    const int64_t slo = U * xs / nsl, shi = U * (xs + 1) / nsl;
+    unsigned long long* const uctr = ra.ctr + kCtrStride * xs;
+    unsigned long long g0 = 0;
+    if (lane == 0) g0 = atomicAdd(uctr, (unsigned long long)kCullGrab);
+    int64_t ub = slo + (int64_t)uni64(g0);
+    while (ub < shi) {
+      unsigned long long gnext = 0;
+      if (lane == 0) gnext = atomicAdd(uctr, (unsigned long long)kCullGrab);
+      const int64_t ue = ub + kCullGrab < shi ? ub + kCullGrab : shi;
+      int64_t pl = -1;
+      int32_t ia = 0, jb = 0;
+      for (int64_t u = ub; u < ue; ++u) {
+        if ((u >> 1) != pl) {
+          pl = u >> 1;
+          ia = pairs[2 * pl];
+          jb = pairs[2 * pl + 1];
+        }
+        cull_unit(u, ia, jb);
+      }
+      ub = slo + (int64_t)uni64(gnext);
     }
   }
   if (nbuf) flush_survivors(buf, nbuf, slice, ra, st);

@@ -252,6 +252,24 @@ def test_c3_scaled_all_widths_and_schedules(env):
                 assert np.array_equal(flags.cpu().numpy(), want), (w, l, cfg)
 
 
+def test_many_units_per_wave_cull(env):
+    """60,000 pairs (120,000 units, more than eight per culling wave on this
+    GPU), so that the culling waves take their units a few at a time from
+    per-XCD shares: every box-overlapping tetrahedron pair, mixed with random
+    pairs and repeats, against the oracle in FP32-filter and exact modes."""
+    torch, pa, synth, oracle = env
+    A, B = _tetra_set(synth, 600, 31, 6.0), _tetra_set(synth, 600, 32, 6.0)
+    cand = synth.candidate_pairs(A.aabbs(), B.aabbs()).astype(np.int32)
+    rng = np.random.default_rng(3)
+    extra = rng.integers(0, 600, size=(60_000 - cand.shape[0], 2)).astype(np.int32)
+    pairs = np.concatenate([cand, extra])[rng.permutation(60_000)]
+    want = oracle.join(A, B, pairs, mode=1)
+    assert 0 < want.sum() < pairs.shape[0]
+    for prec in (0, 1):
+        got, _ = _run(env, A, B, pairs, persistent=1, schedule=3, precision=prec)
+        assert np.array_equal(got, want), prec
+
+
 def test_block_sharing_matches_unshared(env):
     """Schedule 3 with the waves of a block sharing pending stack entries (the
     default) against sharing off (trace_budget=-1) and the oracle, on the
