@@ -252,8 +252,9 @@ def main():
         from paper_2609_24513_amd import autotune
         pairs_for_tune = given_pairs
         if pairs_for_tune is None:
-            from paper_2609_24513_amd import synth
-            pairs_for_tune = synth.candidate_pairs(A.aabbs(), B.aabbs()).astype(np.int32)
+            g4a, g4b = pa.MeshBlob.build(A), pa.MeshBlob.build(B)
+            pairs_for_tune = pa.filter_pairs(g4a, g4b).cpu().numpy()
+            del g4a, g4b
         tuned = autotune.tune(A, B, pairs_for_tune, log=log)
         args.width, args.leaf, args.schedule = (tuned["best"]["width"], tuned["best"]["leaf_size"],
                                                 tuned["best"]["schedule"])

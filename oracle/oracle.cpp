@@ -35,6 +35,12 @@
 //    intersecting couple.
 // Degenerate triangles (exactly collinear vertices) are rejected with
 // ORACLE_E_DEGENERATE: the paper leaves them to preprocessing (Section 3.6).
+// The check comes before any other test, so a degenerate triangle is refused
+// wherever it lies; at mesh level every pair holding its mesh is refused.
+// Face ids outside the mesh's vertex range and non-finite coordinates are
+// argument errors (ORACLE_E_ARG).  A value that would not fit the fixed-width
+// integers is reported as ORACLE_E_OVERFLOW (never for finite FP32 input:
+// 1280 bits cover degree-4 products over the whole FP32 exponent range).
 
 #include <algorithm>
 #include <atomic>
@@ -58,6 +64,12 @@ struct Big {
 
 thread_local bool g_overflow = false;  // set if a value would not fit (never expected)
 
+// Limbs a value may use.  LIMBS in normal operation; a test lowers it
+// (oracle_set_limb_budget) to check that a value which does not fit is
+// reported as ORACLE_E_OVERFLOW instead of giving a silently wrong sign.
+std::atomic<int> g_limb_budget{LIMBS};
+inline int limb_budget() { return g_limb_budget.load(std::memory_order_relaxed); }
+
 inline void big_norm(Big& r) {
   while (r.n > 0 && r.d[r.n - 1] == 0) --r.n;
   if (r.n == 0) r.neg = false;
@@ -75,7 +87,7 @@ Big big_from(uint64_t mag, bool neg, int shift) {
   Big r = big_zero();
   if (mag == 0) return r;
   int q = shift / 64, s = shift % 64;
-  if (q + 1 >= LIMBS) { g_overflow = true; return r; }
+  if (q + 1 >= limb_budget()) { g_overflow = true; return r; }
   r.d[q] = mag << s;
   if (s) r.d[q + 1] = mag >> (64 - s);
   r.n = q + 2;
@@ -101,7 +113,7 @@ Big mag_add(const Big& a, const Big& b) {
     carry = t >> 64;
   }
   if (carry) {
-    if (n >= LIMBS) { g_overflow = true; return r; }
+    if (n >= limb_budget()) { g_overflow = true; return r; }
     r.d[n++] = (uint64_t)carry;
   }
   r.n = n;
@@ -144,7 +156,7 @@ Big sub(const Big& a, const Big& b) { return add(a, negate(b)); }
 Big mul(const Big& a, const Big& b) {
   Big r = big_zero();
   if (a.n == 0 || b.n == 0) return r;
-  if (a.n + b.n > LIMBS) { g_overflow = true; return r; }
+  if (a.n + b.n > limb_budget()) { g_overflow = true; return r; }
   for (int i = 0; i < a.n; ++i) {
     unsigned __int128 carry = 0;
     for (int j = 0; j < b.n; ++j) {
@@ -222,8 +234,18 @@ bool separates(const V3& L, const V3* T, const V3* U) {
 
 std::atomic<uint64_t> g_tests{0};
 
-// 1 = closed triangles share a point, 0 = disjoint, -3 = degenerate input
-int tri_tri(const float* t, const float* u) {
+// Exact test of a degenerate triangle: its three vertices are collinear
+// (or coincide) iff the cross product of two edge vectors is exactly zero.
+bool tri_degenerate(const float* t) {
+  const float* pts[3] = {t, t + 3, t + 6};
+  V3 X[3];
+  to_ints(pts, 3, X);
+  return is_zero(cross(vsub(X[1], X[0]), vsub(X[2], X[0])));
+}
+
+// 1 = closed triangles share a point, 0 = disjoint.  Both triangles must be
+// non-degenerate (checked by the callers before this is reached).
+int tri_tri_core(const float* t, const float* u) {
   // coordinate axes first: exact float comparisons
   for (int k = 0; k < 3; ++k) {
     float t0 = std::min(std::min(t[k], t[3 + k]), t[6 + k]);
@@ -241,7 +263,6 @@ int tri_tri(const float* t, const float* u) {
   V3 eu[3] = {vsub(U[1], U[0]), vsub(U[2], U[1]), vsub(U[0], U[2])};
   V3 nt = cross(et[0], vsub(T[2], T[0]));
   V3 nu = cross(eu[0], vsub(U[2], U[0]));
-  if (is_zero(nt) || is_zero(nu)) return -3;
   g_tests.fetch_add(1, std::memory_order_relaxed);
   if (separates(nt, T, U)) return 0;
   if (separates(nu, T, U)) return 0;
@@ -257,6 +278,13 @@ int tri_tri(const float* t, const float* u) {
     if (separates(L, T, U)) return 0;
   }
   return 1;
+}
+
+// 1 = closed triangles share a point, 0 = disjoint, -3 = a degenerate input
+// (decided first, whatever the triangles' positions).
+int tri_tri(const float* t, const float* u) {
+  if (tri_degenerate(t) || tri_degenerate(u)) return ORACLE_E_DEGENERATE;
+  return tri_tri_core(t, u);
 }
 
 // ---- orientation signs (exported for predicate pins) ----------------------
@@ -309,14 +337,24 @@ bool mesh_valid(const MeshView& m) {
   return true;
 }
 
-// returns 1 / 0, or -3 on a degenerate triangle
+// 0 if every triangle of the mesh is non-degenerate, else ORACLE_E_DEGENERATE.
+int mesh_degenerate(const MeshView& m) {
+  float t[9];
+  for (int64_t i = 0; i < m.nf; ++i) {
+    tri_pts(m, i, t);
+    if (tri_degenerate(t)) return ORACLE_E_DEGENERATE;
+  }
+  return 0;
+}
+
+// Both meshes have been checked for degenerate triangles; returns 1 / 0.
 int pair_brute(const MeshView& A, const MeshView& B) {
   float t[9], u[9];
   for (int64_t i = 0; i < A.nf; ++i) {
     tri_pts(A, i, t);
     for (int64_t j = 0; j < B.nf; ++j) {
       tri_pts(B, j, u);
-      int r = tri_tri(t, u);
+      int r = tri_tri_core(t, u);
       if (r != 0) return r;
     }
   }
@@ -350,7 +388,7 @@ int pair_pruned(const MeshView& A, const MeshView& B) {
       for (size_t k = j; k < sb.size() && sb[k].lo[0] <= a.hi[0]; ++k) {
         if (!boxes_meet(a.lo, a.hi, sb[k].lo, sb[k].hi)) continue;
         tri_pts(A, a.id, t); tri_pts(B, sb[k].id, u);
-        int r = tri_tri(t, u);
+        int r = tri_tri_core(t, u);
         if (r != 0) return r;
       }
       ++i;
@@ -359,7 +397,7 @@ int pair_pruned(const MeshView& A, const MeshView& B) {
       for (size_t k = i; k < sa.size() && sa[k].lo[0] <= b.hi[0]; ++k) {
         if (!boxes_meet(b.lo, b.hi, sa[k].lo, sa[k].hi)) continue;
         tri_pts(A, sa[k].id, t); tri_pts(B, b.id, u);
-        int r = tri_tri(t, u);
+        int r = tri_tri_core(t, u);
         if (r != 0) return r;
       }
       ++j;
@@ -382,6 +420,14 @@ int oracle_tri_tri(const float* t9, const float* u9) {
   return g_overflow ? ORACLE_E_OVERFLOW : r;
 }
 
+// Test hook: limbs a value may use (1..LIMBS); returns the previous budget.
+// Lowering it makes large intermediate values overflow on purpose, so that a
+// test can see the overflow reported instead of a wrong answer.
+int oracle_set_limb_budget(int limbs) {
+  if (limbs < 1 || limbs > LIMBS) return ORACLE_E_ARG;
+  return g_limb_budget.exchange(limbs);
+}
+
 int oracle_orient3d(const float* a, const float* b, const float* c, const float* d) {
   g_overflow = false;
   int r = orient3d_sign(a, b, c, d);
@@ -402,6 +448,19 @@ int oracle_join(const float* va, const int32_t* fa, const int64_t* voa, const in
   for (int64_t m = 0; m < ma; ++m) if (!mesh_valid(view(va, fa, voa, foa, m))) return ORACLE_E_ARG;
   for (int64_t m = 0; m < mb; ++m) if (!mesh_valid(view(vb, fb, vob, fob, m))) return ORACLE_E_ARG;
   g_tests.store(0);
+  // Degenerate triangles are refused for every pair that holds their mesh,
+  // whatever the triangles' positions (each mesh is checked once, on first use).
+  std::vector<std::atomic<int>> okA(ma), okB(mb);  // 0 unchecked, 1 valid, 2 degenerate
+  for (auto& x : okA) x.store(0);
+  for (auto& x : okB) x.store(0);
+  auto checked = [](std::atomic<int>& st, const MeshView& m) {
+    int v = st.load();
+    if (v == 0) {
+      v = mesh_degenerate(m) == 0 ? 1 : 2;
+      st.store(v);
+    }
+    return v == 1;
+  };
   std::atomic<int64_t> next{0};
   std::atomic<int> status{0};
   auto worker = [&]() {
@@ -411,7 +470,9 @@ int oracle_join(const float* va, const int32_t* fa, const int64_t* voa, const in
       MeshView A = view(va, fa, voa, foa, pairs[2 * p]);
       MeshView B = view(vb, fb, vob, fob, pairs[2 * p + 1]);
       g_overflow = false;
-      int r = mode == 0 ? pair_brute(A, B) : pair_pruned(A, B);
+      int r;
+      if (!checked(okA[pairs[2 * p]], A) || !checked(okB[pairs[2 * p + 1]], B)) r = ORACLE_E_DEGENERATE;
+      else r = mode == 0 ? pair_brute(A, B) : pair_pruned(A, B);
       if (g_overflow) r = ORACLE_E_OVERFLOW;
       if (r < 0) { status.store(r); flags[p] = 0; }
       else flags[p] = (uint8_t)r;

@@ -25,7 +25,9 @@ ORACLE_E_OVERFLOW = -6
 
 
 class OracleError(RuntimeError):
-    pass
+    def __init__(self, msg: str, code: int = 0):
+        super().__init__(msg)
+        self.code = code
 
 
 def build(force: bool = True) -> str:
@@ -58,6 +60,8 @@ def _load():
                                         ctypes.c_int, ctypes.c_int,
                                         ctypes.POINTER(ctypes.c_uint64)]
             lib.oracle_join.restype = ctypes.c_int
+            lib.oracle_set_limb_budget.argtypes = [ctypes.c_int]
+            lib.oracle_set_limb_budget.restype = ctypes.c_int
             _lib = lib
     return _lib
 
@@ -73,7 +77,7 @@ def tri_tri(t, u) -> bool:
     u = np.ascontiguousarray(np.asarray(u, np.float32).reshape(9))
     r = _load().oracle_tri_tri(_ptr(t, ctypes.c_float), _ptr(u, ctypes.c_float))
     if r < 0:
-        raise OracleError("oracle_tri_tri failed with code %d" % r)
+        raise OracleError("oracle_tri_tri failed with code %d" % r, r)
     return bool(r)
 
 
@@ -82,7 +86,7 @@ def orient3d(a, b, c, d) -> int:
     arrs = [np.ascontiguousarray(np.asarray(x, np.float32).reshape(3)) for x in (a, b, c, d)]
     r = _load().oracle_orient3d(*[_ptr(x, ctypes.c_float) for x in arrs])
     if r < -1:
-        raise OracleError("oracle_orient3d failed with code %d" % r)
+        raise OracleError("oracle_orient3d failed with code %d" % r, r)
     return int(r)
 
 
@@ -108,8 +112,17 @@ def join(A, B, pairs, mode: int = 1, threads: int = 0, return_tests: bool = Fals
                         _ptr(flags, ctypes.c_uint8), ctypes.c_int(mode), ctypes.c_int(threads),
                         ctypes.byref(ntests))
     if r != 0:
-        raise OracleError("oracle_join failed with code %d" % r)
+        raise OracleError("oracle_join failed with code %d" % r, r)
     return (flags, int(ntests.value)) if return_tests else flags
+
+
+def set_limb_budget(limbs: int) -> int:
+    """Test hook: the number of 64-bit limbs an exact integer may use (1..20,
+    default 20).  Returns the previous value."""
+    r = _load().oracle_set_limb_budget(int(limbs))
+    if r < 0:
+        raise OracleError("bad limb budget %d" % limbs, r)
+    return r
 
 
 def threads_used(threads: int = 0) -> int:

@@ -58,37 +58,15 @@ class Request:
 
 
 def make_trace(box_r: np.ndarray, box_s: np.ndarray, n: int, lam: float, seed: int = 5,
-               k_lo: float = 1.0, k_hi: float = 5000.0, space: float = 58.5, max_pairs: int = 5000):
-    """Poisson arrivals at rate lam; each request has a target size
-    k ~ LogUniform[k_lo, k_hi] and a cubic box of side k^(1/3) at a uniform
-    centre, redrawn until it selects between 1 and max_pairs candidate pairs
-    (counted on the host with exact closed-box comparisons)."""
-    rng = np.random.Generator(np.random.PCG64(seed))
-    t = 0.0
-    out = []
-    for rid in range(n):
-        t += rng.exponential(1.0 / lam)
-        while True:
-            k = float(np.exp(rng.uniform(np.log(k_lo), np.log(k_hi))))
-            side = k ** (1.0 / 3.0)
-            c = rng.uniform(0.0, space, size=3)
-            q = np.concatenate([c - side / 2, c + side / 2]).astype(np.float32)
-            cnt = count_candidates(box_r, box_s, q)
-            if 1 <= cnt <= max_pairs:
-                break
-        out.append(Request(rid, t, q))
-    return out
-
-
-def count_candidates(box_r, box_s, q) -> int:
-    sr = np.nonzero(np.all(box_r[:, :3] <= q[3:], 1) & np.all(box_r[:, 3:] >= q[:3], 1))[0]
-    ss = np.nonzero(np.all(box_s[:, :3] <= q[3:], 1) & np.all(box_s[:, 3:] >= q[:3], 1))[0]
-    if sr.size == 0 or ss.size == 0:
-        return 0
-    a, b = box_r[sr], box_s[ss]
-    lo = np.maximum(np.maximum(a[:, None, :3], b[None, :, :3]), q[None, None, :3])
-    hi = np.minimum(np.minimum(a[:, None, 3:], b[None, :, 3:]), q[None, None, 3:])
-    return int(np.all(lo <= hi, axis=2).sum())
+               k_lo: float = 1.0, k_hi: float = 5000.0, space: float = 58.5, min_pairs: int = 1,
+               max_pairs: int = 5000) -> List[Request]:
+    """Requests of the seeded serving trace (synth.c5_queries): Poisson
+    arrivals at rate lam, query boxes selecting min_pairs..max_pairs
+    candidate pairs."""
+    from . import synth
+    q = synth.c5_queries(box_r, box_s, n, lam, seed=seed, k_lo=k_lo, k_hi=k_hi, space=space,
+                         min_pairs=min_pairs, max_pairs=max_pairs)
+    return [Request(rid, t, box) for rid, (t, box) in enumerate(q)]
 
 
 def latency_summary(reqs: Sequence[Request]) -> dict:

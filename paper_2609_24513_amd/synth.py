@@ -23,8 +23,8 @@ import numpy as np
 
 __all__ = [
     "MeshSet", "icosphere", "geodesic_sphere", "capped_tube",
-    "make_c1", "make_c2", "make_c3", "make_c4", "make_c5_pool",
-    "concat_meshes", "mesh_stats",
+    "make_c1", "make_c2", "make_c3", "make_c4", "make_c5_pool", "c5_queries",
+    "concat_meshes",
 ]
 
 
@@ -256,22 +256,6 @@ def _tube_faces(rings: int, sides: int) -> np.ndarray:
     return _TUBE_CACHE[key].copy()
 
 
-# ---------------------------------------------------------------------------
-# Mesh sanity (used by tests and by the generators' self-checks)
-# ---------------------------------------------------------------------------
-
-def mesh_stats(verts: np.ndarray, faces: np.ndarray) -> dict:
-    """V, F, unique E, Euler characteristic, edge multiplicities."""
-    f = np.asarray(faces, np.int64)
-    e = np.concatenate([f[:, [0, 1]], f[:, [1, 2]], f[:, [2, 0]]])
-    e.sort(axis=1)
-    uniq, counts = np.unique(e, axis=0, return_counts=True)
-    V = int(np.unique(f).shape[0])
-    return dict(V=V, F=int(f.shape[0]), E=int(uniq.shape[0]),
-                euler=V - int(uniq.shape[0]) + int(f.shape[0]),
-                edge_mult_min=int(counts.min()), edge_mult_max=int(counts.max()))
-
-
 def _f32(x: np.ndarray) -> np.ndarray:
     return np.ascontiguousarray(np.asarray(x, np.float64).astype(np.float32))
 
@@ -400,7 +384,7 @@ def make_c3(seed: int = 3, n_pairs: int = 50_000, n_pool: int = 4096,
         off = side * unit_c
         # fl(x + o) is monotone in x, so the placed FP32 box is the rounded placed box
         box = np.concatenate([lo + off, hi + off], axis=1).astype(np.float32)
-        cand = candidate_pairs(box[0::2], box[1::2])
+        cand = _overlap_pairs(box[0::2], box[1::2])
         if cand.shape[0] >= n_pairs or side < 1.0:
             break
         side /= 2.0
@@ -411,19 +395,15 @@ def make_c3(seed: int = 3, n_pairs: int = 50_000, n_pool: int = 4096,
     return A, B, np.ascontiguousarray(pairs.astype(np.int32))
 
 
-def candidate_pairs(box_a: np.ndarray, box_b: np.ndarray,
-                    query: np.ndarray | None = None) -> np.ndarray:
-    """Closed AABB overlap candidates (host-side helper for building workloads,
-    not the device filter).  Sorted (i, j), int64[P, 2]."""
+def _overlap_pairs(box_a: np.ndarray, box_b: np.ndarray) -> np.ndarray:
+    """Pairs of closed boxes that overlap, sorted (i, j): used only to place
+    the batching workload (the cube is shrunk until enough pairs overlap).
+    The device filter is checked against the oracle's own definition."""
     out = []
     for i in range(box_a.shape[0]):
         a = box_a[i]
         ok = np.all(box_b[:, :3] <= a[3:][None, :], axis=1) & \
             np.all(box_b[:, 3:] >= a[:3][None, :], axis=1)
-        if query is not None:
-            ok &= np.all(box_b[:, :3] <= query[3:], axis=1) & np.all(box_b[:, 3:] >= query[:3], axis=1)
-            if not (np.all(a[:3] <= query[3:]) and np.all(a[3:] >= query[:3])):
-                ok[:] = False
         js = np.nonzero(ok)[0]
         out.append(np.stack([np.full(js.shape, i), js], 1))
     return np.concatenate(out).astype(np.int64) if out else np.zeros((0, 2), np.int64)
@@ -496,3 +476,40 @@ def make_c5_pool(seed: int = 5, n_meshes: int = 50_000, side: float = 58.5):
         c = rng.uniform(0.0, side, size=3)
         meshes.append((_f32(_jittered_sphere(rng, tv, c, r, 0.02)), tf))
     return concat_meshes(meshes[0::2]), concat_meshes(meshes[1::2])
+
+
+def _count_in_box(box_r: np.ndarray, box_s: np.ndarray, q: np.ndarray) -> int:
+    """Pairs (r, s) whose closed boxes and the closed query box q share a
+    point: used only to redraw query boxes of the serving trace."""
+    sr = np.nonzero(np.all(box_r[:, :3] <= q[3:], 1) & np.all(box_r[:, 3:] >= q[:3], 1))[0]
+    ss = np.nonzero(np.all(box_s[:, :3] <= q[3:], 1) & np.all(box_s[:, 3:] >= q[:3], 1))[0]
+    if sr.size == 0 or ss.size == 0:
+        return 0
+    a, b = box_r[sr], box_s[ss]
+    lo = np.maximum(np.maximum(a[:, None, :3], b[None, :, :3]), q[None, None, :3])
+    hi = np.minimum(np.minimum(a[:, None, 3:], b[None, :, 3:]), q[None, None, 3:])
+    return int(np.all(lo <= hi, axis=2).sum())
+
+
+def c5_queries(box_r: np.ndarray, box_s: np.ndarray, n: int, lam: float, seed: int = 5, k_lo: float = 1.0,
+               k_hi: float = 5000.0, space: float = 58.5, min_pairs: int = 1, max_pairs: int = 5000):
+    """Serving trace: n requests with Poisson arrivals at rate lam (seconds
+    from the start); each has a target size k ~ LogUniform[k_lo, k_hi] and a
+    cubic query box of side k^(1/3) at a uniform centre in [0, space]^3,
+    redrawn until it selects between min_pairs and max_pairs candidate pairs.
+    Returns [(t_arrival, box f32[6])]."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    t = 0.0
+    out = []
+    for _ in range(n):
+        t += rng.exponential(1.0 / lam)
+        while True:
+            k = float(np.exp(rng.uniform(np.log(k_lo), np.log(k_hi))))
+            side = k ** (1.0 / 3.0)
+            c = rng.uniform(0.0, space, size=3)
+            q = np.concatenate([c - side / 2, c + side / 2]).astype(np.float32)
+            cnt = _count_in_box(box_r, box_s, q)
+            if min_pairs <= cnt <= max_pairs:
+                break
+        out.append((t, q))
+    return out

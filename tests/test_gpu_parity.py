@@ -68,11 +68,11 @@ def test_build_metadata_c1(env):
     torch, pa, synth, oracle = env
     A, B = synth.make_c1()
     ga = pa.MeshBlob.build(A)
-    assert np.array_equal(ga.boxes().cpu().numpy(), A.aabbs())
+    assert np.array_equal(ga.boxes().cpu().numpy(), oracle.mesh_boxes(A))
     ec = ga.edge_counts().cpu().numpy()
     for m in range(A.n_meshes):
         v, f = A.mesh(m)
-        assert ec[m] == synth.mesh_stats(v, f)["E"]
+        assert ec[m] == oracle.unique_edges(f).shape[0]
 
 
 def test_filter_matches_exact_boxes(env):
@@ -81,7 +81,7 @@ def test_filter_matches_exact_boxes(env):
         A, B = synth.make_c1(seed=seed, n=20)
         ga, gb = pa.MeshBlob.build(A), pa.MeshBlob.build(B)
         got = pa.filter_pairs(ga, gb).cpu().numpy()
-        assert np.array_equal(got, synth.candidate_pairs(A.aabbs(), B.aabbs()))
+        assert np.array_equal(got, oracle.candidate_pairs(oracle.mesh_boxes(A), oracle.mesh_boxes(B)))
 
 
 def _tetra_set(synth, n, seed, side):
@@ -103,7 +103,7 @@ def test_filter_large_mesh_counts(env, na, nb):
     A, B = _tetra_set(synth, na, 11, 30.0), _tetra_set(synth, nb, 12, 30.0)
     ga, gb = pa.MeshBlob.build(A), pa.MeshBlob.build(B)
     got = pa.filter_pairs(ga, gb).cpu().numpy()
-    assert np.array_equal(got, synth.candidate_pairs(A.aabbs(), B.aabbs()))
+    assert np.array_equal(got, oracle.candidate_pairs(oracle.mesh_boxes(A), oracle.mesh_boxes(B)))
 
 
 def _tetra_set_with_empties(synth, n, seed, side, every=7):
@@ -126,13 +126,13 @@ def test_filter_row_block_path_limits(env, na, nb):
     A = _tetra_set_with_empties(synth, na, 21, 30.0)
     B = _tetra_set_with_empties(synth, nb, 22, 30.0)
     ga, gb = pa.MeshBlob.build(A), pa.MeshBlob.build(B)
-    ba, bb = A.aabbs(), B.aabbs()
-    want = synth.candidate_pairs(ba, bb)
+    ba, bb = oracle.mesh_boxes(A), oracle.mesh_boxes(B)
+    want = oracle.candidate_pairs(ba, bb)
     got = pa.filter_pairs(ga, gb).cpu().numpy()
     assert np.array_equal(got, want)
     q = np.array([5, 2, 4, 22, 25, 19], np.float32)
     got = pa.filter_pairs(ga, gb, query_box=q).cpu().numpy()
-    assert np.array_equal(got, synth.candidate_pairs(ba, bb, q))
+    assert np.array_equal(got, oracle.candidate_pairs(ba, bb, q))
     if want.shape[0] > 1:
         cap = want.shape[0] // 2
         buf, cnt = pa.filter_pairs(ga, gb, cap=cap, sync=False)
@@ -184,8 +184,8 @@ def test_filter_query_box_and_capacity(env):
         c = rng.uniform(0, 4, size=3); h = rng.uniform(0.2, 2.0, size=3)
         q = np.concatenate([c - h, c + h]).astype(np.float32)
         got = pa.filter_pairs(ga, gb, query_box=q).cpu().numpy()
-        assert np.array_equal(got, synth.candidate_pairs(A.aabbs(), B.aabbs(), q))
-    full = synth.candidate_pairs(A.aabbs(), B.aabbs())
+        assert np.array_equal(got, oracle.candidate_pairs(oracle.mesh_boxes(A), oracle.mesh_boxes(B), q))
+    full = oracle.candidate_pairs(oracle.mesh_boxes(A), oracle.mesh_boxes(B))
     got = pa.filter_pairs(ga, gb, cap=3).cpu().numpy()  # relaunch path
     assert np.array_equal(got, full)
 
@@ -259,7 +259,7 @@ def test_many_units_per_wave_cull(env):
     pairs and repeats, against the oracle in FP32-filter and exact modes."""
     torch, pa, synth, oracle = env
     A, B = _tetra_set(synth, 600, 31, 6.0), _tetra_set(synth, 600, 32, 6.0)
-    cand = synth.candidate_pairs(A.aabbs(), B.aabbs()).astype(np.int32)
+    cand = oracle.candidate_pairs(oracle.mesh_boxes(A), oracle.mesh_boxes(B)).astype(np.int32)
     rng = np.random.default_rng(3)
     extra = rng.integers(0, 600, size=(60_000 - cand.shape[0], 2)).astype(np.int32)
     pairs = np.concatenate([cand, extra])[rng.permutation(60_000)]
@@ -335,7 +335,7 @@ def test_c2_full_size_against_oracle(env):
     ga, gb = pa.MeshBlob.build(A), pa.MeshBlob.build(B)
     pairs = pa.filter_pairs(ga, gb)
     hp = pairs.cpu().numpy()
-    assert np.array_equal(hp, synth.candidate_pairs(A.aabbs(), B.aabbs()))
+    assert np.array_equal(hp, oracle.candidate_pairs(oracle.mesh_boxes(A), oracle.mesh_boxes(B)))
     want = oracle.join(A, B, hp, mode=1)
     flags, stats, status = pa.refine(ga, gb, pairs, pa.RefineConfig(persistent=1))
     torch.cuda.synchronize()
@@ -361,7 +361,7 @@ def test_c2_scaled_against_oracle(env):
     ga, gb = pa.MeshBlob.build(A), pa.MeshBlob.build(B)
     pairs = pa.filter_pairs(ga, gb)
     hp = pairs.cpu().numpy()
-    assert np.array_equal(hp, synth.candidate_pairs(A.aabbs(), B.aabbs()))
+    assert np.array_equal(hp, oracle.candidate_pairs(oracle.mesh_boxes(A), oracle.mesh_boxes(B)))
     assert hp.shape[0] > 100
     want = oracle.join(A, B, hp, mode=1)
     assert 0 < want.sum() < hp.shape[0]

@@ -219,6 +219,196 @@ def test_tritri_rejects_degenerate(oracle_mod):
         oracle_mod.tri_tri(t, u)
 
 
+def test_tritri_degenerate_refused_before_any_early_out(oracle_mod):
+    """A degenerate triangle is refused wherever it lies, including far from
+    the other triangle (boxes separated on a coordinate axis)."""
+    u = _f32([[0, 0, 0], [1, 0, 0], [0, 1, 0]])
+    for t in (_f32([[50, 50, 50], [51, 51, 51], [53, 53, 53]]),     # collinear, far away
+              _f32([[-9, 4, 2], [-9, 4, 2], [-7, 1, 0]]),            # repeated vertex
+              _f32([[3, 3, 3], [3, 3, 3], [3, 3, 3]])):              # a point
+        for a, b in ((t, u), (u, t)):
+            with pytest.raises(oracle_mod.OracleError) as ei:
+                oracle_mod.tri_tri(a, b)
+            assert ei.value.code == oracle_mod.ORACLE_E_DEGENERATE
+
+
+def _one_mesh(v, f):
+    return synth.concat_meshes([(np.asarray(v, np.float64), np.asarray(f))])
+
+
+def test_join_refuses_bad_meshes(oracle_mod):
+    """Face ids must lie in [0, V) of their mesh and coordinates must be
+    finite (argument errors); a mesh holding a degenerate triangle is refused
+    for every pair, even when that triangle is far from the other mesh."""
+    tet_v = [[0, 0, 0], [1, 0, 0], [0, 1, 0], [0, 0, 1]]
+    tet_f = [[0, 2, 1], [0, 1, 3], [1, 2, 3], [0, 3, 2]]
+    good = _one_mesh(tet_v, tet_f)
+    near = _one_mesh(np.asarray(tet_v) + 0.25, tet_f)
+    pairs = np.zeros((1, 2), np.int32)
+    assert oracle_mod.join(good, near, pairs)[0] == 1
+    last_ok = _one_mesh(tet_v, [[0, 2, 1], [0, 1, 3], [1, 2, 3], [0, 3, 2], [1, 2, 3]])
+    assert oracle_mod.join(last_ok, near, pairs)[0] == 1          # id V-1 is fine
+    bad = {
+        "id_equal_to_V": _one_mesh(tet_v, tet_f + [[1, 2, 4]]),
+        "negative_id": _one_mesh(tet_v, tet_f + [[1, -1, 2]]),
+        "nan": _one_mesh(tet_v[:3] + [[0, np.nan, 1]], tet_f),
+        "inf": _one_mesh(tet_v[:3] + [[np.inf, 0, 1]], tet_f),
+    }
+    for name, m in bad.items():
+        for a, b in ((m, near), (near, m)):
+            with pytest.raises(oracle_mod.OracleError) as ei:
+                oracle_mod.join(a, b, pairs)
+            assert ei.value.code == -1, name
+    far_deg = _one_mesh(tet_v + [[90, 90, 90], [91, 91, 91], [93, 93, 93]], tet_f + [[4, 5, 6]])
+    for mode in (0, 1):
+        for a, b in ((far_deg, near), (near, far_deg)):
+            with pytest.raises(oracle_mod.OracleError) as ei:
+                oracle_mod.join(a, b, pairs, mode=mode)
+            assert ei.value.code == oracle_mod.ORACLE_E_DEGENERATE
+
+
+def _extreme_pairs(rng, n):
+    """Triangle pairs whose coordinates span the whole FP32 range, from the
+    smallest subnormal to the largest finite value, with touching cases."""
+    big = np.float32(np.finfo(np.float32).max)
+    tiny = np.float32(2.0 ** -149)
+    out = []
+    for k in range(n):
+        t = rng.uniform(-1, 1, size=(3, 3))
+        u = rng.uniform(-1, 1, size=(3, 3))
+        t[0] *= 2.0 ** 127 * rng.uniform(0.5, 1.0)
+        u[1] = t[1]                                    # shared vertex: touching
+        u[2] = [tiny, -tiny, 0.0] if k % 2 else [big, -big, tiny]
+        out.append((_f32(t), _f32(u)))
+    return out
+
+
+def test_full_width_integers_cover_fp32_range(oracle_mod):
+    """1280-bit integers hold every degree-4 product over the FP32 exponent
+    range: extreme inputs decide without overflow and agree with exact
+    rationals."""
+    rng = np.random.default_rng(25)
+    n = 0
+    for t, u in _extreme_pairs(rng, 24):
+        if not (_nondegenerate(t) and _nondegenerate(u)):
+            continue
+        assert oracle_mod.tri_tri(t, u) == exact_ref.tri_tri_edges(t, u)
+        n += 1
+    assert n >= 16
+
+
+def test_overflow_is_reported_not_guessed(oracle_mod):
+    """With the integer width lowered on purpose, values that do not fit are
+    reported as an overflow error (single tests and mesh joins), never
+    answered; the full width then answers the same inputs."""
+    t = _f32([[0, 0, 0], [3, 0, 0], [0, 3, 0]])
+    u = _f32([[1, 1, -1], [1, 1, 1], [2, 0.5, 1]])
+    A, B = synth.make_c1(n=2)
+    pairs = np.array([[0, 0], [1, 1]], np.int32)
+    prev = oracle_mod.set_limb_budget(2)
+    try:
+        with pytest.raises(oracle_mod.OracleError) as ei:
+            oracle_mod.tri_tri(t, u)
+        assert ei.value.code == oracle_mod.ORACLE_E_OVERFLOW
+        # exponents 80 bits apart: every scaled coordinate needs two limbs
+        w = _f32([[0, 0, 0], [2.0 ** 40, 0, 0], [0, 2.0 ** 40, 0], [2.0 ** -40, 2.0 ** -40, 2.0 ** -40]])
+        with pytest.raises(oracle_mod.OracleError) as ei:
+            oracle_mod.orient3d(*w)
+        assert ei.value.code == oracle_mod.ORACLE_E_OVERFLOW
+        with pytest.raises(oracle_mod.OracleError) as ei:
+            oracle_mod.join(A, B, np.array([[0, 0]], np.int32), mode=0)
+        assert ei.value.code == oracle_mod.ORACLE_E_OVERFLOW
+    finally:
+        oracle_mod.set_limb_budget(prev)
+    assert prev == 20
+    assert oracle_mod.tri_tri(t, u) is True
+    assert oracle_mod.orient3d(*w) == 1
+    oracle_mod.join(A, B, pairs)
+
+
+# ---------------------------------------------------------------------------
+# candidate filter and unique edges (oracle/filter.py)
+# ---------------------------------------------------------------------------
+
+def _boxes_brute(S):
+    out = []
+    for m in range(S.n_meshes):
+        v, f = S.mesh(m)
+        if f.shape[0] == 0:
+            out.append([np.inf] * 3 + [-np.inf] * 3)
+            continue
+        lo = [min(float(v[i][k]) for tri in f for i in tri) for k in range(3)]
+        hi = [max(float(v[i][k]) for tri in f for i in tri) for k in range(3)]
+        out.append(lo + hi)
+    return np.array(out, np.float32)
+
+
+def _pairs_brute(ba, bb, q=None):
+    out = []
+    for i in range(ba.shape[0]):
+        for j in range(bb.shape[0]):
+            ok = True
+            for k in range(3):
+                lo = max(ba[i][k], bb[j][k]) if q is None else max(ba[i][k], bb[j][k], q[k])
+                hi = min(ba[i][3 + k], bb[j][3 + k]) if q is None else min(ba[i][3 + k], bb[j][3 + k], q[3 + k])
+                ok = ok and lo <= hi
+            if ok:
+                out.append((i, j))
+    return np.array(out, np.int64).reshape(-1, 2)
+
+
+def test_filter_definition_brute_force(oracle_mod):
+    """Closed-box candidates against a pure-Python double loop, on boxes that
+    touch exactly (shared faces, edges, corners), miss by one ulp, nest, and
+    with query boxes; mesh boxes against a loop over face vertices (unused
+    vertices do not count, empty meshes have no box)."""
+    rng = np.random.default_rng(41)
+    for trial in range(6):
+        na, nb = rng.integers(1, 25, size=2)
+        lo = rng.integers(0, 6, size=(na + nb, 3)).astype(np.float32)
+        hi = lo + rng.integers(0, 3, size=(na + nb, 3)).astype(np.float32)
+        bx = np.concatenate([lo, hi], 1)
+        # one-ulp misses and exact touches
+        nudge = rng.uniform(size=na + nb) < 0.2
+        bx[nudge, 3] = np.nextafter(bx[nudge, 3], np.float32(-np.inf))
+        ba, bb = bx[:na], bx[na:]
+        assert np.array_equal(oracle_mod.candidate_pairs(ba, bb), _pairs_brute(ba, bb))
+        q = np.array([1, 0.5, 2, 3, 4, 3.5], np.float32)
+        assert np.array_equal(oracle_mod.candidate_pairs(ba, bb, q), _pairs_brute(ba, bb, q))
+    tet_f = [[0, 2, 1], [0, 1, 3], [1, 2, 3], [0, 3, 2]]
+    meshes = [(rng.uniform(-2, 2, size=(5, 3)), tet_f) for _ in range(6)]   # vertex 4 unused
+    meshes.append((np.zeros((0, 3)), np.zeros((0, 3), np.int64)))          # empty mesh
+    S = synth.concat_meshes(meshes)
+    got = oracle_mod.mesh_boxes(S)
+    assert np.array_equal(got, _boxes_brute(S))
+    assert np.all(np.isinf(got[-1]))
+    # an empty mesh is never a candidate, even against an infinite query box
+    cand = oracle_mod.candidate_pairs(got, got, np.array([-np.inf] * 3 + [np.inf] * 3, np.float32))
+    assert not np.any(cand == S.n_meshes - 1)
+    assert cand.shape[0] >= 6
+
+
+def test_unique_edges_closed_forms(oracle_mod):
+    """Closed genus-0 triangle meshes: every edge is shared by two faces, so
+    E = 3F/2, and Euler's formula V - E + F = 2 holds; icosphere level k has
+    E = 30 * 4^k."""
+    cases = [synth.icosphere(k) for k in (0, 1, 2, 4)]
+    cases += [synth.geodesic_sphere(nu) for nu in (2, 5, 9)]
+    ctrl = np.array([[0, 0, 0], [1, 2, 0], [3, 1, 1], [4, 4, 2]], np.float64)
+    cases += [synth.capped_tube(ctrl, 0.5, r, s) for r, s in ((2, 4), (64, 32), (7, 11))]
+    for k, (v, f) in enumerate(cases):
+        e = oracle_mod.unique_edges(f)
+        F, V = f.shape[0], v.shape[0]
+        assert 2 * e.shape[0] == 3 * F, k
+        assert V - e.shape[0] + F == 2, k
+        assert np.all(e[:, 0] < e[:, 1])
+    for lvl in (0, 1, 2, 4):
+        assert oracle_mod.unique_edges(synth.icosphere(lvl)[1]).shape[0] == 30 * 4 ** lvl
+    # a lone triangle has three edges; the same edge in both orientations counts once
+    assert oracle_mod.unique_edges(np.array([[0, 1, 2]])).tolist() == [[0, 1], [0, 2], [1, 2]]
+    assert oracle_mod.unique_edges(np.array([[0, 1, 2], [2, 1, 3]])).shape[0] == 5
+
+
 # ---------------------------------------------------------------------------
 # mesh level
 # ---------------------------------------------------------------------------
@@ -381,15 +571,50 @@ MUTANTS = {
     "cross_sign": ("return {sub(mul(a.y, b.z), mul(a.z, b.y)),", "return {sub(mul(a.z, b.y), mul(a.y, b.z)),"),
     "lost_low_bits": ("std::ldexp((double)std::fabs(f), 24)", "std::floor(std::ldexp((double)std::fabs(f), 20))"),
     "borrow_dropped": ("uint64_t t = a.d[i] - bi - borrow;", "uint64_t t = a.d[i] - bi;"),
+    "face_id_off_by_one": ("if (m.f[i] < 0 || m.f[i] >= m.nv) return false;",
+                           "if (m.f[i] < 0 || m.f[i] > m.nv) return false;"),
+    "nonfinite_accepted": ("if (!std::isfinite(m.v[i])) return false;", "if (std::isnan(m.v[i])) return false;"),
+    "degenerate_checked_late": ("  if (tri_degenerate(t) || tri_degenerate(u)) return ORACLE_E_DEGENERATE;\n  return tri_tri_core(t, u);",
+                                "  int r = tri_tri_core(t, u);\n  if (r && (tri_degenerate(t) || tri_degenerate(u))) return ORACLE_E_DEGENERATE;\n  return r;"),
+    "mesh_degeneracy_skipped": ("v = mesh_degenerate(m) == 0 ? 1 : 2;", "v = 1;"),
+    "too_few_limbs": ("constexpr int LIMBS = 20;", "constexpr int LIMBS = 12;"),
+    "overflow_not_reported": ("if (a.n + b.n > limb_budget()) { g_overflow = true; return r; }",
+                              "if (a.n + b.n > LIMBS) { g_overflow = true; return r; }"),
 }
 
 
 def _load_variant(path):
     lib = ctypes.CDLL(path)
     fp = ctypes.POINTER(ctypes.c_float)
+    ip = ctypes.POINTER(ctypes.c_int32)
+    lp = ctypes.POINTER(ctypes.c_int64)
     lib.oracle_tri_tri.argtypes = [fp, fp]
     lib.oracle_orient3d.argtypes = [fp, fp, fp, fp]
+    lib.oracle_join.argtypes = [fp, ip, lp, lp, ctypes.c_int64, fp, ip, lp, lp, ctypes.c_int64,
+                                ip, ctypes.c_int64, ctypes.POINTER(ctypes.c_uint8), ctypes.c_int, ctypes.c_int,
+                                ctypes.POINTER(ctypes.c_uint64)]
+    lib.oracle_set_limb_budget.argtypes = [ctypes.c_int]
     return lib
+
+
+def _variant_join(lib, A, B, pairs, mode=1):
+    """oracle_join of a compiled variant: (return code, flags)."""
+    pairs = np.ascontiguousarray(np.asarray(pairs, np.int32).reshape(-1, 2))
+    flags = np.zeros(pairs.shape[0], np.uint8)
+    args = []
+    keep = []
+    for S in (A, B):
+        v = np.ascontiguousarray(S.verts, np.float32); f = np.ascontiguousarray(S.faces, np.int32)
+        vo = np.ascontiguousarray(S.vert_off, np.int64); fo = np.ascontiguousarray(S.face_off, np.int64)
+        keep += [v, f, vo, fo]
+        args += [v.ctypes.data_as(ctypes.POINTER(ctypes.c_float)), f.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+                 vo.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), fo.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
+                 ctypes.c_int64(vo.shape[0] - 1)]
+    n = ctypes.c_uint64(0)
+    r = lib.oracle_join(*args, pairs.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), ctypes.c_int64(pairs.shape[0]),
+                        flags.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8)), ctypes.c_int(mode), ctypes.c_int(1),
+                        ctypes.byref(n))
+    return r, flags
 
 
 def _variant_pins_pass(lib):
@@ -435,6 +660,34 @@ def _variant_pins_pass(lib):
             continue
         if bool(tt(t, u)) != exact_ref.tri_tri_edges(t, u):
             return False
+    for t, u in _extreme_pairs(np.random.default_rng(25), 24):   # whole FP32 range
+        if not (_nondegenerate(t) and _nondegenerate(u)):
+            continue
+        if tt(t, u) != int(exact_ref.tri_tri_edges(t, u)):
+            return False
+    # a degenerate triangle far away is refused, not answered
+    if tt(_f32([[50, 50, 50], [51, 51, 51], [53, 53, 53]]), _f32([[0, 0, 0], [1, 0, 0], [0, 1, 0]])) != -3:
+        return False
+    # mesh-level argument checks and degenerate meshes
+    tet_v = [[0, 0, 0], [1, 0, 0], [0, 1, 0], [0, 0, 1]]
+    tet_f = [[0, 2, 1], [0, 1, 3], [1, 2, 3], [0, 3, 2]]
+    near = _one_mesh(np.asarray(tet_v) + 0.25, tet_f)
+    pr = np.zeros((1, 2), np.int32)
+    r, f = _variant_join(lib, _one_mesh(tet_v, tet_f), near, pr)
+    if r != 0 or f[0] != 1:
+        return False
+    for m in (_one_mesh(tet_v, tet_f + [[1, 2, 4]]), _one_mesh(tet_v[:3] + [[np.inf, 0, 1]], tet_f)):
+        if _variant_join(lib, m, near, pr)[0] != -1:
+            return False
+    far_deg = _one_mesh(tet_v + [[90, 90, 90], [91, 91, 91], [93, 93, 93]], tet_f + [[4, 5, 6]])
+    if _variant_join(lib, far_deg, near, pr)[0] != -3:
+        return False
+    # lowered integer width: overflow reported
+    lib.oracle_set_limb_budget(2)
+    r = tt(_f32([[0, 0, 0], [3, 0, 0], [0, 3, 0]]), _f32([[1, 1, -1], [1, 1, 1], [2, 0.5, 1]]))
+    lib.oracle_set_limb_budget(20)
+    if r != -6:
+        return False
     return True
 
 
