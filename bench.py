@@ -1,17 +1,26 @@
 """Benchmark of the mesh-join refinement path on one MI355X.
 
-Workload (default): the pathology-shaped dataset - 10,000 nuclei (level-4
-icospheres, 5,120 triangles, r~U[3,8], 15% low-frequency noise) against
-1,000 vessels (capped tubes, 64 rings x 32 sides, 4,096 triangles, r~U[2,6])
-in a 1000^3 box, FP32 coordinates, seeded synthetic data standing in for the
-paper's Tissue datasets.
+Headline workload (default): the batching workload - 50,000 candidate pairs
+drawn from a pool of 4,096 meshes (noise-displaced geodesic spheres and
+capped tubes) whose face counts are log-uniform in [500, 100,000], all
+refined in one persistent launch, FP32 filter with FP64/exact re-decision.
+It is the largest configuration that fits one GPU.  The BVH width, leaf size
+and schedule come from the autotuner (2% stratified sample).
 
-One step = one join query on device-resident BVHs: closed-box candidate
-filter, bidirectional refinement of every candidate (one persistent launch,
-FP32 filter with FP64/exact re-decision), and compaction of the result.
-BVH construction is timed separately (the paper excludes acceleration
-structure builds from query time, Section 4.2 "Measurement").  The per-pair
-launch form of the same refinement is timed beside it.
+One step = one pass of the hot path over the batch, inputs resident in HBM:
+bidirectional refinement of every given candidate pair and compaction of
+the result (for workloads without a given pair list the closed-box filter
+runs first).  BVH construction is timed separately (the paper excludes
+acceleration-structure builds from query time, Section 4.2 "Measurement").
+
+Reported beside the headline: segment queries/s, the roofline object of the
+traversal kernels, the per-pair launch form of the same refinement, the
+FP64/exact-only precision mode batched and per pair, the exact CPU oracle on
+a bounded sample, and, under "workloads", the pathology-shaped workload
+(filter + refine + compaction), the precision-stress workload (re-test
+fraction, mismatches against the oracle) and the serving workload (p50/p99
+latency at 50, 200 and 1,000 requests/s against first-in first-out per-pair
+launches on the same trace).
 
 Prints ONE JSON line.  Usage: python bench.py [--steps K] [--warmup W]
 """
@@ -30,10 +39,11 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "refine_cull_trace_%s_traffic.json")  # % workload
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "refine_traversal_%s_traffic.json")  # % workload
 KERNEL_SOURCES = ["paper_2609_24513_amd/csrc/refine.hip", "paper_2609_24513_amd/csrc/predicates.h",
                   "paper_2609_24513_amd/csrc/common.h"]
 METRIC = "refined mesh pairs/s + segment queries/s on 1 MI355X; p50/p99 join latency"
+SCHEDULE_NAMES = {0: "auto", 1: "wave-per-pair", 2: "wave-per-segment"}
 
 
 def log(*a):
@@ -72,26 +82,34 @@ def kernel_source_sha() -> str:
     return h.hexdigest()
 
 
+DESCS = {
+    "c2": ("pathology-shaped: 10,000 nuclei (icosphere L4, 5,120 tris, r~U[3,8], 15% noise) x 1,000 vessels "
+           "(Bezier tubes 64x32, 4,096 tris, r~U[2,6]) in 1000^3, FP32"),
+    "c2-small": "pathology-shaped, 1/10 scale (1,000 x 100 in 464^3)",
+    "c1": "tiny: 8 x 8 level-2 icospheres",
+    "c3": ("batching: 50,000 candidate pairs from a pool of 4,096 meshes (geodesic spheres and capped tubes) with "
+           "face counts log-uniform in [500, 100,000], FP32"),
+    "c4": "precision stress: 2,000 pairs of level-4 icospheres on a 2^-10 grid (30% tangent, 20% coplanar, "
+          "10% vertex on surface, 40% random)",
+}
+
+
 def make_workload(name: str):
     from paper_2609_24513_amd import synth
     if name == "c2":
         A, B = synth.make_c2()
-        desc = ("pathology-shaped: 10,000 nuclei (icosphere L4, 5,120 tris, r~U[3,8], 15% noise) x "
-                "1,000 vessels (Bezier tubes 64x32, 4,096 tris, r~U[2,6]) in 1000^3, FP32")
-        return A, B, None, desc
+        return A, B, None
     if name == "c2-small":
         A, B = synth.make_c2(n_nuclei=1000, n_vessels=100, box=464.0)
-        return A, B, None, "pathology-shaped, 1/10 scale (1,000 x 100 in 464^3)"
+        return A, B, None
     if name == "c1":
         A, B = synth.make_c1()
-        return A, B, None, "tiny: 8 x 8 level-2 icospheres"
+        return A, B, None
     if name == "c4":
         A, B, pairs, _ = synth.make_c4()
-        return A, B, pairs, "precision stress: 2,000 pairs of level-4 icospheres on a 2^-10 grid"
+        return A, B, pairs
     if name == "c3":
-        A, B, pairs = synth.make_c3()
-        return A, B, pairs, ("batching: 50,000 candidate pairs from a pool of 4,096 meshes (geodesic spheres and "
-                             "capped tubes) with face counts log-uniform in [500, 100,000], FP32")
+        return synth.make_c3()
     raise SystemExit("unknown workload " + name)
 
 
@@ -116,29 +134,32 @@ def achievable_hbm_gbs(torch, mib: int = 2048, reps: int = 5) -> float:
 
 
 def cpu_baseline(A, B, pairs_np, gpu_flags, budget_s: float, seed: int = 0):
-    """The exact CPU oracle on a bounded random sample of the same candidates."""
+    """The exact CPU oracle, as it stands, on a bounded random sample of the
+    same candidates (about budget_s seconds of work), with the oracle's default
+    thread count: the host cores this process may use, at most 16 (the CPU
+    share of one GPU on the GPU hosts)."""
     import oracle
     oracle.build(force=False)
+    threads = oracle.default_threads()
     try:
-        threads = min(16, len(os.sched_getaffinity(0)))
+        visible = len(os.sched_getaffinity(0))
     except AttributeError:
-        threads = min(16, os.cpu_count() or 1)
+        visible = os.cpu_count() or 1
     rng = np.random.default_rng(seed)
     P = pairs_np.shape[0]
     order = rng.permutation(P)
-    n = min(P, 256)
+    n = min(P, 128)
     t = time.perf_counter()
     f = oracle.join(A, B, pairs_np[order[:n]], mode=1, threads=threads)
     dt = time.perf_counter() - t
     idx = order[:n]
-    if dt < budget_s and n < P:
+    ntests = None
+    if dt < budget_s / 4 and n < P:
         n2 = int(min(P, max(n, n * budget_s / max(dt, 1e-3))))
         idx = order[:n2]
         t = time.perf_counter()
         f, ntests = oracle.join(A, B, pairs_np[idx], mode=1, threads=threads, return_tests=True)
         dt = time.perf_counter() - t
-    else:
-        ntests = None
     agree = bool(np.array_equal(f, gpu_flags[idx]))
     # single-thread rate on a sub-sample of about a quarter of the budget
     n1 = int(min(len(idx), max(16, len(idx) * (0.25 * budget_s) / max(dt * threads, 1e-3))))
@@ -147,108 +168,48 @@ def cpu_baseline(A, B, pairs_np, gpu_flags, budget_s: float, seed: int = 0):
     dt1 = time.perf_counter() - t
     agree = agree and bool(np.array_equal(f1, gpu_flags[idx[:n1]]))
     return {"value": len(idx) / dt, "unit": "pairs/s", "cores": threads, "kind": "oracle",
+            "host_cores_visible": visible,
             "single_thread_pairs_per_s": n1 / dt1, "single_thread_sample": n1,
             "sample": "%d of %d candidate pairs (seeded random), exact SAT triangle tests with exact box "
-                      "sweep-and-prune, %.1f s" % (len(idx), P, dt),
+                      "sweep-and-prune, %d threads, %.1f s" % (len(idx), P, threads, dt),
             "tri_tests_per_s": (ntests / dt) if ntests else None, "gpu_agrees_on_sample": agree}
 
 
-def serve_bench(args):
-    """Serving: 50,000 resident level-2 icospheres (two datasets of 25,000, split
-    by id parity), Poisson arrivals at several rates, each request a query box
-    selecting 1-5,000 candidate pairs.  Continuous batching (persistent refine
-    per batch) against first-in first-out per-pair launches on the same trace."""
+def roofline_of(st: dict, W: int, kern_ms: float, workload: str) -> dict:
+    """Roofline of the traversal kernels of one refinement pass.  Algorithmic
+    bytes: 24 B per segment started, 28 W B per (wave-level) node visit, 36 B
+    per segment-triangle test.  Also the bytes the kernels' loads cover as
+    issued (group boxes in the cull, segments of traced groups, nodes, leaf
+    triangles once per wave)."""
+    alg = 24 * st["segments"] + 28 * W * st["node_visits"] + 36 * st["tri_tests"]
+    loaded = (24 * st["groups"] + 24 * st["groups_box_pass"] + 24 * st["segments"]
+              + 28 * W * st["node_visits"] + 36 * st["tri_fetches"])
+    achieved = alg / (kern_ms * 1e-3) / 1e9
+    traffic = None
+    path = TRAFFIC_FILE % workload
+    if os.path.exists(path):
+        tr = json.load(open(path))
+        if tr.get("kernel_source_sha") == kernel_source_sha() and tr.get("workload") == workload:
+            traffic = tr.get("hbm_bytes_per_launch")
+    return {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS, "traffic": traffic, "kernel": "k_cull + k_trace",
+            "kernel_ms": kern_ms, "algorithmic_bytes": int(alg), "loaded_bytes_model": int(loaded),
+            "loaded_gbs": loaded / (kern_ms * 1e-3) / 1e9}
+
+
+def run_join(name: str, args, tune: bool, plain: bool, compare_precision: bool, cpu: bool, steps: int,
+             warmup: int, check_oracle: bool = False) -> dict:
+    """Times one join workload: returns the measurements as a dict."""
     import torch
     import paper_2609_24513_amd as pa
-    from paper_2609_24513_amd import serve, synth
     t = time.perf_counter()
-    R, S = synth.make_c5_pool()
-    gr = pa.MeshBlob.build(R, width=args.width, leaf_size=args.leaf)
-    gs = pa.MeshBlob.build(S, width=args.width, leaf_size=args.leaf)
-    br, bs = R.aabbs(), S.aabbs()
-    log("serving pool ready in %.1f s: %d + %d meshes" % (time.perf_counter() - t, R.n_meshes, S.n_meshes))
-    rates = [(50.0, args.serve_requests // 4), (200.0, args.serve_requests // 2), (1000.0, args.serve_requests)]
-    out = {}
-    for lam, n in rates:
-        trace = serve.make_trace(br, bs, n, lam, seed=5)
-        srv = serve.JoinServer(gr, gs, max_req_per_batch=32, slots=3, hbm_budget=args.hbm_budget)
-        srv.run([serve.Request(r.rid, r.t_arrival, r.box) for r in trace[:8]], realtime=False)  # warm-up
-        served = srv.run(trace)
-        s1 = serve.latency_summary(served)
-        s1["batches"] = srv.batches
-        s1["max_slots_in_flight"] = srv.max_in_flight
-        plain_trace = [serve.Request(r.rid, r.t_arrival, r.box) for r in trace[:args.plain_requests]]
-        plain = serve.run_plain(gr, gs, plain_trace)
-        s2 = serve.latency_summary(plain)
-        same = all(np.array_equal(a.flags, b.flags) and np.array_equal(a.pairs, b.pairs)
-                   for a, b in zip(served[:len(plain)], plain))
-        out["%g" % lam] = {"served": s1, "plain_fifo_per_pair": s2, "same_results": bool(same)}
-        log("lambda=%g/s: served p50 %.2f ms p99 %.2f ms %.0f pairs/s (%d batches); plain p50 %.2f p99 %.2f ms; same %s"
-            % (lam, s1["p50_ms"], s1["p99_ms"], s1["pairs_per_s"], srv.batches, s2["p50_ms"], s2["p99_ms"], same))
-    # saturation: the whole highest-rate trace released at once (closed loop)
-    trace = serve.make_trace(br, bs, args.serve_requests, 1000.0, seed=6)
-    srv = serve.JoinServer(gr, gs, max_req_per_batch=32, slots=3, hbm_budget=args.hbm_budget)
-    sat = serve.latency_summary(srv.run(trace, realtime=False))
-    sat["batches"] = srv.batches
-    out["saturation"] = sat
-    log("saturation: %.0f pairs/s, %.0f requests/s over %d batches" % (
-        sat["pairs_per_s"], sat["requests"] / sat["span_s"], srv.batches))
-    top = out["1000"]["served"]
-    line = {"metric": METRIC, "value": top["pairs_per_s"], "unit": "pairs/s", "n_gpus": 1,
-            "steps": args.serve_requests, "warmup": 8, "ms_per_step": top["mean_ms"], "higher_is_better": True,
-            "scaling": "weak", "vs_baseline": None, "dtype": "f32+f64", "data": "synthetic",
-            "config": {"workload": "serving: 2 x 25,000 resident level-2 icospheres, Poisson arrivals, query boxes "
-                                   "selecting 1-5,000 candidate pairs", "workload_id": "c5",
-                       "p50_ms_at_1000_per_s": top["p50_ms"], "p99_ms_at_1000_per_s": top["p99_ms"],
-                       "saturation_pairs_per_s": sat["pairs_per_s"]},
-            "latency": out}
-    print(json.dumps(line), flush=True)
-
-
-def main():
-    ap = argparse.ArgumentParser()
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="c2")
-    ap.add_argument("--width", type=int, default=4)
-    ap.add_argument("--leaf", type=int, default=4)
-    ap.add_argument("--precision", type=int, default=0)
-    ap.add_argument("--schedule", type=int, default=3)
-    ap.add_argument("--trace-budget", type=int, default=0,
-                    help="schedule 3: 0 = library default (waves of a block share pending subtrees), "
-                         "> 0 = steps before a long group hands its stack to a continuation pass, "
-                         "-1 = no hand-over")
-    ap.add_argument("--autotune", action="store_true", help="pick width, leaf size and schedule first")
-    ap.add_argument("--serve-requests", type=int, default=2000, help="requests at the highest serving rate")
-    ap.add_argument("--plain-requests", type=int, default=400, help="requests replayed on the plain path")
-    ap.add_argument("--hbm-budget", type=int, default=1 << 30, help="serving: HBM bytes for in-flight requests")
-    ap.add_argument("--compare-precision", action="store_true",
-                    help="also time the FP64/exact-only precision mode, batched and per pair")
-    ap.add_argument("--cpu-seconds", type=float, default=15.0)
-    ap.add_argument("--skip-cpu", action="store_true")
-    ap.add_argument("--skip-plain", action="store_true")
-    ap.add_argument("--calibrate-copy-mib", type=int, default=0,
-                    help="also run one device-to-device copy of this many MiB (HBM counter calibration)")
-    args = ap.parse_args()
-    if args.gpus != 1:
-        print("bench.py runs on one GPU only: candidate pairs shard independently across GPUs, but no "
-              "multi-GPU path is implemented; run with --gpus 1", file=sys.stderr)
-        sys.exit(2)
-
-    import torch
-    import paper_2609_24513_amd as pa
-
-    torch.cuda.set_device(0)
-    if args.workload == "c5":
-        return serve_bench(args)
-    t = time.perf_counter()
-    A, B, given_pairs, desc = make_workload(args.workload)
-    log("generated %s in %.1f s: %d+%d meshes, %d+%d triangles" % (
-        args.workload, time.perf_counter() - t, A.n_meshes, B.n_meshes, A.faces.shape[0], B.faces.shape[0]))
-
+    A, B, given_pairs = make_workload(name)
+    gen_s = time.perf_counter() - t
+    log("%s: generated in %.1f s: %d+%d meshes, %d+%d triangles" % (
+        name, gen_s, A.n_meshes, B.n_meshes, A.faces.shape[0], B.faces.shape[0]))
+    W, L, sched = args.width, args.leaf, args.schedule
     tuned = None
-    if args.autotune:
+    if tune:
         from paper_2609_24513_amd import autotune
         pairs_for_tune = given_pairs
         if pairs_for_tune is None:
@@ -256,37 +217,38 @@ def main():
             pairs_for_tune = pa.filter_pairs(g4a, g4b).cpu().numpy()
             del g4a, g4b
         tuned = autotune.tune(A, B, pairs_for_tune, log=log)
-        args.width, args.leaf, args.schedule = (tuned["best"]["width"], tuned["best"]["leaf_size"],
-                                                tuned["best"]["schedule"])
-        log("autotune picked W=%d L=%d schedule=%d (%.1f s, cached=%s)" % (
-            args.width, args.leaf, args.schedule, tuned["tune_seconds"], tuned["cached"]))
+        W, L, sched = tuned["best"]["width"], tuned["best"]["leaf_size"], tuned["best"]["schedule"]
+        log("%s: autotune picked W=%d L=%d schedule=%d (%.1f s, cached=%s)" % (
+            name, W, L, sched, tuned["tune_seconds"], tuned["cached"]))
+        tuned = {k: tuned[k] for k in ("best", "per_bucket", "sample", "tune_seconds", "cached")}
 
     ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     ev0.record()
-    ga = pa.MeshBlob.build(A, width=args.width, leaf_size=args.leaf, check_status=False)
-    gb = pa.MeshBlob.build(B, width=args.width, leaf_size=args.leaf, check_status=False)
+    ga = pa.MeshBlob.build(A, width=W, leaf_size=L, check_status=False)
+    gb = pa.MeshBlob.build(B, width=W, leaf_size=L, check_status=False)
     ev1.record()
     torch.cuda.synchronize()
     build_ms = ev0.elapsed_time(ev1)
     assert ga.status() == -1 and gb.status() == -1, "invalid geometry"
-    log("built blobs in %.1f ms (%.2f + %.2f GB)" % (build_ms, ga.blob.numel() / 1e9, gb.blob.numel() / 1e9))
+    log("%s: built blobs in %.1f ms (%.2f + %.2f GB)" % (name, build_ms, ga.blob.numel() / 1e9,
+                                                         gb.blob.numel() / 1e9))
 
     given = None if given_pairs is None else torch.as_tensor(given_pairs).cuda()
     first = pa.filter_pairs(ga, gb) if given is None else given
     P = int(first.shape[0])
-    cfg_events = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
-                  for _ in range(args.steps)]
-    base_cfg = dict(persistent=1, precision=args.precision, schedule=args.schedule, trace_budget=args.trace_budget)
-    ws = pa.refine_workspace(P, args.width, pa.RefineConfig(**base_cfg))
+    kern_events = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+                   for _ in range(steps)]
+    base_cfg = dict(persistent=1, precision=args.precision, schedule=sched, trace_budget=args.trace_budget)
+    ws = pa.refine_workspace(P, W, pa.RefineConfig(**base_cfg))
     flags = torch.empty(P, dtype=torch.uint8, device="cuda")
     stats = torch.zeros(len(pa.STATS_FIELDS), dtype=torch.int64, device="cuda")
     status = torch.zeros(1, dtype=torch.int32, device="cuda")
-    n_split = min(args.steps, 5)
+    n_split = min(steps, 5)
     filt_ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(n_split)]
     ref_ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(n_split)]
 
     def step(k=None, split=None):
-        # one pass on the device: filter -> refine -> compaction, the pair count
+        # one pass on the device: (filter ->) refine -> compaction, the pair count
         # handed from stage to stage on the device (no host round trip).  The
         # kernel events ride on the dispatches themselves; the stage-split
         # events (`split`) insert marker packets and are only used outside the
@@ -300,8 +262,8 @@ def main():
         if split is not None:
             filt_ev[split][1].record()
             ref_ev[split][0].record()
-        cfg = pa.RefineConfig(**base_cfg, ev_begin=None if k is None else cfg_events[k][0],
-                              ev_end=None if k is None else cfg_events[k][1], n_dev=cnt)
+        cfg = pa.RefineConfig(**base_cfg, ev_begin=None if k is None else kern_events[k][0],
+                              ev_end=None if k is None else kern_events[k][1], n_dev=cnt)
         pa.refine(ga, gb, pairs, cfg, ws=ws, flags=flags, stats=stats, status=status)
         if split is not None:
             ref_ev[split][1].record()
@@ -310,121 +272,222 @@ def main():
 
     # torch creates an event at its first record: create them all here, so
     # that no marker packet lands inside the timed loop
-    for e in [e for pair in cfg_events + filt_ev + ref_ev for e in pair]:
+    for e in [e for pair in kern_events + filt_ev + ref_ev for e in pair]:
         e.record()
-    for _ in range(args.warmup):
+    for _ in range(warmup):
         step()
     torch.cuda.synchronize()
-    log("warmup done (%d steps), %d candidate pairs" % (args.warmup, P))
     t0 = time.perf_counter()
-    for k in range(args.steps):
+    for k in range(steps):
         pairs, cnt, res, rcnt = step(k)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     if cnt is not None and int(cnt.item()) != P:
         raise RuntimeError("filter count %d != %d" % (int(cnt.item()), P))
     res = res[:int(rcnt.item())]
-    ms_step = (t1 - t0) * 1e3 / args.steps
-    kern_ms = float(np.mean([a.elapsed_time(b) for a, b in cfg_events]))
-    # stage split (filter vs refine), measured after the timed loop
+    ms_step = (t1 - t0) * 1e3 / steps
+    kern_ms = float(np.mean([a.elapsed_time(b) for a, b in kern_events]))
     for k in range(len(filt_ev)):
         step(split=k)
     torch.cuda.synchronize()
     refine_ms = float(np.mean([a.elapsed_time(b) for a, b in ref_ev]))
-    filter_ms = float(np.mean([a.elapsed_time(b) for a, b in filt_ev]))
+    filter_ms = float(np.mean([a.elapsed_time(b) for a, b in filt_ev])) if given is None else 0.0
     assert int(status.item()) == 0
     st = pa.stats_dict(stats)
     n_true = int(res.shape[0])
-    log("timed %d steps: %.3f ms/step (kernel %.3f ms, refine %.3f ms, filter %.3f ms), %d intersecting" % (
-        args.steps, ms_step, kern_ms, refine_ms, filter_ms, n_true))
+    log("%s: %d steps: %.3f ms/step (traversal kernels %.3f ms, refine %.3f ms, filter %.3f ms), %d of %d "
+        "intersecting" % (name, steps, ms_step, kern_ms, refine_ms, filter_ms, n_true, P))
 
-    W = args.width
-    # algorithmic bytes of one traversal launch: every group box read by the cull,
-    # the box and the 64 segments of every traced group, one node per wave-level
-    # visit (28 W bytes of boxes and child references) and one triangle per
-    # wave-level leaf fetch
-    alg_bytes = (24 * st["groups"] + 24 * st["groups_box_pass"] + 24 * st["segments"]
-                 + 28 * W * st["node_visits"] + 36 * st["tri_fetches"])
-    achieved = alg_bytes / (kern_ms * 1e-3) / 1e9
-    traffic = None
-    if os.path.exists(TRAFFIC_FILE % args.workload):
-        tr = json.load(open(TRAFFIC_FILE % args.workload))
-        if tr.get("kernel_source_sha") == kernel_source_sha() and tr.get("workload") == args.workload:
-            traffic = tr.get("hbm_bytes_per_launch")
-    roofline = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-                "kernel": {1: "k_refine_persistent", 2: "k_refine_wave", 3: "k_cull + k_trace"}[args.schedule],
-                "kernel_ms": kern_ms, "algorithmic_bytes": int(alg_bytes)}
-
-    out_pairs = pairs.cpu().numpy()
-    gflags = flags.cpu().numpy()
+    roof = roofline_of(st, W, kern_ms, name)
+    out_pairs = pairs.cpu().numpy()[:P]
+    gflags = flags.cpu().numpy()[:P]
     ea = ga.edge_counts().cpu().numpy().astype(np.int64)
     eb = gb.edge_counts().cpu().numpy().astype(np.int64)
     nominal_segments = int((ea[out_pairs[:, 0]] + eb[out_pairs[:, 1]]).sum()) if P else 0
-    # compulsory floor: every unique edge of every candidate's two meshes read once
-    # (8 B vertex ids + 24 B endpoints)
-    roofline["compulsory_floor_bytes"] = 32 * nominal_segments
-    roofline["achievable_gbs"] = achievable_hbm_gbs(torch)
-    roofline["frac_of_achievable"] = roofline["achieved"] / roofline["achievable_gbs"]
+
     def one_run(persistent, precision):
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         k0, k1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         fl = torch.empty(P, dtype=torch.uint8, device="cuda")
-        cfg = pa.RefineConfig(persistent=persistent, precision=precision, schedule=args.schedule,
-                              ev_begin=k0, ev_end=k1)
+        cfg = pa.RefineConfig(persistent=persistent, precision=precision, schedule=sched, ev_begin=k0, ev_end=k1)
         w_ = pa.refine_workspace(P, W, cfg)
-        pa.refine(ga, gb, pairs, cfg, ws=w_, flags=fl)  # warm
+        pa.refine(ga, gb, first, cfg, ws=w_, flags=fl)  # warm
         torch.cuda.synchronize()
         e0.record()
-        _, pst, pstatus = pa.refine(ga, gb, pairs, cfg, ws=w_, flags=fl)
+        _, pst, pstatus = pa.refine(ga, gb, first, cfg, ws=w_, flags=fl)
         e1.record()
         torch.cuda.synchronize()
         ms = e0.elapsed_time(e1)
+        assert int(pstatus.item()) == 0
         return {"refine_ms": ms, "kernels_ms": k0.elapsed_time(k1), "pairs_per_s": P / (ms * 1e-3),
-                "same_flags": bool(np.array_equal(fl.cpu().numpy(), gflags)),
-                "stats": pa.stats_dict(pst)}
+                "same_flags": bool(np.array_equal(fl.cpu().numpy()[:P], gflags)), "stats": pa.stats_dict(pst)}
 
-    plain = None
-    if not args.skip_plain:
-        plain = one_run(0, args.precision)
-        plain["launches"] = P
-        plain["batched_speedup"] = plain["refine_ms"] / refine_ms
-        log("plain per-pair launches: %.2f ms (%.1fx slower), same flags: %s" % (
-            plain["refine_ms"], plain["batched_speedup"], plain["same_flags"]))
-    precision_cmp = None
-    if args.compare_precision:
-        precision_cmp = {"batched_fp64_exact": one_run(1, 1)}
-        if not args.skip_plain:
-            precision_cmp["per_pair_fp64_exact"] = one_run(0, 1)
-        for k, v in precision_cmp.items():
-            log("%s: %.2f ms, same flags: %s" % (k, v["refine_ms"], v["same_flags"]))
-
-    cpu = None
-    if not args.skip_cpu:
-        cpu = cpu_baseline(A, B, out_pairs, gflags, args.cpu_seconds)
-        log("cpu oracle: %.1f pairs/s on %d threads, agrees: %s" % (cpu["value"], cpu["cores"],
-                                                                     cpu["gpu_agrees_on_sample"]))
-
-    value = P / (ms_step * 1e-3)
-    line = {
-        "metric": METRIC, "value": value, "unit": "pairs/s", "n_gpus": 1, "steps": args.steps,
-        "warmup": args.warmup, "ms_per_step": ms_step, "higher_is_better": True, "scaling": "weak",
-        "vs_baseline": None, "dtype": "f32+f64", "data": "synthetic",
-        "config": {"workload": desc, "workload_id": args.workload, "candidate_pairs": P,
-                   "intersecting_pairs": n_true, "bvh_width": W, "leaf_size": args.leaf,
-                   "precision": ["fp32 filter + fp64/exact fallback", "fp64/exact", "forced deferral"][args.precision],
-                   "refine": "one persistent launch (batched)", "schedule": args.schedule,
-                   "step": ("filter + refine + compact" if given is None else "refine + compact (pairs given)")},
+    plain_r = None
+    if plain:
+        plain_r = one_run(0, args.precision)
+        plain_r["launches"] = P
+        plain_r["batched_speedup"] = plain_r["refine_ms"] / refine_ms
+        log("%s: per-pair launches %.2f ms (batched is %.1fx faster), same flags: %s" % (
+            name, plain_r["refine_ms"], plain_r["batched_speedup"], plain_r["same_flags"]))
+    prec = None
+    if compare_precision:
+        prec = {"batched_fp32_fp64_fallback_ms": refine_ms, "batched_fp64_exact": one_run(1, 1)}
+        if plain:
+            prec["per_pair_fp32_fp64_fallback_ms"] = plain_r["refine_ms"]
+            prec["per_pair_fp64_exact"] = one_run(0, 1)
+            prec["speedup_batched_fp32_over_per_pair_fp64"] = prec["per_pair_fp64_exact"]["refine_ms"] / refine_ms
+        prec["speedup_fp32_fallback_over_fp64_exact_batched"] = prec["batched_fp64_exact"]["refine_ms"] / refine_ms
+        for k, v in prec.items():
+            if isinstance(v, dict):
+                log("%s: %s %.2f ms, same flags: %s" % (name, k, v["refine_ms"], v["same_flags"]))
+    cpu_r = None
+    if cpu:
+        cpu_r = cpu_baseline(A, B, out_pairs, gflags, args.cpu_seconds)
+        log("%s: cpu oracle %.1f pairs/s on %d threads, agrees: %s" % (
+            name, cpu_r["value"], cpu_r["cores"], cpu_r["gpu_agrees_on_sample"]))
+    oracle_check = None
+    if check_oracle:
+        import oracle
+        t = time.perf_counter()
+        want = oracle.join(A, B, out_pairs, mode=1)
+        oracle_check = {"pairs": P, "mismatches": int((want != gflags).sum()),
+                        "oracle_true": int(want.sum()), "oracle_s": time.perf_counter() - t}
+        log("%s: oracle on every pair: %d mismatches" % (name, oracle_check["mismatches"]))
+    out = {
+        "workload": DESCS[name], "workload_id": name, "candidate_pairs": P, "intersecting_pairs": n_true,
+        "bvh_width": W, "leaf_size": L, "schedule": sched, "schedule_name": SCHEDULE_NAMES.get(sched, str(sched)),
+        "precision": ["fp32 filter + fp64/exact fallback", "fp64/exact", "forced deferral"][args.precision],
+        "step": ("filter + refine + compact" if given is None else "refine + compact (pairs given)"),
+        "ms_per_step": ms_step, "pairs_per_s": P / (ms_step * 1e-3),
+        "refine_ms": refine_ms, "filter_ms": filter_ms, "traversal_kernels_ms": kern_ms,
+        "refine_pairs_per_s": P / (refine_ms * 1e-3),
         "segment_queries_per_s": st["segments"] / (refine_ms * 1e-3),
         "nominal_segments": nominal_segments,
-        "nominal_segment_queries_per_s": nominal_segments / (refine_ms * 1e-3),
-        "refine_pairs_per_s": P / (refine_ms * 1e-3),
-        "refine_ms": refine_ms, "filter_ms": filter_ms, "build_ms": build_ms,
-        "roofline": roofline, "cpu_baseline": cpu, "plain_per_pair": plain,
-        "precision_comparison": precision_cmp, "autotune": tuned,
-        "stats": st,
+        "nominal_segment_rate_per_s": nominal_segments / (refine_ms * 1e-3),
+        "build_ms": build_ms, "generate_s": gen_s, "roofline": roof, "plain_per_pair": plain_r,
+        "precision_comparison": prec, "autotune": tuned, "cpu_baseline": cpu_r, "stats": st,
         "retest_fraction": (st["fp32_ambiguous"] / st["tri_tests"]) if st["tri_tests"] else 0.0,
+        "oracle_check": oracle_check,
     }
+    del ga, gb, ws, given, first
+    torch.cuda.empty_cache()
+    return out
+
+
+def serve_bench(args) -> dict:
+    """Serving: 50,000 resident level-2 icospheres (two datasets of 25,000, split
+    by id parity), Poisson arrivals at several rates, each request a query box
+    selecting 1-5,000 candidate pairs.  Continuous batching (persistent refine
+    per batch) against first-in first-out per-pair launches on the same trace."""
+    import torch
+    import paper_2609_24513_amd as pa
+    from paper_2609_24513_amd import serve, synth
+    t = time.perf_counter()
+    R, S = synth.make_c5_pool()
+    gr = pa.MeshBlob.build(R, width=4, leaf_size=4)
+    gs = pa.MeshBlob.build(S, width=4, leaf_size=4)
+    br, bs = R.aabbs(), S.aabbs()
+    log("serving pool ready in %.1f s: %d + %d meshes" % (time.perf_counter() - t, R.n_meshes, S.n_meshes))
+    n = args.serve_requests
+    rates = [(50.0, max(8, n // 8)), (200.0, max(8, n // 4)), (1000.0, n)]
+    out = {}
+    for lam, nreq in rates:
+        trace = serve.make_trace(br, bs, nreq, lam, seed=5)
+        srv = serve.JoinServer(gr, gs, max_req_per_batch=32, slots=3, hbm_budget=args.hbm_budget)
+        srv.run([serve.Request(r.rid, r.t_arrival, r.box) for r in trace[:8]], realtime=False)  # warm-up
+        srv.batches = 0
+        srv.max_in_flight = 0
+        served = srv.run(trace)
+        s1 = serve.latency_summary(served)
+        s1["batches"] = srv.batches
+        s1["max_slots_in_flight"] = srv.max_in_flight
+        plain_trace = [serve.Request(r.rid, r.t_arrival, r.box) for r in trace[:args.plain_requests]]
+        plain = serve.run_plain(gr, gs, plain_trace)
+        s2 = serve.latency_summary(plain)
+        same = all(np.array_equal(a.flags, b.flags) and np.array_equal(a.pairs, b.pairs)
+                   for a, b in zip(served[:len(plain)], plain))
+        out["%g" % lam] = {"served": s1, "plain_fifo_per_pair": s2, "same_results": bool(same)}
+        log("serving lambda=%g/s: p50 %.2f ms p99 %.2f ms %.0f pairs/s (%d batches); plain FIFO p50 %.2f p99 %.2f ms;"
+            " same %s" % (lam, s1["p50_ms"], s1["p99_ms"], s1["pairs_per_s"], srv.batches, s2["p50_ms"],
+                          s2["p99_ms"], same))
+    # saturation: the whole highest-rate trace released at once (closed loop)
+    trace = serve.make_trace(br, bs, n, 1000.0, seed=6)
+    srv = serve.JoinServer(gr, gs, max_req_per_batch=32, slots=3, hbm_budget=args.hbm_budget)
+    sat = serve.latency_summary(srv.run(trace, realtime=False))
+    sat["batches"] = srv.batches
+    out["saturation"] = sat
+    log("serving saturation: %.0f pairs/s, %.0f requests/s over %d batches" % (
+        sat["pairs_per_s"], sat["requests"] / sat["span_s"], srv.batches))
+    del gr, gs
+    torch.cuda.empty_cache()
+    top = out["1000"]["served"]
+    return {"workload": "serving: 2 x 25,000 resident level-2 icospheres in 58.5^3, Poisson arrivals, query boxes "
+                        "selecting 1-5,000 candidate pairs, batches of up to 32 requests on 3 streams",
+            "p50_ms": {k: v["served"]["p50_ms"] for k, v in out.items() if k != "saturation"},
+            "p99_ms": {k: v["served"]["p99_ms"] for k, v in out.items() if k != "saturation"},
+            "plain_fifo_p50_ms": {k: v["plain_fifo_per_pair"]["p50_ms"] for k, v in out.items() if k != "saturation"},
+            "plain_fifo_p99_ms": {k: v["plain_fifo_per_pair"]["p99_ms"] for k, v in out.items()
+                                  if k != "saturation"},
+            "pairs_per_s_at_1000": top["pairs_per_s"], "saturation_pairs_per_s": sat["pairs_per_s"],
+            "same_results_as_plain": all(v["same_results"] for k, v in out.items() if k != "saturation"),
+            "detail": out}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="c3", help="headline workload: c3 (default), c2, c4, c2-small, c1, c5")
+    ap.add_argument("--width", type=int, default=4)
+    ap.add_argument("--leaf", type=int, default=4)
+    ap.add_argument("--precision", type=int, default=0)
+    ap.add_argument("--schedule", type=int, default=1, help="0 auto, 1 wave-per-pair, 2 wave-per-segment")
+    ap.add_argument("--trace-budget", type=int, default=0,
+                    help="0 = library default (waves of a block share pending subtrees), > 0 = steps before a long "
+                         "group hands its stack to a continuation pass, -1 = no hand-over")
+    ap.add_argument("--no-tune", action="store_true", help="use --width/--leaf/--schedule instead of the autotuner")
+    ap.add_argument("--no-extras", action="store_true", help="headline workload only")
+    ap.add_argument("--serve-requests", type=int, default=1000, help="requests at the highest serving rate")
+    ap.add_argument("--plain-requests", type=int, default=200, help="requests replayed on the plain path")
+    ap.add_argument("--hbm-budget", type=int, default=1 << 30, help="serving: HBM bytes for in-flight requests")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--skip-cpu", action="store_true")
+    ap.add_argument("--skip-plain", action="store_true")
+    ap.add_argument("--calibrate-copy-mib", type=int, default=0,
+                    help="also run one device-to-device copy of this many MiB (HBM counter calibration)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU: this build has no multi-GPU path (candidate pairs shard independently "
+              "across GPUs, but nothing here launches more than one); run with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    torch.cuda.set_device(0)
+    if args.workload == "c5":
+        r = serve_bench(args)
+        line = {"metric": METRIC, "value": r["pairs_per_s_at_1000"], "unit": "pairs/s", "n_gpus": 1,
+                "steps": args.serve_requests, "warmup": 8, "ms_per_step": None, "higher_is_better": True,
+                "scaling": "weak", "vs_baseline": None, "dtype": "f32+f64", "data": "synthetic",
+                "config": {"workload": r["workload"], "workload_id": "c5"}, "serving": r}
+        print(json.dumps(line), flush=True)
+        return
+
+    head = run_join(args.workload, args, tune=not args.no_tune, plain=not args.skip_plain,
+                    compare_precision=not args.skip_plain, cpu=not args.skip_cpu, steps=args.steps,
+                    warmup=args.warmup)
+    head["roofline"]["achievable_gbs"] = achievable_hbm_gbs(torch)
+    head["roofline"]["frac_of_achievable"] = head["roofline"]["achieved"] / head["roofline"]["achievable_gbs"]
+    extras = {}
+    if not args.no_extras:
+        if args.workload != "c2":
+            extras["c2"] = run_join("c2", args, tune=False, plain=False, compare_precision=False, cpu=False,
+                                    steps=args.steps, warmup=args.warmup)
+        if args.workload != "c4":
+            extras["c4"] = run_join("c4", args, tune=False, plain=not args.skip_plain,
+                                    compare_precision=not args.skip_plain, cpu=False, steps=args.steps,
+                                    warmup=args.warmup, check_oracle=True)
+        extras["c5"] = serve_bench(args)
     if args.calibrate_copy_mib > 0:
         n = args.calibrate_copy_mib << 20
         src = torch.ones(n // 4, dtype=torch.float32, device="cuda")
@@ -433,6 +496,35 @@ def main():
         dst.copy_(src)
         torch.cuda.synchronize()
         log("calibration copy of %d MiB done" % args.calibrate_copy_mib)
+
+    def brief(r):
+        keys = ("workload", "candidate_pairs", "intersecting_pairs", "bvh_width", "leaf_size", "schedule_name",
+                "step", "ms_per_step", "pairs_per_s", "refine_ms", "filter_ms", "refine_pairs_per_s",
+                "segment_queries_per_s", "traversal_kernels_ms", "build_ms", "retest_fraction", "roofline",
+                "oracle_check", "plain_per_pair", "precision_comparison", "stats")
+        return {k: r[k] for k in keys if k in r}
+
+    line = {
+        "metric": METRIC, "value": head["pairs_per_s"], "unit": "pairs/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": head["ms_per_step"], "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32+f64", "data": "synthetic",
+        "config": {"workload": head["workload"], "workload_id": head["workload_id"],
+                   "candidate_pairs": head["candidate_pairs"], "intersecting_pairs": head["intersecting_pairs"],
+                   "bvh_width": head["bvh_width"], "leaf_size": head["leaf_size"],
+                   "schedule": head["schedule_name"], "precision": head["precision"],
+                   "refine": "one persistent launch (batched)", "step": head["step"]},
+        "segment_queries_per_s": head["segment_queries_per_s"],
+        "refine_pairs_per_s": head["refine_pairs_per_s"], "refine_ms": head["refine_ms"],
+        "nominal_segments": head["nominal_segments"], "nominal_segment_rate_per_s": head["nominal_segment_rate_per_s"],
+        "build_ms": head["build_ms"],
+        "roofline": head["roofline"], "cpu_baseline": head["cpu_baseline"],
+        "plain_per_pair": head["plain_per_pair"], "precision_comparison": head["precision_comparison"],
+        "autotune": head["autotune"], "stats": head["stats"], "retest_fraction": head["retest_fraction"],
+        "workloads": {k: (brief(v) if k != "c5" else v) for k, v in extras.items()},
+    }
+    if "c5" in extras:
+        line["p50_ms"] = extras["c5"]["p50_ms"]
+        line["p99_ms"] = extras["c5"]["p99_ms"]
     print(json.dumps(line), flush=True)
 
 

@@ -35,13 +35,18 @@ def mesh_boxes(S) -> np.ndarray:
     out[:, 3:] = -np.inf
     verts = np.asarray(S.verts, np.float32).reshape(-1, 3)
     faces = np.asarray(S.faces, np.int64).reshape(-1, 3)
-    for m in range(M):
-        f = faces[S.face_off[m]:S.face_off[m + 1]]
-        if f.shape[0] == 0:
-            continue
-        p = verts[S.vert_off[m] + f.reshape(-1)]
-        out[m, :3] = p.min(axis=0)
-        out[m, 3:] = p.max(axis=0)
+    fo = np.asarray(S.face_off, np.int64)
+    nf = np.diff(fo)
+    if faces.shape[0] == 0:
+        return out
+    # every face's three vertices (global ids: the mesh's vertex offset plus
+    # the face's local ids), then the minimum and maximum over a mesh's faces
+    owner = np.repeat(np.arange(M), nf)
+    p = verts[np.asarray(S.vert_off, np.int64)[owner][:, None] + faces]       # [F, 3 vertices, 3 coords]
+    lo, hi = p.min(axis=1), p.max(axis=1)
+    has = nf > 0
+    out[has, :3] = np.minimum.reduceat(lo, fo[:-1][has], axis=0)
+    out[has, 3:] = np.maximum.reduceat(hi, fo[:-1][has], axis=0)
     return out
 
 
@@ -50,19 +55,26 @@ def candidate_pairs(box_a: np.ndarray, box_b: np.ndarray, query=None) -> np.ndar
     when given) share a point, sorted by (i, j)."""
     box_a = np.asarray(box_a, np.float32).reshape(-1, 6)
     box_b = np.asarray(box_b, np.float32).reshape(-1, 6)
-    lo_b, hi_b = box_b[:, :3], box_b[:, 3:]
+    ia = np.arange(box_a.shape[0])
+    ib = np.arange(box_b.shape[0])
     if query is not None:
+        # a box that misses Q cannot share a point with Q and another box:
+        # such rows and columns are dropped before the pairwise test
         q = np.asarray(query, np.float32).reshape(6)
+        ia = ia[np.all(np.maximum(box_a[:, :3], q[:3]) <= np.minimum(box_a[:, 3:], q[3:]), axis=1)]
+        ib = ib[np.all(np.maximum(box_b[:, :3], q[:3]) <= np.minimum(box_b[:, 3:], q[3:]), axis=1)]
+    lo_b, hi_b = box_b[ib, :3], box_b[ib, 3:]
+    if query is not None:
         lo_b = np.maximum(lo_b, q[None, :3])
         hi_b = np.minimum(hi_b, q[None, 3:])
     out = []
-    rows = max(1, (1 << 22) // max(1, box_b.shape[0]))
-    for i0 in range(0, box_a.shape[0], rows):
-        a = box_a[i0:i0 + rows]
+    rows = max(1, (1 << 22) // max(1, ib.shape[0]))
+    for i0 in range(0, ia.shape[0], rows):
+        a = box_a[ia[i0:i0 + rows]]
         lo = np.maximum(a[:, None, :3], lo_b[None, :, :])
         hi = np.minimum(a[:, None, 3:], hi_b[None, :, :])
         ii, jj = np.nonzero(np.all(lo <= hi, axis=2))
-        out.append(np.stack([ii + i0, jj], 1))
+        out.append(np.stack([ia[ii + i0], ib[jj]], 1))
     if not out:
         return np.zeros((0, 2), np.int64)
     return np.concatenate(out).astype(np.int64)

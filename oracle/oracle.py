@@ -95,8 +95,10 @@ def join(A, B, pairs, mode: int = 1, threads: int = 0, return_tests: bool = Fals
 
     A, B: objects with verts f32[V,3], faces i32[F,3], vert_off i64[M+1],
     face_off i64[M+1].  mode 0 = all triangle pairs, 1 = exact box
-    sweep-and-prune first.  threads 0 = all host cores."""
+    sweep-and-prune first.  threads 0 = default_threads()."""
     lib = _load()
+    if threads <= 0:
+        threads = default_threads()
     pairs = np.ascontiguousarray(np.asarray(pairs, np.int32).reshape(-1, 2))
     flags = np.zeros(pairs.shape[0], np.uint8)
     arrs = []
@@ -125,5 +127,18 @@ def set_limb_budget(limbs: int) -> int:
     return r
 
 
+def default_threads() -> int:
+    """Threads the oracle uses by default: the cores this process may run
+    on, at most 16 (a GPU host's CPU share per GPU), or PIERCE_ORACLE_THREADS."""
+    env = os.environ.get("PIERCE_ORACLE_THREADS")
+    if env:
+        return max(1, int(env))
+    try:
+        n = len(os.sched_getaffinity(0))
+    except AttributeError:
+        n = os.cpu_count() or 1
+    return max(1, min(16, n))
+
+
 def threads_used(threads: int = 0) -> int:
-    return threads if threads > 0 else (os.cpu_count() or 1)
+    return threads if threads > 0 else default_threads()

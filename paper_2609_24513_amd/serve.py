@@ -135,6 +135,8 @@ class JoinServer:
         self.in_flight_bytes = 0
         self.batches = 0
         self.max_in_flight = 0
+        self.oversized = 0      # requests beyond max_pairs, answered on their own
+        self._t0 = None
 
     # --- phases ------------------------------------------------------------
     def _start(self, slot: _Slot, reqs: List[Request]):
@@ -171,7 +173,8 @@ class JoinServer:
             slot.event.record(slot.stream)
 
     def _finish(self, slot: _Slot, now: float):
-        counts = np.minimum(np.maximum(slot.counts_h[:len(slot.reqs)].numpy().astype(np.int64), 0), self.max_pairs)
+        raw = slot.counts_h[:len(slot.reqs)].numpy().astype(np.int64)
+        counts = np.minimum(np.maximum(raw, 0), self.max_pairs)
         offsets = np.concatenate([[0], np.cumsum(counts)])
         n = int(offsets[-1])
         if n and int(slot.status_h.item()) != 0:
@@ -179,14 +182,33 @@ class JoinServer:
         flags = slot.flags[:n].cpu().numpy() if n else np.zeros(0, np.uint8)
         pairs = slot.batch[:n].cpu().numpy() if n else np.zeros((0, 2), np.int32)
         for k, r in enumerate(slot.reqs):
-            a, b = int(offsets[k]), int(offsets[k + 1])
-            r.pairs = pairs[a:b]
-            r.flags = flags[a:b]
-            r.t_done = now
+            if raw[k] > self.max_pairs:
+                # more candidates than a slot region holds: this request's
+                # region was truncated, so it is answered again on its own
+                # with a buffer of the exact size
+                r.pairs, r.flags = self._serve_large(r.box, int(raw[k]))
+                self.oversized += 1
+                r.t_done = time.perf_counter() - self._t0
+            else:
+                a, b = int(offsets[k]), int(offsets[k + 1])
+                r.pairs = pairs[a:b]
+                r.flags = flags[a:b]
+                r.t_done = now
         self.in_flight_bytes -= self.req_bytes * len(slot.reqs)
         slot.reqs = []
         slot.phase = 0
         slot.event = None
+
+    def _serve_large(self, box: np.ndarray, count: int):
+        """A request whose candidate count exceeds max_pairs: filter with a
+        buffer of exactly `count` pairs, then one refinement, synchronously."""
+        pa, torch = self.pa, self.torch
+        pairs = pa.filter_pairs(self.R, self.S, query_box=box, cap=count)
+        flags, _, status = pa.refine(self.R, self.S, pairs, self.cfg)
+        torch.cuda.synchronize()
+        if int(status.item()) != 0:
+            raise RuntimeError("refine status %d" % int(status.item()))
+        return pairs.cpu().numpy(), flags.cpu().numpy()
 
     # --- loop ----------------------------------------------------------------
     def run(self, trace: Sequence[Request], realtime: bool = True) -> List[Request]:
@@ -195,6 +217,7 @@ class JoinServer:
         pending = deque()
         todo = deque(sorted(trace, key=lambda r: r.t_arrival))
         t0 = time.perf_counter()
+        self._t0 = t0
         done = 0
         n = len(todo)
         while done < n:
@@ -233,7 +256,8 @@ class JoinServer:
         return list(trace)
 
     def query_alone(self, box: np.ndarray):
-        """One request on its own (filter, then refine): (pairs, flags)."""
+        """One request on its own (filter with relaunch on overflow, then
+        refine): (pairs, flags)."""
         pa, torch = self.pa, self.torch
         pairs = pa.filter_pairs(self.R, self.S, query_box=box, cap=self.max_pairs)
         if pairs.shape[0] == 0:

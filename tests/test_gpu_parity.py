@@ -8,6 +8,7 @@ coordinates outside the FP32-safe range, and argument/geometry errors.
 """
 import json
 import os
+import sys
 
 import numpy as np
 import pytest
@@ -343,12 +344,24 @@ def test_c2_full_size_against_oracle(env):
     assert int((flags.cpu().numpy() != want).sum()) == 0
 
 
+def _c3_expected(A, B, pairs):
+    """The oracle's flags for the full batching workload, stored by
+    tests/golden/make_expected_flags.py (which calls only the oracle); the
+    input digest must match the inputs generated here."""
+    sys.path.insert(0, os.path.join(HERE, "golden"))
+    import make_expected_flags as mef
+    digest, want = mef.load()
+    assert digest == mef.input_digest(A, B, pairs), "inputs changed: rerun tests/golden/make_expected_flags.py"
+    return want
+
+
 def test_c3_full_size_against_oracle(env):
     """The batching workload at full size (50,000 pairs, faces up to 100,000
-    per mesh), one persistent launch: every pair checked."""
+    per mesh), one persistent launch per schedule: every pair checked."""
     torch, pa, synth, oracle = env
     A, B, pairs = synth.make_c3()
-    want = oracle.join(A, B, pairs, mode=1)
+    want = _c3_expected(A, B, pairs)
+    assert want.shape[0] == 50_000 and 0 < want.sum() < 50_000
     for sc in (3, 1):
         got, st = _run(env, A, B, pairs, persistent=1, schedule=sc)
         assert int((got != want).sum()) == 0, sc
