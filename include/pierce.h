@@ -14,9 +14,11 @@
  *  - Pointers documented "dev" are device pointers (HIP global memory) owned
  *    by the caller; "host" pointers are ordinary host memory.  The library
  *    never allocates or frees memory in these calls; scratch space comes
- *    from the caller's workspace `ws`.  The only state kept between calls is
- *    a per-device cache of launch figures (compute-unit count, resident
- *    blocks per compute unit of each persistent kernel), filled on first use.
+ *    from the caller's workspace `ws` (refine_intersects_static: from a
+ *    static device buffer of the library).  The only state kept between
+ *    calls is a per-device cache of launch figures (compute-unit count,
+ *    resident blocks per compute unit of each persistent kernel) and of the
+ *    static buffer's address, filled on first use.
  *  - Work is enqueued on `stream` (a hipStream_t passed as void*); nothing
  *    synchronises the host.  Results are valid once the stream has reached
  *    the end of the call.
@@ -40,7 +42,7 @@
 extern "C" {
 #endif
 
-#define PR_ABI_VERSION 4
+#define PR_ABI_VERSION 5
 
 enum {
   PR_OK = 0,
@@ -223,6 +225,31 @@ int refine_intersects(const void* blob_a, int64_t n_meshes_a, const void* blob_b
                       int64_t n_meshes_b, const int32_t* pairs, int64_t n_pairs, uint8_t* flags,
                       const pr_refine_params* params, pr_refine_stats* dev_stats,
                       int32_t* dev_status, void* ws, size_t ws_bytes, void* stream);
+
+/* ------------------------------------------------------------------------ */
+/* Allocation-free refinement, for callers that cannot allocate device memory
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): refine_intersects without a workspace argument.
+ *
+ * Scratch space comes from a static device buffer inside the library, one
+ * copy per GPU, of refine_static_scratch_bytes() bytes (64 MiB), held until
+ * the process ends.  With queue_cap / survivor_cap 0 the queues default to
+ * 2^18 deferred tests and 2^21 surviving groups (overflow falls back to the
+ * exact rerun, as with refine_intersects); n_pairs is limited by what fits:
+ * a call that would need more scratch returns PR_E_CAPACITY (message in
+ * pr_last_error) before enqueuing anything.  The first call on a GPU looks up
+ * that GPU's copy of the buffer (with the caller's current device current).
+ * Every call on a GPU uses that GPU's single buffer: calls that overlap on
+ * one GPU (several streams, several host threads) race and give undefined
+ * results, so the caller serialises them.  Each call clears, with a kernel,
+ * every counter and state that must start at zero; the buffer keeps the
+ * last call's contents otherwise.  Nothing is allocated or freed.  The other
+ * arguments and the results are those of refine_intersects. */
+size_t refine_static_scratch_bytes(void);
+int refine_intersects_static(const void* blob_a, int64_t n_meshes_a, const void* blob_b,
+                             int64_t n_meshes_b, const int32_t* pairs, int64_t n_pairs,
+                             uint8_t* flags, const pr_refine_params* params,
+                             pr_refine_stats* dev_stats, int32_t* dev_status, void* stream);
 
 /* ------------------------------------------------------------------------ */
 /* Result materialisation (Section 3.5): keeps the pairs whose flag is 1, in

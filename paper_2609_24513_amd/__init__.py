@@ -20,8 +20,8 @@ import numpy as np
 from . import _lib
 from ._lib import PierceError, RefineStats, STATS_FIELDS  # noqa: F401
 
-__all__ = ["MeshBlob", "filter_pairs", "refine", "compact", "gather_regions", "refine_workspace", "PierceError",
-           "RefineConfig"]
+__all__ = ["MeshBlob", "filter_pairs", "refine", "refine_static", "compact", "gather_regions", "refine_workspace",
+           "PierceError", "RefineConfig"]
 
 
 def _torch():
@@ -212,6 +212,30 @@ def refine(A: MeshBlob, B: MeshBlob, pairs, cfg: Optional[RefineConfig] = None, 
                                              flags.data_ptr(), ctypes.byref(prm), stats.data_ptr(),
                                              status.data_ptr(), ws.data_ptr(), ws.numel(),
                                              _stream_ptr(stream)))
+    return flags[:P], stats, status
+
+
+def refine_static(A: MeshBlob, B: MeshBlob, pairs, cfg: Optional[RefineConfig] = None, stream=None,
+                  flags=None, stats=None, status=None) -> Tuple[object, object, object]:
+    """refine_intersects_static: as refine(), with the library's static scratch
+    buffer instead of a workspace (nothing is allocated by the library).  Calls
+    that overlap on one GPU race: the caller serialises them."""
+    torch = _torch()
+    cfg = cfg or RefineConfig()
+    if A.width != B.width:
+        raise ValueError("blobs built with different widths")
+    pairs = _dev(pairs, torch.int32).reshape(-1, 2)
+    P = int(pairs.shape[0])
+    prm = cfg.params(A.width)
+    if flags is None:
+        flags = torch.empty(max(P, 1), dtype=torch.uint8, device="cuda")
+    if stats is None:
+        stats = torch.zeros(len(STATS_FIELDS), dtype=torch.int64, device="cuda")
+    if status is None:
+        status = torch.zeros(1, dtype=torch.int32, device="cuda")
+    _lib.check(_lib.load().refine_intersects_static(A.ptr, A.n_meshes, B.ptr, B.n_meshes, pairs.data_ptr(), P,
+                                                    flags.data_ptr(), ctypes.byref(prm), stats.data_ptr(),
+                                                    status.data_ptr(), _stream_ptr(stream)))
     return flags[:P], stats, status
 
 

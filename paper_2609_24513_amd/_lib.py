@@ -18,12 +18,13 @@ PR_E_CAPACITY = -2
 PR_E_GEOMETRY = -3
 PR_E_DEVICE = -4
 PR_E_UNSUPPORTED = -5
-ABI_VERSION = 4
+ABI_VERSION = 5
 
 EXPORTS = [
     "pr_last_error", "pr_abi_version", "build_mesh_bvh_sizes", "build_mesh_bvh", "blob_mesh_boxes",
     "blob_edge_counts", "filter_aabb_pairs_ws_bytes", "filter_aabb_pairs", "refine_workspace_bytes",
     "refine_intersects", "compact_pairs_ws_bytes", "compact_pairs", "gather_pair_regions",
+    "refine_static_scratch_bytes", "refine_intersects_static",
 ]
 
 
@@ -94,8 +95,12 @@ def load():
         lib.compact_pairs_ws_bytes.argtypes = [i64, szp]
         lib.compact_pairs.argtypes = [vp, vp, i64, vp, vp, i64, vp, vp, ctypes.c_size_t, vp]
         lib.gather_pair_regions.argtypes = [vp, i64, vp, i64, vp, i64, vp, vp]
+        lib.refine_intersects_static.argtypes = [vp, i64, vp, i64, vp, i64, vp, ctypes.POINTER(RefineParams),
+                                                 vp, vp, vp]
+        lib.refine_static_scratch_bytes.argtypes = []
         for name in EXPORTS[2:]:
             getattr(lib, name).restype = ctypes.c_int
+        lib.refine_static_scratch_bytes.restype = ctypes.c_size_t
         if lib.pr_abi_version() != ABI_VERSION:
             raise RuntimeError("libpierce_hip.so ABI %d != %d" % (lib.pr_abi_version(), ABI_VERSION))
         _lib = lib

@@ -28,6 +28,7 @@
 
 #include <atomic>
 #include <climits>
+#include <mutex>
 
 #include "common.h"
 #include "predicates.h"
@@ -577,8 +578,10 @@ __global__ void k_init(RefineArgs ra) {
   if (i < kQueues) {
     ra.surv_cnt[kCtrStride * i] = 0ull;
     ra.surv_pop[kCtrStride * i] = 0ull;
-    ra.task_cnt[kCtrStride * i] = 0ull;
-    ra.task_pop[kCtrStride * i] = 0ull;
+    if (ra.task_cnt) {
+      ra.task_cnt[kCtrStride * i] = 0ull;
+      ra.task_pop[kCtrStride * i] = 0ull;
+    }
   }
   if (i == 0) {
     *ra.fin_done = 0u;
@@ -1450,7 +1453,7 @@ struct WsLayout {
   size_t scan_bytes;
 };
 
-int carve(Carve& cv, RefineArgs& ra, int64_t P, uint32_t qcap, uint32_t surv_cap, void** scan_tmp,
+int carve(Carve& cv, RefineArgs& ra, int64_t P, uint32_t qcap, uint32_t surv_cap, bool with_tasks, void** scan_tmp,
           size_t* scan_bytes) {
   ra.state = cv.take<uint32_t>(P);
   ra.unit_cnt = cv.take<int64_t>(2 * P + 1);
@@ -1464,11 +1467,13 @@ int carve(Carve& cv, RefineArgs& ra, int64_t P, uint32_t qcap, uint32_t surv_cap
   ra.surv_cnt = cv.take<unsigned long long>(kQueues * kCtrStride);
   ra.surv_pop = cv.take<unsigned long long>(kQueues * kCtrStride);
   ra.surv = cv.take<int4>((int64_t)kQueues * surv_cap);
-  ra.task_cap = kTaskCap;
-  ra.tasks = cv.take<int4>((int64_t)kQueues * kTaskCap);
-  ra.tmask = cv.take<uint64_t>((int64_t)kQueues * kTaskCap);
-  ra.task_cnt = cv.take<unsigned long long>(kQueues * kCtrStride);
-  ra.task_pop = cv.take<unsigned long long>(kQueues * kCtrStride);
+  if (with_tasks) {  // continuation task lists: only with a step budget
+    ra.task_cap = kTaskCap;
+    ra.tasks = cv.take<int4>((int64_t)kQueues * kTaskCap);
+    ra.tmask = cv.take<uint64_t>((int64_t)kQueues * kTaskCap);
+    ra.task_cnt = cv.take<unsigned long long>(kQueues * kCtrStride);
+    ra.task_pop = cv.take<unsigned long long>(kQueues * kCtrStride);
+  }
   size_t b = 0;
   hipError_t e = hipcub::DeviceScan::ExclusiveSum(nullptr, b, (int64_t*)nullptr, (int64_t*)nullptr, (int)(2 * P + 1));
   if (e != hipSuccess) return hip_fail(e, "hipcub scan size");
@@ -1491,11 +1496,19 @@ int check(int64_t P, const pr_refine_params* p) {
   return PR_OK;
 }
 
-uint32_t qcap_of(const pr_refine_params* p) { return p->queue_cap > 0 ? (uint32_t)p->queue_cap : (1u << 20); }
-uint32_t scap_of(const pr_refine_params* p) {
-  const uint32_t total = p->survivor_cap > 0 ? (uint32_t)p->survivor_cap : (1u << 24);
+uint32_t qcap_of(const pr_refine_params* p, uint32_t dflt) { return p->queue_cap > 0 ? (uint32_t)p->queue_cap : dflt; }
+uint32_t scap_of(const pr_refine_params* p, uint32_t dflt) {
+  const uint32_t total = p->survivor_cap > 0 ? (uint32_t)p->survivor_cap : dflt;
   return (total + kQueues - 1) / kQueues;
 }
+int budget_of(const pr_refine_params* p) {
+  return p->trace_budget == 0 ? kBudget : (p->trace_budget < 0 ? 0 : p->trace_budget);
+}
+
+// Default capacities of the deferred-test and surviving-group queues: with a
+// caller workspace, and with the library's static scratch buffer.
+constexpr uint32_t kQcapDefault = 1u << 20, kScapDefault = 1u << 24;
+constexpr uint32_t kQcapStatic = 1u << 18, kScapStatic = 1u << 21;
 
 // Launches a kernel whose one argument is the RefineArgs.  The optional
 // events take the dispatch's own start and end time stamps, so that timing
@@ -1572,43 +1585,30 @@ int launch(RefineArgs& ra, const pr_refine_params* prm, void* scan_tmp, size_t s
   return PR_OK;
 }
 
-}  // namespace
-}  // namespace pr
-
-using namespace pr;
-
-extern "C" int refine_workspace_bytes(int64_t n_pairs, const pr_refine_params* params, size_t* ws_bytes) {
-  int r = check(n_pairs, params);
-  if (r) return r;
-  if (!ws_bytes) { set_error("ws_bytes is NULL"); return PR_E_ARG; }
+// Workspace bytes of a refinement of P pairs with the given queue defaults.
+int ws_needed(int64_t P, const pr_refine_params* params, uint32_t qdef, uint32_t sdef, size_t* bytes) {
   Carve cv{nullptr, 0};
   RefineArgs ra{};
   void* t;
   size_t b;
-  r = carve(cv, ra, n_pairs, qcap_of(params), scap_of(params), &t, &b);
+  int r = carve(cv, ra, P, qcap_of(params, qdef), scap_of(params, sdef), budget_of(params) > 0, &t, &b);
   if (r) return r;
-  *ws_bytes = cv.used + 256;
+  *bytes = cv.used + 256;
   return PR_OK;
 }
 
-extern "C" int refine_intersects(const void* blob_a, int64_t n_meshes_a, const void* blob_b, int64_t n_meshes_b,
-                                 const int32_t* pairs, int64_t n_pairs, uint8_t* flags,
-                                 const pr_refine_params* params, pr_refine_stats* dev_stats, int32_t* dev_status,
-                                 void* ws, size_t ws_bytes, void* stream) {
-  int r = check(n_pairs, params);
-  if (r) return r;
-  if (!blob_a || !blob_b || !ws || (n_pairs > 0 && (!pairs || !flags)) || n_meshes_a < 0 || n_meshes_b < 0) {
-    set_error("null pointer or negative size");
-    return PR_E_ARG;
-  }
-  hipStream_t s = (hipStream_t)stream;
+int refine_run(const void* blob_a, int64_t n_meshes_a, const void* blob_b, int64_t n_meshes_b,
+               const int32_t* pairs, int64_t n_pairs, uint8_t* flags, const pr_refine_params* params,
+               pr_refine_stats* dev_stats, int32_t* dev_status, void* ws, size_t ws_bytes, uint32_t qdef,
+               uint32_t sdef, hipStream_t s) {
   RefineArgs ra{};
   Carve cv{(char*)ws, ws_bytes};
   void* scan_tmp = nullptr;
   size_t scan_bytes = 0;
-  const uint32_t qcap = qcap_of(params);
-  const uint32_t scap = scap_of(params);
-  r = carve(cv, ra, n_pairs, qcap, scap, &scan_tmp, &scan_bytes);
+  const uint32_t qcap = qcap_of(params, qdef);
+  const uint32_t scap = scap_of(params, sdef);
+  const int budget = budget_of(params);
+  int r = carve(cv, ra, n_pairs, qcap, scap, budget > 0, &scan_tmp, &scan_bytes);
   if (r) return r;
   if (cv.used > ws_bytes || !scan_tmp) { set_error("ws_bytes %zu < required %zu", ws_bytes, cv.used); return PR_E_CAPACITY; }
   ra.blob_a = (const char*)blob_a;
@@ -1622,8 +1622,8 @@ extern "C" int refine_intersects(const void* blob_a, int64_t n_meshes_a, const v
   ra.qcap = qcap;
   ra.surv_cap = scap;
   ra.item_groups = params->chunks_per_pop > 0 ? params->chunks_per_pop : 256;
-  ra.budget = params->trace_budget == 0 ? kBudget : (params->trace_budget < 0 ? 0 : params->trace_budget);
-  ra.share = params->trace_budget == 0 && ra.budget == 0 ? 1 : 0;
+  ra.budget = budget;
+  ra.share = params->trace_budget == 0 && budget == 0 ? 1 : 0;
   if (ra.item_groups > kMaxItemGroups) ra.item_groups = kMaxItemGroups;
   hipLaunchKernelGGL(k_init, dim3(grid_for(n_pairs > kStatCopies * S_N ? n_pairs : kStatCopies * S_N, kBlock)),
                      dim3(kBlock), 0, s, ra);
@@ -1635,10 +1635,9 @@ extern "C" int refine_intersects(const void* blob_a, int64_t n_meshes_a, const v
     PR_LAUNCH(8, 0); PR_LAUNCH(8, 1); PR_LAUNCH(8, 2);
 #undef PR_LAUNCH
     if (r) return r;
-    const int W2 = params->bvh_width;
     const int fb = 1024;  // enough threads for the deferred tests, blocks for the reruns
-    if (W2 == 2) hipLaunchKernelGGL(k_fix<2>, dim3(fb), dim3(kBlock), 0, s, ra);
-    else if (W2 == 4) hipLaunchKernelGGL(k_fix<4>, dim3(fb), dim3(kBlock), 0, s, ra);
+    if (W == 2) hipLaunchKernelGGL(k_fix<2>, dim3(fb), dim3(kBlock), 0, s, ra);
+    else if (W == 4) hipLaunchKernelGGL(k_fix<4>, dim3(fb), dim3(kBlock), 0, s, ra);
     else hipLaunchKernelGGL(k_fix<8>, dim3(fb), dim3(kBlock), 0, s, ra);
     hipLaunchKernelGGL(k_finalize, dim3(grid_for(n_pairs, kBlock)), dim3(kBlock), 0, s, ra, dev_stats, dev_status);
   } else {
@@ -1646,4 +1645,93 @@ extern "C" int refine_intersects(const void* blob_a, int64_t n_meshes_a, const v
   }
   PR_HIP(hipGetLastError());
   return PR_OK;
+}
+
+int check_refine_args(const void* blob_a, const void* blob_b, const int32_t* pairs, int64_t n_pairs,
+                      const uint8_t* flags, int64_t n_meshes_a, int64_t n_meshes_b) {
+  if (!blob_a || !blob_b || (n_pairs > 0 && (!pairs || !flags)) || n_meshes_a < 0 || n_meshes_b < 0) {
+    set_error("null pointer or negative size");
+    return PR_E_ARG;
+  }
+  return PR_OK;
+}
+
+// ---- allocation-free variant: the library's own static scratch buffer ----------
+
+// Device scratch for refine_intersects_static: one copy per GPU, held until
+// the process ends.  Host code never uses this name as an address; it uses
+// the per-device address from hipGetSymbolAddress.
+constexpr size_t kStaticScratchBytes = (size_t)64 << 20;
+static __device__ __align__(256) char scratch[kStaticScratchBytes];
+
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[64] = {};
+
+// Address of this GPU's copy of `scratch`, looked up once per device with
+// that device current (the caller's current device).
+int static_scratch(void** out) {
+  int dev = 0;
+  PR_HIP(hipGetDevice(&dev));
+  if (dev < 0 || dev >= 64) { set_error("device index %d beyond 63", dev); return PR_E_UNSUPPORTED; }
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return hip_fail(e, "hipGetSymbolAddress(scratch)");
+    if (!p) { set_error("hipGetSymbolAddress(scratch) returned NULL"); return PR_E_DEVICE; }
+    g_scratch_ptr[dev] = p;
+  }
+  *out = g_scratch_ptr[dev];
+  return PR_OK;
+}
+
+}  // namespace
+}  // namespace pr
+
+using namespace pr;
+
+extern "C" int refine_workspace_bytes(int64_t n_pairs, const pr_refine_params* params, size_t* ws_bytes) {
+  int r = check(n_pairs, params);
+  if (r) return r;
+  if (!ws_bytes) { set_error("ws_bytes is NULL"); return PR_E_ARG; }
+  return ws_needed(n_pairs, params, kQcapDefault, kScapDefault, ws_bytes);
+}
+
+extern "C" int refine_intersects(const void* blob_a, int64_t n_meshes_a, const void* blob_b, int64_t n_meshes_b,
+                                 const int32_t* pairs, int64_t n_pairs, uint8_t* flags,
+                                 const pr_refine_params* params, pr_refine_stats* dev_stats, int32_t* dev_status,
+                                 void* ws, size_t ws_bytes, void* stream) {
+  int r = check(n_pairs, params);
+  if (r) return r;
+  r = check_refine_args(blob_a, blob_b, pairs, n_pairs, flags, n_meshes_a, n_meshes_b);
+  if (r) return r;
+  if (!ws) { set_error("ws is NULL"); return PR_E_ARG; }
+  return refine_run(blob_a, n_meshes_a, blob_b, n_meshes_b, pairs, n_pairs, flags, params, dev_stats, dev_status, ws,
+                    ws_bytes, kQcapDefault, kScapDefault, (hipStream_t)stream);
+}
+
+extern "C" size_t refine_static_scratch_bytes(void) { return kStaticScratchBytes; }
+
+extern "C" int refine_intersects_static(const void* blob_a, int64_t n_meshes_a, const void* blob_b,
+                                        int64_t n_meshes_b, const int32_t* pairs, int64_t n_pairs, uint8_t* flags,
+                                        const pr_refine_params* params, pr_refine_stats* dev_stats,
+                                        int32_t* dev_status, void* stream) {
+  int r = check(n_pairs, params);
+  if (r) return r;
+  r = check_refine_args(blob_a, blob_b, pairs, n_pairs, flags, n_meshes_a, n_meshes_b);
+  if (r) return r;
+  size_t need = 0;
+  r = ws_needed(n_pairs, params, kQcapStatic, kScapStatic, &need);
+  if (r) return r;
+  if (need > kStaticScratchBytes) {
+    set_error("refine_intersects_static: %lld pairs with these queue capacities need %zu bytes of scratch; the "
+              "static buffer holds %zu (use refine_intersects with a workspace)",
+              (long long)n_pairs, need, kStaticScratchBytes);
+    return PR_E_CAPACITY;
+  }
+  void* ws = nullptr;
+  r = static_scratch(&ws);
+  if (r) return r;
+  return refine_run(blob_a, n_meshes_a, blob_b, n_meshes_b, pairs, n_pairs, flags, params, dev_stats, dev_status, ws,
+                    kStaticScratchBytes, kQcapStatic, kScapStatic, (hipStream_t)stream);
 }
