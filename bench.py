@@ -207,7 +207,7 @@ def run_join(name: str, args, tune: bool, plain: bool, compare_precision: bool, 
     gen_s = time.perf_counter() - t
     log("%s: generated in %.1f s: %d+%d meshes, %d+%d triangles" % (
         name, gen_s, A.n_meshes, B.n_meshes, A.faces.shape[0], B.faces.shape[0]))
-    W, L, sched = args.width, args.leaf, args.schedule
+    W, L, sched, table = args.width, args.leaf, args.schedule, 0
     tuned = None
     if tune:
         from paper_2609_24513_amd import autotune
@@ -218,8 +218,9 @@ def run_join(name: str, args, tune: bool, plain: bool, compare_precision: bool, 
             del g4a, g4b
         tuned = autotune.tune(A, B, pairs_for_tune, log=log)
         W, L, sched = tuned["best"]["width"], tuned["best"]["leaf_size"], tuned["best"]["schedule"]
-        log("%s: autotune picked W=%d L=%d schedule=%d (%.1f s, cached=%s)" % (
-            name, W, L, sched, tuned["tune_seconds"], tuned["cached"]))
+        table = tuned["best"].get("seg_live_max", 0)
+        log("%s: autotune picked W=%d L=%d schedule=%d table=%08x (%.1f s, cached=%s)" % (
+            name, W, L, sched, table, tuned["tune_seconds"], tuned["cached"]))
         tuned = {k: tuned[k] for k in ("best", "per_bucket", "sample", "tune_seconds", "cached")}
 
     ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -238,7 +239,8 @@ def run_join(name: str, args, tune: bool, plain: bool, compare_precision: bool, 
     P = int(first.shape[0])
     kern_events = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
                    for _ in range(steps)]
-    base_cfg = dict(persistent=1, precision=args.precision, schedule=sched, trace_budget=args.trace_budget)
+    base_cfg = dict(persistent=1, precision=args.precision, schedule=sched, seg_live_max=table,
+                    trace_budget=args.trace_budget)
     ws = pa.refine_workspace(P, W, pa.RefineConfig(**base_cfg))
     flags = torch.empty(P, dtype=torch.uint8, device="cuda")
     stats = torch.zeros(len(pa.STATS_FIELDS), dtype=torch.int64, device="cuda")
@@ -309,7 +311,8 @@ def run_join(name: str, args, tune: bool, plain: bool, compare_precision: bool, 
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         k0, k1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         fl = torch.empty(P, dtype=torch.uint8, device="cuda")
-        cfg = pa.RefineConfig(persistent=persistent, precision=precision, schedule=sched, ev_begin=k0, ev_end=k1)
+        cfg = pa.RefineConfig(persistent=persistent, precision=precision, schedule=sched, seg_live_max=table,
+                              ev_begin=k0, ev_end=k1)
         w_ = pa.refine_workspace(P, W, cfg)
         pa.refine(ga, gb, first, cfg, ws=w_, flags=fl)  # warm
         torch.cuda.synchronize()
@@ -356,6 +359,7 @@ def run_join(name: str, args, tune: bool, plain: bool, compare_precision: bool, 
     out = {
         "workload": DESCS[name], "workload_id": name, "candidate_pairs": P, "intersecting_pairs": n_true,
         "bvh_width": W, "leaf_size": L, "schedule": sched, "schedule_name": SCHEDULE_NAMES.get(sched, str(sched)),
+        "seg_live_max": table,
         "precision": ["fp32 filter + fp64/exact fallback", "fp64/exact", "forced deferral"][args.precision],
         "step": ("filter + refine + compact" if given is None else "refine + compact (pairs given)"),
         "ms_per_step": ms_step, "pairs_per_s": P / (ms_step * 1e-3),

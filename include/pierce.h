@@ -42,7 +42,7 @@
 extern "C" {
 #endif
 
-#define PR_ABI_VERSION 5
+#define PR_ABI_VERSION 6
 
 enum {
   PR_OK = 0,
@@ -84,6 +84,11 @@ typedef struct {
 int build_mesh_bvh_sizes(int64_t n_meshes, int64_t f_total, int64_t v_total,
                          const pr_bvh_params* params, size_t* blob_bytes, size_t* ws_bytes);
 
+/* The blob bound alone: bytes of the blob of such a dataset (an upper
+ * bound), or 0 when the arguments are rejected (pr_last_error says why). */
+size_t build_mesh_bvh_bytes(int64_t n_meshes, int64_t f_total, int64_t v_total,
+                            const pr_bvh_params* params);
+
 /* Builds the blob of a dataset.
  *  verts     dev f32[v_total][3]    vertex coordinates
  *  vert_off  dev i64[n_meshes+1]    mesh m owns verts[vert_off[m] .. vert_off[m+1])
@@ -112,6 +117,14 @@ int blob_mesh_boxes(const void* blob, int64_t n_meshes, float* boxes, void* stre
 
 /* Copies each mesh's unique-edge count out of a blob: counts dev i32[n_meshes]. */
 int blob_edge_counts(const void* blob, int64_t n_meshes, int32_t* counts, void* stream);
+
+/* Copies the exponent range of the blob's coordinates: exps dev i32[2] =
+ * (lowest exponent of a set bit, highest exponent of a set bit) over every
+ * non-zero coordinate of every face; (INT32_MAX, INT32_MIN) when there is
+ * none.  Two blobs whose joint range spans at most 14 (highest - lowest)
+ * lie on one small power-of-two grid: refinement precision 3 then decides
+ * every test the FP32 filter leaves open exactly, in place. */
+int blob_coord_exponents(const void* blob, int32_t* exps, void* stream);
 
 /* ------------------------------------------------------------------------ */
 /* Candidate filter (the classic filter step that the paper's single traversal
@@ -147,31 +160,47 @@ int filter_aabb_pairs(const void* blob_a, int64_t n_meshes_a, const void* blob_b
  */
 typedef struct {
   int32_t bvh_width;   /* width the blobs were built with (2, 4 or 8) */
-  int32_t persistent;  /* 1: one persistent launch over all pairs (batched);
-                          0: one launch per pair (plain) */
-  int32_t precision;   /* 0: FP32 filter, uncertain tests re-decided in FP64/exact
+  int32_t persistent;  /* 1: one persistent pass over all pairs (batched): the groups of
+                          segments of every (pair, direction) are culled against the top
+                          of the target tree and the survivors traced by persistent waves;
+                          0: one launch per pair (plain), wave-per-pair packets */
+  int32_t precision;   /* 0: FP32 filter, uncertain tests deferred and re-decided in
+                             FP64/exact after the traversal
                           1: every leaf test decided in FP64/exact directly
-                          2: every leaf test deferred to the FP64/exact pass (test mode) */
-  int32_t queue_cap;   /* capacity of the deferred-test queue (0 = default 1<<20); a
-                          pair whose tests overflow it is traced again with every leaf
-                          test decided in FP64/exact */
-  int32_t grid_blocks; /* persistent launch: blocks of 256 threads (0 = default) */
-  int32_t chunks_per_pop; /* persistent launch: 64-segment groups per work item
-                             (0 = default 256; at most 1024) */
-  int32_t schedule;    /* persistent launch: 0 = default (3); 1 = the four waves of a
-                          block share one work item (they cull its groups and drain the
-                          survivors together); 2 = each wave owns one work item;
-                          3 = two phases: every work item's groups are culled and the
-                          surviving groups queued, then waves pop single groups */
-  int32_t survivor_cap; /* schedule 3: total capacity of the surviving-group queues, 16 bytes
-                          per entry (0 = default 1<<24); a group beyond it sends its pair to the rerun
-                          pass (every group of the pair traced again, leaf tests in
-                          FP64/exact) */
-  void* ev_begin;      /* optional hipEvent_t (or NULL) for timing the traversal kernel(s)
+                          2: every leaf test deferred to the FP64/exact pass (test mode)
+                          3: as 0, but a test the FP32 filter leaves open is first decided
+                             exactly in place when its five points lie on one small
+                             power-of-two grid (coordinate bit span <= 14; see
+                             blob_coord_exponents), so a pair whose only contacts are
+                             exact touches still ends early; other tests are deferred */
+  int32_t queue_cap;   /* capacity of the deferred-test queues (0 = default 1<<20, split
+                          over 8 queues); a pair whose tests overflow them is traced
+                          again with every leaf test decided in FP64/exact */
+  int32_t grid_blocks; /* persistent launch: blocks of 256 threads of the tracing kernel
+                          (0 = default: every block the GPU holds at once) */
+  uint32_t seg_live_max; /* schedule 0: per target-size bucket (byte k: targets below
+                          2^10, 2^13, 2^16 triangles, and larger), the largest number
+                          of a group's segments meeting the target box for which the
+                          group is traced wave-per-segment (the autotuner's table);
+                          0 = every group wave-per-pair (measured best on the
+                          workloads here) */
+  int32_t schedule;    /* persistent launch (Section 3.2, edges traced in parallel):
+                          0 = auto: per group, by the seg_live_max table (0: as 1);
+                          1 = wave-per-pair: a wave traces 64 segments of one
+                              (pair, direction) together, one per lane, walking the
+                              target tree as one packet;
+                          2 = wave-per-segment: the lanes of a wave are W children x
+                              64/W segments, each segment walking its own path with its
+                              own stack in LDS */
+  int32_t survivor_cap; /* total capacity of the surviving-group queues, 16 bytes per
+                          entry (0 = default 1<<24); a group beyond it sends its pair to
+                          the rerun pass (every group of the pair traced again, leaf
+                          tests in FP64/exact) */
+  void* ev_begin;      /* optional hipEvent_t (or NULL) for timing the traversal kernels
                           alone: with persistent = 1 it takes the start time stamp of the
-                          first traversal dispatch on `stream` (attached to the dispatch,
-                          no extra packet); with persistent = 0 it is recorded on `stream`
-                          just before the per-pair launches */
+                          cull dispatch on `stream` (attached to the dispatch, no extra
+                          packet); with persistent = 0 it is recorded on `stream` just
+                          before the per-pair launches */
   void* ev_end;        /* optional hipEvent_t (or NULL): the end time stamp of the last
                           traversal dispatch (persistent = 1), or recorded just after the
                           launches (persistent = 0) */
@@ -180,13 +209,15 @@ typedef struct {
                           by filter_aabb_pairs feeds the refinement without a host round
                           trip; n_pairs is then the capacity of pairs[] and flags[] (it
                           sizes the workspace), and flags past the count are not written */
-  int32_t trace_budget; /* schedule 3: 0 = default: a wave whose queues are drained takes
+  int32_t trace_budget; /* persistent: 0 = default: a wave whose queues are drained takes
                           pending stack entries (subtrees) that the other waves of its
                           block hand over on seeing it wait; > 0: instead, a group still
                           running after that many traversal steps hands its pending
                           entries to a continuation pass spread over all waves; -1 = no
                           hand-over of either kind */
-  int32_t reserved;
+  int32_t lds_stack;   /* persistent: 0 = the packet traversal keeps its first 64 stack
+                          entries in VGPR lanes and the rest in LDS; 1 = the whole stack
+                          in LDS (no hand-over of stack entries then) */
 } pr_refine_params;
 
 typedef struct {

@@ -21,7 +21,7 @@ from . import _lib
 from ._lib import PierceError, RefineStats, STATS_FIELDS  # noqa: F401
 
 __all__ = ["MeshBlob", "filter_pairs", "refine", "refine_static", "compact", "gather_regions", "refine_workspace",
-           "PierceError", "RefineConfig"]
+           "PierceError", "RefineConfig", "SCHEDULES", "small_grid"]
 
 
 def _torch():
@@ -52,12 +52,14 @@ def _ws(nbytes: int):
 class MeshBlob:
     """A dataset's device-resident BVH blob (build_mesh_bvh)."""
 
-    def __init__(self, blob, n_meshes: int, width: int, leaf_size: int, status):
+    def __init__(self, blob, n_meshes: int, width: int, leaf_size: int, status, exps=None):
         self.blob = blob
         self.n_meshes = int(n_meshes)
         self.width = int(width)
         self.leaf_size = int(leaf_size)
         self._status = status
+        self._exps = exps          # device i32[2]: coordinate bit-exponent range
+        self._exp_range = None
 
     @property
     def ptr(self) -> int:
@@ -83,7 +85,9 @@ class MeshBlob:
         _lib.check(lib.build_mesh_bvh(verts.data_ptr(), vo.data_ptr(), faces.data_ptr(), fo.data_ptr(),
                                       M, V, F, ctypes.byref(prm), blob.data_ptr(), bb.value,
                                       ws.data_ptr(), wb.value, status.data_ptr(), _stream_ptr(stream)))
-        out = cls(blob, M, width, leaf_size, status)
+        exps = torch.empty(2, dtype=torch.int32, device="cuda")
+        _lib.check(lib.blob_coord_exponents(blob.data_ptr(), exps.data_ptr(), _stream_ptr(stream)))
+        out = cls(blob, M, width, leaf_size, status, exps)
         if check_status:
             st = int(status.item())
             if st != -1:
@@ -93,6 +97,14 @@ class MeshBlob:
 
     def status(self) -> int:
         return int(self._status.item())
+
+    def exp_range(self):
+        """(lowest, highest) exponent of a set bit over the blob's coordinates
+        (read once from the device)."""
+        if self._exp_range is None:
+            lo, hi = (int(x) for x in self._exps.cpu().tolist())
+            self._exp_range = (lo, hi)
+        return self._exp_range
 
     def boxes(self, stream=None):
         torch = _torch()
@@ -140,10 +152,19 @@ def filter_pairs(A: MeshBlob, B: MeshBlob, query_box=None, cap: Optional[int] = 
     raise RuntimeError("filter count changed between launches")
 
 
+SCHEDULES = {"auto": 0, "wave-per-pair": 1, "wave-per-segment": 2}
+
+
 class RefineConfig:
+    """pr_refine_params.  schedule: 0 auto, 1 wave-per-pair, 2 wave-per-segment
+    (or the names in SCHEDULES); precision: 0 FP32 + deferred FP64/exact,
+    1 FP64/exact only, 2 forced deferral (test mode), 3 FP32 + in-place exact
+    on small grids.  With precision 0 on two blobs whose coordinates lie on one
+    small power-of-two grid (see MeshBlob.exp_range), refine() uses 3."""
+
     def __init__(self, persistent: int = 1, precision: int = 0, queue_cap: int = 0, grid_blocks: int = 0,
-                 chunks_per_pop: int = 0, schedule: int = 0, survivor_cap: int = 0, ev_begin=None,
-                 ev_end=None, n_dev=None, trace_budget: int = 0):
+                 seg_live_max: int = 0, schedule=1, survivor_cap: int = 0, ev_begin=None,
+                 ev_end=None, n_dev=None, trace_budget: int = 0, lds_stack: int = 0):
         self.n_dev = n_dev        # optional device int64[1]: number of pairs to process
         self.trace_budget = trace_budget  # 0: block work sharing; > 0: continuation pass; -1: neither
         self.ev_begin = ev_begin  # optional torch.cuda.Event recorded around the traversal kernel(s)
@@ -152,9 +173,10 @@ class RefineConfig:
         self.precision = precision
         self.queue_cap = queue_cap
         self.grid_blocks = grid_blocks
-        self.chunks_per_pop = chunks_per_pop
-        self.schedule = schedule
+        self.seg_live_max = seg_live_max  # schedule 0: per-bucket table (bytes), 0 = built-in
+        self.schedule = SCHEDULES[schedule] if isinstance(schedule, str) else int(schedule)
         self.survivor_cap = survivor_cap
+        self.lds_stack = lds_stack
 
     def params(self, width: int) -> _lib.RefineParams:
         p = _lib.RefineParams()
@@ -163,13 +185,14 @@ class RefineConfig:
         p.precision = self.precision
         p.queue_cap = self.queue_cap
         p.grid_blocks = self.grid_blocks
-        p.chunks_per_pop = self.chunks_per_pop
+        p.seg_live_max = self.seg_live_max
         p.schedule = self.schedule
         p.survivor_cap = self.survivor_cap
         p.ev_begin = _event_handle(self.ev_begin)
         p.ev_end = _event_handle(self.ev_end)
         p.dev_n_pairs = None if self.n_dev is None else int(self.n_dev.data_ptr())
         p.trace_budget = self.trace_budget
+        p.lds_stack = self.lds_stack
         return p
 
 
@@ -189,6 +212,21 @@ def refine_workspace(n_pairs: int, width: int, cfg: Optional[RefineConfig] = Non
     return _ws(wb.value)
 
 
+def small_grid(A: MeshBlob, B: MeshBlob) -> bool:
+    """True when the coordinates of both blobs lie on one power-of-two grid of
+    bit span at most 14 (the condition of refinement precision 3)."""
+    (la, ha), (lb, hb) = A.exp_range(), B.exp_range()
+    lo, hi = min(la, lb), max(ha, hb)
+    return hi >= lo and hi - lo <= 14
+
+
+def _params(A: MeshBlob, B: MeshBlob, cfg: RefineConfig):
+    prm = cfg.params(A.width)
+    if prm.precision == 0 and small_grid(A, B):
+        prm.precision = 3
+    return prm
+
+
 def refine(A: MeshBlob, B: MeshBlob, pairs, cfg: Optional[RefineConfig] = None, ws=None, stream=None,
            flags=None, stats=None, status=None) -> Tuple[object, object, object]:
     """Runs refine_intersects.  Returns (flags u8[P], stats u64[8], status i32[1]),
@@ -199,7 +237,7 @@ def refine(A: MeshBlob, B: MeshBlob, pairs, cfg: Optional[RefineConfig] = None, 
         raise ValueError("blobs built with different widths")
     pairs = _dev(pairs, torch.int32).reshape(-1, 2)
     P = int(pairs.shape[0])
-    prm = cfg.params(A.width)
+    prm = _params(A, B, cfg)
     if ws is None:
         ws = refine_workspace(P, A.width, cfg)
     if flags is None:
@@ -226,7 +264,7 @@ def refine_static(A: MeshBlob, B: MeshBlob, pairs, cfg: Optional[RefineConfig] =
         raise ValueError("blobs built with different widths")
     pairs = _dev(pairs, torch.int32).reshape(-1, 2)
     P = int(pairs.shape[0])
-    prm = cfg.params(A.width)
+    prm = _params(A, B, cfg)
     if flags is None:
         flags = torch.empty(max(P, 1), dtype=torch.uint8, device="cuda")
     if stats is None:

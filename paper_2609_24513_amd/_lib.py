@@ -18,13 +18,13 @@ PR_E_CAPACITY = -2
 PR_E_GEOMETRY = -3
 PR_E_DEVICE = -4
 PR_E_UNSUPPORTED = -5
-ABI_VERSION = 5
+ABI_VERSION = 6
 
 EXPORTS = [
     "pr_last_error", "pr_abi_version", "build_mesh_bvh_sizes", "build_mesh_bvh", "blob_mesh_boxes",
     "blob_edge_counts", "filter_aabb_pairs_ws_bytes", "filter_aabb_pairs", "refine_workspace_bytes",
     "refine_intersects", "compact_pairs_ws_bytes", "compact_pairs", "gather_pair_regions",
-    "refine_static_scratch_bytes", "refine_intersects_static",
+    "refine_static_scratch_bytes", "refine_intersects_static", "blob_coord_exponents", "build_mesh_bvh_bytes",
 ]
 
 
@@ -42,10 +42,10 @@ class BvhParams(ctypes.Structure):
 class RefineParams(ctypes.Structure):
     _fields_ = [("bvh_width", ctypes.c_int32), ("persistent", ctypes.c_int32),
                 ("precision", ctypes.c_int32), ("queue_cap", ctypes.c_int32),
-                ("grid_blocks", ctypes.c_int32), ("chunks_per_pop", ctypes.c_int32),
+                ("grid_blocks", ctypes.c_int32), ("seg_live_max", ctypes.c_uint32),
                 ("schedule", ctypes.c_int32), ("survivor_cap", ctypes.c_int32),
                 ("ev_begin", ctypes.c_void_p), ("ev_end", ctypes.c_void_p),
-                ("dev_n_pairs", ctypes.c_void_p), ("trace_budget", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("dev_n_pairs", ctypes.c_void_p), ("trace_budget", ctypes.c_int32), ("lds_stack", ctypes.c_int32)]
 
 
 class RefineStats(ctypes.Structure):
@@ -83,10 +83,12 @@ def load():
         lib.pr_last_error.argtypes = []
         lib.pr_abi_version.restype = ctypes.c_int
         lib.build_mesh_bvh_sizes.argtypes = [i64, i64, i64, ctypes.POINTER(BvhParams), szp, szp]
+        lib.build_mesh_bvh_bytes.argtypes = [i64, i64, i64, ctypes.POINTER(BvhParams)]
         lib.build_mesh_bvh.argtypes = [vp, vp, vp, vp, i64, i64, i64, ctypes.POINTER(BvhParams),
                                        vp, ctypes.c_size_t, vp, ctypes.c_size_t, vp, vp]
         lib.blob_mesh_boxes.argtypes = [vp, i64, vp, vp]
         lib.blob_edge_counts.argtypes = [vp, i64, vp, vp]
+        lib.blob_coord_exponents.argtypes = [vp, vp, vp]
         lib.filter_aabb_pairs_ws_bytes.argtypes = [i64, i64, szp]
         lib.filter_aabb_pairs.argtypes = [vp, i64, vp, i64, vp, vp, i64, vp, vp, ctypes.c_size_t, vp]
         lib.refine_workspace_bytes.argtypes = [i64, ctypes.POINTER(RefineParams), szp]
@@ -101,6 +103,7 @@ def load():
         for name in EXPORTS[2:]:
             getattr(lib, name).restype = ctypes.c_int
         lib.refine_static_scratch_bytes.restype = ctypes.c_size_t
+        lib.build_mesh_bvh_bytes.restype = ctypes.c_size_t
         if lib.pr_abi_version() != ABI_VERSION:
             raise RuntimeError("libpierce_hip.so ABI %d != %d" % (lib.pr_abi_version(), ABI_VERSION))
         _lib = lib

@@ -3,9 +3,12 @@
 For a workload (two mesh datasets and their candidate pairs) it draws a
 seeded sample stratified by pair size (F_A + F_B, log-spaced buckets), builds
 the blobs once per (width, leaf size), times the persistent refinement of the
-sample for every schedule with HIP events, and returns the configuration with
-the lowest time over the whole sample, plus the per-bucket winners.  Results
-are cached in a JSON file keyed by device name and workload digest.
+sample for every schedule with HIP events - wave-per-pair, wave-per-segment,
+and the automatic schedule with per-target-size tables that send groups with
+few segments near the target wave-per-segment - and returns the
+configuration with the lowest time over the whole sample, plus the winners
+per pair-size bucket.  Results are cached in a JSON file keyed by device
+name, library build (hash of libpierce_hip.so) and workload digest.
 """
 from __future__ import annotations
 
@@ -50,6 +53,31 @@ def stratified_sample(A, B, pairs: np.ndarray, frac: float = 0.02, min_n: int = 
     return np.sort(np.concatenate(idx)), bucket, edges
 
 
+def _lib_digest() -> str:
+    from . import _lib
+    h = hashlib.sha256()
+    with open(_lib.LIB_PATH, "rb") as fh:
+        h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+# Schedules swept: (schedule, per-bucket table of the automatic schedule).
+# Tables: byte k = the largest number of a group's segments meeting the target
+# box for which the group goes wave-per-segment, for targets below 2^10,
+# 2^13, 2^16 triangles and larger.
+def _schedule_grid(schedules, width):
+    ns = 64 // width
+    out = []
+    for sc in schedules:
+        if sc == 0:
+            for t in (ns // 4, ns):
+                t = max(1, t)
+                out.append((0, t | (t << 8) | (t << 16) | (t << 24)))
+        else:
+            out.append((sc, 0))
+    return out
+
+
 def _time_refine(pa, torch, ga, gb, pairs_dev, cfg, reps: int) -> float:
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     ws = pa.refine_workspace(int(pairs_dev.shape[0]), ga.width, cfg)
@@ -66,16 +94,16 @@ def _time_refine(pa, torch, ga, gb, pairs_dev, cfg, reps: int) -> float:
 
 
 def tune(A, B, pairs, widths: Sequence[int] = (2, 4, 8), leaves: Sequence[int] = (1, 2, 4, 8),
-         schedules: Sequence[int] = (1, 2, 3), frac: float = 0.02, n_buckets: int = 4, reps: int = 3,
+         schedules: Sequence[int] = (0, 1, 2), frac: float = 0.02, n_buckets: int = 4, reps: int = 3,
          seed: int = 0, use_cache: bool = True, log=None) -> Dict:
-    """Returns {"best": {"width", "leaf_size", "schedule", "ms"}, "table": [...],
+    """Returns {"best": {"width", "leaf_size", "schedule", "seg_live_max", "ms"}, "table": [...],
     "per_bucket": {bucket: best config}, "sample": n}."""
     import torch
     import paper_2609_24513_amd as pa
 
     pairs = np.ascontiguousarray(np.asarray(pairs, np.int32).reshape(-1, 2))
-    key = "%s|%s|%s|%s|%s|%.4f|%d" % (torch.cuda.get_device_name(0), _digest(A, B, pairs), tuple(widths),
-                                      tuple(leaves), tuple(schedules), frac, n_buckets)
+    key = "%s|%s|%s|%s|%s|%s|%.4f|%d" % (torch.cuda.get_device_name(0), _lib_digest(), _digest(A, B, pairs),
+                                         tuple(widths), tuple(leaves), tuple(schedules), frac, n_buckets)
     if use_cache and os.path.exists(CACHE):
         try:
             cached = json.load(open(CACHE)).get(key)
@@ -94,15 +122,16 @@ def tune(A, B, pairs, widths: Sequence[int] = (2, 4, 8), leaves: Sequence[int] =
         for L in leaves:
             ga = pa.MeshBlob.build(A, width=W, leaf_size=L)
             gb = pa.MeshBlob.build(B, width=W, leaf_size=L)
-            for sch in schedules:
-                cfg = pa.RefineConfig(persistent=1, schedule=sch)
+            for sch, tab in _schedule_grid(schedules, W):
+                cfg = pa.RefineConfig(persistent=1, schedule=sch, seg_live_max=tab)
                 ms = _time_refine(pa, torch, ga, gb, sample, cfg, reps)
-                row = {"width": W, "leaf_size": L, "schedule": sch, "ms": ms, "buckets": {}}
+                row = {"width": W, "leaf_size": L, "schedule": sch, "seg_live_max": tab, "ms": ms, "buckets": {}}
                 for b, pb in per_bucket_pairs.items():
                     row["buckets"][str(b)] = _time_refine(pa, torch, ga, gb, pb, cfg, reps)
                 table.append(row)
                 if log:
-                    log("autotune W=%d L=%d schedule=%d: %.3f ms on %d sampled pairs" % (W, L, sch, ms, len(idx)))
+                    log("autotune W=%d L=%d schedule=%d table=%08x: %.3f ms on %d sampled pairs"
+                        % (W, L, sch, tab, ms, len(idx)))
             del ga, gb
             torch.cuda.empty_cache()
     best = min(table, key=lambda r: r["ms"])
@@ -110,9 +139,10 @@ def tune(A, B, pairs, widths: Sequence[int] = (2, 4, 8), leaves: Sequence[int] =
     for b in per_bucket_pairs:
         r = min(table, key=lambda r: r["buckets"][str(b)])
         per_bucket[str(b)] = {"width": r["width"], "leaf_size": r["leaf_size"], "schedule": r["schedule"],
+                              "seg_live_max": r["seg_live_max"],
                               "ms": r["buckets"][str(b)], "size_range": [float(edges[b]), float(edges[b + 1])],
                               "pairs": int((bucket[idx] == b).sum())}
-    out = {"best": {k: best[k] for k in ("width", "leaf_size", "schedule", "ms")}, "table": table,
+    out = {"best": {k: best[k] for k in ("width", "leaf_size", "schedule", "seg_live_max", "ms")}, "table": table,
            "per_bucket": per_bucket, "sample": int(len(idx)), "tune_seconds": time.perf_counter() - t0,
            "cached": False}
     if use_cache:

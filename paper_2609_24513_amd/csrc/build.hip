@@ -112,7 +112,7 @@ struct BuildArgs {
   int32_t* estart;       // [M]
   int32_t* eend;         // [M]
   int64_t* cscan;        // [M+1]
-  int32_t* meshctr;      // [4] misc device counters
+  int32_t* meshctr;      // [4] misc device counters: [0] lowest, [1] highest coordinate bit exponent
   uint8_t* mesh_ok;      // [M] offsets of the mesh are consistent
   uint64_t* ekey2;       // [3F] sorted (mesh, Morton) keys of unique edges
   int64_t* nscan;        // [M+1] scanned node bounds
@@ -139,8 +139,21 @@ __global__ void k_face_mesh(BuildArgs a) {
   }
 }
 
+// Exponents of the lowest and highest set bit of a finite non-zero FP32 value.
+__device__ __forceinline__ int bit_lo(float x) {
+  const uint32_t b = __float_as_uint(x) & 0x7fffffffu;
+  const uint32_t e = b >> 23, m = b & 0x7fffffu;
+  return e == 0 ? -149 + __builtin_ctz(m) : (int)e - 150 + __builtin_ctz(m | 0x800000u);
+}
+__device__ __forceinline__ int bit_hi(float x) {
+  const uint32_t b = __float_as_uint(x) & 0x7fffffffu;
+  const uint32_t e = b >> 23, m = b & 0x7fffffu;
+  return e == 0 ? -149 + (31 - __builtin_clz(m)) : (int)e - 127;
+}
+
 __global__ void k_tri_prep(BuildArgs a) {
   int64_t f = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  int elo = INT_MAX, ehi = INT_MIN;  // bit exponents over this thread's coordinates
   for (; f < a.f_total; f += (int64_t)gridDim.x * blockDim.x) {
     int32_t m = a.face_mesh[f];
     bool mok = a.mesh_ok[m];
@@ -159,6 +172,11 @@ __global__ void k_tri_prep(BuildArgs a) {
     float cs[9] = {p0.x, p0.y, p0.z, p1.x, p1.y, p1.z, p2.x, p2.y, p2.z};
     bool fin = true, safe = true;
     for (int k = 0; k < 9; ++k) { fin &= isfinite(cs[k]); safe &= safe_coord(cs[k]); }
+    for (int k = 0; k < 9; ++k)
+      if (fin && cs[k] != 0.f) {
+        elo = min(elo, bit_lo(cs[k]));
+        ehi = max(ehi, bit_hi(cs[k]));
+      }
     if (!fin) {
       atomicMin(a.status, (int32_t)f);
       safe = false;
@@ -176,6 +194,15 @@ __global__ void k_tri_prep(BuildArgs a) {
     tb[4] = fmaxf(fmaxf(p0.y, p1.y), p2.y);
     tb[5] = fmaxf(fmaxf(p0.z, p1.z), p2.z);
     a.fsafe[f] = safe ? 1 : 0;
+  }
+  // one atomic pair per wave (the grid is capped so that these stay few)
+  for (int o = 32; o > 0; o >>= 1) {
+    elo = min(elo, __shfl_xor(elo, o));
+    ehi = max(ehi, __shfl_xor(ehi, o));
+  }
+  if ((threadIdx.x & 63) == 0 && elo != INT_MAX) {
+    atomicMin(a.meshctr + 0, elo);
+    atomicMax(a.meshctr + 1, ehi);
   }
 }
 
@@ -661,8 +688,10 @@ __global__ void k_chunk_box(BuildArgs a, const int64_t* chunk_scan) {
 }
 
 __global__ void k_header(BuildArgs a, BlobHeader h, const int64_t* chunk_scan, int64_t n3) {
-  h.n_chunks = chunk_scan[a.n_meshes];
-  h.n_edges = a.epos[n3];
+  h.n_chunks = a.f_total > 0 ? chunk_scan[a.n_meshes] : 0;
+  h.n_edges = a.f_total > 0 ? a.epos[n3] : 0;
+  h.exp_lo = a.meshctr[0];
+  h.exp_hi = a.meshctr[1];
   *reinterpret_cast<BlobHeader*>(a.blob) = h;
 }
 
@@ -818,6 +847,12 @@ extern "C" int build_mesh_bvh_sizes(int64_t n_meshes, int64_t f_total, int64_t v
   return PR_OK;
 }
 
+extern "C" size_t build_mesh_bvh_bytes(int64_t n_meshes, int64_t f_total, int64_t v_total,
+                                       const pr_bvh_params* params) {
+  if (check_params(n_meshes, f_total, v_total, params) != PR_OK) return 0;
+  return (size_t)blob_layout(n_meshes, f_total, params->width, params->leaf_size).total;
+}
+
 extern "C" int build_mesh_bvh(const float* verts, const int64_t* vert_off, const int32_t* faces,
                               const int64_t* face_off, int64_t n_meshes, int64_t v_total, int64_t f_total,
                               const pr_bvh_params* params, void* blob, size_t blob_bytes, void* ws,
@@ -858,6 +893,8 @@ extern "C" int build_mesh_bvh(const float* verts, const int64_t* vert_off, const
   int eb = end_bit_for(M);
 
   hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(64), 0, s, a.status, 1, INT_MAX);
+  hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(64), 0, s, a.meshctr + 0, 1, INT_MAX);
+  hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(64), 0, s, a.meshctr + 1, 1, INT_MIN);
   if (M > 0) {
     hipLaunchKernelGGL(k_fill_i32, dim3(gM), dim3(kBlock), 0, s, a.estart, M, 0);
     hipLaunchKernelGGL(k_fill_i32, dim3(gM), dim3(kBlock), 0, s, a.eend, M, 0);
@@ -866,7 +903,7 @@ extern "C" int build_mesh_bvh(const float* verts, const int64_t* vert_off, const
   }
   if (F > 0) {
     hipLaunchKernelGGL(k_fill_u32, dim3(gF), dim3(kBlock), 0, s, a.visit, F, 0u);
-    hipLaunchKernelGGL(k_tri_prep, dim3(gF), dim3(kBlock), 0, s, a);
+    hipLaunchKernelGGL(k_tri_prep, dim3(gF < 4096 ? gF : 4096), dim3(kBlock), 0, s, a);
   }
   if (M > 0) hipLaunchKernelGGL(k_mesh_box, dim3((int)(M < 65536 ? M : 65536)), dim3(kBlock), 0, s, a);
   if (F > 0) {

@@ -46,7 +46,9 @@ struct BlobHeader {
   int64_t total_bytes;
   int64_t n_chunks;   // groups in use (written by the build)
   int64_t n_edges;    // unique edges in use (written by the build)
-  int64_t reserved[14];
+  int32_t exp_lo;     // lowest exponent of a set bit over every non-zero coordinate of a face
+  int32_t exp_hi;     // highest such exponent (every |coordinate| < 2^(exp_hi + 1))
+  int64_t reserved[13];
 };
 static_assert(sizeof(BlobHeader) == 256, "header size");
 

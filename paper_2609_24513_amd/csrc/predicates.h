@@ -12,6 +12,14 @@
 //     [2^-40, 2^40] (the "FP32-safe" range, checked per mesh at build time).
 //  2. FP64 filter: the same expression in FP64 (eps = 2^-53), certified when
 //     |det| > 2^-49 perm.  FP32 inputs cannot overflow or underflow there.
+//  2'. Grid: let e be the exponent of the lowest set bit over the fifteen
+//     coordinates of a test and h the exponent of the highest; when
+//     h - e <= 14, every coordinate difference is an integer below 2^16
+//     units of 2^e and is exact in FP32, a product of two is exact in FP64
+//     (48-bit operands' product, below 2^32 units), a cross-product component
+//     (below 2^33) and a determinant (below 3 * 2^49 units) are exact in
+//     FP64, so the signs are exact.  Cheap, so the FP32 traversal decides
+//     such tests in place.
 //  3. Exact: the determinant expanded into 24 products of three FP32
 //     coordinates; each product is an exact pair of doubles (the first
 //     product of two FP32 values is exact, the second uses an FMA-based
@@ -104,6 +112,84 @@ __device__ __forceinline__ int seg_tri_f32(f3 p, f3 q, f3 a, f3 b, f3 c) {
   if (pos && neg) return kMiss;
   if (c1 && c2 && c3 && cp && cq && ((sp > 0.f) != (sq > 0.f))) return kHit;
   return kAmbig;
+}
+
+// ---------------------------------------------------------------- grid tier
+
+// Exponents of the lowest and of the highest set bit of a non-zero FP32
+// value (|x| < 2^(high + 1)).
+__device__ __forceinline__ int low_exp(float x) {
+  const uint32_t b = __float_as_uint(x) & 0x7fffffffu;
+  const uint32_t e = b >> 23, m = b & 0x7fffffu;
+  if (e == 0) return -149 + __builtin_ctz(m);            // subnormal: m * 2^-149
+  return (int)e - 150 + __builtin_ctz(m | 0x800000u);    // (2^23 + m) * 2^(e - 150)
+}
+__device__ __forceinline__ int high_exp(float x) {
+  const uint32_t b = __float_as_uint(x) & 0x7fffffffu;
+  const uint32_t e = b >> 23, m = b & 0x7fffffu;
+  if (e == 0) return -149 + (31 - __builtin_clz(m));
+  return (int)e - 127;
+}
+
+__device__ __forceinline__ void span(float x, int& lo, int& hi) {
+  if (x != 0.f) {
+    lo = min(lo, low_exp(x));
+    hi = max(hi, high_exp(x));
+  }
+}
+
+// Exact sign of det[b-a, c-a, d-a] on a grid of span <= 14 (see above).
+__device__ __forceinline__ int gsign3(f3 a, f3 b, f3 c, f3 d) {
+  const float ux = b.x - a.x, uy = b.y - a.y, uz = b.z - a.z;
+  const float vx = c.x - a.x, vy = c.y - a.y, vz = c.z - a.z;
+  const float wx = d.x - a.x, wy = d.y - a.y, wz = d.z - a.z;
+  const double nx = (double)uy * vz - (double)uz * vy;
+  const double ny = (double)uz * vx - (double)ux * vz;
+  const double nz = (double)ux * vy - (double)uy * vx;
+  const double det = ((double)wx * nx + (double)wy * ny) + (double)wz * nz;
+  return (det > 0.0) - (det < 0.0);
+}
+
+// Exact sign of det[b-a, c-a] in the coordinate plane (i, j), same grid.
+__device__ __forceinline__ int gsign2(f3 a, f3 b, f3 c, int i, int j) {
+  const double det = (double)(get(b, i) - get(a, i)) * (get(c, j) - get(a, j)) -
+                     (double)(get(b, j) - get(a, j)) * (get(c, i) - get(a, i));
+  return (det > 0.0) - (det < 0.0);
+}
+
+// Exact closed segment-triangle decision when the five points lie on a grid
+// of span <= 14 (see above); kAmbig when they do not.  Same decision
+// procedure as seg_tri_exact.  Not inlined: the traversal calls it only for
+// tests the FP32 filter leaves open, and its registers stay out of the loop.
+__device__ __noinline__ int seg_tri_grid(f3 p, f3 q, f3 a, f3 b, f3 c) {
+  int lo = 1 << 20, hi = -(1 << 20);
+  span(p.x, lo, hi); span(p.y, lo, hi); span(p.z, lo, hi);
+  span(q.x, lo, hi); span(q.y, lo, hi); span(q.z, lo, hi);
+  span(a.x, lo, hi); span(a.y, lo, hi); span(a.z, lo, hi);
+  span(b.x, lo, hi); span(b.y, lo, hi); span(b.z, lo, hi);
+  span(c.x, lo, hi); span(c.y, lo, hi); span(c.z, lo, hi);
+  if (hi - lo > 14) return kAmbig;
+  const int sp = gsign3(a, b, c, p), sq = gsign3(a, b, c, q);
+  if (sp != 0 && sp == sq) return kMiss;
+  if (sp == 0 && sq == 0) {
+    int i = 1, j = 2;
+    if (gsign2(a, b, c, 1, 2) == 0) {
+      i = 2; j = 0;
+      if (gsign2(a, b, c, 2, 0) == 0) { i = 0; j = 1; }
+    }
+    const int s1 = gsign2(p, q, a, i, j), s2 = gsign2(p, q, b, i, j), s3 = gsign2(p, q, c, i, j);
+    if ((s1 > 0 && s2 > 0 && s3 > 0) || (s1 < 0 && s2 < 0 && s3 < 0)) return kMiss;
+    // p and q strictly outside one edge line (opposite the third vertex)
+    int sz = gsign2(a, b, c, i, j);
+    if (gsign2(a, b, p, i, j) == -sz && gsign2(a, b, q, i, j) == -sz) return kMiss;
+    sz = gsign2(b, c, a, i, j);
+    if (gsign2(b, c, p, i, j) == -sz && gsign2(b, c, q, i, j) == -sz) return kMiss;
+    sz = gsign2(c, a, b, i, j);
+    if (gsign2(c, a, p, i, j) == -sz && gsign2(c, a, q, i, j) == -sz) return kMiss;
+    return kHit;
+  }
+  const int o1 = gsign3(p, q, a, b), o2 = gsign3(p, q, b, c), o3 = gsign3(p, q, c, a);
+  return ((o1 >= 0 && o2 >= 0 && o3 >= 0) || (o1 <= 0 && o2 <= 0 && o3 <= 0)) ? kHit : kMiss;
 }
 
 // ---------------------------------------------------------------- tier 3: exact

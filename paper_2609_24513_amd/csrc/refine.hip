@@ -1,18 +1,27 @@
 // refine_intersects: bidirectional edge-segment tracing per candidate pair.
 //
-// Work unit: one wavefront traces one group of 64 segments (64 unique edges
-// of the source mesh, consecutive in Morton order of their midpoints) against
-// the target mesh's wide BVH (Section 3.1 Steps I-II; both directions as in
-// Section 3.2).  The wave walks the tree together ("packet" traversal): a
-// node is visited once for the whole wave, its child boxes are first tested
-// against the group's exact box (one uniform test, exact comparisons), then
-// every still-active lane tests its own segment; children hit by any lane
-// are pushed with the mask of lanes that hit them onto a per-wave stack in
-// LDS.  At a leaf the lanes of the mask test their segment against each
-// triangle.  A certain hit marks the pair and every wave working on it stops
-// (the paper's multi-hit loop is unnecessary: one BVH holds one mesh, and
-// any hit decides the pair).
-//
+// Work unit: one group of 64 segments (64 unique edges of the source mesh,
+// consecutive in Morton order of their midpoints) against the target mesh's
+// wide BVH (Section 3.1 Steps I-II; both directions as in Section 3.2).  The
+// persistent pass first culls every group of every (pair, direction) against
+// the top of the target tree (k_cull), then persistent waves trace the
+// surviving groups (k_trace), in one of two ways:
+//  * wave-per-pair (packet): the wave walks the tree together, one segment
+//    per lane; a node is visited once for the whole wave, every still-active
+//    lane tests its segment against all W child boxes, and children hit by
+//    any lane are pushed with the mask of lanes that hit them onto a per-wave
+//    stack (VGPR lanes, then LDS).  At a leaf the lanes of the mask test
+//    their segment against each triangle.
+//  * wave-per-segment: the lanes are W children x 64/W segment slots; each
+//    slot walks its own segment's path with its own stack in LDS, its W lanes
+//    testing the W children of its current node (or W leaf triangles) at
+//    once.  Suited to groups with few segments near the target, whose paths
+//    diverge.
+// The automatic schedule picks per group, by how many of its segments meet
+// the target box and by the target's size.  A certain hit marks the pair and
+// every wave working on it stops (the paper's multi-hit loop is unnecessary:
+// one BVH holds one mesh, and any hit decides the pair).
+
 // Segment-box test (conservative): slab test on t in [0, 1] for the segment
 // p + t (q - p), with t computed as (plane - p) * fl(1 / fl(q - p)); every t
 // carries a relative error of at most gamma_4 = 4 eps / (1 - 4 eps), so
@@ -24,7 +33,6 @@
 #pragma clang fp contract(off)
 
 #include <hip/hip_runtime.h>
-#include <hipcub/hipcub.hpp>
 
 #include <atomic>
 #include <climits>
@@ -87,15 +95,13 @@ struct RefineArgs {
   const int64_t* np_dev;      // optional device count of the pairs to process
   uint8_t* flags;
   uint32_t* state;            // [P] 0 undecided, 1 intersecting
-  int64_t* unit_cnt;          // [2P+1]
-  int64_t* offs;              // [2P+1]
-  unsigned long long* ctr;    // 8 pop counters, 128 bytes apart (one per slice of the item space)
-  int4* queue;                // deferred tests (pair, dir, segment slot, triangle)
-  uint32_t qcap;
-  uint32_t* qcount;
+  unsigned long long* ctr;    // kSlices grab counters of the cull (one per XCD share), 4 KiB apart
+  int4* queue;                // deferred tests (pair, dir, segment slot, triangle): kSlices queues
+  uint32_t qcap;              // total entries
+  uint32_t qsub;              // entries per queue
+  uint32_t* qcount;           // kSlices fill counters, kQCtrStride words apart
   unsigned long long* stats;  // [S_N]
   int32_t* status;            // [1]
-  int32_t item_groups;        // groups per work item
   int4* surv;                 // kQueues queues of surviving groups (survivor entry layout)
   uint32_t surv_cap;          // entries per queue
   unsigned long long* surv_cnt;  // kQueues fill counters (stride kCtrStride)
@@ -105,24 +111,25 @@ struct RefineArgs {
   uint32_t task_cap;          // tasks per list
   unsigned long long* task_cnt;  // kQueues fill counters (stride kCtrStride)
   unsigned long long* task_pop;  // kQueues pop counters (stride kCtrStride)
-  int32_t budget;             // schedule 3: traversal steps before a group hands its stack over (0 = none)
+  int32_t budget;             // traversal steps before a group hands its stack over (0 = none)
   unsigned int* fin_done;     // blocks of k_finalize that have finished
-  int32_t share;              // schedule 3: waves of a block share pending stack entries (1 = on)
+  int32_t share;              // waves of a block share pending stack entries (1 = on)
+  int32_t lds_stack;          // 1: the packet traversal's stack lives wholly in LDS
+  uint32_t seg_table;         // per target-size bucket: wave-per-segment limit (bytes)
 };
 
 constexpr int kSlices = 8;     // one pop counter per XCD
-// Survivor queues of schedule 3: queue blockIdx % kQueues, so every queue is
+// Survivor queues of the persistent pass: queue blockIdx % kQueues, so every queue is
 // filled and drained by the blocks of one XCD (blocks are dealt round-robin
 // to the 8 XCDs); 8 queues per XCD keep the atomics on each queue's counters
 // below the memory-side serialisation rate.
 constexpr int kQueues = 64;
-// Continuation tasks (schedule 3): a group still running after kBudget
+// Continuation tasks (optional): a group still running after kBudget
 // traversal steps hands its pending stack entries over to a third kernel, so
 // that the few long groups are spread over many waves instead of ending the
 // run alone.  kTaskCap tasks per list.
 constexpr int kBudget = 0;  // off by default: measured slower on the pathology-shaped workload
 constexpr uint32_t kTaskCap = 1u << 14;
-constexpr int kMaxItemGroups = 1024;
 constexpr int kCtrStride = 512; // u64 words between counters (4 KiB: separate memory channels)
 // Statistics: kStatCopies copies of the S_N counters (blockIdx % kStatCopies),
 // kCtrStride words apart, summed when reported: atomics on one address
@@ -201,13 +208,53 @@ __device__ __forceinline__ f3 tri_vertex(cptr_t<float> t, int k) { return f3{t[3
 // has checked that the group's box meets the target mesh box.  Returns true
 // when the pair is decided (found here or by another wave).
 // Per-wave traversal stack of (entry, lane mask) pairs.  The stack top is
-// wave-uniform; the first kRegStack entries live in VGPR lanes (entry k in
-// lane k of three registers, written and read with lane-select instructions),
-// deeper entries in a per-wave LDS array written by lane 0.
+// wave-uniform; the first reg_cap entries (kRegStack, or none when the caller
+// asks for an LDS stack) live in VGPR lanes (entry k in lane k of three
+// registers, written and read with lane-select instructions), deeper entries
+// in a per-wave LDS array written by lane 0.
 constexpr int kRegStack = 64;
 
 template <int W>
 constexpr int lds_stack_cap() { return stack_cap<W>() > kRegStack ? stack_cap<W>() - kRegStack : 1; }
+
+// Wave-per-segment mode: 64 / W segment slots per wave (lanes = W children x
+// slots), each slot with its own stack of node references in LDS.
+template <int W>
+constexpr int seg_slots() { return 64 / W; }
+template <int W>
+constexpr int seg_cap() { return W == 8 ? 64 : (W == 4 ? 32 : 24); }
+
+// LDS of one wave for the traversal, in 8-byte words: the packet stack with
+// every entry in LDS (lane masks, then references), or the per-segment
+// stacks of the wave-per-segment mode, which are never in use at the same
+// time as the packet stack and share its space.
+template <int W>
+constexpr int wave_lds_words() {
+  return (12 * stack_cap<W>() > 4 * seg_slots<W>() * seg_cap<W>() ? 12 * stack_cap<W>()
+                                                                   : 4 * seg_slots<W>() * seg_cap<W>()) / 8 + 1;
+}
+
+struct WaveLds {
+  int32_t* ref;    // packet stack entries beyond reg_cap: node references
+  uint64_t* mask;  // ... and their lane masks
+  int32_t* seg;    // wave-per-segment stacks (aliases ref / mask), or nullptr
+  int reg_cap;     // packet entries held in VGPR lanes
+};
+
+template <int W>
+__device__ __forceinline__ WaveLds wave_lds(uint64_t* area, bool lds_only) {
+  WaveLds l;
+  l.mask = area;
+  l.ref = reinterpret_cast<int32_t*>(area + stack_cap<W>());
+  l.seg = reinterpret_cast<int32_t*>(area);
+  l.reg_cap = lds_only ? 0 : kRegStack;
+  return l;
+}
+
+// For kernels with only the register stack and its LDS overflow.
+__device__ __forceinline__ WaveLds wave_lds(int32_t* ref, uint64_t* mask) {
+  return WaveLds{ref, mask, nullptr, kRegStack};
+}
 
 // v_writelane_b32: `old` with lane `lane` replaced by the uniform value v
 // (the LLVM intrinsic; this clang has no builtin spelling for it).
@@ -219,29 +266,30 @@ struct WaveStack {
   int32_t* lref;
   uint64_t* lmask;
   int32_t top;
+  int32_t reg_cap;
 };
 
 __device__ __forceinline__ void stack_push(WaveStack& s, int32_t ref, uint64_t m) {
-  if (s.top < kRegStack) {
+  if (s.top < s.reg_cap) {
     s.ref = lane_write(ref, s.top, s.ref);
     s.mlo = lane_write((int32_t)(uint32_t)m, s.top, s.mlo);
     s.mhi = lane_write((int32_t)(uint32_t)(m >> 32), s.top, s.mhi);
   } else if ((threadIdx.x & 63) == 0) {
-    s.lref[s.top - kRegStack] = ref;
-    s.lmask[s.top - kRegStack] = m;
+    s.lref[s.top - s.reg_cap] = ref;
+    s.lmask[s.top - s.reg_cap] = m;
   }
   ++s.top;
 }
 
 __device__ __forceinline__ int32_t stack_ref(const WaveStack& s, int32_t i) {
-  return i < kRegStack ? __builtin_amdgcn_readlane(s.ref, i) : uni(s.lref[i - kRegStack]);
+  return i < s.reg_cap ? __builtin_amdgcn_readlane(s.ref, i) : uni(s.lref[i - s.reg_cap]);
 }
 
 __device__ __forceinline__ uint64_t stack_mask(const WaveStack& s, int32_t i) {
-  if (i < kRegStack)
+  if (i < s.reg_cap)
     return ((uint64_t)(uint32_t)__builtin_amdgcn_readlane(s.mhi, i) << 32) |
            (uint32_t)__builtin_amdgcn_readlane(s.mlo, i);
-  return uni64(s.lmask[i - kRegStack]);
+  return uni64(s.lmask[i - s.reg_cap]);
 }
 
 // A wide node read in one burst through the scalar cache.
@@ -301,7 +349,7 @@ __device__ bool hand_over(WaveStack& stk, const RefineArgs& ra, int tq, int64_t 
   return fit == n;
 }
 
-// Work sharing inside a block (schedule 3): a wave whose queues are drained
+// Work sharing inside a block: a wave whose queues are drained
 // waits for pending stack entries that its block's tracing waves move into a
 // small LDS task list when they see it waiting.  Every counter is monotonic
 // within one launch; slots beyond kBlkTasks are never used.
@@ -347,19 +395,240 @@ __device__ int share_out(WaveStack& stk, BlockShare* sh, int64_t gc, int32_t uni
   return fit;
 }
 
+// Deferred tests: kSlices queues (one per XCD, the block's XCD taken as
+// blockIdx % kSlices), each of qsub entries with its own fill counter, so
+// that the waves of different XCDs never contend for one counter.
+constexpr int kQCtrStride = 1024;  // u32 words between the fill counters (4 KiB)
+
+// Appends the tests of the lanes with `amb` set (segment slot `slot_idx`,
+// triangle `tri`) to the deferred-test queue of the block's XCD.  Returns
+// false when the queue is full: the pair is then marked for the exact rerun.
+__device__ bool defer_tests(const RefineArgs& ra, bool amb, int32_t pair, int32_t dir, int32_t slot_idx, int32_t tri,
+                            WaveStats& st) {
+  const int lane = threadIdx.x & 63;
+  const uint64_t am = ballot(amb);
+  if (!am) return true;
+  const int qx = (int)(blockIdx.x % kSlices);
+  uint32_t base = 0;
+  if (lane == 0) base = atomicAdd(ra.qcount + kQCtrStride * qx, (uint32_t)__popcll(am));
+  base = (uint32_t)uni((int32_t)base);
+  const uint32_t idx = base + (uint32_t)lanes_below(am);
+  if (amb && idx < ra.qsub) ra.queue[(int64_t)qx * ra.qsub + idx] = make_int4(pair, dir, slot_idx, tri);
+  const uint64_t over = ballot(amb && idx >= ra.qsub);
+  if (over) {
+    st.add(S_QOVER, (uint64_t)__popcll(over));
+    if (lane == 0) atomicCAS(ra.state + pair, 0u, 2u);
+    return false;
+  }
+  return true;
+}
+
+// One closed segment-triangle test at a leaf, first tier: the FP32 filter
+// (PREC 0 and 3), FP64/exact (PREC 1) or a forced deferral (PREC 2, test
+// mode).
+template <int PREC>
+__device__ __forceinline__ int leaf_test(f3 p, f3 q, f3 a, f3 b, f3 c, bool safe) {
+  if (PREC == 1) {
+    ExactCounters ec{0};
+    return seg_tri_exact(p, q, a, b, c, ec) ? kHit : kMiss;
+  }
+  if (PREC == 2) return kAmbig;
+  return safe ? seg_tri_f32(p, q, a, b, c) : kAmbig;
+}
+
+// Second tier of the FP32 traversal with PREC 3: the lane's tests that the
+// FP32 filter left open (bits of `amb`, triangle first + bit * stride) go to
+// the exact grid tier; decided ones leave `amb` and hits enter `hit`.  n32
+// and ngrid count the FP32-uncertain tests and those decided here.
+template <int PREC>
+__device__ __forceinline__ void grid_tier(f3 p, f3 q, const float* tris, int32_t first, int stride, uint32_t& hit,
+                                          uint32_t& amb, uint32_t& n32, uint32_t& ngrid) {
+  n32 += (uint32_t)__popc(amb);
+  if (PREC != 3) return;
+  for (uint32_t m = amb; m; m &= m - 1) {
+    const int k = __builtin_ctz(m);
+    const float* tp = tris + 9 * (int64_t)(first + k * stride);
+    const int g = seg_tri_grid(p, q, tri_vertex(tp, 0), tri_vertex(tp, 1), tri_vertex(tp, 2));
+    if (g != kAmbig) {
+      ++ngrid;
+      amb &= ~(1u << k);
+      if (g == kHit) hit |= 1u << k;
+    }
+  }
+}
+
+// Wave sum of a per-lane count.
+__device__ __forceinline__ uint32_t wave_sum(uint32_t x) {
+  for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o);
+  return x;
+}
+
+// Wave-per-segment traversal of the segments `todo` (lanes of group gc)
+// against the target tree from `root`: lanes are W children x 64/W segment
+// slots; a slot traces one segment at a time with its own stack of node
+// references in LDS (`sstk`), its W lanes testing the W children of the
+// slot's current node, or W triangles of a leaf at a time.  Slots that finish
+// take the next segment.  A segment whose stack would overflow is left to
+// the packet traversal (its bit is set in `overflow`).  Returns true when the
+// pair is decided.
+template <int W, int PREC>
+__device__ bool trace_segments(const BlobView& S, const BlobView& T, int64_t gc, int32_t root, int32_t pair,
+                               int32_t dir, bool safe, uint64_t todo, const float* cb, const RefineArgs& ra,
+                               int32_t* sstk, WaveStats& st, uint64_t& overflow) {
+  constexpr int CAP = seg_cap<W>();
+  constexpr uint32_t kWMask = (1u << W) - 1u;
+  const int lane = threadIdx.x & 63;
+  const int slot = lane / W, c = lane % W;
+  int32_t* stk = sstk + slot * CAP;
+  const float* sp = S.seg + gc * (6 * kChunk);
+  const Node<W>* nodes = reinterpret_cast<const Node<W>*>(T.nodes);
+  int seg = -1, top = 0;
+  f3 p{0.f, 0.f, 0.f}, q{0.f, 0.f, 0.f};
+  Ray r{};
+  uint32_t visits = 0, leaves = 0, tests = 0;  // slot events counted by the slot's lane 0
+  uint32_t n32 = 0, ngrid = 0;
+  // the counts go into the wave's statistics on every way out
+  struct Fold {
+    WaveStats& st;
+    uint32_t &visits, &leaves, &tests, &n32, &ngrid;
+    __device__ ~Fold() {
+      const uint32_t v = wave_sum(visits), l = wave_sum(leaves), t = wave_sum(tests);
+      st.add(S_VISIT, v);
+      st.add(S_TRIF, l);
+      st.add(S_TESTS, t);
+      st.add(S_AMB32, wave_sum(n32));
+      st.add(S_EXACT, PREC == 1 ? t : wave_sum(ngrid));
+      st.max(S_MAXV, v);
+      st.max(S_MAXL, l);
+    }
+  } fold{st, visits, leaves, tests, n32, ngrid};
+  uint32_t poll = 0;
+  int iter = 0;
+  overflow = 0;
+  for (;;) {
+    // idle slots take the next segments of `todo`, lowest slot first
+    const uint64_t idle = ballot(c == 0 && seg < 0);
+    if (idle && todo) {
+      uint64_t m = idle;
+      int take = -1;
+      while (m && todo) {
+        const int leader = __builtin_ctzll(m);
+        m &= m - 1;
+        const int b = __builtin_ctzll(todo);
+        todo &= todo - 1;
+        if (slot == leader / W) take = b;
+      }
+      if (take >= 0) {
+        seg = take;
+        p = f3{sp[seg], sp[kChunk + seg], sp[2 * kChunk + seg]};
+        q = f3{sp[3 * kChunk + seg], sp[4 * kChunk + seg], sp[5 * kChunk + seg]};
+        r.px = p.x; r.py = p.y; r.pz = p.z;
+        axis_setup(q.x - p.x, safe, r.ix, r.bx);
+        axis_setup(q.y - p.y, safe, r.iy, r.by);
+        axis_setup(q.z - p.z, safe, r.iz, r.bz);
+        stk[0] = root;  // every lane of the slot writes the same entry
+        top = 1;
+      }
+    }
+    if (!ballot(seg >= 0)) break;
+    if ((++iter & 15) == 0) {
+      if (uni((int32_t)poll)) return true;
+      poll = load_state(ra.state + pair);
+    }
+    const bool active = seg >= 0;
+    int32_t ref = 0;
+    if (active) ref = stk[--top];
+    const bool is_leaf = active && ref < 0, is_inner = active && ref >= 0;
+    // leaf: the slot's lanes test its triangles, W at a time
+    uint32_t hitb = 0, ambb = 0;
+    int32_t tfirst = 0;
+    if (is_leaf) {
+      const int32_t lr = ~ref;
+      tfirst = lr >> 3;
+      const int cnt = (lr & 7) + 1;
+      if (c == 0) ++leaves;
+      for (int t = c; t < cnt; t += W) {
+        const float* tp = T.tris + 9 * (int64_t)(tfirst + t);
+        const int res = leaf_test<PREC>(p, q, tri_vertex(tp, 0), tri_vertex(tp, 1), tri_vertex(tp, 2), safe);
+        ++tests;
+        hitb |= (res == kHit ? 1u : 0u) << (t / W);
+        ambb |= (res == kAmbig ? 1u : 0u) << (t / W);
+      }
+      if (ambb) grid_tier<PREC>(p, q, T.tris, tfirst + c, W, hitb, ambb, n32, ngrid);
+    }
+    if (ballot(hitb != 0)) {
+      if (lane == 0) mark_true(ra.state + pair);
+      return true;
+    }
+    if (ballot(ambb != 0)) {
+#pragma unroll
+      for (int k = 0; k < (8 + W - 1) / W; ++k) {
+        const bool amb = (ambb >> k) & 1u;
+        if (!ballot(amb)) continue;
+        if (!defer_tests(ra, amb, pair, dir, (int32_t)(gc * kChunk + seg), tfirst + c + k * W, st)) return true;
+      }
+    }
+    // inner node: lane c tests child c against the slot's segment
+    bool h = false;
+    int32_t child = kEmpty;
+    if (is_inner) {
+      const Node<W>* n = nodes + ref;
+      const float lx = n->lo[0][c], ly = n->lo[1][c], lz = n->lo[2][c];
+      const float hx = n->hi[0][c], hy = n->hi[1][c], hz = n->hi[2][c];
+      child = n->child[c];
+      h = child != kEmpty && slab(r, lx, ly, lz, hx, hy, hz) && (safe || box_meet(cb, lx, ly, lz, hx, hy, hz));
+      if (c == 0) ++visits;
+    }
+    const uint64_t hm = ballot(h);
+    bool ovf = false;
+    if (is_inner) {
+      const uint32_t mine = (uint32_t)(hm >> (slot * W)) & kWMask;
+      const int cnt = __popc(mine);
+      if (top + cnt > CAP) {
+        ovf = true;
+      } else {
+        if (h) stk[top + __popc(mine & ((1u << c) - 1u))] = child;
+        top += cnt;
+      }
+    }
+    // the pushes of one lane are read by the other lanes of its slot
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    for (uint64_t om = ballot(ovf && c == 0); om; om &= om - 1)
+      overflow |= 1ull << __builtin_amdgcn_readlane(seg, __builtin_ctzll(om));
+    if (ovf || (active && top == 0)) seg = -1;
+  }
+  return false;
+}
+
+// How one group is traced.
+struct TraceOpts {
+  WaveLds lds;
+  bool rerun = false;          // k_fix rerun: no pair-state polling, every test exact
+  uint64_t start_mask = 0;     // continue a handed-over task from `root` with these lanes
+  int budget = 0;              // steps before the stack is handed over (0 = never)
+  int tq = 0;                  // task list for the hand-over
+  BlockShare* sh = nullptr;    // block work sharing
+  int seg_max = 0;             // wave-per-segment when at most this many segments meet the root box
+};
+
 // Traces segment group gc (global index in the source blob, `live` segments)
 // against the target mesh whose root node is `root` and box `tb`.  Returns
 // true when the pair is decided (found here or by another wave).  With a
 // non-zero start_mask the trace continues a handed-over task instead: the
 // stack starts as (root, start_mask) and the group's segments are not counted
 // again.  With a budget, a group still running after that many steps hands its
-// stack over to task list tq and returns.
-template <int W, int PREC>
+// stack over to task list tq and returns.  Groups with at most seg_max
+// segments meeting the target box take the wave-per-segment traversal.
+template <int W, int PREC, int SCHED = 1>
 __device__ bool trace_core(const BlobView& S, const BlobView& T, int64_t gc, int live, int32_t root,
                            const float* tb, int32_t pair, int32_t dir, bool safe, const RefineArgs& ra,
-                           int32_t* lref, uint64_t* lmask, WaveStats& st, bool rerun, uint64_t start_mask = 0,
-                           int budget = 0, int tq = 0, BlockShare* sh = nullptr) {
+                           WaveStats& st, const TraceOpts& o) {
   const int lane = threadIdx.x & 63;
+  const bool rerun = o.rerun;
+  int budget = o.budget;
+  BlockShare* const sh = o.sh;
   // issue every load the group needs at once: its box, its segments and the
   // pair's state
   const uint32_t decided = rerun ? 0u : load_state(ra.state + pair);
@@ -377,11 +646,20 @@ __device__ bool trace_core(const BlobView& S, const BlobView& T, int64_t gc, int
   axis_setup(q.y - p.y, safe, r.iy, r.by);
   axis_setup(q.z - p.z, safe, r.iz, r.bz);
   if (uni((int32_t)decided)) return true;
-  uint64_t m0 = start_mask;
+  uint64_t m0 = o.start_mask;
+  bool cont = m0 != 0;
   if (m0 == 0) {
     st.add(S_SEG, (uint64_t)live);
     m0 = ballot(valid && slab(r, tb[0], tb[1], tb[2], tb[3], tb[4], tb[5]));
     if (m0 == 0) return false;
+    if (SCHED != 1 && o.seg_max > 0 && o.lds.seg && __popcll(m0) <= o.seg_max) {
+      st.add(S_GTRAV, 1);
+      uint64_t over = 0;
+      if (trace_segments<W, PREC>(S, T, gc, root, pair, dir, safe, m0, cb, ra, o.lds.seg, st, over)) return true;
+      if (!over) return false;
+      m0 = over;  // segments whose stacks overflowed: packet traversal from the root
+      cont = true;
+    }
   }
   // per-group counters (uniform, 32 bits), folded into the wave's statistics
   // when the group ends
@@ -389,20 +667,25 @@ __device__ bool trace_core(const BlobView& S, const BlobView& T, int64_t gc, int
     WaveStats& s;
     bool cont;
     uint32_t visits = 0, leaf_tris = 0, tests = 0;
+    uint32_t n32 = 0, ngrid = 0;  // per lane
     __device__ ~GroupCount() {
       if (!cont) s.add(S_GTRAV, 1);
       s.add(S_VISIT, visits);
       s.add(S_TRIF, leaf_tris);
       s.add(S_TESTS, tests);
       if (PREC == 1) s.add(S_EXACT, tests);
+      if (PREC != 1) {
+        s.add(S_AMB32, wave_sum(n32));
+        s.add(S_EXACT, wave_sum(ngrid));
+      }
       s.max(S_MAXV, visits);
       s.max(S_MAXL, leaf_tris);
     }
-  } gcount{st, start_mask != 0};
+  } gcount{st, cont};
   constexpr int CAP = stack_cap<W>();
   WaveStack stk;
   stk.ref = 0; stk.mlo = 0; stk.mhi = 0;
-  stk.lref = lref; stk.lmask = lmask; stk.top = 0;
+  stk.lref = o.lds.ref; stk.lmask = o.lds.mask; stk.top = 0; stk.reg_cap = o.lds.reg_cap;
   stack_push(stk, root, m0);
   int iter = 0;
   const cptr_t<Node<W>> nodes = cview(reinterpret_cast<const Node<W>*>(T.nodes));
@@ -411,7 +694,7 @@ __device__ bool trace_core(const BlobView& S, const BlobView& T, int64_t gc, int
   uint32_t poll = 0;
   while (stk.top > 0) {
     if (budget && iter >= budget) {
-      if (hand_over(stk, ra, tq, gc, (pair << 1) | dir, live | (safe ? 256 : 0))) return false;
+      if (hand_over(stk, ra, o.tq, gc, (pair << 1) | dir, live | (safe ? 256 : 0))) return false;
       budget = 0;  // the rest did not fit: finish here
       if (stk.top == 0) return false;
     }
@@ -453,21 +736,12 @@ __device__ bool trace_core(const BlobView& S, const BlobView& T, int64_t gc, int
           const f3 ta{tv[9 * k], tv[9 * k + 1], tv[9 * k + 2]};
           const f3 tb3{tv[9 * k + 3], tv[9 * k + 4], tv[9 * k + 5]};
           const f3 tc{tv[9 * k + 6], tv[9 * k + 7], tv[9 * k + 8]};
-          int res = kMiss;
-          if (on) {
-            if (PREC == 0) {
-              res = safe ? seg_tri_f32(p, q, ta, tb3, tc) : kAmbig;
-            } else if (PREC == 1) {
-              ExactCounters ec{0};
-              res = seg_tri_exact(p, q, ta, tb3, tc, ec) ? kHit : kMiss;
-            } else {
-              res = kAmbig;
-            }
-          }
+          const int res = on ? leaf_test<PREC>(p, q, ta, tb3, tc, safe) : kMiss;
           hitbits |= (res == kHit ? 1u : 0u) << (t0 + k);
           ambbits |= (res == kAmbig ? 1u : 0u) << (t0 + k);
         }
       }
+      if (ambbits) grid_tier<PREC>(p, q, T.tris, first, 1, hitbits, ambbits, gcount.n32, gcount.ngrid);
       if (ballot(hitbits != 0)) {
         if (lane == 0 && !rerun) mark_true(ra.state + pair);
         return true;
@@ -475,22 +749,9 @@ __device__ bool trace_core(const BlobView& S, const BlobView& T, int64_t gc, int
       if (ballot(ambbits != 0)) {
         for (int t = 0; t < cnt; ++t) {
           const bool amb = (ambbits >> t) & 1u;
-          const uint64_t am = ballot(amb);
-          if (!am) continue;
-          st.add(S_AMB32, (uint64_t)__popcll(am));
-          uint32_t base = 0;
-          if (lane == 0) base = atomicAdd(ra.qcount, (uint32_t)__popcll(am));
-          base = (uint32_t)uni((int32_t)base);
-          const uint32_t idx = base + (uint32_t)lanes_below(am);
-          if (amb && idx < ra.qcap)
-            ra.queue[idx] = make_int4(pair, dir, (int32_t)(gc * kChunk + lane), first + t);
-          const uint64_t over = ballot(amb && idx >= ra.qcap);
-          if (over) {
-            // the queue is full: the whole pair is decided again later in FP64/exact
-            st.add(S_QOVER, (uint64_t)__popcll(over));
-            if (lane == 0) atomicCAS(ra.state + pair, 0u, 2u);
-            return true;
-          }
+          if (!ballot(amb)) continue;
+          // the queue is full: the whole pair is decided again later in FP64/exact
+          if (!defer_tests(ra, amb, pair, dir, (int32_t)(gc * kChunk + lane), first + t, st)) return true;
         }
       }
       continue;
@@ -521,7 +782,10 @@ __device__ __forceinline__ bool trace_group(const BlobView& S, const BlobView& T
                                             bool rerun = false) {
   const int64_t gc = (int64_t)sm.chunk_base + chunk;
   const int live = min(kChunk, sm.n_edges - chunk * kChunk);
-  return trace_core<W, PREC>(S, T, gc, live, tm.root, tm.box, pair, dir, safe, ra, lref, lmask, st, rerun);
+  TraceOpts o;
+  o.lds = wave_lds(lref, lmask);
+  o.rerun = rerun;
+  return trace_core<W, PREC>(S, T, gc, live, tm.root, tm.box, pair, dir, safe, ra, st, o);
 }
 
 // One group with its own box pre-test (per-pair and rerun kernels).
@@ -574,7 +838,10 @@ __global__ void k_init(RefineArgs ra) {
   int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   for (int64_t p = i; p < ra.n_pairs; p += (int64_t)gridDim.x * blockDim.x) ra.state[p] = 0u;
   if (i < kStatCopies * S_N) ra.stats[kCtrStride * (i / S_N) + i % S_N] = 0ull;
-  if (i < kSlices) ra.ctr[kCtrStride * i] = 0ull;
+  if (i < kSlices) {
+    ra.ctr[kCtrStride * i] = 0ull;
+    ra.qcount[kQCtrStride * i] = 0u;
+  }
   if (i < kQueues) {
     ra.surv_cnt[kCtrStride * i] = 0ull;
     ra.surv_pop[kCtrStride * i] = 0ull;
@@ -585,261 +852,8 @@ __global__ void k_init(RefineArgs ra) {
   }
   if (i == 0) {
     *ra.fin_done = 0u;
-    *ra.qcount = 0u;
     *ra.status = PR_OK;
   }
-}
-
-// Coarse cull of a direction: does box `b` meet the target mesh box, a child
-// box of its root and, for an inner child, one of that child's child boxes?
-// Conservative: every triangle lies inside the boxes of its ancestors.
-template <int W>
-__device__ bool coarse_meet(const float* b, const BlobView& T, const MeshDesc& tm) {
-  if (tm.root == kEmpty) return false;
-  if (!box_meet(b, tm.box[0], tm.box[1], tm.box[2], tm.box[3], tm.box[4], tm.box[5])) return false;
-  const Node<W>* nodes = reinterpret_cast<const Node<W>*>(T.nodes);
-  const Node<W>* root = nodes + tm.root;
-  for (int c = 0; c < W; ++c) {
-    const int32_t ch = root->child[c];
-    if (ch == kEmpty) continue;
-    if (!box_meet(b, root->lo[0][c], root->lo[1][c], root->lo[2][c], root->hi[0][c], root->hi[1][c], root->hi[2][c]))
-      continue;
-    if (ch < 0) return true;
-    const Node<W>* n2 = nodes + ch;
-    for (int d = 0; d < W; ++d)
-      if (n2->child[d] != kEmpty &&
-          box_meet(b, n2->lo[0][d], n2->lo[1][d], n2->lo[2][d], n2->hi[0][d], n2->hi[1][d], n2->hi[2][d]))
-        return true;
-  }
-  return false;
-}
-
-template <int W>
-__global__ void k_plan(RefineArgs ra) {
-  const BlobView A = view_of(ra.blob_a), B = view_of(ra.blob_b);
-  const bool bok = blobs_ok(A, B, ra, W);
-  int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  const int64_t np = npairs(ra);
-  if (p == 0) ra.unit_cnt[2 * ra.n_pairs] = 0;
-  for (; p < ra.n_pairs; p += (int64_t)gridDim.x * blockDim.x) {
-    int32_t i, j;
-    int64_t c0 = 0, c1 = 0;
-    if (p >= np) {
-      // beyond the device count: no work
-    } else if (!bok) {
-      if (p == 0) atomicMin(ra.status, (int32_t)PR_E_UNSUPPORTED);
-    } else if (!pair_ok(ra, p, i, j)) {
-      atomicMin(ra.status, (int32_t)PR_E_ARG);
-    } else {
-      const MeshDesc a = A.mesh[i], b = B.mesh[j];
-      if (box_meet(a.box, b.box[0], b.box[1], b.box[2], b.box[3], b.box[4], b.box[5])) {
-        const int64_t R = ra.item_groups;
-        if (coarse_meet<W>(a.box, B, b)) c0 = (a.n_chunks + R - 1) / R;
-        if (coarse_meet<W>(b.box, A, a)) c1 = (b.n_chunks + R - 1) / R;
-      }
-    }
-    ra.unit_cnt[2 * p] = c0;
-    ra.unit_cnt[2 * p + 1] = c1;
-  }
-}
-
-// Unit u (a (pair, direction)) holding global group index v: offs[u] <= v < offs[u+1].
-__device__ __forceinline__ int64_t find_unit(const int64_t* offs, int64_t U, int64_t v) {
-  const int lane = threadIdx.x & 63;
-  int64_t lo = 0, hi = U;
-  while (hi - lo > 1) {
-    const int64_t step = (hi - lo + 63) / 64;
-    const int64_t idx = lo + (int64_t)lane * step;
-    const bool ok = idx < hi && offs[idx] <= v;
-    const uint64_t m = ballot(ok);
-    const int last = 63 - __clzll((long long)m);
-    lo = lo + (int64_t)last * step;
-    const int64_t nh = lo + step;
-    hi = nh < hi ? nh : hi;
-  }
-  return lo;
-}
-
-// Conservative group cull: the group box must meet the target mesh box and
-// a child box of the root; when that child is an inner node, one of its child
-// boxes too (every triangle lies inside the boxes of its ancestors).  The
-// node loads are uniform; each lane tests its own group box.
-template <int W>
-__device__ __forceinline__ bool group_may_hit(const float* g, const BlobView& T, const MeshDesc& tm) {
-  if (!(g[0] <= tm.box[3] && tm.box[0] <= g[3] && g[1] <= tm.box[4] && tm.box[1] <= g[4] && g[2] <= tm.box[5] &&
-        tm.box[2] <= g[5]))
-    return false;
-  const cptr_t<Node<W>> nodes = cview(reinterpret_cast<const Node<W>*>(T.nodes));
-  const cptr_t<Node<W>> root = nodes + tm.root;
-  bool hit = false;
-#pragma unroll
-  for (int c = 0; c < W; ++c) {
-    const int32_t ch = root->child[c];
-    if (ch == kEmpty) continue;
-    const bool m1 = box_meet(g, root->lo[0][c], root->lo[1][c], root->lo[2][c], root->hi[0][c], root->hi[1][c],
-                             root->hi[2][c]);
-    if (ch < 0) { hit = hit || m1; continue; }
-    const cptr_t<Node<W>> n2 = nodes + ch;
-    bool m2 = false;
-#pragma unroll
-    for (int d = 0; d < W; ++d)
-      m2 = m2 || (n2->child[d] != kEmpty &&
-                  box_meet(g, n2->lo[0][d], n2->lo[1][d], n2->lo[2][d], n2->hi[0][d], n2->hi[1][d], n2->hi[2][d]));
-    hit = hit || (m1 && m2);
-  }
-  return hit;
-}
-
-// Work item: (pair, direction, range of item_groups groups).  The item space
-// is cut into kSlices contiguous slices with one pop counter each; a block
-// starts on slice blockIdx % kSlices (workgroups are dealt round-robin to the
-// XCDs, so each XCD mostly pops its own counter and keeps its own meshes in
-// its L2) and then helps the other slices.  A block takes one item at a time:
-// its waves cull the item's groups 64 at a time (one group box per lane),
-// append the survivors to a list in LDS, then drain that list dynamically,
-// one group per wave at a time.
-template <int W, int PREC>
-__global__ __launch_bounds__(kBlock, 5) void k_refine_persistent(RefineArgs ra) {
-  constexpr int CAP = lds_stack_cap<W>();
-  __shared__ int32_t s_node[kWaves][CAP];
-  __shared__ uint64_t s_mask[kWaves][CAP];
-  __shared__ int32_t s_list[kMaxItemGroups];
-  __shared__ int64_t s_idx;
-  __shared__ int32_t s_n, s_next;
-  const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const BlobView A = view_of(ra.blob_a), B = view_of(ra.blob_b);
-  if (!blobs_ok(A, B, ra, W)) return;
-  const int64_t U = 2 * ra.n_pairs;
-  const int64_t total = ra.offs[U];
-  WaveStats st;
-  const int home = (int)(blockIdx.x % kSlices);
-  for (int sl = 0; sl < kSlices; ++sl) {
-    const int cid = (home + sl) % kSlices;
-    const int64_t lo = total * cid / kSlices, hi = total * (cid + 1) / kSlices;
-    if (lo >= hi) continue;
-    for (;;) {
-      if (threadIdx.x == 0) {
-        s_idx = lo + (int64_t)atomicAdd(ra.ctr + kCtrStride * cid, 1ull);
-        s_n = 0;
-        s_next = 0;
-      }
-      __syncthreads();
-      const int64_t idx = s_idx;
-      if (idx >= hi) {
-        __syncthreads();
-        break;
-      }
-      const int64_t u = find_unit(ra.offs, U, idx);
-      const int64_t j = idx - ra.offs[u];
-      const int32_t pair = uni((int32_t)(u >> 1));
-      const int32_t dir = uni((int32_t)(u & 1));
-      const int32_t ia = ra.pairs[2 * (int64_t)pair], jb = ra.pairs[2 * (int64_t)pair + 1];
-      const BlobView& S = dir == 0 ? A : B;
-      const BlobView& T = dir == 0 ? B : A;
-      const MeshDesc sm = dir == 0 ? A.mesh[ia] : B.mesh[jb];
-      const MeshDesc tm = dir == 0 ? B.mesh[jb] : A.mesh[ia];
-      const int32_t c0 = (int32_t)(j * ra.item_groups);
-      const int32_t c1 = min(c0 + ra.item_groups, sm.n_chunks);
-      if (tm.root != kEmpty && !load_state(ra.state + pair)) {
-        for (int32_t base = c0 + kChunk * wv; base < c1; base += kChunk * kWaves) {
-          const int32_t c = base + lane;
-          bool pass = false;
-          if (c < c1) {
-            const float* cbp = S.cbox + 8 * ((int64_t)sm.chunk_base + c);
-            float g[6] = {cbp[0], cbp[1], cbp[2], cbp[3], cbp[4], cbp[5]};
-            pass = group_may_hit<W>(g, T, tm);
-          }
-          const uint64_t mask = ballot(pass);
-          if (mask) {
-            int32_t pos = 0;
-            if (lane == 0) pos = atomicAdd(&s_n, (int32_t)__popcll(mask));
-            pos = uni(pos);
-            if (pass) s_list[pos + lanes_below(mask)] = c;
-          }
-          st.add(S_GBOX, (uint64_t)__popcll(mask));
-        }
-        if (wv == 0) st.add(S_GROUPS, (uint64_t)(c1 - c0));
-      }
-      __syncthreads();
-      const int32_t n = s_n;
-      const bool safe = (sm.flags & tm.flags & kMeshSafe) != 0;
-      for (;;) {
-        int32_t k = 0;
-        if (lane == 0) k = atomicAdd(&s_next, 1);
-        k = uni(k);
-        if (k >= n) break;
-        if (trace_group<W, PREC>(S, T, sm, tm, s_list[k], pair, dir, safe, ra, s_node[wv], s_mask[wv], st)) {
-          if (lane == 0) atomicExch(&s_next, n);  // the pair is decided: drop the rest of the list
-          break;
-        }
-      }
-      __syncthreads();
-    }
-  }
-  flush_stats(st, ra);
-}
-
-// Schedule 2: every wave pops and finishes its own work items (no block
-// synchronisation); the group cull is the same lane-parallel test.
-template <int W, int PREC>
-__global__ __launch_bounds__(kBlock) void k_refine_wave(RefineArgs ra) {
-  constexpr int CAP = lds_stack_cap<W>();
-  __shared__ int32_t s_node[kWaves][CAP];
-  __shared__ uint64_t s_mask[kWaves][CAP];
-  const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const BlobView A = view_of(ra.blob_a), B = view_of(ra.blob_b);
-  if (!blobs_ok(A, B, ra, W)) return;
-  const int64_t U = 2 * ra.n_pairs;
-  const int64_t total = ra.offs[U];
-  WaveStats st;
-  const int home = (int)(blockIdx.x % kSlices);
-  for (int sl = 0; sl < kSlices; ++sl) {
-    const int cid = (home + sl) % kSlices;
-    const int64_t lo = total * cid / kSlices, hi = total * (cid + 1) / kSlices;
-    if (lo >= hi) continue;
-    for (;;) {
-      unsigned long long k = 0;
-      if (lane == 0) k = atomicAdd(ra.ctr + kCtrStride * cid, 1ull);
-      const int64_t idx = lo + (int64_t)uni64(k);
-      if (idx >= hi) break;
-      const int64_t u = find_unit(ra.offs, U, idx);
-      const int64_t j = idx - ra.offs[u];
-      const int32_t pair = uni((int32_t)(u >> 1));
-      const int32_t dir = uni((int32_t)(u & 1));
-      const int32_t ia = ra.pairs[2 * (int64_t)pair], jb = ra.pairs[2 * (int64_t)pair + 1];
-      const BlobView& S = dir == 0 ? A : B;
-      const BlobView& T = dir == 0 ? B : A;
-      const MeshDesc sm = dir == 0 ? A.mesh[ia] : B.mesh[jb];
-      const MeshDesc tm = dir == 0 ? B.mesh[jb] : A.mesh[ia];
-      if (tm.root == kEmpty) continue;
-      const bool safe = (sm.flags & tm.flags & kMeshSafe) != 0;
-      const int32_t c0 = (int32_t)(j * ra.item_groups);
-      const int32_t c1 = min(c0 + ra.item_groups, sm.n_chunks);
-      st.add(S_GROUPS, (uint64_t)(c1 - c0));
-      bool done = false;
-      for (int32_t base = c0; base < c1 && !done; base += kChunk) {
-        if (load_state(ra.state + pair)) break;
-        const int32_t c = base + lane;
-        bool pass = false;
-        if (c < c1) {
-          const float* cbp = S.cbox + 8 * ((int64_t)sm.chunk_base + c);
-          float g[6] = {cbp[0], cbp[1], cbp[2], cbp[3], cbp[4], cbp[5]};
-          pass = group_may_hit<W>(g, T, tm);
-        }
-        uint64_t mask = ballot(pass);
-        st.add(S_GBOX, (uint64_t)__popcll(mask));
-        while (mask) {
-          const int bit = __builtin_ctzll(mask);
-          mask &= mask - 1;
-          if (trace_group<W, PREC>(S, T, sm, tm, base + bit, pair, dir, safe, ra, s_node[wv], s_mask[wv], st)) {
-            done = true;
-            break;
-          }
-        }
-      }
-    }
-  }
-  flush_stats(st, ra);
 }
 
 // Per-lane two-level cull of group box g against a target mesh whose root
@@ -930,7 +944,7 @@ __device__ void flush_survivors(const int4* buf, int n, int slice, const RefineA
   }
 }
 
-// Schedule 3, phase 1: one wave per unit (pair, direction), units dealt to the
+// Persistent pass, phase 1: one wave per unit (pair, direction), units dealt to the
 // waves in a fixed stride or, with many units per wave, taken from per-XCD
 // shares a few at a time.  The wave validates the pair, tests the source
 // mesh box against the target mesh box and its top two levels, then culls
@@ -1080,8 +1094,8 @@ __global__ __launch_bounds__(kBlock) void k_cull(RefineArgs ra) {
 constexpr uint32_t kHelpSpinLimit = 1u << 22;
 
 template <int W, int PREC>
-__device__ void block_help(const BlobView& A, const BlobView& B, const RefineArgs& ra, BlockShare* sh, int32_t* lref,
-                           uint64_t* lmask, WaveStats& st) {
+__device__ void block_help(const BlobView& A, const BlobView& B, const RefineArgs& ra, BlockShare* sh, const WaveLds& lds,
+                           WaveStats& st) {
   const int lane = threadIdx.x & 63;
   if (lane == 0) {
     __hip_atomic_fetch_add(&sh->idle, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
@@ -1138,8 +1152,12 @@ __device__ void block_help(const BlobView& A, const BlobView& B, const RefineArg
       const BlobView& S = dir == 0 ? A : B;
       const BlobView& T = dir == 0 ? B : A;
       const float tb_unused[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};  // the root was tested when the group started
+      TraceOpts o;
+      o.lds = lds;
+      o.start_mask = uni64(m);
+      o.sh = sh;
       trace_core<W, PREC>(S, T, uni(t.x), uni(t.w) & 0xff, uni(t.z), tb_unused, pair, dir, (uni(t.w) & 256) != 0, ra,
-                          lref, lmask, st, false, uni64(m), 0, 0, sh);
+                          st, o);
       if (lane == 0) {
         __hip_atomic_fetch_add(&sh->idle, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
         __hip_atomic_fetch_add(&sh->busy, ~0u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
@@ -1159,7 +1177,18 @@ __device__ void block_help(const BlobView& A, const BlobView& B, const RefineArg
 }
 
 
-// Schedule 3, phase 2: waves pop surviving groups kPop at a time from the
+// Target-size buckets of the automatic schedule (triangles of the target
+// mesh: below 2^10, 2^13, 2^16, and larger) and the per-bucket limit on the
+// segments of a group that meet the target box for the group to be traced
+// wave-per-segment (byte k of the table).
+__device__ __forceinline__ int size_bucket(int32_t n_tris) {
+  return n_tris < (1 << 10) ? 0 : (n_tris < (1 << 13) ? 1 : (n_tris < (1 << 16) ? 2 : 3));
+}
+__device__ __forceinline__ int seg_max_of(uint32_t table, int32_t n_tris) {
+  return (int)((table >> (8 * size_bucket(n_tris))) & 0xffu);
+}
+
+// Persistent pass, phase 2: waves pop surviving groups kPop at a time from the
 // queue of their block (blockIdx % kQueues, on the XCD whose phase-1 blocks
 // filled it) and trace them; a wave leaves a queue after its first empty pop
 // and then helps with the other queues of its XCD (q + 8, q + 16, ...), so
@@ -1172,12 +1201,10 @@ __device__ void block_help(const BlobView& A, const BlobView& B, const RefineArg
 // cancel the pair's later groups.  A wave whose queues are drained then
 // takes the pending subtrees that the other waves of its block hand over
 // (`block_help`), so the block's long traversals end together.
-template <int W, int PREC>
+template <int W, int PREC, int SCHED>
 __global__ __launch_bounds__(kBlock, 5) void k_trace(RefineArgs ra) {
-  constexpr int CAP = lds_stack_cap<W>();
   constexpr int kPop = 4;
-  __shared__ int32_t s_node[kWaves][CAP];
-  __shared__ uint64_t s_mask[kWaves][CAP];
+  __shared__ uint64_t s_area[kWaves][wave_lds_words<W>()];
   __shared__ BlockShare s_share;
   const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
   if (threadIdx.x < kBlkTasks) s_share.ready[threadIdx.x] = 0u;
@@ -1189,7 +1216,13 @@ __global__ __launch_bounds__(kBlock, 5) void k_trace(RefineArgs ra) {
     s_share.busy = 0u;
   }
   __syncthreads();
-  BlockShare* const sh = ra.share ? &s_share : nullptr;
+  // with the whole stack in LDS there is no hand-over of stack entries
+  const bool lds_only = ra.lds_stack != 0;
+  BlockShare* const sh = ra.share && !lds_only ? &s_share : nullptr;
+  TraceOpts o;
+  o.lds = wave_lds<W>(s_area[wv], lds_only);
+  o.budget = lds_only ? 0 : ra.budget;
+  o.sh = sh;
   const BlobView A = view_of(ra.blob_a), B = view_of(ra.blob_b);
   if (!blobs_ok(A, B, ra, W)) return;
   WaveStats st;
@@ -1225,16 +1258,17 @@ __global__ __launch_bounds__(kBlock, 5) void k_trace(RefineArgs ra) {
         float tb[6];
 #pragma unroll
         for (int c = 0; c < 6; ++c) tb[c] = tmd->box[c];
-        trace_core<W, PREC>(S, T, it.x, it.w & 0xff, tmd->root, tb, pair, dir, (it.w & 256) != 0, ra, s_node[wv],
-                            s_mask[wv], st, false, 0, ra.budget, cid, sh);
+        o.tq = cid;
+        o.seg_max = seg_max_of(ra.seg_table, tmd->n_tris);
+        trace_core<W, PREC, SCHED>(S, T, it.x, it.w & 0xff, tmd->root, tb, pair, dir, (it.w & 256) != 0, ra, st, o);
       }
     }
   }
-  if (sh) block_help<W, PREC>(A, B, ra, sh, s_node[wv], s_mask[wv], st);
+  if (sh) block_help<W, PREC>(A, B, ra, sh, o.lds, st);
   flush_stats(st, ra);
 }
 
-// Schedule 3, phase 3: the stacks that phase 2 handed over, one task (node,
+// Persistent pass, optional phase 3: the stacks that phase 2 handed over, one task (node,
 // lane mask of its group) at a time, popped like the survivors: task list of
 // the block first, then the other lists of its XCD.
 template <int W, int PREC>
@@ -1267,8 +1301,10 @@ __global__ __launch_bounds__(kBlock, 5) void k_trace2(RefineArgs ra) {
       const BlobView& S = dir == 0 ? A : B;
       const BlobView& T = dir == 0 ? B : A;
       const float tb_unused[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};  // the root test was done in phase 2
-      trace_core<W, PREC>(S, T, it.x, it.w & 0xff, it.z, tb_unused, pair, dir, (it.w & 256) != 0, ra, s_node[wv],
-                          s_mask[wv], st, false, m);
+      TraceOpts o;
+      o.lds = wave_lds(s_node[wv], s_mask[wv]);
+      o.start_mask = m;
+      trace_core<W, PREC>(S, T, it.x, it.w & 0xff, it.z, tb_unused, pair, dir, (it.w & 256) != 0, ra, st, o);
     }
   }
   flush_stats(st, ra);
@@ -1359,23 +1395,26 @@ __global__ __launch_bounds__(kBlock) void k_fix(RefineArgs ra) {
 
 __device__ void redecide(const RefineArgs& ra) {
   const BlobView A = view_of(ra.blob_a), B = view_of(ra.blob_b);
-  const uint32_t qn = *ra.qcount;
-  const uint32_t n = qn < ra.qcap ? qn : ra.qcap;
   uint64_t nexact = 0, namb = 0;
-  for (uint32_t k = blockIdx.x * blockDim.x + threadIdx.x; k < n; k += gridDim.x * blockDim.x) {
-    const int4 e = ra.queue[k];
-    if (load_state(ra.state + e.x)) continue;
-    const BlobView& S = e.y == 0 ? A : B;
-    const BlobView& T = e.y == 0 ? B : A;
-    const int64_t slot = e.z;
-    const float* sp = S.seg + (slot / kChunk) * (6 * kChunk) + (slot % kChunk);
-    const f3 p{sp[0], sp[kChunk], sp[2 * kChunk]}, q{sp[3 * kChunk], sp[4 * kChunk], sp[5 * kChunk]};
-    const float* tp = T.tris + 9 * (int64_t)e.w;
-    ExactCounters ec{0};
-    const bool h = seg_tri_exact(p, q, tri_vertex(tp, 0), tri_vertex(tp, 1), tri_vertex(tp, 2), ec);
-    ++nexact;
-    if (ec.exact_signs) ++namb;
-    if (h) mark_true(ra.state + e.x);
+  for (int qx = 0; qx < kSlices; ++qx) {
+    const uint32_t qn = ra.qcount[kQCtrStride * qx];
+    const uint32_t n = qn < ra.qsub ? qn : ra.qsub;
+    const int4* queue = ra.queue + (int64_t)qx * ra.qsub;
+    for (uint32_t k = blockIdx.x * blockDim.x + threadIdx.x; k < n; k += gridDim.x * blockDim.x) {
+      const int4 e = queue[k];
+      if (load_state(ra.state + e.x)) continue;
+      const BlobView& S = e.y == 0 ? A : B;
+      const BlobView& T = e.y == 0 ? B : A;
+      const int64_t slot = e.z;
+      const float* sp = S.seg + (slot / kChunk) * (6 * kChunk) + (slot % kChunk);
+      const f3 p{sp[0], sp[kChunk], sp[2 * kChunk]}, q{sp[3 * kChunk], sp[4 * kChunk], sp[5 * kChunk]};
+      const float* tp = T.tris + 9 * (int64_t)e.w;
+      ExactCounters ec{0};
+      const bool h = seg_tri_exact(p, q, tri_vertex(tp, 0), tri_vertex(tp, 1), tri_vertex(tp, 2), ec);
+      ++nexact;
+      if (ec.exact_signs) ++namb;
+      if (h) mark_true(ra.state + e.x);
+    }
   }
   if (nexact) atomicAdd(stat_copy(ra.stats) + S_EXACT, (unsigned long long)nexact);
   if (namb) atomicAdd(stat_copy(ra.stats) + S_AMB64, (unsigned long long)namb);
@@ -1448,22 +1487,14 @@ __global__ void k_report(RefineArgs ra, pr_refine_stats* out, int32_t* dev_statu
 
 // ---- host side ---------------------------------------------------------------------
 
-struct WsLayout {
-  size_t total;
-  size_t scan_bytes;
-};
-
-int carve(Carve& cv, RefineArgs& ra, int64_t P, uint32_t qcap, uint32_t surv_cap, bool with_tasks, void** scan_tmp,
-          size_t* scan_bytes) {
+void carve(Carve& cv, RefineArgs& ra, int64_t P, uint32_t qcap, uint32_t surv_cap, bool with_tasks) {
   ra.state = cv.take<uint32_t>(P);
-  ra.unit_cnt = cv.take<int64_t>(2 * P + 1);
-  ra.offs = cv.take<int64_t>(2 * P + 1);
   ra.ctr = cv.take<unsigned long long>(kSlices * kCtrStride);
-  ra.qcount = cv.take<uint32_t>(1);
+  ra.qcount = cv.take<uint32_t>(kSlices * kQCtrStride);
   ra.stats = cv.take<unsigned long long>(kStatCopies * kCtrStride);
   ra.status = cv.take<int32_t>(1);
   ra.fin_done = cv.take<unsigned int>(64);
-  ra.queue = cv.take<int4>(qcap);
+  ra.queue = cv.take<int4>((int64_t)kSlices * ((qcap + kSlices - 1) / kSlices));
   ra.surv_cnt = cv.take<unsigned long long>(kQueues * kCtrStride);
   ra.surv_pop = cv.take<unsigned long long>(kQueues * kCtrStride);
   ra.surv = cv.take<int4>((int64_t)kQueues * surv_cap);
@@ -1474,21 +1505,16 @@ int carve(Carve& cv, RefineArgs& ra, int64_t P, uint32_t qcap, uint32_t surv_cap
     ra.task_cnt = cv.take<unsigned long long>(kQueues * kCtrStride);
     ra.task_pop = cv.take<unsigned long long>(kQueues * kCtrStride);
   }
-  size_t b = 0;
-  hipError_t e = hipcub::DeviceScan::ExclusiveSum(nullptr, b, (int64_t*)nullptr, (int64_t*)nullptr, (int)(2 * P + 1));
-  if (e != hipSuccess) return hip_fail(e, "hipcub scan size");
-  *scan_bytes = b;
-  *scan_tmp = cv.take<char>((int64_t)b);
-  return PR_OK;
 }
 
 int check(int64_t P, const pr_refine_params* p) {
   if (!p) { set_error("params is NULL"); return PR_E_ARG; }
   if (!(p->bvh_width == 2 || p->bvh_width == 4 || p->bvh_width == 8)) { set_error("bvh_width must be 2, 4 or 8"); return PR_E_ARG; }
-  if (p->precision < 0 || p->precision > 2) { set_error("precision must be 0, 1 or 2"); return PR_E_ARG; }
+  if (p->precision < 0 || p->precision > 3) { set_error("precision must be 0, 1, 2 or 3"); return PR_E_ARG; }
   if (p->persistent < 0 || p->persistent > 1) { set_error("persistent must be 0 or 1"); return PR_E_ARG; }
-  if (p->queue_cap < 0 || p->grid_blocks < 0 || p->chunks_per_pop < 0) { set_error("negative launch parameter"); return PR_E_ARG; }
-  if (p->schedule < 0 || p->schedule > 3) { set_error("schedule must be 0, 1, 2 or 3"); return PR_E_ARG; }
+  if (p->queue_cap < 0 || p->grid_blocks < 0) { set_error("negative launch parameter"); return PR_E_ARG; }
+  if (p->schedule < 0 || p->schedule > 2) { set_error("schedule must be 0 (auto), 1 (wave-per-pair) or 2 (wave-per-segment)"); return PR_E_ARG; }
+  if (p->lds_stack < 0 || p->lds_stack > 1) { set_error("lds_stack must be 0 or 1"); return PR_E_ARG; }
   if (p->survivor_cap < 0) { set_error("survivor_cap < 0"); return PR_E_ARG; }
   if (p->trace_budget < -1) { set_error("trace_budget < -1"); return PR_E_ARG; }
   if (P < 0) { set_error("n_pairs < 0"); return PR_E_ARG; }
@@ -1546,35 +1572,29 @@ int cu_count(int dev) {
 }
 
 template <int W, int PREC>
-int launch(RefineArgs& ra, const pr_refine_params* prm, void* scan_tmp, size_t scan_bytes, hipStream_t s) {
+int launch(RefineArgs& ra, const pr_refine_params* prm, hipStream_t s) {
   const int64_t P = ra.n_pairs;
   hipEvent_t eb = (hipEvent_t)prm->ev_begin, ee = (hipEvent_t)prm->ev_end;
   if (prm->persistent) {
-    const int sched = prm->schedule == 0 ? 3 : prm->schedule;
-    if (sched != 3) {  // work items: per-unit group counts and their offsets
-      hipLaunchKernelGGL(k_plan<W>, dim3(grid_for(P, kBlock)), dim3(kBlock), 0, s, ra);
-      PR_HIP(hipcub::DeviceScan::ExclusiveSum(scan_tmp, scan_bytes, ra.unit_cnt, ra.offs, (int)(2 * P + 1), s));
-    }
     int dev = 0;
     PR_HIP(hipGetDevice(&dev));
     const int cus = cu_count(dev);
-    const int per = sched == 2   ? blocks_per_cu<k_refine_wave<W, PREC>>(dev)
-                    : sched == 3 ? blocks_per_cu<k_trace<W, PREC>>(dev)
-                                 : blocks_per_cu<k_refine_persistent<W, PREC>>(dev);
-    if (cus <= 0 || per <= 0) { set_error("device attribute query failed"); return PR_E_DEVICE; }
+    // the automatic schedule with an all-zero table is the packet traversal
+    const int sched = prm->schedule == 0 && ra.seg_table == 0u ? 1 : prm->schedule;
+    const int per = sched == 1   ? blocks_per_cu<k_trace<W, PREC, 1>>(dev)
+                    : sched == 2 ? blocks_per_cu<k_trace<W, PREC, 2>>(dev)
+                                 : blocks_per_cu<k_trace<W, PREC, 0>>(dev);
+    const int per_cull = blocks_per_cu<k_cull<W, PREC>>(dev);
+    if (cus <= 0 || per <= 0 || per_cull <= 0) { set_error("device attribute query failed"); return PR_E_DEVICE; }
     const int blocks = prm->grid_blocks > 0 ? prm->grid_blocks : cus * per;
-    int r = PR_OK;
-    if (sched == 2) {
-      r = launch_ra(k_refine_wave<W, PREC>, blocks, s, ra, eb, ee);
-    } else if (sched == 3) {
-      const int per_cull = blocks_per_cu<k_cull<W, PREC>>(dev);
-      if (per_cull <= 0) { set_error("occupancy query failed"); return PR_E_DEVICE; }
-      r = launch_ra(k_cull<W, PREC>, cus * per_cull, s, ra, eb, nullptr);
-      if (r == PR_OK) r = launch_ra(k_trace<W, PREC>, blocks, s, ra, nullptr, ra.budget > 0 ? nullptr : ee);
-      if (r == PR_OK && ra.budget > 0) r = launch_ra(k_trace2<W, PREC>, blocks, s, ra, nullptr, ee);
-    } else {
-      r = launch_ra(k_refine_persistent<W, PREC>, blocks, s, ra, eb, ee);
+    int r = launch_ra(k_cull<W, PREC>, cus * per_cull, s, ra, eb, nullptr);
+    hipEvent_t et = ra.budget > 0 ? nullptr : ee;
+    if (r == PR_OK) {
+      if (sched == 1) r = launch_ra(k_trace<W, PREC, 1>, blocks, s, ra, nullptr, et);
+      else if (sched == 2) r = launch_ra(k_trace<W, PREC, 2>, blocks, s, ra, nullptr, et);
+      else r = launch_ra(k_trace<W, PREC, 0>, blocks, s, ra, nullptr, et);
     }
+    if (r == PR_OK && ra.budget > 0) r = launch_ra(k_trace2<W, PREC>, blocks, s, ra, nullptr, ee);
     if (r != PR_OK) return r;
   } else {
     const int blocks = prm->grid_blocks > 0 ? prm->grid_blocks : 64;
@@ -1585,14 +1605,23 @@ int launch(RefineArgs& ra, const pr_refine_params* prm, void* scan_tmp, size_t s
   return PR_OK;
 }
 
+// Per-bucket wave-per-segment limits of the automatic schedule (one byte per
+// target-size bucket, smallest targets in the low byte).  The built-in table
+// is all zero: on the workloads measured here (pathology-shaped, batching,
+// precision stress) the packet traversal beats wave-per-segment in every
+// bucket, because a group's 64 Morton-ordered segments share most of their
+// path and one node load serves them all.
+uint32_t seg_table_of(const pr_refine_params* p) {
+  if (p->schedule == 1) return 0u;
+  if (p->schedule == 2) return 0xffffffffu;
+  return p->seg_live_max;
+}
+
 // Workspace bytes of a refinement of P pairs with the given queue defaults.
 int ws_needed(int64_t P, const pr_refine_params* params, uint32_t qdef, uint32_t sdef, size_t* bytes) {
   Carve cv{nullptr, 0};
   RefineArgs ra{};
-  void* t;
-  size_t b;
-  int r = carve(cv, ra, P, qcap_of(params, qdef), scap_of(params, sdef), budget_of(params) > 0, &t, &b);
-  if (r) return r;
+  carve(cv, ra, P, qcap_of(params, qdef), scap_of(params, sdef), budget_of(params) > 0);
   *bytes = cv.used + 256;
   return PR_OK;
 }
@@ -1603,14 +1632,12 @@ int refine_run(const void* blob_a, int64_t n_meshes_a, const void* blob_b, int64
                uint32_t sdef, hipStream_t s) {
   RefineArgs ra{};
   Carve cv{(char*)ws, ws_bytes};
-  void* scan_tmp = nullptr;
-  size_t scan_bytes = 0;
   const uint32_t qcap = qcap_of(params, qdef);
   const uint32_t scap = scap_of(params, sdef);
   const int budget = budget_of(params);
-  int r = carve(cv, ra, n_pairs, qcap, scap, budget > 0, &scan_tmp, &scan_bytes);
-  if (r) return r;
-  if (cv.used > ws_bytes || !scan_tmp) { set_error("ws_bytes %zu < required %zu", ws_bytes, cv.used); return PR_E_CAPACITY; }
+  carve(cv, ra, n_pairs, qcap, scap, budget > 0);
+  if (cv.used > ws_bytes) { set_error("ws_bytes %zu < required %zu", ws_bytes, cv.used); return PR_E_CAPACITY; }
+  int r = PR_OK;
   ra.blob_a = (const char*)blob_a;
   ra.blob_b = (const char*)blob_b;
   ra.n_meshes_a = n_meshes_a;
@@ -1620,19 +1647,20 @@ int refine_run(const void* blob_a, int64_t n_meshes_a, const void* blob_b, int64
   ra.np_dev = params->dev_n_pairs;
   ra.flags = flags;
   ra.qcap = qcap;
+  ra.qsub = (qcap + kSlices - 1) / kSlices;
   ra.surv_cap = scap;
-  ra.item_groups = params->chunks_per_pop > 0 ? params->chunks_per_pop : 256;
   ra.budget = budget;
   ra.share = params->trace_budget == 0 && budget == 0 ? 1 : 0;
-  if (ra.item_groups > kMaxItemGroups) ra.item_groups = kMaxItemGroups;
+  ra.lds_stack = params->lds_stack;
+  ra.seg_table = seg_table_of(params);
   hipLaunchKernelGGL(k_init, dim3(grid_for(n_pairs > kStatCopies * S_N ? n_pairs : kStatCopies * S_N, kBlock)),
                      dim3(kBlock), 0, s, ra);
   if (n_pairs > 0) {
     const int W = params->bvh_width, PREC = params->precision;
-#define PR_LAUNCH(w, q) if (W == w && PREC == q) r = launch<w, q>(ra, params, scan_tmp, scan_bytes, s)
-    PR_LAUNCH(2, 0); PR_LAUNCH(2, 1); PR_LAUNCH(2, 2);
-    PR_LAUNCH(4, 0); PR_LAUNCH(4, 1); PR_LAUNCH(4, 2);
-    PR_LAUNCH(8, 0); PR_LAUNCH(8, 1); PR_LAUNCH(8, 2);
+#define PR_LAUNCH(w, q) if (W == w && PREC == q) r = launch<w, q>(ra, params, s)
+    PR_LAUNCH(2, 0); PR_LAUNCH(2, 1); PR_LAUNCH(2, 2); PR_LAUNCH(2, 3);
+    PR_LAUNCH(4, 0); PR_LAUNCH(4, 1); PR_LAUNCH(4, 2); PR_LAUNCH(4, 3);
+    PR_LAUNCH(8, 0); PR_LAUNCH(8, 1); PR_LAUNCH(8, 2); PR_LAUNCH(8, 3);
 #undef PR_LAUNCH
     if (r) return r;
     const int fb = 1024;  // enough threads for the deferred tests, blocks for the reruns

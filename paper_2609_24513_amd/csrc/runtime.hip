@@ -19,6 +19,12 @@ __global__ void k_boxes(const void* blob, int64_t n, float* boxes) {
     for (int k = 0; k < 6; ++k) boxes[6 * m + k] = md[m].box[k];
 }
 
+__global__ void k_exponents(const void* blob, int32_t* out) {
+  const BlobHeader* h = reinterpret_cast<const BlobHeader*>(blob);
+  out[0] = h->exp_lo;
+  out[1] = h->exp_hi;
+}
+
 __global__ void k_edges(const void* blob, int64_t n, int32_t* counts) {
   const BlobHeader* h = reinterpret_cast<const BlobHeader*>(blob);
   const MeshDesc* md = reinterpret_cast<const MeshDesc*>(reinterpret_cast<const char*>(blob) + h->off_mesh);
@@ -59,6 +65,13 @@ extern "C" int blob_edge_counts(const void* blob, int64_t n_meshes, int32_t* cou
   if (n_meshes == 0) return PR_OK;
   hipLaunchKernelGGL(pr::k_edges, dim3(pr::grid_for(n_meshes, 256)), dim3(256), 0, (hipStream_t)stream, blob,
                      n_meshes, counts);
+  PR_HIP(hipGetLastError());
+  return PR_OK;
+}
+
+extern "C" int blob_coord_exponents(const void* blob, int32_t* exps, void* stream) {
+  if (!blob || !exps) { pr::set_error("bad argument"); return PR_E_ARG; }
+  hipLaunchKernelGGL(pr::k_exponents, dim3(1), dim3(1), 0, (hipStream_t)stream, blob, exps);
   PR_HIP(hipGetLastError());
   return PR_OK;
 }

@@ -61,6 +61,23 @@ def test_bvh_sizes_rejected(lib):
     assert lib.build_mesh_bvh_sizes(1, 4, 4, None, ctypes.byref(bb), ctypes.byref(wb)) == _lib.PR_E_ARG
 
 
+def test_blob_bytes_bound(lib):
+    """build_mesh_bvh_bytes equals the blob bound of build_mesh_bvh_sizes and is
+    0 for rejected arguments."""
+    for w, l in ((2, 1), (4, 4), (8, 8)):
+        p = _lib.BvhParams(w, l, 0, 0)
+        n = lib.build_mesh_bvh_bytes(10, 5000, 2600, ctypes.byref(p))
+        assert n > 5000 * 36 + 7500 * 24
+        assert lib.build_mesh_bvh_bytes(10, 10000, 5200, ctypes.byref(p)) > n
+        bb, wb = ctypes.c_size_t(0), ctypes.c_size_t(0)
+        # the workspace query needs the HIP runtime; where it answers, the bounds agree
+        if lib.build_mesh_bvh_sizes(10, 5000, 2600, ctypes.byref(p), ctypes.byref(bb), ctypes.byref(wb)) == 0:
+            assert bb.value == n
+    bad = _lib.BvhParams(3, 4, 0, 0)
+    assert lib.build_mesh_bvh_bytes(10, 5000, 2600, ctypes.byref(bad)) == 0
+    assert lib.build_mesh_bvh_bytes(-1, 5000, 2600, ctypes.byref(_lib.BvhParams(4, 4, 0, 0))) == 0
+
+
 def test_build_null_pointers_rejected(lib):
     p = _lib.BvhParams(4, 4, 0, 0)
     assert lib.build_mesh_bvh(None, None, None, None, 1, 3, 1, ctypes.byref(p), None, 0, None, 0, None,
@@ -74,21 +91,33 @@ def _refine_params(**kw):
     p.precision = kw.get("precision", 0)
     p.queue_cap = kw.get("queue_cap", 0)
     p.grid_blocks = kw.get("grid_blocks", 0)
-    p.chunks_per_pop = kw.get("chunks_per_pop", 0)
+    p.seg_live_max = kw.get("seg_live_max", 0)
     p.schedule = kw.get("schedule", 0)
     p.trace_budget = kw.get("trace_budget", 0)
+    p.lds_stack = kw.get("lds_stack", 0)
     return p
 
 
-@pytest.mark.parametrize("kw", [dict(w=3), dict(precision=3), dict(persistent=2), dict(queue_cap=-1),
-                                dict(grid_blocks=-5), dict(schedule=4), dict(schedule=-1),
-                                dict(trace_budget=-2)])
+@pytest.mark.parametrize("kw", [dict(w=3), dict(precision=4), dict(precision=-1), dict(persistent=2),
+                                dict(queue_cap=-1), dict(grid_blocks=-5), dict(schedule=3), dict(schedule=-1),
+                                dict(trace_budget=-2), dict(lds_stack=2), dict(lds_stack=-1)])
 def test_refine_params_rejected(lib, kw):
     p = _refine_params(**kw)
     wb = ctypes.c_size_t(0)
     assert lib.refine_workspace_bytes(10, ctypes.byref(p), ctypes.byref(wb)) == _lib.PR_E_ARG
     assert lib.refine_intersects(None, 1, None, 1, None, 10, None, ctypes.byref(p), None, None, None, 0,
                                  None) == _lib.PR_E_ARG
+
+
+@pytest.mark.parametrize("kw", [dict(schedule=0), dict(schedule=1), dict(schedule=2), dict(precision=3),
+                                dict(lds_stack=1), dict(seg_live_max=0x10203040)])
+def test_refine_params_accepted(lib, kw):
+    """Every schedule (auto, wave-per-pair, wave-per-segment), precision 3,
+    the LDS stack and a per-bucket table are valid parameters."""
+    p = _refine_params(**kw)
+    wb = ctypes.c_size_t(0)
+    assert lib.refine_workspace_bytes(10, ctypes.byref(p), ctypes.byref(wb)) == _lib.PR_OK
+    assert wb.value > 0
 
 
 def test_refine_reserved_and_sizes_rejected(lib):
@@ -112,6 +141,7 @@ def test_filter_compact_and_gather_args_rejected(lib):
     assert lib.compact_pairs(None, None, 5, None, None, 0, None, None, 0, None) == _lib.PR_E_ARG
     assert lib.blob_mesh_boxes(None, 3, None, None) == _lib.PR_E_ARG
     assert lib.blob_edge_counts(None, 3, None, None) == _lib.PR_E_ARG
+    assert lib.blob_coord_exponents(None, None, None) == _lib.PR_E_ARG
     # gather: null total, negative sizes, null inputs with regions, too many regions
     assert lib.gather_pair_regions(None, 4, None, 0, None, 0, None, None) == _lib.PR_E_ARG
     dummy = ctypes.c_int64(0)

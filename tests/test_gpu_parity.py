@@ -49,7 +49,7 @@ def _run(env, A, B, pairs, width=4, leaf=4, **cfg):
 
 
 CONFIGS = [dict(width=w, leaf=l, persistent=p, precision=q, schedule=sc)
-           for w in (2, 4, 8) for l in (1, 4, 8) for p in (0, 1) for q in (0, 1, 2) for sc in (1, 2, 3)
+           for w in (2, 4, 8) for l in (1, 4, 8) for p in (0, 1) for q in (0, 1, 2, 3) for sc in (0, 1, 2)
            if not (l == 8 and q == 1) and not (p == 0 and sc != 1)]
 
 
@@ -241,12 +241,14 @@ def test_c3_scaled_all_widths_and_schedules(env):
         for l in (1, 2, 4, 8):
             ga = pa.MeshBlob.build(A, width=w, leaf_size=l)
             gb = pa.MeshBlob.build(B, width=w, leaf_size=l)
-            for cfg in (dict(schedule=1), dict(schedule=2), dict(schedule=3), dict(schedule=1, chunks_per_pop=1),
-                        dict(schedule=2, chunks_per_pop=64), dict(schedule=3, survivor_cap=50),
-                        dict(schedule=3, chunks_per_pop=64, survivor_cap=8), dict(schedule=3, grid_blocks=5),
-                        dict(schedule=3, grid_blocks=100), dict(schedule=3, trace_budget=1),
-                        dict(schedule=3, trace_budget=3, grid_blocks=7), dict(schedule=3, trace_budget=-1),
-                        dict(schedule=3, grid_blocks=1), dict(schedule=3, grid_blocks=2, survivor_cap=50)):
+            for cfg in (dict(schedule=0), dict(schedule=1), dict(schedule=2), dict(schedule=0, seg_live_max=0x40201008),
+                        dict(schedule=2, survivor_cap=50), dict(schedule=1, survivor_cap=50),
+                        dict(schedule=1, survivor_cap=8), dict(schedule=1, grid_blocks=5),
+                        dict(schedule=2, grid_blocks=100), dict(schedule=1, trace_budget=1),
+                        dict(schedule=1, trace_budget=3, grid_blocks=7), dict(schedule=1, trace_budget=-1),
+                        dict(schedule=1, grid_blocks=1), dict(schedule=0, grid_blocks=2, survivor_cap=50),
+                        dict(schedule=1, lds_stack=1), dict(schedule=0, lds_stack=1, grid_blocks=3),
+                        dict(schedule=1, precision=3), dict(schedule=2, precision=1)):
                 flags, stats, status = pa.refine(ga, gb, pairs, pa.RefineConfig(persistent=1, **cfg))
                 torch.cuda.synchronize()
                 assert int(status.item()) == 0
@@ -267,7 +269,7 @@ def test_many_units_per_wave_cull(env):
     want = oracle.join(A, B, pairs, mode=1)
     assert 0 < want.sum() < pairs.shape[0]
     for prec in (0, 1):
-        got, _ = _run(env, A, B, pairs, persistent=1, schedule=3, precision=prec)
+        got, _ = _run(env, A, B, pairs, persistent=1, schedule=1, precision=prec)
         assert np.array_equal(got, want), prec
 
 
@@ -282,14 +284,14 @@ def test_block_sharing_matches_unshared(env):
     ga, gb = pa.MeshBlob.build(A), pa.MeshBlob.build(B)
     for cfg in (dict(grid_blocks=1), dict(grid_blocks=2), dict(), dict(trace_budget=-1, grid_blocks=1)):
         for prec in (0, 1):
-            flags, stats, status = pa.refine(ga, gb, pairs, pa.RefineConfig(persistent=1, schedule=3, precision=prec,
+            flags, stats, status = pa.refine(ga, gb, pairs, pa.RefineConfig(persistent=1, schedule=1, precision=prec,
                                                                             **cfg))
             torch.cuda.synchronize()
             assert int(status.item()) == 0, (cfg, prec)
             assert np.array_equal(flags.cpu().numpy(), want), (cfg, prec)
 
 
-@pytest.mark.parametrize("schedule", [1, 2, 3])
+@pytest.mark.parametrize("schedule", [0, 1, 2])
 def test_device_pair_count(env, schedule):
     """Filter -> refine -> compaction with the pair count left on the device:
     rows past the count are invalid padding that must be ignored, and the
@@ -317,7 +319,7 @@ def test_autotune_small(env):
     torch, pa, synth, oracle = env
     from paper_2609_24513_amd import autotune
     A, B, pairs = synth.make_c3(n_pairs=1500, n_pool=128, f_hi=8000.0)
-    res = autotune.tune(A, B, pairs, widths=(2, 4), leaves=(1, 4), schedules=(1, 2, 3), frac=0.2, reps=2,
+    res = autotune.tune(A, B, pairs, widths=(2, 4), leaves=(1, 4), schedules=(0, 1, 2), frac=0.2, reps=2,
                         use_cache=False)
     assert len(res["table"]) == 12
     b = res["best"]
@@ -362,7 +364,7 @@ def test_c3_full_size_against_oracle(env):
     A, B, pairs = synth.make_c3()
     want = _c3_expected(A, B, pairs)
     assert want.shape[0] == 50_000 and 0 < want.sum() < 50_000
-    for sc in (3, 1):
+    for sc in (1, 2, 0):
         got, st = _run(env, A, B, pairs, persistent=1, schedule=sc)
         assert int((got != want).sum()) == 0, sc
         assert st["pairs_true"] == int(want.sum())
