@@ -216,7 +216,7 @@ def run_join(name: str, args, tune: bool, plain: bool, compare_precision: bool, 
             g4a, g4b = pa.MeshBlob.build(A), pa.MeshBlob.build(B)
             pairs_for_tune = pa.filter_pairs(g4a, g4b).cpu().numpy()
             del g4a, g4b
-        tuned = autotune.tune(A, B, pairs_for_tune, log=log)
+        tuned = autotune.tune(A, B, pairs_for_tune, frac=args.tune_frac, log=log)
         W, L, sched = tuned["best"]["width"], tuned["best"]["leaf_size"], tuned["best"]["schedule"]
         table = tuned["best"].get("seg_live_max", 0)
         log("%s: autotune picked W=%d L=%d schedule=%d table=%08x (%.1f s, cached=%s)" % (
@@ -451,6 +451,8 @@ def main():
                     help="0 = library default (waves of a block share pending subtrees), > 0 = steps before a long "
                          "group hands its stack to a continuation pass, -1 = no hand-over")
     ap.add_argument("--no-tune", action="store_true", help="use --width/--leaf/--schedule instead of the autotuner")
+    ap.add_argument("--tune-frac", type=float, default=0.25,
+                    help="autotuner sample (stratified by pair size); the blob builds dominate its time")
     ap.add_argument("--no-extras", action="store_true", help="headline workload only")
     ap.add_argument("--serve-requests", type=int, default=1000, help="requests at the highest serving rate")
     ap.add_argument("--plain-requests", type=int, default=200, help="requests replayed on the plain path")

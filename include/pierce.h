@@ -73,7 +73,10 @@ int pr_abi_version(void);
 typedef struct {
   int32_t width;      /* 2, 4 or 8 children per node */
   int32_t leaf_size;  /* 1, 2, 4 or 8 triangles per leaf at most */
-  int32_t builder;    /* 0: LBVH (Morton order) collapsed by largest-surface-area expansion */
+  int32_t builder;    /* LBVH (Morton order, Karras radix tree) collapsed to width W by
+                         greedy expansion: 0 opens the child of largest surface area,
+                         1 the child of largest surface area x triangle count (its term
+                         of the surface-area cost) */
   int32_t reserved;   /* must be 0 */
 } pr_bvh_params;
 

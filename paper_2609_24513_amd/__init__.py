@@ -66,9 +66,12 @@ class MeshBlob:
         return int(self.blob.data_ptr())
 
     @classmethod
-    def build(cls, meshes, width: int = 4, leaf_size: int = 4, stream=None, check_status: bool = True):
+    def build(cls, meshes, width: int = 4, leaf_size: int = 4, stream=None, check_status: bool = True,
+              builder: int = 0):
         """meshes: object with verts f32[V,3], faces i32[F,3] (mesh-local ids),
-        vert_off i64[M+1], face_off i64[M+1] (numpy arrays or tensors)."""
+        vert_off i64[M+1], face_off i64[M+1] (numpy arrays or tensors).
+        builder 0: the collapse opens the largest-area child; 1: the child of
+        largest area x triangle count."""
         torch = _torch()
         lib = _lib.load()
         verts = _dev(meshes.verts, torch.float32).reshape(-1, 3)
@@ -76,7 +79,7 @@ class MeshBlob:
         vo = _dev(meshes.vert_off, torch.int64)
         fo = _dev(meshes.face_off, torch.int64)
         M, V, F = int(vo.numel() - 1), int(verts.shape[0]), int(faces.shape[0])
-        prm = _lib.BvhParams(width, leaf_size, 0, 0)
+        prm = _lib.BvhParams(width, leaf_size, builder, 0)
         bb, wb = ctypes.c_size_t(0), ctypes.c_size_t(0)
         _lib.check(lib.build_mesh_bvh_sizes(M, F, V, ctypes.byref(prm), ctypes.byref(bb), ctypes.byref(wb)))
         blob = torch.empty(int(bb.value), dtype=torch.uint8, device="cuda")
@@ -88,6 +91,7 @@ class MeshBlob:
         exps = torch.empty(2, dtype=torch.int32, device="cuda")
         _lib.check(lib.blob_coord_exponents(blob.data_ptr(), exps.data_ptr(), _stream_ptr(stream)))
         out = cls(blob, M, width, leaf_size, status, exps)
+        out.builder = int(builder)
         if check_status:
             st = int(status.item())
             if st != -1:

@@ -73,6 +73,7 @@ struct BuildArgs {
   const int64_t* face_off;
   int64_t n_meshes, v_total, f_total;
   int width, leaf;
+  int builder;           // 0: open the largest-area child, 1: the largest area x triangle count
   // blob sections
   char* blob;
   MeshDesc* mesh;
@@ -381,102 +382,143 @@ __device__ __forceinline__ float half_area(const float* b) {
   return dx * dy + dy * dz + dz * dx;
 }
 
+// Collapse of each mesh's binary tree into a width-W tree, one block per
+// mesh, one level of wide nodes per round.  An item is (binary subtree root,
+// wide slot, depth); the block's threads take the items of the current
+// level one each.  A thread starts from the two children of its binary node
+// and keeps opening one of them until it holds W children or none can be
+// opened (only subtrees of more than L triangles are opened): builder 0 opens
+// the child of largest surface area, builder 1 the child of largest surface
+// area x triangle count (its term of the surface-area cost).  It writes the
+// wide node and appends an item, with a fresh slot, for every child that
+// needs a wide node of its own.  Slots are numbered in creation order (root
+// 0), so the top levels of a tree sit together.  Items live in the mesh's
+// part of the work array (at most one per internal binary node).
+template <int W>
+__device__ void collapse_item(const BuildArgs& a, Node<W>* nodes, int64_t nb, int64_t bound, int32_t* items,
+                              int it, int32_t* s_used, int32_t* s_tail, int32_t* s_depth, int32_t* s_over) {
+  const int32_t x = items[3 * it], w = items[3 * it + 1], dep = items[3 * it + 2];
+  atomicMax(s_depth, dep);
+  const int L = a.leaf;
+  int32_t S[W];
+  float Sb[W][6];
+  int32_t Sc[W], Sf[W];
+  int ns = 2;
+  S[0] = a.left[x];
+  S[1] = a.right[x];
+  child_info(a, S[0], a.val1, Sb[0], Sc[0], Sf[0]);
+  child_info(a, S[1], a.val1, Sb[1], Sc[1], Sf[1]);
+  while (ns < W) {
+    int best = -1;
+    float bscore = -1.f;
+    for (int k = 0; k < ns; ++k)
+      if (S[k] >= 0 && Sc[k] > L) {
+        const float ar = half_area(Sb[k]);
+        const float score = a.builder == 1 ? ar * (float)Sc[k] : ar;
+        if (score > bscore) { bscore = score; best = k; }
+      }
+    if (best < 0) break;
+    const int32_t y = S[best];
+    S[best] = a.left[y];
+    S[ns] = a.right[y];
+    child_info(a, S[best], a.val1, Sb[best], Sc[best], Sf[best]);
+    child_info(a, S[ns], a.val1, Sb[ns], Sc[ns], Sf[ns]);
+    ++ns;
+  }
+  Node<W> nd;
+  for (int c = 0; c < W; ++c) {
+    nd.pad[c] = 0;
+    if (c < ns) {
+      for (int k = 0; k < 3; ++k) { nd.lo[k][c] = Sb[c][k]; nd.hi[k][c] = Sb[c][3 + k]; }
+      if (Sc[c] <= L) {
+        nd.child[c] = leaf_ref(Sf[c], Sc[c]);
+      } else {
+        const int32_t slot = atomicAdd(s_used, 1);
+        if (slot >= bound) {
+          *s_over = 1;
+          nd.child[c] = kEmpty;
+          continue;
+        }
+        nd.child[c] = (int32_t)(nb + slot);
+        const int32_t pos = atomicAdd(s_tail, 1);
+        items[3 * pos] = S[c];
+        items[3 * pos + 1] = slot;
+        items[3 * pos + 2] = dep + 1;
+      }
+    } else {
+      for (int k = 0; k < 3; ++k) { nd.lo[k][c] = INFINITY; nd.hi[k][c] = -INFINITY; }
+      nd.child[c] = kEmpty;
+    }
+  }
+  nodes[nb + w] = nd;
+}
+
 template <int W>
 __global__ void k_collapse(BuildArgs a, const int64_t* node_base_scan) {
+  __shared__ int32_t s_used, s_tail, s_depth, s_over;
   if (*a.status != INT_MAX) return;  // invalid input: the blob is not built
-  int64_t m = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  for (; m < a.n_meshes; m += (int64_t)gridDim.x * blockDim.x) {
-    MeshDesc d = a.mesh[m];
-    int n = d.n_tris;
-    int64_t fbase = a.face_off[m];
-    int64_t nb = node_base_scan[m];
-    int64_t bound = node_base_scan[m + 1] - nb;
-    Node<W>* nodes = reinterpret_cast<Node<W>*>(a.tnodes);
+  Node<W>* nodes = reinterpret_cast<Node<W>*>(a.tnodes);
+  for (int64_t m = blockIdx.x; m < a.n_meshes; m += gridDim.x) {
+    const int n = a.mesh[m].n_tris;
+    const int64_t fbase = a.face_off[m];
+    const int64_t nb = node_base_scan[m];
+    const int64_t bound = node_base_scan[m + 1] - nb;
     if (n == 0) {
-      a.mesh[m].root = kEmpty;
-      a.mesh[m].n_nodes = 0;
-      a.mesh[m].node_base = (int32_t)nb;
+      if (threadIdx.x == 0) {
+        a.mesh[m].root = kEmpty;
+        a.mesh[m].n_nodes = 0;
+        a.mesh[m].node_base = (int32_t)nb;
+      }
       continue;
     }
-    int L = a.leaf;
-    int32_t used = 1;
-    int depth = 1;
-    bool overflow = false;
-    if (n <= L) {
-      Node<W> nd;
-      for (int c = 0; c < W; ++c) {
-        for (int k = 0; k < 3; ++k) { nd.lo[k][c] = INFINITY; nd.hi[k][c] = -INFINITY; }
-        nd.child[c] = kEmpty;
-        nd.pad[c] = 0;
-      }
-      for (int k = 0; k < 3; ++k) { nd.lo[k][0] = d.box[k]; nd.hi[k][0] = d.box[3 + k]; }
-      nd.child[0] = leaf_ref((int32_t)fbase, n);
-      nodes[nb] = nd;
-    } else {
-      // stack entries: (binary node, wide slot, depth)
-      int32_t* st = a.stk + 3 * fbase;
-      int sp = 0;
-      st[0] = (int32_t)fbase;  // binary root: internal node 0 of the mesh
-      st[1] = 0;
-      st[2] = 1;
-      sp = 1;
-      while (sp > 0) {
-        --sp;
-        int32_t x = st[3 * sp], w = st[3 * sp + 1], dep = st[3 * sp + 2];
-        if (dep > depth) depth = dep;
-        int32_t S[W];
-        float Sb[W][6];
-        int32_t Sc[W], Sf[W];
-        int ns = 2;
-        S[0] = a.left[x];
-        S[1] = a.right[x];
-        child_info(a, S[0], a.val1, Sb[0], Sc[0], Sf[0]);
-        child_info(a, S[1], a.val1, Sb[1], Sc[1], Sf[1]);
-        while (ns < W) {
-          int best = -1;
-          float barea = -1.f;
-          for (int k = 0; k < ns; ++k)
-            if (S[k] >= 0 && Sc[k] > L) {
-              float ar = half_area(Sb[k]);
-              if (ar > barea) { barea = ar; best = k; }
-            }
-          if (best < 0) break;
-          int32_t y = S[best];
-          S[best] = a.left[y];
-          S[ns] = a.right[y];
-          child_info(a, S[best], a.val1, Sb[best], Sc[best], Sf[best]);
-          child_info(a, S[ns], a.val1, Sb[ns], Sc[ns], Sf[ns]);
-          ++ns;
-        }
+    if (n <= a.leaf) {
+      if (threadIdx.x == 0) {
+        const MeshDesc d = a.mesh[m];
         Node<W> nd;
         for (int c = 0; c < W; ++c) {
-          if (c < ns) {
-            for (int k = 0; k < 3; ++k) { nd.lo[k][c] = Sb[c][k]; nd.hi[k][c] = Sb[c][3 + k]; }
-            if (Sc[c] <= L) {
-              nd.child[c] = leaf_ref(Sf[c], Sc[c]);
-            } else {
-              int32_t slot = used++;
-              if (slot >= bound) { overflow = true; nd.child[c] = kEmpty; continue; }
-              nd.child[c] = (int32_t)(nb + slot);
-              st[3 * sp] = S[c];
-              st[3 * sp + 1] = slot;
-              st[3 * sp + 2] = dep + 1;
-              ++sp;
-            }
-          } else {
-            for (int k = 0; k < 3; ++k) { nd.lo[k][c] = INFINITY; nd.hi[k][c] = -INFINITY; }
-            nd.child[c] = kEmpty;
-          }
+          for (int k = 0; k < 3; ++k) { nd.lo[k][c] = INFINITY; nd.hi[k][c] = -INFINITY; }
+          nd.child[c] = kEmpty;
           nd.pad[c] = 0;
         }
-        nodes[nb + w] = nd;
+        for (int k = 0; k < 3; ++k) { nd.lo[k][0] = d.box[k]; nd.hi[k][0] = d.box[3 + k]; }
+        nd.child[0] = leaf_ref((int32_t)fbase, n);
+        nodes[nb] = nd;
+        a.mesh[m].node_base = (int32_t)nb;
+        a.mesh[m].root = (int32_t)nb;
+        a.mesh[m].n_nodes = 1;
+        a.mesh[m].depth = 1;
       }
+      continue;
     }
-    if (overflow || depth > kMaxDepth) atomicMin(a.status, (int32_t)fbase);
-    a.mesh[m].node_base = (int32_t)nb;
-    a.mesh[m].root = (int32_t)nb;
-    a.mesh[m].n_nodes = used;
-    a.mesh[m].depth = depth;
+    int32_t* items = a.stk + 3 * fbase;
+    if (threadIdx.x == 0) {
+      items[0] = (int32_t)fbase;  // binary root: internal node 0 of the mesh
+      items[1] = 0;
+      items[2] = 1;
+      s_used = 1;
+      s_tail = 1;
+      s_depth = 1;
+      s_over = 0;
+    }
+    __syncthreads();
+    int head = 0;
+    for (;;) {
+      const int tail = s_tail;
+      __syncthreads();  // every thread has the level's end before items are appended
+      if (head >= tail) break;
+      for (int it = head + (int)threadIdx.x; it < tail; it += (int)blockDim.x)
+        collapse_item<W>(a, nodes, nb, bound, items, it, &s_used, &s_tail, &s_depth, &s_over);
+      head = tail;
+      __syncthreads();  // the next level's items are written
+    }
+    if (threadIdx.x == 0) {
+      if (s_over || s_depth > kMaxDepth) atomicMin(a.status, (int32_t)fbase);
+      a.mesh[m].node_base = (int32_t)nb;
+      a.mesh[m].root = (int32_t)nb;
+      a.mesh[m].n_nodes = s_used < bound ? s_used : (int32_t)bound;
+      a.mesh[m].depth = s_depth;
+    }
+    __syncthreads();
   }
 }
 
@@ -814,7 +856,8 @@ int check_params(int64_t M, int64_t F, int64_t V, const pr_bvh_params* p) {
     set_error("leaf_size must be 1, 2, 4 or 8");
     return PR_E_ARG;
   }
-  if (p->builder != 0 || p->reserved != 0) { set_error("builder and reserved must be 0"); return PR_E_ARG; }
+  if (p->builder < 0 || p->builder > 1) { set_error("builder must be 0 or 1"); return PR_E_ARG; }
+  if (p->reserved != 0) { set_error("reserved must be 0"); return PR_E_ARG; }
   if (M < 0 || F < 0 || V < 0) { set_error("negative size"); return PR_E_ARG; }
   if (M == 0 && (F > 0 || V > 0)) { set_error("faces or vertices without meshes"); return PR_E_ARG; }
   if (F >= ((int64_t)1 << 28) || V >= ((int64_t)1 << 31) || M >= ((int64_t)1 << 24)) {
@@ -876,6 +919,7 @@ extern "C" int build_mesh_bvh(const float* verts, const int64_t* vert_off, const
   if (cv.used > ws_bytes || !tmp) { set_error("ws_bytes %zu < required %zu", ws_bytes, cv.used); return PR_E_CAPACITY; }
   a.verts = verts; a.vert_off = vert_off; a.faces = faces; a.face_off = face_off;
   a.n_meshes = n_meshes; a.v_total = v_total; a.f_total = f_total; a.width = W; a.leaf = L;
+  a.builder = params->builder;
   a.blob = (char*)blob;
   a.mesh = reinterpret_cast<MeshDesc*>(a.blob + y.off_mesh);
   a.nodes = a.blob + y.off_node;
@@ -915,9 +959,10 @@ extern "C" int build_mesh_bvh(const float* verts, const int64_t* vert_off, const
   if (M > 0) {
     hipLaunchKernelGGL(k_node_bound, dim3(gM), dim3(kBlock), 0, s, a);
     PR_HIP(hipcub::DeviceScan::ExclusiveSum(tmp, tmp_bytes, a.nbound, a.nscan, (int)(M + 1), s));
-    if (W == 2) hipLaunchKernelGGL(k_collapse<2>, dim3(gM), dim3(kBlock), 0, s, a, (const int64_t*)a.nscan);
-    else if (W == 4) hipLaunchKernelGGL(k_collapse<4>, dim3(gM), dim3(kBlock), 0, s, a, (const int64_t*)a.nscan);
-    else hipLaunchKernelGGL(k_collapse<8>, dim3(gM), dim3(kBlock), 0, s, a, (const int64_t*)a.nscan);
+    const int gC = (int)(M < 65536 ? M : 65536);  // one block per mesh
+    if (W == 2) hipLaunchKernelGGL(k_collapse<2>, dim3(gC), dim3(kBlock), 0, s, a, (const int64_t*)a.nscan);
+    else if (W == 4) hipLaunchKernelGGL(k_collapse<4>, dim3(gC), dim3(kBlock), 0, s, a, (const int64_t*)a.nscan);
+    else hipLaunchKernelGGL(k_collapse<8>, dim3(gC), dim3(kBlock), 0, s, a, (const int64_t*)a.nscan);
     hipLaunchKernelGGL(k_node_count, dim3(gM), dim3(kBlock), 0, s, a);
     PR_HIP(hipcub::DeviceScan::ExclusiveSum(tmp, tmp_bytes, a.ncount, a.nbound, (int)(M + 1), s));
     const int gMB = (int)(M < 65536 ? M : 65536);

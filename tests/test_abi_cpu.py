@@ -44,7 +44,8 @@ def test_struct_sizes():
     assert ctypes.sizeof(_lib.RefineStats) == 112
 
 
-@pytest.mark.parametrize("w,l,b,r", [(3, 4, 0, 0), (4, 3, 0, 0), (4, 4, 1, 0), (4, 4, 0, 1), (16, 4, 0, 0)])
+@pytest.mark.parametrize("w,l,b,r", [(3, 4, 0, 0), (4, 3, 0, 0), (4, 4, 2, 0), (4, 4, -1, 0), (4, 4, 0, 1),
+                                     (16, 4, 0, 0)])
 def test_bvh_params_rejected(lib, w, l, b, r):
     p = _lib.BvhParams(w, l, b, r)
     bb, wb = ctypes.c_size_t(0), ctypes.c_size_t(0)
@@ -75,6 +76,9 @@ def test_blob_bytes_bound(lib):
             assert bb.value == n
     bad = _lib.BvhParams(3, 4, 0, 0)
     assert lib.build_mesh_bvh_bytes(10, 5000, 2600, ctypes.byref(bad)) == 0
+    # both builders (greedy largest-area / area x triangle-count collapse) are accepted
+    assert lib.build_mesh_bvh_bytes(10, 5000, 2600, ctypes.byref(_lib.BvhParams(4, 4, 1, 0))) == \
+        lib.build_mesh_bvh_bytes(10, 5000, 2600, ctypes.byref(_lib.BvhParams(4, 4, 0, 0)))
     assert lib.build_mesh_bvh_bytes(-1, 5000, 2600, ctypes.byref(_lib.BvhParams(4, 4, 0, 0))) == 0
 
 

@@ -38,23 +38,23 @@ def _hand(synth):
     return A, B, pairs, exp
 
 
-def _run(env, A, B, pairs, width=4, leaf=4, **cfg):
+def _run(env, A, B, pairs, width=4, leaf=4, builder=0, **cfg):
     torch, pa, synth, oracle = env
-    ga = pa.MeshBlob.build(A, width=width, leaf_size=leaf)
-    gb = pa.MeshBlob.build(B, width=width, leaf_size=leaf)
+    ga = pa.MeshBlob.build(A, width=width, leaf_size=leaf, builder=builder)
+    gb = pa.MeshBlob.build(B, width=width, leaf_size=leaf, builder=builder)
     flags, stats, status = pa.refine(ga, gb, pairs, pa.RefineConfig(**cfg))
     torch.cuda.synchronize()
     assert int(status.item()) == 0
     return flags.cpu().numpy(), pa.stats_dict(stats)
 
 
-CONFIGS = [dict(width=w, leaf=l, persistent=p, precision=q, schedule=sc)
+CONFIGS = [dict(width=w, leaf=l, persistent=p, precision=q, schedule=sc, builder=(w + l + q) % 2)
            for w in (2, 4, 8) for l in (1, 4, 8) for p in (0, 1) for q in (0, 1, 2, 3) for sc in (0, 1, 2)
            if not (l == 8 and q == 1) and not (p == 0 and sc != 1)]
 
 
-@pytest.mark.parametrize("c", CONFIGS, ids=lambda c: "w%d_l%d_p%d_q%d_s%d" % (
-    c["width"], c["leaf"], c["persistent"], c["precision"], c["schedule"]))
+@pytest.mark.parametrize("c", CONFIGS, ids=lambda c: "w%d_l%d_p%d_q%d_s%d_b%d" % (
+    c["width"], c["leaf"], c["persistent"], c["precision"], c["schedule"], c["builder"]))
 def test_hand_cases_all_configs(env, c):
     torch, pa, synth, oracle = env
     A, B, pairs, exp = _hand(synth)
@@ -74,6 +74,38 @@ def test_build_metadata_c1(env):
     for m in range(A.n_meshes):
         v, f = A.mesh(m)
         assert ec[m] == oracle.unique_edges(f).shape[0]
+
+
+def _exp_range_np(S):
+    """(lowest, highest) set-bit exponent over the coordinates of every face."""
+    v = S.verts.astype(np.float32)
+    used = np.concatenate([S.vert_off[m] + S.faces[S.face_off[m]:S.face_off[m + 1]].reshape(-1)
+                           for m in range(S.n_meshes)])
+    x = np.abs(v[np.unique(used)].reshape(-1).astype(np.float64))
+    x = x[x > 0]
+    hi = np.floor(np.log2(x)).astype(int)
+    lo = hi.copy()
+    for k in range(x.shape[0]):        # lowest set bit: largest e with x / 2^e an integer
+        e = hi[k] - 23
+        while np.ldexp(x[k], -(e + 1)) == np.floor(np.ldexp(x[k], -(e + 1))):
+            e += 1
+        lo[k] = e
+    return int(lo.min()), int(hi.max())
+
+
+def test_coord_exponent_range(env):
+    """The build records the coordinates' bit-exponent range; the precision-
+    stress pairs (2^-10 grid, radius ~1) qualify for the in-place grid tier,
+    the tiny config's random coordinates do not."""
+    torch, pa, synth, oracle = env
+    A, B, pairs, _ = synth.make_c4(n_pairs=20)
+    ga, gb = pa.MeshBlob.build(A), pa.MeshBlob.build(B)
+    assert ga.exp_range() == _exp_range_np(A) and gb.exp_range() == _exp_range_np(B)
+    assert pa.small_grid(ga, gb)
+    A1, B1 = synth.make_c1(n=3)
+    g1 = pa.MeshBlob.build(A1)
+    assert g1.exp_range() == _exp_range_np(A1)
+    assert not pa.small_grid(g1, pa.MeshBlob.build(B1))
 
 
 def test_filter_matches_exact_boxes(env):
@@ -239,8 +271,9 @@ def test_c3_scaled_all_widths_and_schedules(env):
     assert 0 < want.sum() < pairs.shape[0]
     for w in (2, 4, 8):
         for l in (1, 2, 4, 8):
-            ga = pa.MeshBlob.build(A, width=w, leaf_size=l)
-            gb = pa.MeshBlob.build(B, width=w, leaf_size=l)
+            bld = (w // 2 + l) % 2
+            ga = pa.MeshBlob.build(A, width=w, leaf_size=l, builder=bld)
+            gb = pa.MeshBlob.build(B, width=w, leaf_size=l, builder=bld)
             for cfg in (dict(schedule=0), dict(schedule=1), dict(schedule=2), dict(schedule=0, seg_live_max=0x40201008),
                         dict(schedule=2, survivor_cap=50), dict(schedule=1, survivor_cap=50),
                         dict(schedule=1, survivor_cap=8), dict(schedule=1, grid_blocks=5),
@@ -321,12 +354,15 @@ def test_autotune_small(env):
     A, B, pairs = synth.make_c3(n_pairs=1500, n_pool=128, f_hi=8000.0)
     res = autotune.tune(A, B, pairs, widths=(2, 4), leaves=(1, 4), schedules=(0, 1, 2), frac=0.2, reps=2,
                         use_cache=False)
-    assert len(res["table"]) == 12
+    # per (width, leaf): wave-per-pair, wave-per-segment and the automatic schedule with two tables
+    assert len(res["table"]) == 2 * 2 * 4
+    assert sorted({(r["schedule"], r["seg_live_max"] != 0) for r in res["table"]}) == [(0, True), (1, False), (2, False)]
     b = res["best"]
     assert b["ms"] == min(r["ms"] for r in res["table"])
     assert res["per_bucket"]
     want = oracle.join(A, B, pairs, mode=1)
-    got, _ = _run(env, A, B, pairs, width=b["width"], leaf=b["leaf_size"], persistent=1, schedule=b["schedule"])
+    got, _ = _run(env, A, B, pairs, width=b["width"], leaf=b["leaf_size"], persistent=1, schedule=b["schedule"],
+                  seg_live_max=b["seg_live_max"])
     assert np.array_equal(got, want)
 
 
@@ -364,8 +400,8 @@ def test_c3_full_size_against_oracle(env):
     A, B, pairs = synth.make_c3()
     want = _c3_expected(A, B, pairs)
     assert want.shape[0] == 50_000 and 0 < want.sum() < 50_000
-    for sc in (1, 2, 0):
-        got, st = _run(env, A, B, pairs, persistent=1, schedule=sc)
+    for sc, bld in ((1, 0), (2, 0), (0, 0), (1, 1)):
+        got, st = _run(env, A, B, pairs, persistent=1, schedule=sc, builder=bld)
         assert int((got != want).sum()) == 0, sc
         assert st["pairs_true"] == int(want.sum())
 
