@@ -219,8 +219,9 @@ typedef struct {
                           entries to a continuation pass spread over all waves; -1 = no
                           hand-over of either kind */
   int32_t lds_stack;   /* persistent: 0 = the packet traversal keeps its first 64 stack
-                          entries in VGPR lanes and the rest in LDS; 1 = the whole stack
-                          in LDS (no hand-over of stack entries then) */
+                          entries in VGPR lanes and the rest in LDS; 1 = the first
+                          entries in LDS and only those beyond the LDS part in VGPR
+                          lanes (no hand-over of stack entries then) */
 } pr_refine_params;
 
 typedef struct {

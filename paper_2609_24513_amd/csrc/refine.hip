@@ -208,10 +208,11 @@ __device__ __forceinline__ f3 tri_vertex(cptr_t<float> t, int k) { return f3{t[3
 // has checked that the group's box meets the target mesh box.  Returns true
 // when the pair is decided (found here or by another wave).
 // Per-wave traversal stack of (entry, lane mask) pairs.  The stack top is
-// wave-uniform; the first reg_cap entries (kRegStack, or none when the caller
-// asks for an LDS stack) live in VGPR lanes (entry k in lane k of three
-// registers, written and read with lane-select instructions), deeper entries
-// in a per-wave LDS array written by lane 0.
+// wave-uniform; by default the first kRegStack entries live in VGPR lanes
+// (entry k in lane k of three registers, written and read with lane-select
+// instructions) and deeper entries in a per-wave LDS array written by lane 0;
+// with lds_stack the LDS array holds the first entries and the VGPR lanes the
+// deeper ones.
 constexpr int kRegStack = 64;
 
 template <int W>
@@ -224,36 +225,39 @@ constexpr int seg_slots() { return 64 / W; }
 template <int W>
 constexpr int seg_cap() { return W == 8 ? 64 : (W == 4 ? 32 : 24); }
 
-// LDS of one wave for the traversal, in 8-byte words: the packet stack with
-// every entry in LDS (lane masks, then references), or the per-segment
-// stacks of the wave-per-segment mode, which are never in use at the same
-// time as the packet stack and share its space.
+// LDS of one wave for the traversal, in 8-byte words: the LDS part of the
+// packet stack (lds_stack_cap entries: lane masks, then references), or the
+// per-segment stacks of the wave-per-segment mode, which are never in use at
+// the same time as the packet stack and share its space.
 template <int W>
 constexpr int wave_lds_words() {
-  return (12 * stack_cap<W>() > 4 * seg_slots<W>() * seg_cap<W>() ? 12 * stack_cap<W>()
-                                                                   : 4 * seg_slots<W>() * seg_cap<W>()) / 8 + 1;
+  return (12 * lds_stack_cap<W>() > 4 * seg_slots<W>() * seg_cap<W>() ? 12 * lds_stack_cap<W>()
+                                                                       : 4 * seg_slots<W>() * seg_cap<W>()) / 8 + 1;
 }
 
 struct WaveLds {
-  int32_t* ref;    // packet stack entries beyond reg_cap: node references
+  int32_t* ref;    // LDS part of the packet stack: node references
   uint64_t* mask;  // ... and their lane masks
   int32_t* seg;    // wave-per-segment stacks (aliases ref / mask), or nullptr
-  int reg_cap;     // packet entries held in VGPR lanes
+  int lds_first;   // 0: the first kRegStack entries in VGPR lanes, the rest in LDS;
+                   // 1: the first lds_cap entries in LDS, the rest in VGPR lanes
+  int lds_cap;     // entries the LDS part holds
 };
 
 template <int W>
-__device__ __forceinline__ WaveLds wave_lds(uint64_t* area, bool lds_only) {
+__device__ __forceinline__ WaveLds wave_lds(uint64_t* area, bool lds_first) {
   WaveLds l;
   l.mask = area;
-  l.ref = reinterpret_cast<int32_t*>(area + stack_cap<W>());
+  l.ref = reinterpret_cast<int32_t*>(area + lds_stack_cap<W>());
   l.seg = reinterpret_cast<int32_t*>(area);
-  l.reg_cap = lds_only ? 0 : kRegStack;
+  l.lds_first = lds_first ? 1 : 0;
+  l.lds_cap = lds_stack_cap<W>();
   return l;
 }
 
 // For kernels with only the register stack and its LDS overflow.
 __device__ __forceinline__ WaveLds wave_lds(int32_t* ref, uint64_t* mask) {
-  return WaveLds{ref, mask, nullptr, kRegStack};
+  return WaveLds{ref, mask, nullptr, 0, 0};
 }
 
 // v_writelane_b32: `old` with lane `lane` replaced by the uniform value v
@@ -266,30 +270,41 @@ struct WaveStack {
   int32_t* lref;
   uint64_t* lmask;
   int32_t top;
-  int32_t reg_cap;
+  int32_t lds_first;  // see WaveLds
+  int32_t lds_cap;
 };
 
+// Entry i of the stack: in VGPR lane reg_index(i) or at LDS index lds_index(i).
+__device__ __forceinline__ bool in_reg(const WaveStack& s, int32_t i) {
+  return s.lds_first ? i >= s.lds_cap : i < kRegStack;
+}
+__device__ __forceinline__ int32_t reg_index(const WaveStack& s, int32_t i) { return s.lds_first ? i - s.lds_cap : i; }
+__device__ __forceinline__ int32_t lds_index(const WaveStack& s, int32_t i) { return s.lds_first ? i : i - kRegStack; }
+
 __device__ __forceinline__ void stack_push(WaveStack& s, int32_t ref, uint64_t m) {
-  if (s.top < s.reg_cap) {
-    s.ref = lane_write(ref, s.top, s.ref);
-    s.mlo = lane_write((int32_t)(uint32_t)m, s.top, s.mlo);
-    s.mhi = lane_write((int32_t)(uint32_t)(m >> 32), s.top, s.mhi);
+  if (in_reg(s, s.top)) {
+    const int32_t k = reg_index(s, s.top);
+    s.ref = lane_write(ref, k, s.ref);
+    s.mlo = lane_write((int32_t)(uint32_t)m, k, s.mlo);
+    s.mhi = lane_write((int32_t)(uint32_t)(m >> 32), k, s.mhi);
   } else if ((threadIdx.x & 63) == 0) {
-    s.lref[s.top - s.reg_cap] = ref;
-    s.lmask[s.top - s.reg_cap] = m;
+    s.lref[lds_index(s, s.top)] = ref;
+    s.lmask[lds_index(s, s.top)] = m;
   }
   ++s.top;
 }
 
 __device__ __forceinline__ int32_t stack_ref(const WaveStack& s, int32_t i) {
-  return i < s.reg_cap ? __builtin_amdgcn_readlane(s.ref, i) : uni(s.lref[i - s.reg_cap]);
+  return in_reg(s, i) ? __builtin_amdgcn_readlane(s.ref, reg_index(s, i)) : uni(s.lref[lds_index(s, i)]);
 }
 
 __device__ __forceinline__ uint64_t stack_mask(const WaveStack& s, int32_t i) {
-  if (i < s.reg_cap)
-    return ((uint64_t)(uint32_t)__builtin_amdgcn_readlane(s.mhi, i) << 32) |
-           (uint32_t)__builtin_amdgcn_readlane(s.mlo, i);
-  return uni64(s.lmask[i - s.reg_cap]);
+  if (in_reg(s, i)) {
+    const int32_t k = reg_index(s, i);
+    return ((uint64_t)(uint32_t)__builtin_amdgcn_readlane(s.mhi, k) << 32) |
+           (uint32_t)__builtin_amdgcn_readlane(s.mlo, k);
+  }
+  return uni64(s.lmask[lds_index(s, i)]);
 }
 
 // A wide node read in one burst through the scalar cache.
@@ -685,7 +700,8 @@ __device__ bool trace_core(const BlobView& S, const BlobView& T, int64_t gc, int
   constexpr int CAP = stack_cap<W>();
   WaveStack stk;
   stk.ref = 0; stk.mlo = 0; stk.mhi = 0;
-  stk.lref = o.lds.ref; stk.lmask = o.lds.mask; stk.top = 0; stk.reg_cap = o.lds.reg_cap;
+  stk.lref = o.lds.ref; stk.lmask = o.lds.mask; stk.top = 0;
+  stk.lds_first = o.lds.lds_first; stk.lds_cap = o.lds.lds_cap;
   stack_push(stk, root, m0);
   int iter = 0;
   const cptr_t<Node<W>> nodes = cview(reinterpret_cast<const Node<W>*>(T.nodes));
@@ -1216,7 +1232,7 @@ __global__ __launch_bounds__(kBlock, 5) void k_trace(RefineArgs ra) {
     s_share.busy = 0u;
   }
   __syncthreads();
-  // with the whole stack in LDS there is no hand-over of stack entries
+  // with the stack's first entries in LDS there is no hand-over of stack entries
   const bool lds_only = ra.lds_stack != 0;
   BlockShare* const sh = ra.share && !lds_only ? &s_share : nullptr;
   TraceOpts o;
