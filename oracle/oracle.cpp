@@ -410,6 +410,89 @@ MeshView view(const float* v, const int32_t* f, const int64_t* vo, const int64_t
   return {v + 3 * vo[m], f + 3 * fo[m], vo[m + 1] - vo[m], fo[m + 1] - fo[m]};
 }
 
+// ---- point in mesh (containment, Section 3.3) ----------------------------
+//
+// Winding number of a closed triangle mesh about a point p, computed
+// exactly: cast the ray p + t d (t > 0) along an integer direction d and add,
+// for every triangle it crosses through the triangle's interior, the sign of
+// n . d, n = (b - a) x (c - a).  The line meets the interior iff the triple
+// products [a-p, b-p, d], [b-p, c-p, d], [c-p, a-p, d] share one strict sign;
+// the crossing lies ahead of p iff orient(a,b,c,p) and n . d have opposite
+// signs.  When the line meets an edge or a vertex of a triangle, or lies in a
+// triangle's plane, the direction is degenerate for this point and mesh and
+// the next direction of a fixed list is used.  A point on a triangle is
+// reported as such.  For an embedded closed surface with outward faces the
+// winding number is 1 inside and 0 outside.
+
+enum { ORACLE_ON_SURFACE = 2, ORACLE_E_RAY = -7 };
+
+const int kDirs[16][3] = {{1, 2, 3},   {-3, 1, 2},  {2, -1, 5},  {5, 3, -7}, {-2, 7, 1},  {7, -5, 3},
+                          {3, 11, -2}, {-13, 4, 9}, {1, -9, -4}, {6, 1, 13}, {-5, -8, 3}, {11, 2, 6},
+                          {-1, 17, 5}, {4, -3, -11}, {9, 13, 2}, {-7, -2, -15}};
+
+V3 dir_vec(const int* d) {
+  return {big_from((uint64_t)std::abs(d[0]), d[0] < 0, 0), big_from((uint64_t)std::abs(d[1]), d[1] < 0, 0),
+          big_from((uint64_t)std::abs(d[2]), d[2] < 0, 0)};
+}
+
+// One triangle against the ray from p along d: sets *contrib to +-1 for a
+// crossing ahead of p, 0 otherwise; returns 1 when the direction is
+// degenerate for this triangle, 2 when p lies on the triangle, else 0.
+int ray_triangle(const float* p, const float* t, const V3& D, int* contrib) {
+  *contrib = 0;
+  const float* pts[4] = {p, t, t + 3, t + 6};
+  V3 X[4];
+  to_ints(pts, 4, X);
+  const V3 A = vsub(X[1], X[0]), B = vsub(X[2], X[0]), C = vsub(X[3], X[0]);  // a-p, b-p, c-p
+  const int e1 = sgn(dot(cross(A, B), D)), e2 = sgn(dot(cross(B, C), D)), e3 = sgn(dot(cross(C, A), D));
+  const V3 n = cross(vsub(X[2], X[1]), vsub(X[3], X[1]));
+  const int f0 = sgn(dot(n, vsub(X[0], X[1])));  // orient(a,b,c,p)
+  if (f0 == 0) {
+    // p in the triangle's plane: on the triangle iff the 2D tests pass in a
+    // coordinate plane where the normal component is non-zero
+    int i = 1, j = 2;
+    if (n.x.n == 0) { i = 2; j = 0; if (n.y.n == 0) { i = 0; j = 1; } }
+    auto o2 = [&](const V3& u, const V3& v, const V3& w) {
+      const Big* U[3] = {&u.x, &u.y, &u.z};
+      const Big* Vv[3] = {&v.x, &v.y, &v.z};
+      const Big* Ww[3] = {&w.x, &w.y, &w.z};
+      return sgn(sub(mul(sub(*Vv[i], *U[i]), sub(*Ww[j], *U[j])), mul(sub(*Vv[j], *U[j]), sub(*Ww[i], *U[i]))));
+    };
+    const int s1 = o2(X[1], X[2], X[0]), s2 = o2(X[2], X[3], X[0]), s3 = o2(X[3], X[1], X[0]);
+    if ((s1 >= 0 && s2 >= 0 && s3 >= 0) || (s1 <= 0 && s2 <= 0 && s3 <= 0)) return 2;
+  }
+  const bool pos = e1 > 0 || e2 > 0 || e3 > 0, neg = e1 < 0 || e2 < 0 || e3 < 0;
+  if (pos && neg) return 0;                  // the line misses the closed triangle
+  if (e1 == 0 || e2 == 0 || e3 == 0) return 1;  // through an edge or a vertex, or in the plane
+  const int nd = sgn(dot(n, D));
+  if (nd == 0) return 1;
+  if (f0 != 0 && f0 == -nd) *contrib = nd;   // the crossing is ahead of p
+  return 0;
+}
+
+// Winding number of mesh m about p, or ORACLE_ON_SURFACE (as *on = 1), or an
+// error when every direction of the list is degenerate.  Directions are tried
+// from kDirs[first] on (cyclically).
+int winding(const MeshView& m, const float* p, int* w, int* on, int first = 0) {
+  float t[9];
+  *on = 0;
+  for (int kk = 0; kk < 16; ++kk) {
+    const V3 D = dir_vec(kDirs[(first + kk) % 16]);
+    int sum = 0;
+    bool degenerate = false;
+    for (int64_t i = 0; i < m.nf && !degenerate; ++i) {
+      tri_pts(m, i, t);
+      int c = 0;
+      const int r = ray_triangle(p, t, D, &c);
+      if (r == 2) { *on = 1; *w = 0; return 0; }
+      if (r == 1) degenerate = true;
+      sum += c;
+    }
+    if (!degenerate) { *w = sum; return 0; }
+  }
+  return ORACLE_E_RAY;
+}
+
 }  // namespace
 
 extern "C" {
@@ -426,6 +509,72 @@ int oracle_tri_tri(const float* t9, const float* u9) {
 int oracle_set_limb_budget(int limbs) {
   if (limbs < 1 || limbs > LIMBS) return ORACLE_E_ARG;
   return g_limb_budget.exchange(limbs);
+}
+
+// Winding number of mesh m of a set (verts, faces, offsets) about point p,
+// trying the ray directions from number first_dir on; *on_surface = 1 when p
+// lies on one of its triangles.  Returns 0 or an error.
+int oracle_winding(const float* v, const int32_t* f, const int64_t* vo, const int64_t* fo, int64_t nm, int64_t m,
+                   const float* p, int first_dir, int32_t* w, int32_t* on_surface) {
+  if (m < 0 || m >= nm || !p || !w || !on_surface || first_dir < 0 || first_dir >= 16) return ORACLE_E_ARG;
+  MeshView M = view(v, f, vo, fo, m);
+  if (!mesh_valid(M)) return ORACLE_E_ARG;
+  g_overflow = false;
+  int ww = 0, on = 0;
+  const int r = winding(M, p, &ww, &on, first_dir);
+  if (g_overflow) return ORACLE_E_OVERFLOW;
+  *w = ww;
+  *on_surface = on;
+  return r;
+}
+
+// Per candidate pair (i, j): bit 0 = the first vertex of B_j's first face lies
+// inside A_i (winding number non-zero), bit 1 = the first vertex of A_i's first
+// face lies inside B_j; bit 2 / bit 3 = that vertex lies on the other surface
+// (bits 0 / 1 are then 0).  A mesh without faces has no such vertex: 0.
+int oracle_inside_pairs(const float* va, const int32_t* fa, const int64_t* voa, const int64_t* foa, int64_t ma,
+                        const float* vb, const int32_t* fb, const int64_t* vob, const int64_t* fob, int64_t mb,
+                        const int32_t* pairs, int64_t n_pairs, uint8_t* bits, int n_threads) {
+  if (n_pairs < 0 || (n_pairs > 0 && (!pairs || !bits)) || ma < 0 || mb < 0) return ORACLE_E_ARG;
+  for (int64_t p = 0; p < n_pairs; ++p)
+    if (pairs[2 * p] < 0 || pairs[2 * p] >= ma || pairs[2 * p + 1] < 0 || pairs[2 * p + 1] >= mb) return ORACLE_E_ARG;
+  for (int64_t m = 0; m < ma; ++m) if (!mesh_valid(view(va, fa, voa, foa, m))) return ORACLE_E_ARG;
+  for (int64_t m = 0; m < mb; ++m) if (!mesh_valid(view(vb, fb, vob, fob, m))) return ORACLE_E_ARG;
+  std::atomic<int64_t> next{0};
+  std::atomic<int> status{0};
+  auto rep = [](const MeshView& m, float* out) {
+    const int32_t vi = m.f[0];
+    for (int c = 0; c < 3; ++c) out[c] = m.v[3 * vi + c];
+  };
+  auto worker = [&]() {
+    for (;;) {
+      const int64_t p = next.fetch_add(1);
+      if (p >= n_pairs) break;
+      const MeshView A = view(va, fa, voa, foa, pairs[2 * p]);
+      const MeshView B = view(vb, fb, vob, fob, pairs[2 * p + 1]);
+      uint8_t b = 0;
+      g_overflow = false;
+      float q[3];
+      int w = 0, on = 0;
+      if (A.nf > 0 && B.nf > 0) {
+        rep(B, q);
+        int r = winding(A, q, &w, &on);
+        if (r) status.store(r);
+        if (on) b |= 4; else if (w != 0) b |= 1;
+        rep(A, q);
+        r = winding(B, q, &w, &on);
+        if (r) status.store(r);
+        if (on) b |= 8; else if (w != 0) b |= 2;
+      }
+      if (g_overflow) status.store(ORACLE_E_OVERFLOW);
+      bits[p] = b;
+    }
+  };
+  int nt = n_threads > 0 ? n_threads : (int)std::max(1u, std::thread::hardware_concurrency());
+  std::vector<std::thread> pool;
+  for (int i = 0; i < nt; ++i) pool.emplace_back(worker);
+  for (auto& th : pool) th.join();
+  return status.load();
 }
 
 int oracle_orient3d(const float* a, const float* b, const float* c, const float* d) {

@@ -62,6 +62,12 @@ def _load():
             lib.oracle_join.restype = ctypes.c_int
             lib.oracle_set_limb_budget.argtypes = [ctypes.c_int]
             lib.oracle_set_limb_budget.restype = ctypes.c_int
+            lib.oracle_winding.argtypes = [fp, ip, lp, lp, ctypes.c_int64, ctypes.c_int64, fp, ctypes.c_int,
+                                           ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32)]
+            lib.oracle_winding.restype = ctypes.c_int
+            lib.oracle_inside_pairs.argtypes = [fp, ip, lp, lp, ctypes.c_int64, fp, ip, lp, lp, ctypes.c_int64,
+                                                ip, ctypes.c_int64, ctypes.POINTER(ctypes.c_uint8), ctypes.c_int]
+            lib.oracle_inside_pairs.restype = ctypes.c_int
             _lib = lib
     return _lib
 
@@ -116,6 +122,68 @@ def join(A, B, pairs, mode: int = 1, threads: int = 0, return_tests: bool = Fals
     if r != 0:
         raise OracleError("oracle_join failed with code %d" % r, r)
     return (flags, int(ntests.value)) if return_tests else flags
+
+
+def _set_args(S):
+    v = np.ascontiguousarray(S.verts, np.float32)
+    f = np.ascontiguousarray(S.faces, np.int32)
+    vo = np.ascontiguousarray(S.vert_off, np.int64)
+    fo = np.ascontiguousarray(S.face_off, np.int64)
+    return (v, f, vo, fo), [_ptr(v, ctypes.c_float), _ptr(f, ctypes.c_int32), _ptr(vo, ctypes.c_int64),
+                            _ptr(fo, ctypes.c_int64), ctypes.c_int64(vo.shape[0] - 1)]
+
+
+def winding(S, m: int, p, first_dir: int = 0):
+    """(winding number, on_surface) of mesh m of set S about the FP32 point p,
+    computed exactly by ray crossings along a generic integer direction (the
+    first of a fixed list from number first_dir on that meets no edge or
+    vertex).  Inside a closed surface with outward faces: 1; outside: 0."""
+    keep, args = _set_args(S)
+    q = np.ascontiguousarray(np.asarray(p, np.float32).reshape(3))
+    w, on = ctypes.c_int32(0), ctypes.c_int32(0)
+    r = _load().oracle_winding(*args, ctypes.c_int64(m), _ptr(q, ctypes.c_float), ctypes.c_int(first_dir),
+                               ctypes.byref(w), ctypes.byref(on))
+    if r != 0:
+        raise OracleError("oracle_winding failed with code %d" % r, r)
+    return int(w.value), bool(on.value)
+
+
+def inside_pairs(A, B, pairs, threads: int = 0):
+    """u8[P] per pair (i, j): bit 0 = the first vertex of B_j's first face lies
+    inside A_i, bit 1 = the first vertex of A_i's first face lies inside B_j,
+    bits 2 / 3 = that vertex lies on the other surface."""
+    lib = _load()
+    pairs = np.ascontiguousarray(np.asarray(pairs, np.int32).reshape(-1, 2))
+    bits = np.zeros(pairs.shape[0], np.uint8)
+    ka, aa = _set_args(A)
+    kb, ab = _set_args(B)
+    r = lib.oracle_inside_pairs(*aa, *ab, _ptr(pairs, ctypes.c_int32), ctypes.c_int64(pairs.shape[0]),
+                                _ptr(bits, ctypes.c_uint8), ctypes.c_int(threads if threads > 0 else default_threads()))
+    if r != 0:
+        raise OracleError("oracle_inside_pairs failed with code %d" % r, r)
+    return bits
+
+
+PREDICATES = ("overlap", "contains", "within", "intersection")
+
+
+def join_predicates(A, B, pairs, threads: int = 0) -> dict:
+    """The join predicates per candidate pair (i in A, j in B), u8 flags
+    (Sections 3.2-3.4, surface contact read with closed sets):
+      overlap      the closed surfaces share a point;
+      contains     no shared point and B_j lies inside A_i (a vertex of B_j
+                   has non-zero winding number about A_i);
+      within       no shared point and A_i lies inside B_j;
+      intersection overlap or contains or within.
+    For connected closed surfaces that share no point, one vertex decides on
+    which side the whole surface lies."""
+    cross = join(A, B, pairs, mode=1, threads=threads)
+    bits = inside_pairs(A, B, pairs, threads=threads)
+    free = cross == 0
+    contains = (free & ((bits & 1) != 0)).astype(np.uint8)
+    within = (free & ((bits & 2) != 0)).astype(np.uint8)
+    return {"overlap": cross, "contains": contains, "within": within,
+            "intersection": (cross | contains | within).astype(np.uint8), "inside_bits": bits}
 
 
 def set_limb_budget(limbs: int) -> int:

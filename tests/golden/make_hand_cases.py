@@ -3,7 +3,9 @@ their construction (stated in each case's "why").  No oracle or library
 call is made; the expected values are geometric facts about exact dyadic
 coordinates.  Semantics: closed surfaces, touching counts (the reading of
 Section 3.2's overlap predicate for closed sets; Section 3.6 discusses the
-contact cases).
+contact cases).  Each case also states whether A contains B or lies within
+B with no shared surface point (the containment join of Section 3.3 and its
+inverse), the facts the containment predicates are checked against.
 
 Run:  python tests/golden/make_hand_cases.py
 """
@@ -77,7 +79,24 @@ CASES = [
      "B=[1,2]x[1,2]x[1/2,3/2] meets A=[0,1]^3 along the segment x=y=1, z in [1/2,1]"),
     ("cube_corner_contact", CUBE_V, CUBE_F, tr(CUBE_V, [1, 1, 1]), CUBE_F, True,
      "B=[1,2]^3 meets A=[0,1]^3 only at the corner (1,1,1)"),
+    ("nested_octahedra_reversed", sc(OCT_V, 0.5), OCT_F, OCT_V, OCT_F, False,
+     "A={|x|+|y|+|z|<=1/2} lies strictly inside B={|x|+|y|+|z|<=1}"),
+    ("cube_nested_corner_touch", CUBE_V, CUBE_F, sc(CUBE_V, 0.5), CUBE_F, True,
+     "B=[0,1/2]^3 inside A=[0,1]^3 shares A's corner region: the faces x=0, y=0, z=0 of both overlap"),
+    ("cube_nested_offcentre", CUBE_V, CUBE_F, tr(sc(CUBE_V, 0.25), [0.5, 0.125, 0.625]), CUBE_F, False,
+     "B=[1/2,3/4]x[1/8,3/8]x[5/8,7/8] strictly inside A=[0,1]^3"),
+    ("octahedron_in_cube", box([-2, -2, -2], [2, 2, 2]), CUBE_F, OCT_V, OCT_F, False,
+     "B={|x|+|y|+|z|<=1} strictly inside A=[-2,2]^3"),
 ]
+
+# containment facts: (A contains B, A within B) with no shared surface point
+INSIDE = {
+    "nested_octahedra": (True, False),
+    "cube_nested": (True, False),
+    "nested_octahedra_reversed": (False, True),
+    "cube_nested_offcentre": (True, False),
+    "octahedron_in_cube": (True, False),
+}
 
 
 def main():
@@ -86,7 +105,9 @@ def main():
         for v in (va, vb):
             a = np.asarray(v, np.float64)
             assert np.all(a.astype(np.float32).astype(np.float64) == a), name  # exact in FP32
-        out.append(dict(name=name, expected=bool(exp), why=why,
+        contains, within = INSIDE.get(name, (False, False))
+        assert not (exp and (contains or within)), name  # a shared point excludes containment
+        out.append(dict(name=name, expected=bool(exp), contains=contains, within=within, why=why,
                         A=dict(verts=va, faces=fa), B=dict(verts=vb, faces=fb)))
     path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "hand_cases.json")
     with open(path, "w") as fh:

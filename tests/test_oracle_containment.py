@@ -1,0 +1,392 @@
+"""Pins for the oracle's point-in-mesh test and the containment, within and
+intersection predicates (Section 3.3's containment join, its inverse, and
+Section 3.4's intersection join), with no GPU.
+
+The winding number is pinned against facts that do not come from the oracle:
+  * closed forms of a tetrahedron, a cube and an octahedron on dyadic
+    lattices (points inside, outside, on faces, on edges, on the extensions
+    of faces and edges, and points whose first ray passes a vertex);
+  * a torus (genus one, not star-shaped) and a hollow shell, by distance
+    bounds of their construction;
+  * invariances: every starting direction gives the same number; reversed
+    faces negate it;
+  * the hand-built mesh pairs of tests/golden/hand_cases.json, whose nesting
+    and contact follow from their construction;
+  * star-shaped jittered spheres, by their inner and outer radii;
+  * planted mistakes in copies of the oracle source, each caught by a quick
+    subset of these pins.
+"""
+import ctypes
+import itertools
+import json
+import os
+import subprocess
+from fractions import Fraction
+
+import numpy as np
+import pytest
+
+from paper_2609_24513_amd import synth
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(HERE)
+
+TET_V = [[0, 0, 0], [1, 0, 0], [0, 1, 0], [0, 0, 1]]
+TET_F = [[0, 2, 1], [0, 1, 3], [0, 3, 2], [1, 2, 3]]
+OCT_V = [[1, 0, 0], [-1, 0, 0], [0, 1, 0], [0, -1, 0], [0, 0, 1], [0, 0, -1]]
+OCT_F = [[0, 2, 4], [2, 1, 4], [1, 3, 4], [3, 0, 4], [2, 0, 5], [1, 2, 5], [3, 1, 5], [0, 3, 5]]
+CUBE_V = [[x, y, z] for x in (0, 1) for y in (0, 1) for z in (0, 1)]
+CUBE_F = [[0, 1, 3], [0, 3, 2], [4, 6, 7], [4, 7, 5], [0, 4, 5], [0, 5, 1],
+          [2, 3, 7], [2, 7, 6], [0, 2, 6], [0, 6, 4], [1, 5, 7], [1, 7, 3]]
+
+
+def _set(*meshes):
+    return synth.concat_meshes([(np.asarray(v, np.float64), np.asarray(f)) for v, f in meshes])
+
+
+def _status_tet(p):
+    x, y, z = (Fraction(float(c)) for c in p)
+    s = x + y + z
+    if min(x, y, z) < 0 or s > 1:
+        return "out"
+    return "in" if min(x, y, z) > 0 and s < 1 else "on"
+
+
+def _status_cube(p, lo=0, hi=1):
+    c = [Fraction(float(v)) for v in p]
+    if any(v < lo or v > hi for v in c):
+        return "out"
+    return "in" if all(lo < v < hi for v in c) else "on"
+
+
+def _status_oct(p):
+    s = sum(abs(Fraction(float(v))) for v in p)
+    return "in" if s < 1 else ("on" if s == 1 else "out")
+
+
+EXPECT = {"in": (1, False), "out": (0, False), "on": (0, True)}
+
+
+def _lattice(lo, hi, step):
+    ax = np.arange(lo, hi + step / 2, step)
+    return [np.array(p) for p in itertools.product(ax, ax, ax)]
+
+
+@pytest.mark.parametrize("name", ["tet", "cube", "oct"])
+def test_winding_closed_forms_on_lattices(oracle_mod, name):
+    """Every point of a dyadic lattice around the solid: inside -> 1, outside
+    -> 0, on the surface -> reported as such.  The lattice holds points on
+    faces, edges and vertices, points in the planes of faces and on the lines
+    of edges outside the solid, and points whose rays pass vertices."""
+    v, f, status, pts = {
+        "tet": (TET_V, TET_F, _status_tet, _lattice(-0.25, 1.25, 0.125)),
+        "cube": (CUBE_V, CUBE_F, _status_cube, _lattice(-0.5, 1.5, 0.25)),
+        "oct": (OCT_V, OCT_F, _status_oct, _lattice(-1.25, 1.25, 0.25)),
+    }[name]
+    S = _set((v, f))
+    seen = set()
+    for p in pts:
+        st = status(p)
+        seen.add(st)
+        assert oracle_mod.winding(S, 0, p) == EXPECT[st], (name, p, st)
+    assert seen == {"in", "out", "on"}
+
+
+def test_rays_through_vertices_and_edges(oracle_mod):
+    """Points placed so that the first direction of the list, (1,2,3), runs
+    exactly through a vertex or along/through an edge of the cube: the answer
+    must not depend on that."""
+    S = _set((CUBE_V, CUBE_F))
+    d = np.array([1, 2, 3]) / 16.0
+    for corner in CUBE_V:
+        for k in (1, 2, 3, 5):
+            p = np.asarray(corner, np.float64) - k * d
+            assert oracle_mod.winding(S, 0, p) == EXPECT[_status_cube(p)], p
+    # through the middle of an edge: the edge x=1, z=1 at y=1/2
+    for k in (1, 2, 3):
+        p = np.array([1.0, 0.5, 1.0]) - k * d
+        assert oracle_mod.winding(S, 0, p) == EXPECT[_status_cube(p)], p
+
+
+def test_every_start_direction_agrees(oracle_mod):
+    """The winding number does not depend on the ray: all 16 starting
+    directions give the same answer (a mistake in the 'crossing ahead' rule
+    or in the sign of a crossing shows up as a dependence)."""
+    rng = np.random.default_rng(3)
+    S = _set((OCT_V, OCT_F))
+    for p in _lattice(-1.25, 1.25, 0.25)[::5]:
+        want = EXPECT[_status_oct(p)]
+        for fd in range(16):
+            assert oracle_mod.winding(S, 0, p, first_dir=fd) == want, (p, fd)
+    for p in rng.uniform(-1.3, 1.3, size=(60, 3)).astype(np.float32):
+        got = {oracle_mod.winding(S, 0, p, first_dir=fd) for fd in range(16)}
+        assert len(got) == 1, p
+
+
+def test_reversed_faces_negate(oracle_mod):
+    S = _set((CUBE_V, np.asarray(CUBE_F)[:, ::-1]))
+    assert oracle_mod.winding(S, 0, [0.5, 0.25, 0.75]) == (-1, False)
+    assert oracle_mod.winding(S, 0, [1.5, 0.25, 0.75]) == (0, False)
+    assert oracle_mod.winding(S, 0, [1.0, 0.25, 0.75]) == (0, True)
+
+
+def _box(lo, hi):
+    return [[(lo[0], hi[0])[i], (lo[1], hi[1])[j], (lo[2], hi[2])[k]]
+            for i in (0, 1) for j in (0, 1) for k in (0, 1)]
+
+
+def test_shell_and_nested_components(oracle_mod):
+    """A mesh of two cubes: [-2,2]^3 outward and [-1,1]^3.  With the inner cube
+    inward (a hollow shell) the cavity has winding 0 and the shell 1; with both
+    outward the inner region counts twice."""
+    inner_in = np.asarray(CUBE_F)[:, ::-1] + 8
+    inner_out = np.asarray(CUBE_F) + 8
+    verts = _box([-2] * 3, [2] * 3) + _box([-1] * 3, [1] * 3)
+    shell = _set((verts, np.concatenate([CUBE_F, inner_in])))
+    double = _set((verts, np.concatenate([CUBE_F, inner_out])))
+    for p, ws, wd in (([0.25, 0.5, -0.125], 0, 2), ([1.5, 0.5, -0.125], 1, 1), ([2.5, 0, 0], 0, 0),
+                      ([-1.75, 1.875, 1.625], 1, 1)):
+        assert oracle_mod.winding(shell, 0, p) == (ws, False), p
+        assert oracle_mod.winding(double, 0, p) == (wd, False), p
+    assert oracle_mod.winding(shell, 0, [1, 0.5, 0.5]) == (0, True)
+
+
+def _torus(R, r, nu, nv):
+    u = 2 * np.pi * np.arange(nu) / nu
+    v = 2 * np.pi * np.arange(nv) / nv
+    uu, vv = np.meshgrid(u, v, indexing="ij")
+    verts = np.stack([(R + r * np.cos(vv)) * np.cos(uu), (R + r * np.cos(vv)) * np.sin(uu), r * np.sin(vv)],
+                     -1).reshape(-1, 3)
+    faces = []
+    for i in range(nu):
+        for j in range(nv):
+            a, b = i * nv + j, ((i + 1) % nu) * nv + j
+            c, d = ((i + 1) % nu) * nv + (j + 1) % nv, i * nv + (j + 1) % nv
+            faces += [[a, b, c], [a, c, d]]
+    return verts, np.asarray(faces)
+
+
+def test_torus_by_distance_bounds(oracle_mod):
+    """Torus R=2, r=1 (24 x 24 quads, outward): a point closer than 0.85 to
+    the tube's centre circle is inside, one farther than 1.15 (including the
+    hole) is outside.  The flat faces deviate from the smooth torus by less
+    than 0.04, well within those margins."""
+    v, f = _torus(2.0, 1.0, 24, 24)
+    vf = v.astype(np.float32)
+    a, b, c = (vf[f[:, k]].astype(np.float64) for k in range(3))
+    g = (a + b + c) / 3
+    axis = np.concatenate([g[:, :2] * (2.0 / np.hypot(g[:, 0], g[:, 1]))[:, None], np.zeros((len(g), 1))], 1)
+    assert np.all(np.einsum("ij,ij->i", np.cross(b - a, c - a), g - axis) > 0)  # normals point away from the tube axis
+    S = _set((vf, f))
+    rng = np.random.default_rng(11)
+    pts = rng.uniform([-3.4, -3.4, -1.4], [3.4, 3.4, 1.4], size=(400, 3)).astype(np.float32)
+    n_in = n_out = 0
+    for p in pts:
+        q = p.astype(np.float64)
+        d = np.hypot(np.hypot(q[0], q[1]) - 2.0, q[2])
+        if d < 0.85:
+            assert oracle_mod.winding(S, 0, p) == (1, False), p
+            n_in += 1
+        elif d > 1.15:
+            assert oracle_mod.winding(S, 0, p) == (0, False), p
+            n_out += 1
+    assert n_in > 40 and n_out > 100
+    assert oracle_mod.winding(S, 0, [0, 0, 0]) == (0, False)   # the centre of the hole
+
+
+def _hand_cases():
+    with open(os.path.join(HERE, "golden", "hand_cases.json")) as fh:
+        return json.load(fh)["cases"]
+
+
+def _hand_sets():
+    cases = _hand_cases()
+    A = synth.concat_meshes([(np.asarray(c["A"]["verts"], np.float64), np.asarray(c["A"]["faces"])) for c in cases])
+    B = synth.concat_meshes([(np.asarray(c["B"]["verts"], np.float64), np.asarray(c["B"]["faces"])) for c in cases])
+    return cases, A, B, np.stack([np.arange(len(cases))] * 2, 1)
+
+
+def test_predicates_on_hand_cases(oracle_mod):
+    """overlap / contains / within / intersection on pairs whose nesting and
+    contact follow from their construction; swapping the roles swaps
+    contains and within."""
+    cases, A, B, pairs = _hand_sets()
+    r = oracle_mod.join_predicates(A, B, pairs)
+    for k, c in enumerate(cases):
+        want = (int(c["expected"]), int(c["contains"]), int(c["within"]))
+        got = (int(r["overlap"][k]), int(r["contains"][k]), int(r["within"][k]))
+        assert got == want, (c["name"], got, want)
+        assert r["intersection"][k] == int(any(want)), c["name"]
+    s = oracle_mod.join_predicates(B, A, pairs)
+    assert np.array_equal(s["overlap"], r["overlap"])
+    assert np.array_equal(s["contains"], r["within"]) and np.array_equal(s["within"], r["contains"])
+    assert np.array_equal(s["intersection"], r["intersection"])
+
+
+def test_inside_bits_on_hand_cases(oracle_mod):
+    """The raw representative-vertex bits: B's first vertex on A's face
+    (vertex_on_face: (1/4,1/4,1/2) lies on x+y+z=1) sets the on-surface bit;
+    nested cases set the inside bit of the inner mesh's vertex only."""
+    cases, A, B, pairs = _hand_sets()
+    bits = oracle_mod.inside_pairs(A, B, pairs)
+    by = {c["name"]: int(b) for c, b in zip(cases, bits)}
+    assert by["vertex_on_face"] & 4 and not by["vertex_on_face"] & 1
+    assert by["nested_octahedra"] & 3 == 1
+    assert by["nested_octahedra_reversed"] & 3 == 2
+    assert by["cube_nested"] & 3 == 1
+    assert by["octahedron_in_cube"] & 3 == 1
+    assert by["identical"] & 12 == 12      # each first vertex lies on the other surface
+    assert by["disjoint_2e-12"] == 0
+
+
+def _spheres(seed=41, n=250):
+    """Jittered level-2 icospheres around centres c with radii 0.6..1.2 and
+    B's centre at distance 0..2.8 from A's, so that all of disjoint, crossing,
+    A-contains-B and B-contains-A occur."""
+    rng = np.random.default_rng(seed)
+    tv, tf = synth.icosphere(2)
+    As, Bs, info = [], [], []
+    for _ in range(n):
+        ra, rb = rng.uniform(0.3, 1.2, size=2)
+        ca = rng.uniform(0, 4, size=3)
+        d = rng.normal(size=3)
+        d /= np.linalg.norm(d)
+        cb = ca + d * rng.uniform(0.0, 2.8) * rng.uniform(0, 1) ** 2
+        va = (ca[None] + (ra + rng.normal(0, 0.02 * ra, size=162))[:, None] * tv).astype(np.float32)
+        vb = (cb[None] + (rb + rng.normal(0, 0.02 * rb, size=162))[:, None] * tv).astype(np.float32)
+        As.append((va, tf)); Bs.append((vb, tf)); info.append((ca, cb, va, vb))
+    return synth.concat_meshes(As), synth.concat_meshes(Bs), info, tf
+
+
+def _radii(v, f, c):
+    v = v.astype(np.float64)
+    a, b, cc = v[f[:, 0]], v[f[:, 1]], v[f[:, 2]]
+    n = np.cross(b - a, cc - a)
+    n /= np.linalg.norm(n, axis=1, keepdims=True)
+    return np.abs(np.einsum("ij,ij->i", n, a - c[None])).min(), np.linalg.norm(v - c[None], axis=1).max()
+
+
+def test_predicates_star_shaped_closed_forms(oracle_mod):
+    """Each sphere is star-shaped about its centre c and lies between the
+    ball of radius rho (nearest face plane) and the ball of radius R (farthest
+    vertex).  |ca-cb| + R_B < rho_A => A contains B (no contact);
+    |ca-cb| + R_A < rho_B => B contains A; |ca-cb| > R_A + R_B => nothing."""
+    A, B, info, tf = _spheres()
+    pairs = np.stack([np.arange(len(info))] * 2, 1)
+    r = oracle_mod.join_predicates(A, B, pairs)
+    counts = dict(contains=0, within=0, apart=0)
+    for k, (ca, cb, va, vb) in enumerate(info):
+        rho_a, R_a = _radii(va, tf, ca)
+        rho_b, R_b = _radii(vb, tf, cb)
+        d = np.linalg.norm(ca - cb)
+        got = (r["overlap"][k], r["contains"][k], r["within"][k], r["intersection"][k])
+        if d + R_b < rho_a:
+            assert got == (0, 1, 0, 1), k; counts["contains"] += 1
+        elif d + R_a < rho_b:
+            assert got == (0, 0, 1, 1), k; counts["within"] += 1
+        elif d > R_a + R_b:
+            assert got == (0, 0, 0, 0), k; counts["apart"] += 1
+        assert not (r["contains"][k] and r["within"][k])
+        assert r["intersection"][k] == (r["overlap"][k] | r["contains"][k] | r["within"][k])
+    assert min(counts.values()) >= 10, counts
+
+
+def test_empty_and_faceless(oracle_mod):
+    cases, A, B, pairs = _hand_sets()
+    r = oracle_mod.join_predicates(A, B, pairs[:0])
+    assert all(r[k].shape == (0,) for k in oracle_mod.PREDICATES)
+    with pytest.raises(oracle_mod.OracleError):
+        oracle_mod.inside_pairs(A, B, np.array([[0, len(cases)]]))
+
+
+# ---------------------------------------------------------------------------
+# planted mistakes
+# ---------------------------------------------------------------------------
+
+MUTANTS = {
+    "crossing_behind_counted": ("if (f0 != 0 && f0 == -nd) *contrib = nd;", "if (f0 != 0 && f0 == nd) *contrib = nd;"),
+    "crossing_sign_flipped": ("if (f0 != 0 && f0 == -nd) *contrib = nd;", "if (f0 != 0 && f0 == -nd) *contrib = -nd;"),
+    "edge_hits_counted": ("if (e1 == 0 || e2 == 0 || e3 == 0) return 1;", "(void)0;"),
+    "no_retry": ("if (!degenerate) { *w = sum; return 0; }", "{ *w = sum; return 0; }"),
+    "surface_not_detected": ("if ((s1 >= 0 && s2 >= 0 && s3 >= 0) || (s1 <= 0 && s2 <= 0 && s3 <= 0)) return 2;",
+                             "(void)s1; (void)s2; (void)s3;"),
+    "wrong_plane_projection": ("if (n.x.n == 0) { i = 2; j = 0; if (n.y.n == 0) { i = 0; j = 1; } }",
+                               "(void)0;"),
+    "roles_swapped": ("if (on) b |= 4; else if (w != 0) b |= 1;", "if (on) b |= 4; else if (w != 0) b |= 2;"),
+}
+
+
+def _load(path):
+    lib = ctypes.CDLL(path)
+    fp, ip, lp = ctypes.POINTER(ctypes.c_float), ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int64)
+    lib.oracle_winding.argtypes = [fp, ip, lp, lp, ctypes.c_int64, ctypes.c_int64, fp, ctypes.c_int,
+                                   ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32)]
+    lib.oracle_inside_pairs.argtypes = [fp, ip, lp, lp, ctypes.c_int64, fp, ip, lp, lp, ctypes.c_int64,
+                                        ip, ctypes.c_int64, ctypes.POINTER(ctypes.c_uint8), ctypes.c_int]
+    return lib
+
+
+def _args(S):
+    keep = [np.ascontiguousarray(S.verts, np.float32), np.ascontiguousarray(S.faces, np.int32),
+            np.ascontiguousarray(S.vert_off, np.int64), np.ascontiguousarray(S.face_off, np.int64)]
+    types = (ctypes.c_float, ctypes.c_int32, ctypes.c_int64, ctypes.c_int64)
+    return keep, [k.ctypes.data_as(ctypes.POINTER(t)) for k, t in zip(keep, types)] + \
+        [ctypes.c_int64(keep[2].shape[0] - 1)]
+
+
+def _quick_pins_pass(lib):
+    def wn(S, p, fd=0):
+        keep, a = _args(S)
+        q = np.ascontiguousarray(np.asarray(p, np.float32))
+        w, on = ctypes.c_int32(0), ctypes.c_int32(0)
+        r = lib.oracle_winding(*a, ctypes.c_int64(0), q.ctypes.data_as(ctypes.POINTER(ctypes.c_float)), fd,
+                               ctypes.byref(w), ctypes.byref(on))
+        return (r, w.value, bool(on.value))
+
+    cube = _set((CUBE_V, CUBE_F))
+    for p in _lattice(-0.5, 1.5, 0.25):
+        if wn(cube, p) != (0,) + EXPECT[_status_cube(p)]:
+            return False
+    d = np.array([1, 2, 3]) / 16.0
+    for corner in CUBE_V:
+        p = np.asarray(corner, np.float64) - d
+        if wn(cube, p) != (0,) + EXPECT[_status_cube(p)]:
+            return False
+    # a face in a coordinate plane through the origin's axes: x = y plane
+    tilt = _set((TET_V, TET_F))
+    for p in _lattice(-0.25, 1.25, 0.25):
+        if wn(tilt, p) != (0,) + EXPECT[_status_tet(p)]:
+            return False
+    oct_ = _set((OCT_V, OCT_F))
+    for p in _lattice(-1.25, 1.25, 0.25)[::7]:
+        for fd in (0, 5, 11):
+            if wn(oct_, p, fd) != (0,) + EXPECT[_status_oct(p)]:
+                return False
+    cases, A, B, pairs = _hand_sets()
+    ka, aa = _args(A)
+    kb, ab = _args(B)
+    pr = np.ascontiguousarray(pairs, np.int32)
+    bits = np.zeros(len(cases), np.uint8)
+    if lib.oracle_inside_pairs(*aa, *ab, pr.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), len(cases),
+                               bits.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8)), 1) != 0:
+        return False
+    for c, b in zip(cases, bits):
+        if not c["expected"] and ((b & 1) != c["contains"] or bool(b & 2) != c["within"]):
+            return False
+    return True
+
+
+@pytest.mark.slow
+def test_planted_mistakes_are_caught(tmp_path, oracle_mod):
+    src = open(os.path.join(ROOT, "oracle", "oracle.cpp")).read()
+
+    def compile_(text, name):
+        so = str(tmp_path / (name + ".so"))
+        subprocess.run(["g++", "-O1", "-std=c++17", "-shared", "-fPIC", "-pthread", "-x", "c++", "-", "-o", so],
+                       input=text.encode(), check=True)
+        return _load(so)
+
+    assert _quick_pins_pass(compile_(src, "orig"))
+    for name, (old, new) in MUTANTS.items():
+        assert src.count(old) == 1, name
+        assert not _quick_pins_pass(compile_(src.replace(old, new), name)), name
