@@ -42,7 +42,7 @@
 extern "C" {
 #endif
 
-#define PR_ABI_VERSION 6
+#define PR_ABI_VERSION 7
 
 enum {
   PR_OK = 0,
@@ -285,6 +285,84 @@ int refine_intersects_static(const void* blob_a, int64_t n_meshes_a, const void*
                              int64_t n_meshes_b, const int32_t* pairs, int64_t n_pairs,
                              uint8_t* flags, const pr_refine_params* params,
                              pr_refine_stats* dev_stats, int32_t* dev_status, void* stream);
+
+/* ------------------------------------------------------------------------ */
+/* Point-in-mesh test and the containment, within and intersection joins
+ * (Section 3.3, Algorithm 2; Section 3.4).
+ *
+ * For a candidate pair (i in A, j in B) the representative vertex of a mesh
+ * is the first corner of its first face (input order; the build stores it
+ * in the blob).  "rep(B_j) inside A_i" means the winding number of A_i's
+ * surface about that vertex is non-zero: the signed count of crossings of a
+ * +z ray from the vertex, each crossing counted with the sign of the
+ * crossed triangle's normal z component.  Decisions are exact on the FP32
+ * coordinates: orientation signs use the FP64 filter with an exact
+ * expansion fallback, and a ray that would meet an edge or a vertex of the
+ * target is resolved by symbolic perturbation of the vertex to
+ * (x + e, y + e^2, z) for an infinitesimal e > 0 (Simulation of
+ * Simplicity), which never changes the winding number of a point off the
+ * surface.  A vertex lying on a triangle of the other mesh is reported as
+ * such instead.  For closed, embedded, connected surfaces with outward
+ * faces, the winding number is 1 inside and 0 outside, which is the paper's
+ * odd parity; when the two surfaces share no point, the whole of one lies
+ * inside the other iff its representative vertex does. */
+typedef struct {
+  uint64_t rays;           /* rays cast (pair directions not skipped) */
+  uint64_t box_miss;       /* rays that miss the target mesh's box */
+  uint64_t node_visits;    /* BVH nodes loaded */
+  uint64_t tri_tests;      /* leaf triangles whose box the ray column meets */
+  uint64_t crossings;      /* crossings ahead of the vertex (either sign) */
+  uint64_t exact_signs;    /* orientation signs the FP64 filter could not certify */
+  uint64_t on_surface;     /* representative vertices lying on the other surface */
+  uint64_t deep;           /* rays rerun with the full-depth stack */
+} pr_inside_stats;
+
+/* Workspace bytes for inside_pairs on n_pairs pairs. */
+int inside_workspace_bytes(int64_t n_pairs, size_t* ws_bytes);
+
+/* Point-in-mesh test per candidate pair.
+ *  blob_a, blob_b dev   blobs from build_mesh_bvh (any width; both datasets may
+ *                       use different widths)
+ *  n_meshes_a/b         mesh counts (pairs are range-checked on the device:
+ *                       out-of-range pairs get 0 and dev_status PR_E_ARG)
+ *  pairs   dev i32[n_pairs][2]
+ *  mode    0: raw bits; out[p] = bit 0 rep(B_j) inside A_i, bit 1 rep(A_i)
+ *             inside B_j, bit 2 rep(B_j) on A_i's surface, bit 3 rep(A_i)
+ *             on B_j's surface (bits 0 / 1 are 0 when 2 / 3 are set);
+ *             `cross` is not read (may be NULL).
+ *          1: contains      out[p] = !cross[p] && rep(B_j) inside A_i
+ *          2: within        out[p] = !cross[p] && rep(A_i) inside B_j
+ *          3: intersection  out[p] = cross[p] || rep(B_j) inside A_i
+ *                                    || rep(A_i) inside B_j
+ *          Modes 1-3 read cross dev u8[n_pairs] (the overlap flags of
+ *          refine_intersects for the same pairs) and cast rays only for pairs
+ *          with cross[p] == 0; out may alias cross.
+ *  out     dev u8[n_pairs]
+ *  dev_stats dev pr_inside_stats or NULL (overwritten)
+ *  dev_status dev i32[1] or NULL        out: PR_OK, PR_E_ARG (a pair out of range)
+ *                       or PR_E_UNSUPPORTED (a blob that is not a blob of this
+ *                       library, or n_meshes beyond the blob's count)
+ *  ws, ws_bytes dev     scratch of at least inside_workspace_bytes */
+int inside_pairs(const void* blob_a, int64_t n_meshes_a, const void* blob_b, int64_t n_meshes_b,
+                 const int32_t* pairs, int64_t n_pairs, int32_t mode, const uint8_t* cross,
+                 uint8_t* out, pr_inside_stats* dev_stats, int32_t* dev_status, void* ws,
+                 size_t ws_bytes, void* stream);
+
+/* One join predicate over candidate pairs: 0 overlap (refine_intersects),
+ * 1 contains, 2 within, 3 intersection.  Runs refine_intersects, then, for
+ * predicates 1-3, inside_pairs in that mode over the pairs without a shared
+ * surface point; flags dev u8[n_pairs] receives the predicate.  The other
+ * arguments are those of refine_intersects (params->bvh_width must match
+ * both blobs) and inside_pairs (dev_inside_stats is written for predicates
+ * 1-3 only); dev_status keeps the first error of either step; ws of at least
+ * refine_predicate_workspace_bytes. */
+int refine_predicate_workspace_bytes(int64_t n_pairs, const pr_refine_params* params,
+                                     size_t* ws_bytes);
+int refine_predicate(const void* blob_a, int64_t n_meshes_a, const void* blob_b,
+                     int64_t n_meshes_b, const int32_t* pairs, int64_t n_pairs, int32_t predicate,
+                     uint8_t* flags, const pr_refine_params* params, pr_refine_stats* dev_stats,
+                     pr_inside_stats* dev_inside_stats, int32_t* dev_status, void* ws,
+                     size_t ws_bytes, void* stream);
 
 /* ------------------------------------------------------------------------ */
 /* Result materialisation (Section 3.5): keeps the pairs whose flag is 1, in

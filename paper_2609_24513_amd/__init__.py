@@ -9,6 +9,7 @@ arguments and uses PyTorch for device memory and streams.
     pairs = filter_pairs(A, B)                 # closed-box candidates, sorted
     flags, stats = refine(A, B, pairs)         # 1 iff the surfaces share a point
     result = compact(pairs, flags)             # intersecting pairs, sorted
+    flags, *_ = predicate(A, B, pairs, "contains")   # A_i encloses B_j (Section 3.3)
 """
 from __future__ import annotations
 
@@ -18,10 +19,11 @@ from typing import Optional, Tuple
 import numpy as np
 
 from . import _lib
-from ._lib import PierceError, RefineStats, STATS_FIELDS  # noqa: F401
+from ._lib import PierceError, RefineStats, STATS_FIELDS, INSIDE_FIELDS  # noqa: F401
 
 __all__ = ["MeshBlob", "filter_pairs", "refine", "refine_static", "compact", "gather_regions", "refine_workspace",
-           "PierceError", "RefineConfig", "SCHEDULES", "small_grid"]
+           "PierceError", "RefineConfig", "SCHEDULES", "small_grid", "inside", "predicate", "PREDICATES",
+           "predicate_workspace"]
 
 
 def _torch():
@@ -284,6 +286,87 @@ def refine_static(A: MeshBlob, B: MeshBlob, pairs, cfg: Optional[RefineConfig] =
 def stats_dict(stats) -> dict:
     vals = stats.cpu().numpy().astype(np.uint64)
     return {k: int(v) for k, v in zip(STATS_FIELDS, vals)}
+
+
+def inside_stats_dict(stats) -> dict:
+    vals = stats.cpu().numpy().astype(np.uint64)
+    return {k: int(v) for k, v in zip(INSIDE_FIELDS, vals)}
+
+
+# join predicates (Sections 3.2-3.4): code of refine_predicate / inside_pairs mode
+PREDICATES = {"overlap": 0, "contains": 1, "within": 2, "intersection": 3}
+
+
+def inside(A: MeshBlob, B: MeshBlob, pairs, mode=0, cross=None, ws=None, stream=None, out=None, stats=None,
+           status=None) -> Tuple[object, object, object]:
+    """inside_pairs: the point-in-mesh test per candidate pair.  mode 0 returns
+    raw bits (bit 0 rep(B_j) inside A_i, bit 1 rep(A_i) inside B_j, bits 2 / 3
+    the vertex lies on the other surface); modes 1-3 (or "contains", "within",
+    "intersection") combine with `cross`, the overlap flags of refine() for
+    the same pairs.  Returns (out u8[P], stats u64[8], status i32[1]), device
+    tensors, without synchronising."""
+    torch = _torch()
+    lib = _lib.load()
+    mode = PREDICATES[mode] if isinstance(mode, str) else int(mode)
+    pairs = _dev(pairs, torch.int32).reshape(-1, 2)
+    P = int(pairs.shape[0])
+    if mode != 0:
+        if cross is None:
+            raise ValueError("modes 1-3 need the overlap flags")
+        cross = _dev(cross, torch.uint8).reshape(-1)
+    if ws is None:
+        wb = ctypes.c_size_t(0)
+        _lib.check(lib.inside_workspace_bytes(P, ctypes.byref(wb)))
+        ws = _ws(wb.value)
+    if out is None:
+        out = torch.empty(max(P, 1), dtype=torch.uint8, device="cuda")
+    if stats is None:
+        stats = torch.zeros(len(INSIDE_FIELDS), dtype=torch.int64, device="cuda")
+    if status is None:
+        status = torch.zeros(1, dtype=torch.int32, device="cuda")
+    _lib.check(lib.inside_pairs(A.ptr, A.n_meshes, B.ptr, B.n_meshes, pairs.data_ptr(), P, mode,
+                                None if cross is None else cross.data_ptr(), out.data_ptr(), stats.data_ptr(),
+                                status.data_ptr(), ws.data_ptr(), ws.numel(), _stream_ptr(stream)))
+    return out[:P], stats, status
+
+
+def predicate_workspace(n_pairs: int, width: int, cfg: Optional[RefineConfig] = None):
+    cfg = cfg or RefineConfig()
+    prm = cfg.params(width)
+    wb = ctypes.c_size_t(0)
+    _lib.check(_lib.load().refine_predicate_workspace_bytes(int(n_pairs), ctypes.byref(prm), ctypes.byref(wb)))
+    return _ws(wb.value)
+
+
+def predicate(A: MeshBlob, B: MeshBlob, pairs, pred="intersection", cfg: Optional[RefineConfig] = None, ws=None,
+              stream=None, flags=None, stats=None, istats=None, status=None):
+    """refine_predicate: one join predicate ("overlap", "contains", "within",
+    "intersection" or 0-3) per candidate pair.  Returns (flags u8[P], refine
+    stats u64[14], inside stats u64[8], status i32[1]), device tensors, without
+    synchronising."""
+    torch = _torch()
+    cfg = cfg or RefineConfig()
+    if A.width != B.width:
+        raise ValueError("blobs built with different widths")
+    code = PREDICATES[pred] if isinstance(pred, str) else int(pred)
+    pairs = _dev(pairs, torch.int32).reshape(-1, 2)
+    P = int(pairs.shape[0])
+    prm = _params(A, B, cfg)
+    if ws is None:
+        ws = predicate_workspace(P, A.width, cfg)
+    if flags is None:
+        flags = torch.empty(max(P, 1), dtype=torch.uint8, device="cuda")
+    if stats is None:
+        stats = torch.zeros(len(STATS_FIELDS), dtype=torch.int64, device="cuda")
+    if istats is None:
+        istats = torch.zeros(len(INSIDE_FIELDS), dtype=torch.int64, device="cuda")
+    if status is None:
+        status = torch.zeros(1, dtype=torch.int32, device="cuda")
+    _lib.check(_lib.load().refine_predicate(A.ptr, A.n_meshes, B.ptr, B.n_meshes, pairs.data_ptr(), P, code,
+                                            flags.data_ptr(), ctypes.byref(prm), stats.data_ptr(),
+                                            istats.data_ptr(), status.data_ptr(), ws.data_ptr(), ws.numel(),
+                                            _stream_ptr(stream)))
+    return flags[:P], stats, istats, status
 
 
 def gather_regions(regions, region_cap: int, counts, n_regions: int, out, total, stream=None):

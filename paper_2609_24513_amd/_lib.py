@@ -18,13 +18,14 @@ PR_E_CAPACITY = -2
 PR_E_GEOMETRY = -3
 PR_E_DEVICE = -4
 PR_E_UNSUPPORTED = -5
-ABI_VERSION = 6
+ABI_VERSION = 7
 
 EXPORTS = [
     "pr_last_error", "pr_abi_version", "build_mesh_bvh_sizes", "build_mesh_bvh", "blob_mesh_boxes",
     "blob_edge_counts", "filter_aabb_pairs_ws_bytes", "filter_aabb_pairs", "refine_workspace_bytes",
     "refine_intersects", "compact_pairs_ws_bytes", "compact_pairs", "gather_pair_regions",
     "refine_static_scratch_bytes", "refine_intersects_static", "blob_coord_exponents", "build_mesh_bvh_bytes",
+    "inside_workspace_bytes", "inside_pairs", "refine_predicate_workspace_bytes", "refine_predicate",
 ]
 
 
@@ -59,6 +60,15 @@ class RefineStats(ctypes.Structure):
 
 
 STATS_FIELDS = [f for f, _ in RefineStats._fields_]
+
+
+class InsideStats(ctypes.Structure):
+    _fields_ = [("rays", ctypes.c_uint64), ("box_miss", ctypes.c_uint64), ("node_visits", ctypes.c_uint64),
+                ("tri_tests", ctypes.c_uint64), ("crossings", ctypes.c_uint64), ("exact_signs", ctypes.c_uint64),
+                ("on_surface", ctypes.c_uint64), ("deep", ctypes.c_uint64)]
+
+
+INSIDE_FIELDS = [f for f, _ in InsideStats._fields_]
 
 _lock = threading.Lock()
 _lib = None
@@ -100,6 +110,11 @@ def load():
         lib.refine_intersects_static.argtypes = [vp, i64, vp, i64, vp, i64, vp, ctypes.POINTER(RefineParams),
                                                  vp, vp, vp]
         lib.refine_static_scratch_bytes.argtypes = []
+        lib.inside_workspace_bytes.argtypes = [i64, szp]
+        lib.inside_pairs.argtypes = [vp, i64, vp, i64, vp, i64, i32, vp, vp, vp, vp, vp, ctypes.c_size_t, vp]
+        lib.refine_predicate_workspace_bytes.argtypes = [i64, ctypes.POINTER(RefineParams), szp]
+        lib.refine_predicate.argtypes = [vp, i64, vp, i64, vp, i64, i32, vp, ctypes.POINTER(RefineParams),
+                                         vp, vp, vp, vp, ctypes.c_size_t, vp]
         for name in EXPORTS[2:]:
             getattr(lib, name).restype = ctypes.c_int
         lib.refine_static_scratch_bytes.restype = ctypes.c_size_t

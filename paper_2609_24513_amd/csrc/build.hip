@@ -84,6 +84,7 @@ struct BuildArgs {
   int32_t* edge;
   float* cbox;
   int32_t* cmesh;
+  float* rep;            // [M][4] representative vertex of each mesh
   int64_t node_cap, chunk_cap;
   // workspace
   int32_t* status;       // min bad face (INT_MAX if none)
@@ -254,6 +255,19 @@ __global__ void k_mesh_box(BuildArgs a) {
       d.root = kEmpty;
       d.flags = s > 0.f ? kMeshSafe : 0;
       a.mesh[m] = d;
+      // representative vertex for the point-in-mesh test: the first corner
+      // of the mesh's first face (the face id is range-checked here; a bad
+      // id fails the build through the status word anyway)
+      float4 rv = make_float4(0.f, 0.f, 0.f, 0.f);
+      if (f1 > f0) {
+        const int64_t v0 = a.vert_off[m], nv = a.vert_off[m + 1] - v0;
+        const int32_t id = a.faces[3 * f0];
+        if (id >= 0 && id < nv) {
+          const float* x = a.verts + 3 * (v0 + id);
+          rv = make_float4(x[0], x[1], x[2], 1.f);
+        }
+      }
+      reinterpret_cast<float4*>(a.rep)[m] = rv;
     }
   }
 }
@@ -756,7 +770,7 @@ __global__ void k_fill_u32(uint32_t* p, int64_t n, uint32_t v) {
 
 struct Layout {
   int64_t node_cap, chunk_cap;
-  int64_t off_mesh, off_node, off_tri, off_triid, off_seg, off_edge, off_cbox, off_cmesh, total;
+  int64_t off_mesh, off_node, off_tri, off_triid, off_seg, off_edge, off_cbox, off_cmesh, off_rep, total;
 };
 
 Layout blob_layout(int64_t M, int64_t F, int W, int L) {
@@ -774,6 +788,7 @@ Layout blob_layout(int64_t M, int64_t F, int W, int L) {
   y.off_edge = o; o = align256(o + y.chunk_cap * 2 * kChunk * 4);
   y.off_cbox = o; o = align256(o + y.chunk_cap * 32);
   y.off_cmesh = o; o = align256(o + y.chunk_cap * 4);
+  y.off_rep = o; o = align256(o + M * 16);
   y.total = o;
   return y;
 }
@@ -929,6 +944,7 @@ extern "C" int build_mesh_bvh(const float* verts, const int64_t* vert_off, const
   a.edge = reinterpret_cast<int32_t*>(a.blob + y.off_edge);
   a.cbox = reinterpret_cast<float*>(a.blob + y.off_cbox);
   a.cmesh = reinterpret_cast<int32_t*>(a.blob + y.off_cmesh);
+  a.rep = reinterpret_cast<float*>(a.blob + y.off_rep);
   a.node_cap = y.node_cap;
   a.chunk_cap = y.chunk_cap;
 
@@ -1011,6 +1027,7 @@ extern "C" int build_mesh_bvh(const float* verts, const int64_t* vert_off, const
   h.off_edge = y.off_edge;
   h.off_cbox = y.off_cbox;
   h.off_cmesh = y.off_cmesh;
+  h.off_rep = y.off_rep;
   h.total_bytes = y.total;
   hipLaunchKernelGGL(k_header, dim3(1), dim3(1), 0, s, a, h, (const int64_t*)a.chunk_scan, E3);
   hipLaunchKernelGGL(k_status_out, dim3(1), dim3(1), 0, s, (const int32_t*)a.status, dev_status);

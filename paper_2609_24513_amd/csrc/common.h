@@ -48,7 +48,9 @@ struct BlobHeader {
   int64_t n_edges;    // unique edges in use (written by the build)
   int32_t exp_lo;     // lowest exponent of a set bit over every non-zero coordinate of a face
   int32_t exp_hi;     // highest such exponent (every |coordinate| < 2^(exp_hi + 1))
-  int64_t reserved[13];
+  int64_t off_rep;    // f32[n_meshes][4]: first corner of each mesh's first face (input order), w = 1;
+                      // w = 0 for a mesh without faces
+  int64_t reserved[12];
 };
 static_assert(sizeof(BlobHeader) == 256, "header size");
 

@@ -42,6 +42,7 @@ def test_struct_sizes():
     assert ctypes.sizeof(_lib.BvhParams) == 16
     assert ctypes.sizeof(_lib.RefineParams) == 64
     assert ctypes.sizeof(_lib.RefineStats) == 112
+    assert ctypes.sizeof(_lib.InsideStats) == 64
 
 
 @pytest.mark.parametrize("w,l,b,r", [(3, 4, 0, 0), (4, 3, 0, 0), (4, 4, 2, 0), (4, 4, -1, 0), (4, 4, 0, 1),
@@ -154,6 +155,43 @@ def test_filter_compact_and_gather_args_rejected(lib):
     assert lib.gather_pair_regions(None, 4, None, 0, None, 5, ctypes.byref(dummy), None) == _lib.PR_E_ARG
     assert lib.gather_pair_regions(ctypes.byref(dummy), 4, ctypes.byref(dummy), (1 << 20) + 1, None, 0,
                                    ctypes.byref(dummy), None) == _lib.PR_E_UNSUPPORTED
+
+
+def test_inside_and_predicate_args_rejected(lib):
+    """Host-visible errors of the containment entry points, before any device
+    work: negative sizes, null pointers, unknown modes and predicates, a mode
+    that needs overlap flags without them, a too-small workspace."""
+    wb = ctypes.c_size_t(0)
+    assert lib.inside_workspace_bytes(-1, ctypes.byref(wb)) == _lib.PR_E_ARG
+    assert lib.inside_workspace_bytes(10, None) == _lib.PR_E_ARG
+    assert lib.inside_workspace_bytes(1 << 31, ctypes.byref(wb)) == _lib.PR_E_UNSUPPORTED
+    assert lib.inside_workspace_bytes(1000, ctypes.byref(wb)) == _lib.PR_OK and wb.value >= 2 * 1000 * 5
+    d = ctypes.c_int64(0)
+    buf = ctypes.byref(d)
+    # null blobs, null pairs / out with pairs, negative counts
+    assert lib.inside_pairs(None, 1, buf, 1, buf, 1, 0, None, buf, None, None, buf, 1 << 20, None) == _lib.PR_E_ARG
+    assert lib.inside_pairs(buf, 1, buf, 1, None, 1, 0, None, buf, None, None, buf, 1 << 20, None) == _lib.PR_E_ARG
+    assert lib.inside_pairs(buf, -1, buf, 1, buf, 1, 0, None, buf, None, None, buf, 1 << 20, None) == _lib.PR_E_ARG
+    for mode in (-1, 4):
+        assert lib.inside_pairs(buf, 1, buf, 1, buf, 1, mode, buf, buf, None, None, buf, 1 << 20,
+                                None) == _lib.PR_E_ARG
+    assert lib.inside_pairs(buf, 1, buf, 1, buf, 1, 1, None, buf, None, None, buf, 1 << 20, None) == _lib.PR_E_ARG
+    assert lib.inside_pairs(buf, 1, buf, 1, buf, 1, 0, None, buf, None, None, buf, 64, None) == _lib.PR_E_CAPACITY
+    p = _refine_params()
+    assert lib.refine_predicate_workspace_bytes(10, ctypes.byref(p), ctypes.byref(wb)) == _lib.PR_OK
+    need = wb.value
+    rw, iw = ctypes.c_size_t(0), ctypes.c_size_t(0)
+    lib.refine_workspace_bytes(10, ctypes.byref(p), ctypes.byref(rw))
+    lib.inside_workspace_bytes(10, ctypes.byref(iw))
+    assert need == max(rw.value, iw.value)
+    for pred in (-1, 4):
+        assert lib.refine_predicate(buf, 1, buf, 1, buf, 1, pred, buf, ctypes.byref(p), None, None, None, buf,
+                                    need, None) == _lib.PR_E_ARG
+    assert lib.refine_predicate(buf, 1, buf, 1, buf, 1, 1, buf, ctypes.byref(p), None, None, None, buf, 64,
+                                None) == _lib.PR_E_CAPACITY
+    bad = _refine_params(w=3)
+    assert lib.refine_predicate(buf, 1, buf, 1, buf, 1, 1, buf, ctypes.byref(bad), None, None, None, buf, need,
+                                None) == _lib.PR_E_ARG
 
 
 def test_product_path_has_no_oracle_dependency():

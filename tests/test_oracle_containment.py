@@ -21,6 +21,7 @@ import itertools
 import json
 import os
 import subprocess
+import sys
 from fractions import Fraction
 
 import numpy as np
@@ -31,17 +32,9 @@ from paper_2609_24513_amd import synth
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 
-TET_V = [[0, 0, 0], [1, 0, 0], [0, 1, 0], [0, 0, 1]]
-TET_F = [[0, 2, 1], [0, 1, 3], [0, 3, 2], [1, 2, 3]]
-OCT_V = [[1, 0, 0], [-1, 0, 0], [0, 1, 0], [0, -1, 0], [0, 0, 1], [0, 0, -1]]
-OCT_F = [[0, 2, 4], [2, 1, 4], [1, 3, 4], [3, 0, 4], [2, 0, 5], [1, 2, 5], [3, 1, 5], [0, 3, 5]]
-CUBE_V = [[x, y, z] for x in (0, 1) for y in (0, 1) for z in (0, 1)]
-CUBE_F = [[0, 1, 3], [0, 3, 2], [4, 6, 7], [4, 7, 5], [0, 4, 5], [0, 5, 1],
-          [2, 3, 7], [2, 7, 6], [0, 2, 6], [0, 6, 4], [1, 5, 7], [1, 7, 3]]
-
-
-def _set(*meshes):
-    return synth.concat_meshes([(np.asarray(v, np.float64), np.asarray(f)) for v, f in meshes])
+sys.path.insert(0, HERE)
+from containment_inputs import (TET_V, TET_F, OCT_V, OCT_F, CUBE_V, CUBE_F, box as _box,  # noqa: E402
+                                lattice as _lattice, mesh_set as _set, spheres as _spheres, torus as _torus)
 
 
 def _status_tet(p):
@@ -67,9 +60,6 @@ def _status_oct(p):
 EXPECT = {"in": (1, False), "out": (0, False), "on": (0, True)}
 
 
-def _lattice(lo, hi, step):
-    ax = np.arange(lo, hi + step / 2, step)
-    return [np.array(p) for p in itertools.product(ax, ax, ax)]
 
 
 @pytest.mark.parametrize("name", ["tet", "cube", "oct"])
@@ -130,9 +120,6 @@ def test_reversed_faces_negate(oracle_mod):
     assert oracle_mod.winding(S, 0, [1.0, 0.25, 0.75]) == (0, True)
 
 
-def _box(lo, hi):
-    return [[(lo[0], hi[0])[i], (lo[1], hi[1])[j], (lo[2], hi[2])[k]]
-            for i in (0, 1) for j in (0, 1) for k in (0, 1)]
 
 
 def test_shell_and_nested_components(oracle_mod):
@@ -151,19 +138,6 @@ def test_shell_and_nested_components(oracle_mod):
     assert oracle_mod.winding(shell, 0, [1, 0.5, 0.5]) == (0, True)
 
 
-def _torus(R, r, nu, nv):
-    u = 2 * np.pi * np.arange(nu) / nu
-    v = 2 * np.pi * np.arange(nv) / nv
-    uu, vv = np.meshgrid(u, v, indexing="ij")
-    verts = np.stack([(R + r * np.cos(vv)) * np.cos(uu), (R + r * np.cos(vv)) * np.sin(uu), r * np.sin(vv)],
-                     -1).reshape(-1, 3)
-    faces = []
-    for i in range(nu):
-        for j in range(nv):
-            a, b = i * nv + j, ((i + 1) % nu) * nv + j
-            c, d = ((i + 1) % nu) * nv + (j + 1) % nv, i * nv + (j + 1) % nv
-            faces += [[a, b, c], [a, c, d]]
-    return verts, np.asarray(faces)
 
 
 def test_torus_by_distance_bounds(oracle_mod):
@@ -239,23 +213,6 @@ def test_inside_bits_on_hand_cases(oracle_mod):
     assert by["disjoint_2e-12"] == 0
 
 
-def _spheres(seed=41, n=250):
-    """Jittered level-2 icospheres around centres c with radii 0.6..1.2 and
-    B's centre at distance 0..2.8 from A's, so that all of disjoint, crossing,
-    A-contains-B and B-contains-A occur."""
-    rng = np.random.default_rng(seed)
-    tv, tf = synth.icosphere(2)
-    As, Bs, info = [], [], []
-    for _ in range(n):
-        ra, rb = rng.uniform(0.3, 1.2, size=2)
-        ca = rng.uniform(0, 4, size=3)
-        d = rng.normal(size=3)
-        d /= np.linalg.norm(d)
-        cb = ca + d * rng.uniform(0.0, 2.8) * rng.uniform(0, 1) ** 2
-        va = (ca[None] + (ra + rng.normal(0, 0.02 * ra, size=162))[:, None] * tv).astype(np.float32)
-        vb = (cb[None] + (rb + rng.normal(0, 0.02 * rb, size=162))[:, None] * tv).astype(np.float32)
-        As.append((va, tf)); Bs.append((vb, tf)); info.append((ca, cb, va, vb))
-    return synth.concat_meshes(As), synth.concat_meshes(Bs), info, tf
 
 
 def _radii(v, f, c):
