@@ -92,6 +92,9 @@ DESCS = {
     "c4": "precision stress: 2,000 pairs of level-4 icospheres on a 2^-10 grid (30% tangent, 20% coplanar, "
           "10% vertex on surface, 40% random)",
 }
+for _k, _m in enumerate((4, 20, 39, 74, 144)):
+    DESCS["sweep%d" % _k] = ("mesh complexity: 500 x 500 unit UV spheres (%d rings x %d segments, %d triangles each) "
+                             "at fixed placements, 100 intersecting pairs" % (_m, 2 * _m, 2 * ((_m - 1) * 2 * _m + 2) - 4))
 
 
 def make_workload(name: str):
@@ -110,6 +113,9 @@ def make_workload(name: str):
         return A, B, pairs
     if name == "c3":
         return synth.make_c3()
+    if name.startswith("sweep") and name[5:].isdigit() and int(name[5:]) < len(synth.SWEEP_RINGS):
+        A, B = synth.make_sweep(int(name[5:]))
+        return A, B, None
     raise SystemExit("unknown workload " + name)
 
 
@@ -203,8 +209,53 @@ def roofline_of(st: dict, W: int, kern_ms: float, workload: str) -> dict:
             "loaded_gbs": loaded / (kern_ms * 1e-3) / 1e9}
 
 
+def predicate_bench(torch, pa, ga, gb, pairs, cfg_kw: dict, reps: int = 5) -> dict:
+    """The four join predicates on the same candidate pairs (Sections 3.2-3.4),
+    each one refine_predicate call (edge tracing, then for contains / within /
+    intersection the point-in-mesh rays on the pairs without a shared point):
+    the mean time of `reps` calls after one warm-up, the containment phase as
+    the difference to the overlap predicate, the result counts and the ray
+    statistics; and each predicate's flags against the two phases run as
+    separate calls (refine, then inside_pairs in the predicate's mode)."""
+    P = int(pairs.shape[0])
+    cfg = pa.RefineConfig(**cfg_kw)
+    ws = pa.predicate_workspace(P, ga.width, cfg)
+    flags = torch.empty(P, dtype=torch.uint8, device="cuda")
+    st = torch.zeros(len(pa.STATS_FIELDS), dtype=torch.int64, device="cuda")
+    ist = torch.zeros(len(pa.INSIDE_FIELDS), dtype=torch.int64, device="cuda")
+    status = torch.zeros(1, dtype=torch.int32, device="cuda")
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(reps)]
+    for e in [e for pair in evs for e in pair]:
+        e.record()
+    res = {}
+    for name, code in pa.PREDICATES.items():
+        for r in range(-1, reps):
+            if r >= 0:
+                evs[r][0].record()
+            pa.predicate(ga, gb, pairs, code, cfg, ws=ws, flags=flags, stats=st, istats=ist, status=status)
+            if r >= 0:
+                evs[r][1].record()
+        torch.cuda.synchronize()
+        assert int(status.item()) == 0
+        got = flags.cpu().numpy()[:P].copy()
+        total = float(np.mean([a.elapsed_time(b) for a, b in evs]))
+        cross, _, _ = pa.refine(ga, gb, pairs, cfg)
+        sep = pa.inside(ga, gb, pairs, mode=code, cross=cross)[0] if code else cross
+        torch.cuda.synchronize()
+        r_ = {"ms": total, "result_pairs": int(got.sum()), "pairs_per_s": P / (total * 1e-3),
+              "same_as_separate_calls": bool(np.array_equal(sep.cpu().numpy()[:P], got))}
+        if code:
+            r_["containment_rays_ms"] = total - res["overlap"]["ms"]
+            r_["inside_stats"] = pa.inside_stats_dict(ist)
+        res[name] = r_
+        log("predicate %-12s %.3f ms (containment rays %.3f), %d pairs" % (
+            name, total, r_.get("containment_rays_ms", 0.0), r_["result_pairs"]))
+    del ws
+    return res
+
+
 def run_join(name: str, args, tune: bool, plain: bool, compare_precision: bool, cpu: bool, steps: int,
-             warmup: int, check_oracle: bool = False) -> dict:
+             warmup: int, check_oracle: bool = False, predicates: bool = False) -> dict:
     """Times one join workload: returns the measurements as a dict."""
     import torch
     import paper_2609_24513_amd as pa
@@ -230,9 +281,19 @@ def run_join(name: str, args, tune: bool, plain: bool, compare_precision: bool, 
         tuned = {k: tuned[k] for k in ("best", "per_bucket", "sample", "tune_seconds", "cached")}
 
     ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    # the meshes are resident in HBM before the build is timed, and one
+    # untimed build first leaves its device memory in the allocator's cache
+    # (the library allocates nothing itself)
+    import types
+    da, db = (types.SimpleNamespace(**{k: torch.as_tensor(getattr(S, k)).cuda()
+                                       for k in ("verts", "faces", "vert_off", "face_off")}) for S in (A, B))
+    ga = pa.MeshBlob.build(da, width=W, leaf_size=L, check_status=False)
+    gb = pa.MeshBlob.build(db, width=W, leaf_size=L, check_status=False)
+    torch.cuda.synchronize()
+    del ga, gb
     ev0.record()
-    ga = pa.MeshBlob.build(A, width=W, leaf_size=L, check_status=False)
-    gb = pa.MeshBlob.build(B, width=W, leaf_size=L, check_status=False)
+    ga = pa.MeshBlob.build(da, width=W, leaf_size=L, check_status=False)
+    gb = pa.MeshBlob.build(db, width=W, leaf_size=L, check_status=False)
     ev1.record()
     torch.cuda.synchronize()
     build_ms = ev0.elapsed_time(ev1)
@@ -354,6 +415,9 @@ def run_join(name: str, args, tune: bool, plain: bool, compare_precision: bool, 
         cpu_r = cpu_baseline(A, B, out_pairs, gflags, args.cpu_seconds)
         log("%s: cpu oracle %.1f pairs/s on %d threads, agrees: %s" % (
             name, cpu_r["value"], cpu_r["cores"], cpu_r["gpu_agrees_on_sample"]))
+    preds = None
+    if predicates:
+        preds = predicate_bench(torch, pa, ga, gb, first, base_cfg)
     oracle_check = None
     if check_oracle:
         import oracle
@@ -377,9 +441,10 @@ def run_join(name: str, args, tune: bool, plain: bool, compare_precision: bool, 
         "build_ms": build_ms, "generate_s": gen_s, "roofline": roof, "plain_per_pair": plain_r,
         "precision_comparison": prec, "autotune": tuned, "cpu_baseline": cpu_r, "stats": st,
         "retest_fraction": (st["fp32_ambiguous"] / st["tri_tests"]) if st["tri_tests"] else 0.0,
-        "oracle_check": oracle_check,
+        "oracle_check": oracle_check, "predicates": preds,
+        "triangles_per_mesh": int(A.faces.shape[0] // max(A.n_meshes, 1)),
     }
-    del ga, gb, ws, given, first
+    del ga, gb, ws, given, first, da, db
     torch.cuda.empty_cache()
     return out
 
@@ -488,19 +553,29 @@ def main():
 
     head = run_join(args.workload, args, tune=not args.no_tune, plain=not args.skip_plain,
                     compare_precision=not args.skip_plain, cpu=not args.skip_cpu, steps=args.steps,
-                    warmup=args.warmup)
+                    warmup=args.warmup, predicates=True)
     head["roofline"]["achievable_gbs"] = achievable_hbm_gbs(torch)
     head["roofline"]["frac_of_achievable"] = head["roofline"]["achieved"] / head["roofline"]["achievable_gbs"]
     extras = {}
     if not args.no_extras:
         if args.workload != "c2":
             extras["c2"] = run_join("c2", args, tune=False, plain=False, compare_precision=False, cpu=False,
-                                    steps=args.steps, warmup=args.warmup)
+                                    steps=args.steps, warmup=args.warmup, predicates=True)
         if args.workload != "c4":
             extras["c4"] = run_join("c4", args, tune=False, plain=not args.skip_plain,
                                     compare_precision=not args.skip_plain, cpu=False, steps=args.steps,
                                     warmup=args.warmup, check_oracle=True)
         extras["c5"] = serve_bench(args)
+        sweep = []
+        for k in range(5):
+            r = run_join("sweep%d" % k, args, tune=False, plain=False, compare_precision=False, cpu=False,
+                         steps=args.steps, warmup=args.warmup)
+            sweep.append({"triangles_per_sphere": r["triangles_per_mesh"], "ms_per_step": r["ms_per_step"],
+                          "refine_ms": r["refine_ms"], "filter_ms": r["filter_ms"],
+                          "candidate_pairs": r["candidate_pairs"], "intersecting_pairs": r["intersecting_pairs"],
+                          "segment_queries_per_s": r["segment_queries_per_s"], "build_ms": r["build_ms"]})
+        extras["mesh_complexity"] = {"workload": "500 x 500 unit UV spheres at fixed placements, tessellation "
+                                                 "swept over five stages (Section 4.4)", "stages": sweep}
     if args.calibrate_copy_mib > 0:
         n = args.calibrate_copy_mib << 20
         src = torch.ones(n // 4, dtype=torch.float32, device="cuda")
@@ -514,7 +589,7 @@ def main():
         keys = ("workload", "candidate_pairs", "intersecting_pairs", "bvh_width", "leaf_size", "schedule_name",
                 "step", "ms_per_step", "pairs_per_s", "refine_ms", "filter_ms", "refine_pairs_per_s",
                 "segment_queries_per_s", "traversal_kernels_ms", "build_ms", "retest_fraction", "roofline",
-                "oracle_check", "plain_per_pair", "precision_comparison", "stats")
+                "oracle_check", "plain_per_pair", "precision_comparison", "stats", "predicates")
         return {k: r[k] for k in keys if k in r}
 
     line = {
@@ -533,7 +608,8 @@ def main():
         "roofline": head["roofline"], "cpu_baseline": head["cpu_baseline"],
         "plain_per_pair": head["plain_per_pair"], "precision_comparison": head["precision_comparison"],
         "autotune": head["autotune"], "stats": head["stats"], "retest_fraction": head["retest_fraction"],
-        "workloads": {k: (brief(v) if k != "c5" else v) for k, v in extras.items()},
+        "predicates": head["predicates"],
+        "workloads": {k: (brief(v) if k not in ("c5", "mesh_complexity") else v) for k, v in extras.items()},
     }
     if "c5" in extras:
         line["p50_ms"] = extras["c5"]["p50_ms"]

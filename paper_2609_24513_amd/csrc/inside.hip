@@ -2,17 +2,19 @@
 // join (Section 3.3, Algorithm 2) and the containment, within and
 // intersection predicates built on it (Sections 3.3 and 3.4).
 //
-// Work unit: one (pair, direction), the representative vertex v of the
-// source mesh against the target mesh's BVH.  One thread per unit walks the
+// Work unit: one candidate pair, one thread.  A ray is the representative
+// vertex v of one mesh against the other mesh's BVH: the thread walks the
 // target tree along the column {(v.x, v.y, z) : z >= v.z} (the +z ray of the
-// paper's parity test), counting signed crossings.  The paper casts one ray
+// paper's parity test), counting signed crossings; it casts the rays the
+// predicate needs (contains: rep(B_j) in A_i; within: rep(A_i) in B_j;
+// intersection: the second only if the first is outside; raw bits: both).  The paper casts one ray
 // per object against a BVH of a whole dataset and toggles a parity bit per
 // hit object; here each candidate pair has its target mesh's own tree, so
 // the ray meets only that mesh and a signed count per unit replaces the
 // per-object parity array.
 //
 // The thread's stack lives in LDS, entry-major with one column per thread so
-// that lanes at equal depth use distinct banks.  A unit whose stack would
+// that lanes at equal depth use distinct banks.  A pair whose stack would
 // overflow is appended to a list and rerun by a second kernel whose threads
 // hold a stack of the full depth bound.
 //
@@ -47,10 +49,12 @@
 namespace pr {
 namespace {
 
-constexpr int kIB = 256;                      // threads per block, fast kernel
+constexpr int kIB = 64;                       // threads per block, fast kernel (one wave: small
+                                              // launches still reach every compute unit)
 constexpr int kFastCap = 32;                  // LDS stack entries per thread there
 constexpr int kDeepB = 32;                    // threads per block, deep kernel
-constexpr int kDeepCap = 7 * kMaxDepth + 1;   // W - 1 <= 7 pending siblings per level, plus one
+constexpr int kDeepCap = 7 * (kMaxDepth + 1) + 1;  // W - 1 <= 7 pending siblings per level (the
+                                                   // leaf level too), plus one
 constexpr int kDeepGrid = 256;
 constexpr int kCopies = 64;                   // statistics copies (blockIdx % kCopies)
 constexpr int kStride = 512;                  // u64 words between copies
@@ -59,7 +63,7 @@ enum { I_RAYS = 0, I_BOXMISS, I_VISITS, I_TESTS, I_CROSS, I_EXACT, I_ON, I_DEEP,
 static_assert(sizeof(pr_inside_stats) == I_N * 8, "stats layout");
 
 // per-unit result codes
-enum : uint8_t { U_OUT = 0, U_IN = 1, U_ON = 2, U_PENDING = 3 };
+enum : uint8_t { U_OUT = 0, U_IN = 1, U_ON = 2 };
 
 struct Blob {
   const MeshDesc* mesh;
@@ -89,9 +93,8 @@ struct InsideArgs {
   const uint8_t* cross;       // modes 1-3: overlap flags
   uint8_t* out;
   int32_t mode;
-  uint8_t* ubits;             // [2P] per-unit result (U_*)
-  uint32_t* deep;             // [2P] units rerun with the full stack
-  uint32_t* deep_n;           // [1]
+  uint32_t* deep;             // [P] pairs rerun with the full stack
+  uint32_t* ctr;              // [0] pairs in deep, [1] deep-kernel blocks finished
   unsigned long long* stats;  // kCopies copies, kStride words apart
   int32_t* status;            // [1] PR_OK or PR_E_ARG
 };
@@ -109,8 +112,10 @@ __device__ __forceinline__ int sos2(f3 a, f3 b, f3 v, ExactCounters& ec) {
   return 0;
 }
 
-// v (in the triangle's plane) lies in the closed triangle.
-__device__ __noinline__ bool on_triangle(f3 a, f3 b, f3 c, f3 v, ExactCounters& ec) {
+// v (in the triangle's plane) lies in the closed triangle: returns
+// on | exact_signs << 1 (a call, so the counters stay in registers).
+__device__ __noinline__ uint32_t on_triangle(f3 a, f3 b, f3 c, f3 v) {
+  ExactCounters ec{0};
   int i = 1, j = 2;
   if (sign_orient2d(a, b, c, 1, 2, ec) == 0) {
     i = 2; j = 0;
@@ -118,7 +123,8 @@ __device__ __noinline__ bool on_triangle(f3 a, f3 b, f3 c, f3 v, ExactCounters& 
   }
   const int s1 = sign_orient2d(a, b, v, i, j, ec), s2 = sign_orient2d(b, c, v, i, j, ec),
             s3 = sign_orient2d(c, a, v, i, j, ec);
-  return (s1 >= 0 && s2 >= 0 && s3 >= 0) || (s1 <= 0 && s2 <= 0 && s3 <= 0);
+  const bool on = (s1 >= 0 && s2 >= 0 && s3 >= 0) || (s1 <= 0 && s2 <= 0 && s3 <= 0);
+  return (on ? 1u : 0u) | (ec.exact_signs << 1);
 }
 
 // One leaf triangle against the column above v: returns true when v lies on
@@ -141,7 +147,13 @@ __device__ __forceinline__ bool column_tri(const float* t, f3 v, int& wn, Counts
   if (meets || inbox) {
     const int o3 = sign_orient3d(a, b, c, v, ec);
     if (o3 == 0) {
-      on = meets || on_triangle(a, b, c, v, ec);
+      if (meets) {
+        on = true;
+      } else {
+        const uint32_t r = on_triangle(a, b, c, v);
+        on = (r & 1u) != 0;
+        ec.exact_signs += r >> 1;
+      }
     } else if (meets && o3 == -s1) {
       wn += s1;
       ++k.c[I_CROSS];
@@ -154,7 +166,7 @@ __device__ __forceinline__ bool column_tri(const float* t, f3 v, int& wn, Counts
 // Winding test of v against mesh tm of T: U_OUT, U_IN, U_ON, or -1 when the
 // stack (cap entries, stride apart) would overflow.
 template <int W>
-__device__ int column_walk(const Blob& T, int32_t tm, f3 v, int32_t* stk, int stride, int cap, Counts& k) {
+__device__ __forceinline__ int column_walk(const Blob& T, int32_t tm, f3 v, int32_t* stk, int stride, int cap, Counts& k) {
   const MeshDesc* md = T.mesh + tm;
   const int32_t root = md->root;
   if (root == kEmpty || md->n_tris <= 0 || !(md->box[0] <= v.x && v.x <= md->box[3] && md->box[1] <= v.y &&
@@ -166,10 +178,23 @@ __device__ int column_walk(const Blob& T, int32_t tm, f3 v, int32_t* stk, int st
   int sp = 1;
   stk[0] = root;
   int wn = 0;
+  // leaves are pushed like nodes, so the leaf code exists once
   while (sp > 0) {
     --sp;
-    const Node<W>* n = nodes + stk[sp * stride];
+    const int32_t ref = stk[sp * stride];
+    if (ref < 0) {
+      const int32_t lr = ~ref;
+      const int32_t first = lr >> 3, cnt = (lr & 7) + 1;
+      for (int t = 0; t < cnt; ++t)
+        if (column_tri(T.tris + 9 * (int64_t)(first + t), v, wn, k)) {
+          ++k.c[I_ON];
+          return U_ON;
+        }
+      continue;
+    }
+    const Node<W>* n = nodes + ref;
     ++k.c[I_VISITS];
+    // the whole node is loaded at once
     float lx[W], hx[W], ly[W], hy[W], hz[W];
     int32_t ch[W];
 #pragma unroll
@@ -183,19 +208,9 @@ __device__ int column_walk(const Blob& T, int32_t tm, f3 v, int32_t* stk, int st
     for (int q = 0; q < W; ++q) {
       if (ch[q] == kEmpty || !(lx[q] <= v.x && v.x <= hx[q] && ly[q] <= v.y && v.y <= hy[q] && v.z <= hz[q]))
         continue;
-      if (ch[q] < 0) {
-        const int32_t lr = ~ch[q];
-        const int32_t first = lr >> 3, cnt = (lr & 7) + 1;
-        for (int t = 0; t < cnt; ++t)
-          if (column_tri(T.tris + 9 * (int64_t)(first + t), v, wn, k)) {
-            ++k.c[I_ON];
-            return U_ON;
-          }
-      } else {
-        if (sp == cap) return -1;
-        stk[sp * stride] = ch[q];
-        ++sp;
-      }
+      if (sp == cap) return -1;
+      stk[sp * stride] = ch[q];
+      ++sp;
     }
   }
   return wn != 0 ? U_IN : U_OUT;
@@ -208,39 +223,53 @@ __device__ __forceinline__ int walk(const Blob& T, int32_t tm, f3 v, int32_t* st
   return column_walk<8>(T, tm, v, stk, stride, cap, k);
 }
 
-// Whether unit u is cast; *i, *j get the pair (range-checked).
-__device__ __forceinline__ bool unit_live(const InsideArgs& a, int64_t u, int32_t& i, int32_t& j) {
-  const int64_t p = u >> 1;
-  const int d = (int)(u & 1);
-  if (a.mode == 1 && d != 0) return false;
-  if (a.mode == 2 && d != 1) return false;
-  if (a.mode != 0 && a.cross[p] != 0) return false;
+// The two blobs are this library's and hold the meshes the caller names.
+__device__ __forceinline__ bool blobs_ok(const InsideArgs& a) {
   const BlobHeader* ha = reinterpret_cast<const BlobHeader*>(a.blob_a);
   const BlobHeader* hb = reinterpret_cast<const BlobHeader*>(a.blob_b);
-  if (ha->magic != kMagic || hb->magic != kMagic || a.n_meshes_a > ha->n_meshes || a.n_meshes_b > hb->n_meshes ||
-      (ha->width != 2 && ha->width != 4 && ha->width != 8) || (hb->width != 2 && hb->width != 4 && hb->width != 8)) {
-    __hip_atomic_store(a.status, (int32_t)PR_E_UNSUPPORTED, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    return false;
-  }
-  i = a.pairs[2 * p];
-  j = a.pairs[2 * p + 1];
-  if (i < 0 || i >= a.n_meshes_a || j < 0 || j >= a.n_meshes_b) {
-    __hip_atomic_store(a.status, (int32_t)PR_E_ARG, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    return false;
-  }
-  return true;
+  return ha->magic == kMagic && hb->magic == kMagic && a.n_meshes_a <= ha->n_meshes &&
+         a.n_meshes_b <= hb->n_meshes && (ha->width == 2 || ha->width == 4 || ha->width == 8) &&
+         (hb->width == 2 || hb->width == 4 || hb->width == 8);
 }
 
-// Casts unit u: d = 0 tests rep(B_j) against A_i, d = 1 rep(A_i) against B_j.
-__device__ __forceinline__ int cast_unit(const InsideArgs& a, int64_t u, int32_t i, int32_t j, int32_t* stk,
-                                         int stride, int cap, Counts& k) {
-  const Blob A = blob_of(a.blob_a), B = blob_of(a.blob_b);
-  const bool d0 = (u & 1) == 0;
-  const float4 r = d0 ? B.rep[j] : A.rep[i];
+// One ray: the representative vertex r of a source mesh against mesh tm of T.
+__device__ __forceinline__ int ray(float4 r, const Blob& T, int32_t tm, int32_t* stk, int stride, int cap,
+                                   Counts& k) {
   if (r.w == 0.f) return U_OUT;  // the source mesh has no faces
   ++k.c[I_RAYS];
-  const f3 v{r.x, r.y, r.z};
-  return d0 ? walk(A, i, v, stk, stride, cap, k) : walk(B, j, v, stk, stride, cap, k);
+  return walk(T, tm, f3{r.x, r.y, r.z}, stk, stride, cap, k);
+}
+
+// The output byte of pair p in the call's mode, casting only the rays the
+// mode needs (rep(B_j) against A_i first), or -1 when a ray's stack would
+// overflow.
+__device__ __forceinline__ int pair_result(const InsideArgs& a, int64_t p, int32_t* stk, int stride, int cap,
+                                            Counts& k) {
+  if (a.mode != 0 && a.cross[p] != 0) return a.mode == 3 ? 1 : 0;
+  if (!blobs_ok(a)) {
+    __hip_atomic_store(a.status, (int32_t)PR_E_UNSUPPORTED, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    return 0;
+  }
+  const int32_t i = a.pairs[2 * p], j = a.pairs[2 * p + 1];
+  if (i < 0 || i >= a.n_meshes_a || j < 0 || j >= a.n_meshes_b) {
+    __hip_atomic_store(a.status, (int32_t)PR_E_ARG, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    return 0;
+  }
+  const Blob A = blob_of(a.blob_a), B = blob_of(a.blob_b);
+  // d = 0: rep(B_j) against A_i; d = 1: rep(A_i) against B_j
+  int r[2] = {U_OUT, U_OUT};
+  const int d_lo = a.mode == 2 ? 1 : 0, d_hi = a.mode == 1 ? 0 : 1;
+#pragma unroll 1
+  for (int d = d_lo; d <= d_hi; ++d) {
+    const Blob& T = d == 0 ? A : B;
+    const int rd = ray(d == 0 ? B.rep[j] : A.rep[i], T, d == 0 ? i : j, stk, stride, cap, k);
+    if (rd < 0) return -1;
+    if (a.mode == 3 && rd == U_IN) return 1;
+    if (d == 0) r[0] = rd; else r[1] = rd;
+  }
+  if (a.mode == 1) return r[0] == U_IN;
+  if (a.mode != 0) return r[1] == U_IN;
+  return (r[0] == U_IN ? 1 : 0) | (r[1] == U_IN ? 2 : 0) | (r[0] == U_ON ? 4 : 0) | (r[1] == U_ON ? 8 : 0);
 }
 
 __device__ __forceinline__ uint32_t wave_add(uint32_t x) {
@@ -249,107 +278,84 @@ __device__ __forceinline__ uint32_t wave_add(uint32_t x) {
   return x;
 }
 
-// Adds the block's counters to its statistics copy (every thread calls).
-__device__ __forceinline__ void flush(const InsideArgs& a, const Counts& k) {
-  unsigned long long* dst = a.stats + kStride * (blockIdx.x % kCopies);
-#pragma unroll
-  for (int q = 0; q < I_N; ++q) {
-    const uint32_t s = wave_add(k.c[q]);
-    if ((threadIdx.x & 63) == 0 && s) atomicAdd(dst + q, (unsigned long long)s);
-  }
-}
-
 __global__ void k_inside_init(InsideArgs a) {
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
   if (t < kCopies * I_N) a.stats[kStride * (t / I_N) + (t % I_N)] = 0ull;
   if (t == 0) {
-    *a.deep_n = 0u;
+    a.ctr[0] = 0u;  // pairs handed to the deep kernel
+    a.ctr[1] = 0u;  // deep-kernel blocks finished
     *a.status = PR_OK;
   }
 }
 
+// One thread per pair (one wave per block: small launches still spread over
+// every compute unit).
 __global__ __launch_bounds__(kIB) void k_inside(InsideArgs a) {
   __shared__ int32_t stk[kFastCap * kIB];
   Counts k{};
-  const int64_t units = 2 * a.n_pairs;
-  for (int64_t u = blockIdx.x * (int64_t)kIB + threadIdx.x; u < units; u += (int64_t)gridDim.x * kIB) {
-    int32_t i = 0, j = 0;
-    int res = U_OUT;
-    if (unit_live(a, u, i, j)) {
-      res = cast_unit(a, u, i, j, stk + threadIdx.x, kIB, kFastCap, k);
-      if (res < 0) {
-        const uint32_t slot = atomicAdd(a.deep_n, 1u);
-        a.deep[slot] = (uint32_t)u;  // at most 2P units: the list never overflows
-        ++k.c[I_DEEP];
-        res = U_PENDING;
-      }
+  for (int64_t p = blockIdx.x * (int64_t)kIB + threadIdx.x; p < a.n_pairs; p += (int64_t)gridDim.x * kIB) {
+    const int res = pair_result(a, p, stk + threadIdx.x, kIB, kFastCap, k);
+    if (res < 0) {
+      // out[p] is left alone (it may alias cross[p], which the rerun reads)
+      a.deep[atomicAdd(a.ctr, 1u)] = (uint32_t)p;  // at most P pairs: the list never overflows
+      ++k.c[I_DEEP];
+    } else {
+      a.out[p] = (uint8_t)res;
     }
-    a.ubits[u] = (uint8_t)res;
   }
-  flush(a, k);
-}
-
-__global__ __launch_bounds__(kDeepB) void k_inside_deep(InsideArgs a) {
-  __shared__ int32_t stk[kDeepCap * kDeepB];
-  Counts k{};
-  const uint32_t n = *a.deep_n;
-  for (uint32_t q = blockIdx.x * kDeepB + threadIdx.x; q < n; q += gridDim.x * kDeepB) {
-    const int64_t u = a.deep[q];
-    int32_t i = 0, j = 0;
-    int res = U_OUT;
-    if (unit_live(a, u, i, j)) {
-      // counted once already by the fast pass
-      Counts dup{};
-      res = cast_unit(a, u, i, j, stk + threadIdx.x, kDeepB, kDeepCap, dup);
-      for (int c = I_VISITS; c < I_N; ++c) k.c[c] += dup.c[c];
-      if (res < 0) {  // deeper than the build allows: cannot happen for a valid blob
-        __hip_atomic_store(a.status, (int32_t)PR_E_UNSUPPORTED, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        res = U_OUT;
-      }
-    }
-    a.ubits[u] = (uint8_t)res;
-  }
-  // half-wave blocks and few units: each thread adds its own counters
   unsigned long long* dst = a.stats + kStride * (blockIdx.x % kCopies);
-  for (int c = 0; c < I_N; ++c)
-    if (k.c[c]) atomicAdd(dst + c, (unsigned long long)k.c[c]);
-}
-
-__global__ __launch_bounds__(kIB) void k_inside_out(InsideArgs a) {
-  const int64_t p = blockIdx.x * (int64_t)kIB + threadIdx.x;
-  if (p >= a.n_pairs) return;
-  const uint8_t b0 = a.ubits[2 * p], b1 = a.ubits[2 * p + 1];
-  uint8_t o;
-  if (a.mode == 0) {
-    o = (uint8_t)((b0 == U_IN ? 1 : 0) | (b1 == U_IN ? 2 : 0) | (b0 == U_ON ? 4 : 0) | (b1 == U_ON ? 8 : 0));
-  } else {
-    const bool x = a.cross[p] != 0;
-    if (a.mode == 1) o = !x && b0 == U_IN;
-    else if (a.mode == 2) o = !x && b1 == U_IN;
-    else o = x || b0 == U_IN || b1 == U_IN;
+#pragma unroll
+  for (int q = 0; q < I_N; ++q) {
+    const uint32_t sum = wave_add(k.c[q]);
+    if (threadIdx.x == 0 && sum) atomicAdd(dst + q, (unsigned long long)sum);
   }
-  a.out[p] = o;
 }
 
+// Reruns the pairs whose stack overflowed with the full-depth stack, then the
+// last block to finish sums the statistics and reports the status.
 // keep_ok: leave dev_status alone unless this call found an error
 // (refine_predicate: refine_intersects has written it already).
-__global__ void k_inside_report(InsideArgs a, pr_inside_stats* out, int32_t* dev_status, int keep_ok) {
+__global__ __launch_bounds__(kDeepB) void k_inside_deep(InsideArgs a, pr_inside_stats* out, int32_t* dev_status,
+                                                       int keep_ok) {
+  __shared__ int32_t stk[kDeepCap * kDeepB];
+  __shared__ int last;
+  Counts k{};
+  const uint32_t n = __hip_atomic_load(a.ctr, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  for (uint32_t q = blockIdx.x * kDeepB + threadIdx.x; q < n; q += gridDim.x * kDeepB) {
+    const int64_t p = a.deep[q];
+    Counts dup{};  // the rays and box tests were counted by the first pass
+    int res = pair_result(a, p, stk + threadIdx.x, kDeepB, kDeepCap, dup);
+    for (int c = I_VISITS; c < I_N; ++c) k.c[c] += dup.c[c];
+    if (res < 0) {  // deeper than the build allows: not for a valid blob
+      __hip_atomic_store(a.status, (int32_t)PR_E_UNSUPPORTED, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      res = 0;
+    }
+    a.out[p] = (uint8_t)res;
+  }
+  // half-wave blocks and few pairs: each thread adds its own counters
+  for (int c = 0; c < I_N; ++c)
+    if (k.c[c]) atomicAdd(a.stats + c, (unsigned long long)k.c[c]);
+  __threadfence();
+  __syncthreads();
+  if (threadIdx.x == 0) last = atomicAdd(a.ctr + 1, 1u) == gridDim.x - 1;
+  __syncthreads();
+  if (!last) return;
   const int t = threadIdx.x;
   if (t < I_N && out) {
-    unsigned long long s = 0;
-    for (int c = 0; c < kCopies; ++c) s += a.stats[kStride * c + t];
-    reinterpret_cast<uint64_t*>(out)[t] = s;
+    unsigned long long sum = 0;
+    for (int c = 0; c < kCopies; ++c)
+      sum += __hip_atomic_load(a.stats + kStride * c + t, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    reinterpret_cast<uint64_t*>(out)[t] = sum;
   }
   if (t == 0 && dev_status) {
-    const int32_t s = *a.status;
-    if (s != PR_OK || !keep_ok) *dev_status = s;
+    const int32_t st = __hip_atomic_load(a.status, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (st != PR_OK || !keep_ok) *dev_status = st;
   }
 }
 
 void carve_inside(Carve& cv, InsideArgs& a, int64_t P) {
-  a.ubits = cv.take<uint8_t>(2 * P);
-  a.deep = cv.take<uint32_t>(2 * P);
-  a.deep_n = cv.take<uint32_t>(64);
+  a.deep = cv.take<uint32_t>(P);
+  a.ctr = cv.take<uint32_t>(64);
   a.stats = cv.take<unsigned long long>((int64_t)kCopies * kStride);
   a.status = cv.take<int32_t>(64);
 }
@@ -386,15 +392,13 @@ int inside_run(const void* blob_a, int64_t n_meshes_a, const void* blob_b, int64
   a.cross = cross;
   a.out = out;
   a.mode = mode;
-  hipLaunchKernelGGL(k_inside_init, dim3((kCopies * I_N + kIB - 1) / kIB), dim3(kIB), 0, s, a);
+  hipLaunchKernelGGL(k_inside_init, dim3((kCopies * I_N + 255) / 256), dim3(256), 0, s, a);
   if (n_pairs > 0) {
-    const int64_t units = 2 * n_pairs;
-    const int g = (int)std::min<int64_t>((units + kIB - 1) / kIB, 1 << 16);
+    const int g = (int)std::min<int64_t>((n_pairs + kIB - 1) / kIB, 1 << 16);
     hipLaunchKernelGGL(k_inside, dim3(g), dim3(kIB), 0, s, a);
-    hipLaunchKernelGGL(k_inside_deep, dim3(kDeepGrid), dim3(kDeepB), 0, s, a);
-    hipLaunchKernelGGL(k_inside_out, dim3(grid_for(n_pairs, kIB)), dim3(kIB), 0, s, a);
   }
-  hipLaunchKernelGGL(k_inside_report, dim3(1), dim3(64), 0, s, a, dev_stats, dev_status, keep_status ? 1 : 0);
+  hipLaunchKernelGGL(k_inside_deep, dim3(kDeepGrid), dim3(kDeepB), 0, s, a, dev_stats, dev_status,
+                     keep_status ? 1 : 0);
   PR_HIP(hipGetLastError());
   return PR_OK;
 }

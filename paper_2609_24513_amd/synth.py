@@ -24,7 +24,7 @@ import numpy as np
 __all__ = [
     "MeshSet", "icosphere", "geodesic_sphere", "capped_tube",
     "make_c1", "make_c2", "make_c3", "make_c4", "make_c5_pool", "c5_queries",
-    "concat_meshes",
+    "concat_meshes", "uv_sphere", "SWEEP_RINGS", "make_sweep",
 ]
 
 
@@ -513,3 +513,82 @@ def c5_queries(box_r: np.ndarray, box_s: np.ndarray, n: int, lam: float, seed: i
                 break
         out.append((t, q))
     return out
+
+
+# ---------------------------------------------------------------------------
+# Mesh-complexity sweep (Section 4.4, Fig. 3c)
+# ---------------------------------------------------------------------------
+
+def uv_sphere(rings: int, segments: int) -> Tuple[np.ndarray, np.ndarray]:
+    """Unit latitude-longitude sphere: two poles and rings - 1 circles of
+    `segments` vertices, V = (rings - 1) segments + 2, F = 2V - 4, faces
+    outward (fans at the poles, split quads between circles)."""
+    th = np.pi * np.arange(1, rings) / rings
+    ph = 2 * np.pi * np.arange(segments) / segments
+    ring = np.stack([np.sin(th)[:, None] * np.cos(ph)[None, :], np.sin(th)[:, None] * np.sin(ph)[None, :],
+                     np.broadcast_to(np.cos(th)[:, None], (rings - 1, segments))], -1).reshape(-1, 3)
+    v = np.concatenate([[[0.0, 0.0, 1.0]], ring, [[0.0, 0.0, -1.0]]])
+    south = v.shape[0] - 1
+    idx = lambda r, k: 1 + r * segments + (k % segments)  # noqa: E731
+    f = []
+    for k in range(segments):
+        f.append([0, idx(0, k), idx(0, k + 1)])
+        f.append([south, idx(rings - 2, k + 1), idx(rings - 2, k)])
+        for r in range(rings - 2):
+            a, b, c, d = idx(r, k), idx(r + 1, k), idx(r + 1, k + 1), idx(r, k + 1)
+            f += [[a, b, c], [a, c, d]]
+    return v, np.asarray(f, np.int32)
+
+
+# rings of the five tessellation stages: (rings - 1) * 2 rings + 2 vertices =
+# 26, 762, 2,966, 10,806, 41,186 (48 ... 82,368 triangles per sphere)
+SWEEP_RINGS = (4, 20, 39, 74, 144)
+
+
+def make_sweep(stage: int, seed: int = 6, n: int = 500, n_true: int = 100, side: float = 48.0):
+    """Two datasets of n unit spheres at placements fixed across the
+    tessellation stages (only the template changes).  n_true B spheres sit at
+    distance U[0.3, 1.0] from a distinct A sphere (the surfaces cross at every
+    stage: a translate of a convex body by 0 < d <= 1 is neither inside it nor
+    apart from it, the coarsest template's inradius being above 1/2); every
+    other centre distance between A and B is above 2.05 (apart at every stage:
+    the vertices lie on the unit sphere), and a quarter of the remaining B
+    spheres are placed at distance U[2.05, 3.2] from some A sphere, so that
+    their boxes still overlap.  Returns (A, B)."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    ca = np.zeros((0, 3))
+    while ca.shape[0] < n:               # A: centres at least 2.5 apart
+        c = rng.uniform(0.0, side, size=3)
+        if ca.shape[0] == 0 or np.min(np.linalg.norm(ca - c, axis=1)) > 2.5:
+            ca = np.vstack([ca, c])
+    cb = []
+
+    def ok(c, partner):
+        d = np.linalg.norm(ca - c, axis=1)
+        if partner >= 0:
+            d = np.delete(d, partner)
+        far = d.min() > 2.05 if d.size else True
+        return far and all(np.linalg.norm(c - x) > 2.05 for x in cb)
+
+    partners = rng.choice(n, n_true, replace=False)
+    for k in range(n):
+        while True:
+            u = rng.normal(size=3)
+            u /= np.linalg.norm(u)
+            if k < n_true:
+                p = int(partners[k])
+                c = ca[p] + u * rng.uniform(0.3, 1.0)
+            elif k < n_true + (n - n_true) // 4:
+                p = -1
+                c = ca[rng.integers(n)] + u * rng.uniform(2.05, 3.2)
+            else:
+                p = -1
+                c = rng.uniform(0.0, side, size=3)
+            if ok(c, p):
+                cb.append(c)
+                break
+    tv, tf = uv_sphere(SWEEP_RINGS[stage], 2 * SWEEP_RINGS[stage])
+    A = concat_meshes([(_f32(c[None, :] + tv), tf) for c in ca])
+    B = concat_meshes([(_f32(c[None, :] + tv), tf) for c in np.asarray(cb)])
+    return A, B
+
