@@ -85,6 +85,7 @@ struct BuildArgs {
   float* cbox;
   int32_t* cmesh;
   float* rep;            // [M][4] representative vertex of each mesh
+  float* rbox;           // [chunk_cap][8] box of each run of 64 groups, at the run's first group
   int64_t node_cap, chunk_cap;
   // workspace
   int32_t* status;       // min bad face (INT_MAX if none)
@@ -743,6 +744,27 @@ __global__ void k_chunk_box(BuildArgs a, const int64_t* chunk_scan) {
   }
 }
 
+// Run boxes: the box of each run of 64 consecutive groups of a mesh, stored
+// at the run's first group, so that the cull can skip 64 groups with one test.
+__global__ void k_run_box(BuildArgs a, const int64_t* chunk_scan) {
+  if (*a.status != INT_MAX) return;
+  const int64_t total = chunk_scan[a.n_meshes];
+  for (int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; c < total; c += (int64_t)gridDim.x * blockDim.x) {
+    const int32_t m = a.cmesh[c];
+    const int64_t c0 = a.mesh[m].chunk_base, c1 = c0 + a.mesh[m].n_chunks;
+    if ((c - c0) % kChunk != 0) continue;
+    float lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+    const int64_t e = c + kChunk < c1 ? c + kChunk : c1;
+    for (int64_t g = c; g < e; ++g) {
+      const float* b = a.cbox + 8 * g;
+      for (int k = 0; k < 3; ++k) { lo[k] = fminf(lo[k], b[k]); hi[k] = fmaxf(hi[k], b[3 + k]); }
+    }
+    float* r = a.rbox + 8 * c;
+    for (int k = 0; k < 3; ++k) { r[k] = lo[k]; r[3 + k] = hi[k]; }
+    r[6] = 0.f; r[7] = 0.f;
+  }
+}
+
 __global__ void k_header(BuildArgs a, BlobHeader h, const int64_t* chunk_scan, int64_t n3) {
   h.n_chunks = a.f_total > 0 ? chunk_scan[a.n_meshes] : 0;
   h.n_edges = a.f_total > 0 ? a.epos[n3] : 0;
@@ -770,7 +792,7 @@ __global__ void k_fill_u32(uint32_t* p, int64_t n, uint32_t v) {
 
 struct Layout {
   int64_t node_cap, chunk_cap;
-  int64_t off_mesh, off_node, off_tri, off_triid, off_seg, off_edge, off_cbox, off_cmesh, off_rep, total;
+  int64_t off_mesh, off_node, off_tri, off_triid, off_seg, off_edge, off_cbox, off_cmesh, off_rep, off_rbox, total;
 };
 
 Layout blob_layout(int64_t M, int64_t F, int W, int L) {
@@ -789,6 +811,7 @@ Layout blob_layout(int64_t M, int64_t F, int W, int L) {
   y.off_cbox = o; o = align256(o + y.chunk_cap * 32);
   y.off_cmesh = o; o = align256(o + y.chunk_cap * 4);
   y.off_rep = o; o = align256(o + M * 16);
+  y.off_rbox = o; o = align256(o + y.chunk_cap * 32);
   y.total = o;
   return y;
 }
@@ -945,6 +968,7 @@ extern "C" int build_mesh_bvh(const float* verts, const int64_t* vert_off, const
   a.cbox = reinterpret_cast<float*>(a.blob + y.off_cbox);
   a.cmesh = reinterpret_cast<int32_t*>(a.blob + y.off_cmesh);
   a.rep = reinterpret_cast<float*>(a.blob + y.off_rep);
+  a.rbox = reinterpret_cast<float*>(a.blob + y.off_rbox);
   a.node_cap = y.node_cap;
   a.chunk_cap = y.chunk_cap;
 
@@ -1008,6 +1032,8 @@ extern "C" int build_mesh_bvh(const float* verts, const int64_t* vert_off, const
                        (const uint64_t*)a.ekey1, (const int32_t*)a.eval1, E3);
     hipLaunchKernelGGL(k_chunk_box, dim3(grid_for(a.chunk_cap * 64, kBlock)), dim3(kBlock), 0, s, a,
                        (const int64_t*)a.chunk_scan);
+    hipLaunchKernelGGL(k_run_box, dim3(grid_for(a.chunk_cap, kBlock)), dim3(kBlock), 0, s, a,
+                       (const int64_t*)a.chunk_scan);
   }
   BlobHeader h{};
   h.magic = kMagic;
@@ -1028,6 +1054,7 @@ extern "C" int build_mesh_bvh(const float* verts, const int64_t* vert_off, const
   h.off_cbox = y.off_cbox;
   h.off_cmesh = y.off_cmesh;
   h.off_rep = y.off_rep;
+  h.off_rbox = y.off_rbox;
   h.total_bytes = y.total;
   hipLaunchKernelGGL(k_header, dim3(1), dim3(1), 0, s, a, h, (const int64_t*)a.chunk_scan, E3);
   hipLaunchKernelGGL(k_status_out, dim3(1), dim3(1), 0, s, (const int32_t*)a.status, dev_status);

@@ -50,7 +50,9 @@ struct BlobHeader {
   int32_t exp_hi;     // highest such exponent (every |coordinate| < 2^(exp_hi + 1))
   int64_t off_rep;    // f32[n_meshes][4]: first corner of each mesh's first face (input order), w = 1;
                       // w = 0 for a mesh without faces
-  int64_t reserved[12];
+  int64_t off_rbox;   // f32[chunk_cap][8]: at the first group of each run of 64 groups of a mesh
+                      // (group - chunk_base a multiple of 64), the box of the run's groups
+  int64_t reserved[11];
 };
 static_assert(sizeof(BlobHeader) == 256, "header size");
 

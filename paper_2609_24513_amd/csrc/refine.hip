@@ -62,6 +62,7 @@ struct BlobView {
   const float* tris;
   const float* seg;
   const float* cbox;
+  const float* rbox;
   int64_t n_meshes;
   int32_t width;
   uint32_t magic;
@@ -75,6 +76,7 @@ __device__ __forceinline__ BlobView view_of(const char* blob) {
   v.tris = reinterpret_cast<const float*>(blob + h->off_tri);
   v.seg = reinterpret_cast<const float*>(blob + h->off_seg);
   v.cbox = reinterpret_cast<const float*>(blob + h->off_cbox);
+  v.rbox = reinterpret_cast<const float*>(blob + h->off_rbox);
   v.n_meshes = h->n_meshes;
   v.width = h->width;
   v.magic = h->magic;
@@ -327,8 +329,8 @@ __device__ __forceinline__ void load_node(NodeRegs<W>& d, cptr_t<Node<W>> n) {
   }
 }
 
-// Lane masks of the children of a node hit by the segments of mask nm (no
-// branches: every child is tested by every lane and the result masked).  For
+// Lane masks of the children of a node hit by the segments of mask nm: every
+// present child is tested by every lane and the result masked.  For
 // meshes outside the FP32-safe range the slab test accepts everything and the
 // exact uniform test against the group box does the pruning.
 template <int W>
@@ -336,8 +338,9 @@ __device__ __forceinline__ void test_children(const NodeRegs<W>& d, const Ray& r
                                               const float* cb, uint64_t* hm) {
 #pragma unroll
   for (int c = 0; c < W; ++c) {
+    hm[c] = 0;
+    if (d.ch[c] == kEmpty) continue;  // uniform: empty slots cost no vector work
     uint64_t m = ballot(slab(r, d.lo[0][c], d.lo[1][c], d.lo[2][c], d.hi[0][c], d.hi[1][c], d.hi[2][c])) & nm;
-    if (d.ch[c] == kEmpty) m = 0;
     if (!safe && !box_meet(cb, d.lo[0][c], d.lo[1][c], d.lo[2][c], d.hi[0][c], d.hi[1][c], d.hi[2][c])) m = 0;
     hm[c] = m;
   }
@@ -926,6 +929,7 @@ __device__ __forceinline__ void stage_level2(const NodeRegs<W>& root, const char
 }
 
 constexpr int kCullBuf = 256;  // survivor entries buffered per wave in LDS
+constexpr int kRunsMin = 4;    // runs of 64 groups from which the cull tests run boxes first
 // Multiplier of the pop-order permutation of a survivor queue; a prime above
 // any queue length, so coprime with it.
 constexpr uint64_t kSpread = 2654435761ull;
@@ -1005,11 +1009,21 @@ __global__ __launch_bounds__(kBlock) void k_cull(RefineArgs ra) {
     const int32_t n_chunks = smd->n_chunks, n_edges = smd->n_edges, chunk_base = smd->chunk_base;
     const bool safe = (smd->flags & tmd->flags & kMeshSafe) != 0;
     if (troot == kEmpty || n_chunks <= 0 || !box_meet(sb, tb[0], tb[1], tb[2], tb[3], tb[4], tb[5])) return;
-    // the first 64 group boxes load while the top of the target tree is read
+    // Groups come in runs of 64 (one per lane), each with a run box.  With
+    // at least kRunsMin runs, the run boxes are tested first, 64 at a time,
+    // and only the groups of the runs that pass are read; fewer runs are
+    // read group by group (the extra dependent load of the run level costs
+    // more than it saves there).  The first boxes load while the top of the
+    // target tree is read.
     const float* cbox = S.cbox + 8 * (int64_t)chunk_base;
+    const float* rbox = S.rbox + 8 * (int64_t)chunk_base;
+    const int32_t n_all = (n_chunks + kChunk - 1) / kChunk;
+    const bool hier = n_all >= kRunsMin;
+    const int32_t n_runs = hier ? n_all : 1;
     float g[6], gn[6];
     {
-      const float* cp = cbox + 8 * (int64_t)min(lane, n_chunks - 1);
+      const float* cp = hier ? rbox + 8 * (int64_t)kChunk * min(lane, n_runs - 1)
+                                   : cbox + 8 * (int64_t)min(lane, n_chunks - 1);
 #pragma unroll
       for (int k = 0; k < 6; ++k) g[k] = cp[k];
     }
@@ -1021,17 +1035,57 @@ __global__ __launch_bounds__(kBlock) void k_cull(RefineArgs ra) {
     stage_level2<W>(root, T.nodes, s_l2[wv]);
     // the whole source mesh against the top two levels (uniform)
     if (!cull2<W>(sb, root, s_l2[wv])) return;
-    st.add(S_GROUPS, (uint64_t)n_chunks);
-    for (int32_t base = 0; base < n_chunks; base += kChunk) {
-      const int32_t c = base + lane;
-      if (base + kChunk < n_chunks) {  // prefetch the next 64 group boxes
-        const float* cp = cbox + 8 * (int64_t)min(c + kChunk, n_chunks - 1);
+    // One loop over items, each 64 boxes (one per lane) tested by the one
+    // call of cull2 (so that it is inlined once): a batch of run boxes, or the
+    // groups of one run.  After a run batch, the groups of its passing runs
+    // follow, then the next batch.  While a run's groups are tested, the next
+    // item's boxes load.
+    bool runs_item = hier;        // the item in g
+    int32_t r0 = 0;               // first run of the current batch
+    int32_t cur = 0;              // run of the groups in g
+    // passing runs of the batch not yet visited (without the run level:
+    // every run after the first)
+    uint64_t rmask = hier ? 0ull : ((1ull << n_all) - 1ull) & ~1ull;
+    auto load_runs = [&](int32_t rb, float* dst) {
+      const float* cp = rbox + 8 * (int64_t)kChunk * min(rb + lane, n_runs - 1);
 #pragma unroll
-        for (int k = 0; k < 6; ++k) gn[k] = cp[k];
+      for (int k = 0; k < 6; ++k) dst[k] = cp[k];
+    };
+    auto load_groups = [&](int32_t r, float* dst) {
+      const float* cp = cbox + 8 * (int64_t)min(r * kChunk + lane, n_chunks - 1);
+#pragma unroll
+      for (int k = 0; k < 6; ++k) dst[k] = cp[k];
+    };
+    while (true) {
+      // a run's groups: the next item is known before the test
+      int nk = 0;  // 0 none, 1 groups of run nr, 2 run batch r0 + 64
+      int32_t nr = 0;
+      if (!runs_item) {
+        if (rmask) { nk = 1; nr = r0 + __builtin_ctzll(rmask); }
+        else if (r0 + kChunk < n_runs) nk = 2;
+        if (nk == 1) load_groups(nr, gn);
+        else if (nk == 2) load_runs(r0 + kChunk, gn);
       }
-      const bool pass = c < n_chunks && box_meet(g, tb[0], tb[1], tb[2], tb[3], tb[4], tb[5]) &&
-                        cull2<W>(g, root, s_l2[wv]);
+      const int32_t idx = runs_item ? r0 + lane : cur * kChunk + lane;
+      const bool pass = idx < (runs_item ? n_runs : n_chunks) &&
+                        box_meet(g, tb[0], tb[1], tb[2], tb[3], tb[4], tb[5]) && cull2<W>(g, root, s_l2[wv]);
       const uint64_t mask = ballot(pass);
+      if (runs_item) {
+        rmask = mask;
+        if (rmask) {
+          cur = r0 + __builtin_ctzll(rmask);
+          rmask &= rmask - 1;
+          runs_item = false;
+          load_groups(cur, g);
+        } else if (r0 + kChunk < n_runs) {
+          r0 += kChunk;
+          load_runs(r0, g);
+        } else {
+          break;
+        }
+        continue;
+      }
+      st.add(S_GROUPS, (uint64_t)min(kChunk, n_chunks - cur * kChunk));
       if (mask) {
         const int n = __popcll(mask);
         st.add(S_GBOX, (uint64_t)n);
@@ -1040,13 +1094,21 @@ __global__ __launch_bounds__(kBlock) void k_cull(RefineArgs ra) {
           nbuf = 0;
         }
         if (pass) {
-          const int live = min(kChunk, n_edges - c * kChunk);
-          buf[nbuf + lanes_below(mask)] = make_int4(chunk_base + c, (int32_t)u, tid, live | (safe ? 256 : 0));
+          const int live = min(kChunk, n_edges - idx * kChunk);
+          buf[nbuf + lanes_below(mask)] = make_int4(chunk_base + idx, (int32_t)u, tid, live | (safe ? 256 : 0));
         }
         nbuf += n;
       }
+      if (nk == 0) break;
 #pragma unroll
       for (int k = 0; k < 6; ++k) g[k] = gn[k];
+      if (nk == 1) {
+        cur = nr;
+        rmask &= rmask - 1;
+      } else {
+        r0 += kChunk;
+        runs_item = true;
+      }
     }
   };
   const int64_t nw = (int64_t)gridDim.x * kWaves;
@@ -1218,7 +1280,7 @@ __device__ __forceinline__ int seg_max_of(uint32_t table, int32_t n_tris) {
 // takes the pending subtrees that the other waves of its block hand over
 // (`block_help`), so the block's long traversals end together.
 template <int W, int PREC, int SCHED>
-__global__ __launch_bounds__(kBlock, 5) void k_trace(RefineArgs ra) {
+__global__ __launch_bounds__(kBlock, SCHED == 1 ? 7 : 5) void k_trace(RefineArgs ra) {
   constexpr int kPop = 4;
   __shared__ uint64_t s_area[kWaves][wave_lds_words<W>()];
   __shared__ BlockShare s_share;
