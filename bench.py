@@ -41,7 +41,7 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "refine_traversal_%s_traffic.json")  # % workload
 KERNEL_SOURCES = ["paper_2609_24513_amd/csrc/refine.hip", "paper_2609_24513_amd/csrc/predicates.h",
-                  "paper_2609_24513_amd/csrc/common.h"]
+                  "paper_2609_24513_amd/csrc/common.h", "paper_2609_24513_amd/csrc/build.hip"]
 METRIC = "refined mesh pairs/s + segment queries/s on 1 MI355X; p50/p99 join latency"
 SCHEDULE_NAMES = {0: "auto", 1: "wave-per-pair", 2: "wave-per-segment"}
 
@@ -187,7 +187,7 @@ def cpu_baseline(A, B, pairs_np, gpu_flags, budget_s: float, seed: int = 0):
             "tri_tests_per_s": (ntests / dt) if ntests else None, "gpu_agrees_on_sample": agree}
 
 
-def roofline_of(st: dict, W: int, kern_ms: float, workload: str) -> dict:
+def roofline_of(st: dict, W: int, kern_ms: float, workload: str, L: int = 0, sched: int = 1) -> dict:
     """Roofline of the traversal kernels of one refinement pass.  Algorithmic
     bytes: 24 B per segment started, 28 W B per (wave-level) node visit, 36 B
     per segment-triangle test.  Also the bytes the kernels' loads cover as
@@ -201,7 +201,8 @@ def roofline_of(st: dict, W: int, kern_ms: float, workload: str) -> dict:
     path = TRAFFIC_FILE % workload
     if os.path.exists(path):
         tr = json.load(open(path))
-        if tr.get("kernel_source_sha") == kernel_source_sha() and tr.get("workload") == workload:
+        if (tr.get("kernel_source_sha") == kernel_source_sha() and tr.get("workload") == workload
+                and (tr.get("bvh_width"), tr.get("leaf_size"), tr.get("schedule")) == (W, L, sched)):
             traffic = tr.get("hbm_bytes_per_launch")
     return {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS, "traffic": traffic, "kernel": "k_cull + k_trace",
@@ -273,7 +274,8 @@ def run_join(name: str, args, tune: bool, plain: bool, compare_precision: bool, 
             g4a, g4b = pa.MeshBlob.build(A), pa.MeshBlob.build(B)
             pairs_for_tune = pa.filter_pairs(g4a, g4b).cpu().numpy()
             del g4a, g4b
-        tuned = autotune.tune(A, B, pairs_for_tune, frac=args.tune_frac, log=log)
+        tuned = autotune.tune(A, B, pairs_for_tune, frac=args.tune_frac, log=log,
+                              prefer=(args.width, args.leaf, args.schedule))
         W, L, sched = tuned["best"]["width"], tuned["best"]["leaf_size"], tuned["best"]["schedule"]
         table = tuned["best"].get("seg_live_max", 0)
         log("%s: autotune picked W=%d L=%d schedule=%d table=%08x (%.1f s, cached=%s)" % (
@@ -367,7 +369,7 @@ def run_join(name: str, args, tune: bool, plain: bool, compare_precision: bool, 
     log("%s: %d steps: %.3f ms/step (traversal kernels %.3f ms, refine %.3f ms, filter %.3f ms), %d of %d "
         "intersecting" % (name, steps, ms_step, kern_ms, refine_ms, filter_ms, n_true, P))
 
-    roof = roofline_of(st, W, kern_ms, name)
+    roof = roofline_of(st, W, kern_ms, name, L, sched)
     out_pairs = pairs.cpu().numpy()[:P]
     gflags = flags.cpu().numpy()[:P]
     ea = ga.edge_counts().cpu().numpy().astype(np.int64)
@@ -514,8 +516,9 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="c3", help="headline workload: c3 (default), c2, c4, c2-small, c1, c5")
-    ap.add_argument("--width", type=int, default=4)
-    ap.add_argument("--leaf", type=int, default=4)
+    ap.add_argument("--width", type=int, default=8, help="BVH width (the autotuner keeps it unless another "
+                                                           "configuration is more than 3%% faster)")
+    ap.add_argument("--leaf", type=int, default=2)
     ap.add_argument("--precision", type=int, default=0)
     ap.add_argument("--schedule", type=int, default=1, help="0 auto, 1 wave-per-pair, 2 wave-per-segment")
     ap.add_argument("--trace-budget", type=int, default=0,
@@ -557,18 +560,21 @@ def main():
     head["roofline"]["achievable_gbs"] = achievable_hbm_gbs(torch)
     head["roofline"]["frac_of_achievable"] = head["roofline"]["achieved"] / head["roofline"]["achievable_gbs"]
     extras = {}
+    # the other workloads run untuned at width 4 / leaf 4
+    xargs = argparse.Namespace(**vars(args))
+    xargs.width, xargs.leaf, xargs.schedule = 4, 4, 1
     if not args.no_extras:
         if args.workload != "c2":
-            extras["c2"] = run_join("c2", args, tune=False, plain=False, compare_precision=False, cpu=False,
+            extras["c2"] = run_join("c2", xargs, tune=False, plain=False, compare_precision=False, cpu=False,
                                     steps=args.steps, warmup=args.warmup, predicates=True)
         if args.workload != "c4":
-            extras["c4"] = run_join("c4", args, tune=False, plain=not args.skip_plain,
+            extras["c4"] = run_join("c4", xargs, tune=False, plain=not args.skip_plain,
                                     compare_precision=not args.skip_plain, cpu=False, steps=args.steps,
                                     warmup=args.warmup, check_oracle=True)
         extras["c5"] = serve_bench(args)
         sweep = []
         for k in range(5):
-            r = run_join("sweep%d" % k, args, tune=False, plain=False, compare_precision=False, cpu=False,
+            r = run_join("sweep%d" % k, xargs, tune=False, plain=False, compare_precision=False, cpu=False,
                          steps=args.steps, warmup=args.warmup)
             sweep.append({"triangles_per_sphere": r["triangles_per_mesh"], "ms_per_step": r["ms_per_step"],
                           "refine_ms": r["refine_ms"], "filter_ms": r["filter_ms"],
