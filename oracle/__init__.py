@@ -8,3 +8,4 @@ from .oracle import (build, join, tri_tri, orient3d, OracleError, set_limb_budge
                      winding, inside_pairs, join_predicates, PREDICATES,
                      ORACLE_E_ARG, ORACLE_E_DEGENERATE, ORACLE_E_OVERFLOW)
 from .filter import mesh_boxes, candidate_pairs, unique_edges  # noqa: F401
+from . import estimate  # noqa: F401
