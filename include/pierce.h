@@ -42,7 +42,7 @@
 extern "C" {
 #endif
 
-#define PR_ABI_VERSION 7
+#define PR_ABI_VERSION 8
 
 enum {
   PR_OK = 0,
@@ -363,6 +363,81 @@ int refine_predicate(const void* blob_a, int64_t n_meshes_a, const void* blob_b,
                      uint8_t* flags, const pr_refine_params* params, pr_refine_stats* dev_stats,
                      pr_inside_stats* dev_inside_stats, int32_t* dev_status, void* ws,
                      size_t ws_bytes, void* stream);
+
+/* ------------------------------------------------------------------------ */
+/* The paper's own dataset-level design (Sections 3.2 and 3.5), for
+ * comparison with the per-pair path: one BVH over every triangle of the
+ * target dataset (a blob built with build_mesh_bvh from ONE mesh holding all
+ * of the dataset's triangles, faces in the dataset's order), a
+ * triangle-to-object map, each unique source edge traced against that tree
+ * with every hit collected (closed, exact segment-triangle tests, as in
+ * refine_intersects), and the (source object, target object) records
+ * materialised by counting two-pass + sort/unique, or by a single pass into
+ * a hashmap that drops duplicates on insert, sized from the selectivity
+ * estimate or fixed.  Keys are (i << 32 | j), i in A, j in B. */
+typedef struct {
+  int32_t op;       /* 0 count: counts[g] = records of source group g, *dev_n = total;
+                       1 write: the records of the same trace at the scanned offsets of counts
+                         into keys (key_cap entries at least the total);
+                       2 hash: insert into keys, a table of key_cap slots (a power of two) cleared
+                         by op 3; *dev_n = keys inserted by this call;
+                       3 clear: keys[0 .. key_cap) = empty (~0), *dev_n = 0 */
+  int32_t flip;     /* 0: source = A, target = B, key (src << 32 | tgt); 1: source = B, key (tgt << 32 | src) */
+  int32_t width;    /* BVH width of the target dataset-level blob */
+  int32_t reserved;
+  int64_t key_cap;
+} pr_dataset_params;
+
+typedef struct {
+  uint64_t groups;       /* source groups traced */
+  uint64_t node_visits;  /* wave-level node visits */
+  uint64_t tri_tests;    /* segment-triangle tests */
+  uint64_t hits;         /* segment-triangle hits */
+  uint64_t records;      /* records emitted (consecutive repeats of one target object dropped per segment) */
+  uint64_t exact;        /* tests decided in FP64 / exact arithmetic */
+  uint64_t overflow;     /* records that found no room (write beyond the counts, hashmap full) */
+  uint64_t new_keys;     /* op 2: keys newly inserted */
+} pr_dataset_stats;
+
+/* Object of every leaf-order triangle of a dataset-level blob: tri_obj dev
+ * i32[f_total] (out), face_off dev i64[n_objects + 1] (object o owns faces
+ * face_off[o] .. face_off[o+1] of the dataset); dev_status: PR_OK or PR_E_ARG
+ * when a face lies outside every object. */
+int dataset_tri_objects(const void* dblob, const int64_t* face_off, int64_t n_objects, int32_t* tri_obj,
+                        int64_t f_total, int32_t* dev_status, void* stream);
+
+/* Workspace of dataset_trace for a source blob of at most max_groups
+ * 64-segment groups (3 f_total / 64 + n_meshes bounds it). */
+int dataset_trace_ws_bytes(int64_t max_groups, size_t* ws_bytes);
+
+/*  src_blob dev        per-mesh blob of the source dataset (its edges), n_src_objects meshes
+ *  dst_blob dev        dataset-level blob of the target dataset, tri_obj its map, n_dst_objects objects
+ *  counts   dev u64[max_groups + 1]   op 0 out, op 1 in
+ *  keys     dev u64[key_cap]          ops 1-3
+ *  dev_n    dev u64[1] or NULL        see pr_dataset_params.op
+ *  dev_stats dev or NULL; dev_status dev i32[1]: PR_OK, or PR_E_UNSUPPORTED for a target blob
+ *  that is not a one-mesh blob of params->width, or a source of more than max_groups groups. */
+int dataset_trace(const void* src_blob, int64_t n_src_objects, const void* dst_blob, const int32_t* tri_obj,
+                  int64_t n_dst_objects, const pr_dataset_params* params, uint64_t* counts, int64_t max_groups,
+                  uint64_t* keys, uint64_t* dev_n, pr_dataset_stats* dev_stats, int32_t* dev_status, void* ws,
+                  size_t ws_bytes, void* stream);
+
+/* Sorted distinct keys of keys[0 .. n_keys) (empty slots ~0 skipped) as i32
+ * pairs (i, j) into out_pairs[out_cap][2]; dev_count gets the exact number
+ * even beyond out_cap. */
+int pairs_unique_ws_bytes(int64_t n_keys, size_t* ws_bytes);
+int pairs_unique(const uint64_t* keys, int64_t n_keys, int32_t* out_pairs, int64_t out_cap, int64_t* dev_count,
+                 void* ws, size_t ws_bytes, void* stream);
+
+/* Selectivity estimate of Section 3.5 on a cells^3 grid over the union of
+ * both datasets' mesh boxes: per cell and dataset the number of meshes whose
+ * closed box touches the cell, their mean box side and mean volume ratio
+ * (|divergence-theorem volume| / box volume, clamped to [0, 1], 1 for a flat
+ * box); per cell N_A N_B min((S_A + S_B + 10^-3)^3 / V_cell *
+ * sqrt(R_A R_B)^0.8, 1), summed into *dev_estimate (f64, FP64 throughout). */
+int estimate_pairs_ws_bytes(int64_t n_meshes_a, int64_t n_meshes_b, int32_t cells, size_t* ws_bytes);
+int estimate_pairs(const void* blob_a, int64_t n_meshes_a, const void* blob_b, int64_t n_meshes_b, int32_t cells,
+                   double* dev_estimate, void* ws, size_t ws_bytes, void* stream);
 
 /* ------------------------------------------------------------------------ */
 /* Result materialisation (Section 3.5): keeps the pairs whose flag is 1, in

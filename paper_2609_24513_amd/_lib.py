@@ -18,7 +18,7 @@ PR_E_CAPACITY = -2
 PR_E_GEOMETRY = -3
 PR_E_DEVICE = -4
 PR_E_UNSUPPORTED = -5
-ABI_VERSION = 7
+ABI_VERSION = 8
 
 EXPORTS = [
     "pr_last_error", "pr_abi_version", "build_mesh_bvh_sizes", "build_mesh_bvh", "blob_mesh_boxes",
@@ -26,6 +26,8 @@ EXPORTS = [
     "refine_intersects", "compact_pairs_ws_bytes", "compact_pairs", "gather_pair_regions",
     "refine_static_scratch_bytes", "refine_intersects_static", "blob_coord_exponents", "build_mesh_bvh_bytes",
     "inside_workspace_bytes", "inside_pairs", "refine_predicate_workspace_bytes", "refine_predicate",
+    "dataset_tri_objects", "dataset_trace_ws_bytes", "dataset_trace", "pairs_unique_ws_bytes", "pairs_unique",
+    "estimate_pairs_ws_bytes", "estimate_pairs",
 ]
 
 
@@ -69,6 +71,20 @@ class InsideStats(ctypes.Structure):
 
 
 INSIDE_FIELDS = [f for f, _ in InsideStats._fields_]
+
+
+class DatasetParams(ctypes.Structure):
+    _fields_ = [("op", ctypes.c_int32), ("flip", ctypes.c_int32), ("width", ctypes.c_int32),
+                ("reserved", ctypes.c_int32), ("key_cap", ctypes.c_int64)]
+
+
+class DatasetStats(ctypes.Structure):
+    _fields_ = [("groups", ctypes.c_uint64), ("node_visits", ctypes.c_uint64), ("tri_tests", ctypes.c_uint64),
+                ("hits", ctypes.c_uint64), ("records", ctypes.c_uint64), ("exact", ctypes.c_uint64),
+                ("overflow", ctypes.c_uint64), ("new_keys", ctypes.c_uint64)]
+
+
+DATASET_FIELDS = [f for f, _ in DatasetStats._fields_]
 
 _lock = threading.Lock()
 _lib = None
@@ -115,6 +131,14 @@ def load():
         lib.refine_predicate_workspace_bytes.argtypes = [i64, ctypes.POINTER(RefineParams), szp]
         lib.refine_predicate.argtypes = [vp, i64, vp, i64, vp, i64, i32, vp, ctypes.POINTER(RefineParams),
                                          vp, vp, vp, vp, ctypes.c_size_t, vp]
+        lib.dataset_tri_objects.argtypes = [vp, vp, i64, vp, i64, vp, vp]
+        lib.dataset_trace_ws_bytes.argtypes = [i64, szp]
+        lib.dataset_trace.argtypes = [vp, i64, vp, vp, i64, ctypes.POINTER(DatasetParams), vp, i64, vp, vp, vp, vp,
+                                      vp, ctypes.c_size_t, vp]
+        lib.pairs_unique_ws_bytes.argtypes = [i64, szp]
+        lib.pairs_unique.argtypes = [vp, i64, vp, i64, vp, vp, ctypes.c_size_t, vp]
+        lib.estimate_pairs_ws_bytes.argtypes = [i64, i64, i32, szp]
+        lib.estimate_pairs.argtypes = [vp, i64, vp, i64, i32, vp, vp, ctypes.c_size_t, vp]
         for name in EXPORTS[2:]:
             getattr(lib, name).restype = ctypes.c_int
         lib.refine_static_scratch_bytes.restype = ctypes.c_size_t

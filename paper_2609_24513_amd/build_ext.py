@@ -15,7 +15,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libpierce_hip.so")
 BUILD = os.path.join(HERE, "_build")
-SOURCES = ["runtime.hip", "build.hip", "filter.hip", "refine.hip", "inside.hip"]
+SOURCES = ["runtime.hip", "build.hip", "filter.hip", "refine.hip", "inside.hip", "dataset.hip"]
 ARCH = os.environ.get("PIERCE_OFFLOAD_ARCH", "gfx950")
 
 FLAGS = [

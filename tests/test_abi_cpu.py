@@ -43,6 +43,8 @@ def test_struct_sizes():
     assert ctypes.sizeof(_lib.RefineParams) == 64
     assert ctypes.sizeof(_lib.RefineStats) == 112
     assert ctypes.sizeof(_lib.InsideStats) == 64
+    assert ctypes.sizeof(_lib.DatasetParams) == 24
+    assert ctypes.sizeof(_lib.DatasetStats) == 64
 
 
 @pytest.mark.parametrize("w,l,b,r", [(3, 4, 0, 0), (4, 3, 0, 0), (4, 4, 2, 0), (4, 4, -1, 0), (4, 4, 0, 1),
@@ -192,6 +194,32 @@ def test_inside_and_predicate_args_rejected(lib):
     bad = _refine_params(w=3)
     assert lib.refine_predicate(buf, 1, buf, 1, buf, 1, 1, buf, ctypes.byref(bad), None, None, None, buf, need,
                                 None) == _lib.PR_E_ARG
+
+
+def test_dataset_args_rejected(lib):
+    """Host-visible errors of the dataset-level entry points."""
+    wb = ctypes.c_size_t(0)
+    d = ctypes.c_int64(0)
+    buf = ctypes.byref(d)
+    assert lib.dataset_trace_ws_bytes(-1, ctypes.byref(wb)) == _lib.PR_E_ARG
+    assert lib.dataset_trace_ws_bytes(1000, ctypes.byref(wb)) == _lib.PR_OK and wb.value > 8000
+    assert lib.pairs_unique_ws_bytes(-1, ctypes.byref(wb)) == _lib.PR_E_ARG
+    assert lib.estimate_pairs_ws_bytes(1, 1, 0, ctypes.byref(wb)) == _lib.PR_E_ARG
+    assert lib.estimate_pairs_ws_bytes(1, 1, 257, ctypes.byref(wb)) == _lib.PR_E_ARG
+    assert lib.dataset_tri_objects(None, buf, 1, buf, 1, buf, None) == _lib.PR_E_ARG
+    assert lib.dataset_tri_objects(buf, buf, 0, buf, 1, buf, None) == _lib.PR_E_ARG
+    lib.dataset_trace_ws_bytes(10, ctypes.byref(wb))
+    need = wb.value
+    for op, flip, width, cap in ((4, 0, 4, 16), (-1, 0, 4, 16), (0, 2, 4, 16), (0, 0, 3, 16), (2, 0, 4, 12),
+                                 (2, 0, 4, 0)):
+        p = _lib.DatasetParams(op, flip, width, 0, cap)
+        assert lib.dataset_trace(buf, 1, buf, buf, 1, ctypes.byref(p), buf, 10, buf, buf, None, buf, buf, need,
+                                 None) == _lib.PR_E_ARG, (op, flip, width, cap)
+    p = _lib.DatasetParams(0, 0, 4, 0, 0)
+    assert lib.dataset_trace(buf, 1, buf, buf, 1, ctypes.byref(p), buf, 10, buf, buf, None, buf, buf, 64,
+                             None) == _lib.PR_E_CAPACITY
+    assert lib.pairs_unique(None, 5, buf, 5, buf, buf, 1 << 20, None) == _lib.PR_E_ARG
+    assert lib.estimate_pairs(None, 1, buf, 1, 8, buf, buf, 1 << 20, None) == _lib.PR_E_ARG
 
 
 def test_product_path_has_no_oracle_dependency():
