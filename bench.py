@@ -510,6 +510,76 @@ def serve_bench(args) -> dict:
             "detail": out}
 
 
+def _time_pairs_path(torch, pa, ga, gb, reps=3):
+    """Per-pair path (filter -> refine -> compact) time and result count."""
+    def run():
+        pairs = pa.filter_pairs(ga, gb)
+        # a survivor queue large enough for one group per unit of 2^25 pairs
+        flags, _, _ = pa.refine(ga, gb, pairs, pa.RefineConfig(schedule=1, survivor_cap=1 << 26))
+        return pa.compact(pairs, flags)
+    run()
+    torch.cuda.synchronize()
+    ts = []
+    for _ in range(reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        res = run()
+        e1.record()
+        torch.cuda.synchronize()
+        ts.append(e0.elapsed_time(e1))
+    return float(np.median(ts)), res.cpu().numpy()
+
+
+def dataset_bench(args) -> dict:
+    """The paper's dataset-level design against the per-pair path, and its
+    materialisation strategies (Sections 3.2, 3.5; Fig. 5): 50,000 x 50,000
+    axis-aligned cubes at three universe sizes (join selectivity about
+    1e-4, 1e-3, 1e-2), and the pathology-shaped workload."""
+    import torch
+    import paper_2609_24513_amd as pa
+    from paper_2609_24513_amd import dataset as ds, synth
+    out = {"workload": "50,000 x 50,000 axis-aligned cubes (sides U[1, 2]) in a universe whose side sets the "
+                       "selectivity; then the pathology-shaped workload", "rows": []}
+    W, L = 4, 4
+    plans = [("cubes", side) for side in (63.0, 28.5, 12.4)] + [("c2", None)]
+    for name, side in plans:
+        t = time.perf_counter()
+        if name == "cubes":
+            A, B = synth.make_cubes(50_000, side)
+        else:
+            A, B, _ = make_workload("c2")
+        ga, gb = pa.MeshBlob.build(A, width=W, leaf_size=L), pa.MeshBlob.build(B, width=W, leaf_size=L)
+        tb0 = time.perf_counter()
+        da, db = ds.DatasetBlob.build(A, width=8, leaf_size=2), ds.DatasetBlob.build(B, width=8, leaf_size=2)
+        torch.cuda.synchronize()
+        build_s = time.perf_counter() - tb0
+        ma, mb = ds.max_groups(A), ds.max_groups(B)
+        pp_ms, ref = _time_pairs_path(torch, pa, ga, gb)
+        row = {"workload": name, "universe_side": side, "objects": [A.n_meshes, B.n_meshes],
+               "triangles": [int(A.faces.shape[0]), int(B.faces.shape[0])], "result_pairs": int(ref.shape[0]),
+               "selectivity": ref.shape[0] / (A.n_meshes * B.n_meshes), "per_pair_path_ms": pp_ms,
+               "dataset_blob_build_s": build_s, "strategies": {}}
+        for strat in ("estimated", "two_pass", "fixed"):
+            kw = {"fixed_slots": 1 << 28} if strat == "fixed" else {}
+            ds.join_dataset(ga, gb, da, db, ma, mb, strategy=strat, **kw)  # warm-up
+            runs = [ds.join_dataset(ga, gb, da, db, ma, mb, strategy=strat, **kw) for _ in range(3)]
+            got, info = runs[-1]
+            ms = float(np.median([r[1]["ms"] for r in runs]))
+            info = {k: v for k, v in info.items() if k not in ("stats_ab", "stats_ba")}
+            info.update({"ms": ms, "same_pairs_as_per_pair_path": bool(np.array_equal(got, ref)),
+                         "records": info.get("records", runs[-1][1]["stats_ab"]["records"] +
+                                             runs[-1][1]["stats_ba"]["records"])})
+            row["strategies"][strat] = info
+            log("dataset-level %s %s: %s %.2f ms (per-pair path %.2f ms), %d pairs, output %.1f MB, same: %s" % (
+                name, "" if side is None else "side %.1f" % side, strat, ms, pp_ms, info["pairs"],
+                info["output_bytes"] / 1e6, info["same_pairs_as_per_pair_path"]))
+        out["rows"].append(row)
+        log("dataset-level %s: generated + built in %.1f s" % (name, time.perf_counter() - t))
+        del ga, gb, da, db
+        torch.cuda.empty_cache()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -535,6 +605,7 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--skip-cpu", action="store_true")
     ap.add_argument("--skip-plain", action="store_true")
+    ap.add_argument("--skip-dataset", action="store_true", help="skip the dataset-level design study")
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
                     help="also run one device-to-device copy of this many MiB (HBM counter calibration)")
     args = ap.parse_args()
@@ -582,6 +653,8 @@ def main():
                           "segment_queries_per_s": r["segment_queries_per_s"], "build_ms": r["build_ms"]})
         extras["mesh_complexity"] = {"workload": "500 x 500 unit UV spheres at fixed placements, tessellation "
                                                  "swept over five stages (Section 4.4)", "stages": sweep}
+        if not args.skip_dataset:
+            extras["dataset_level"] = dataset_bench(args)
     if args.calibrate_copy_mib > 0:
         n = args.calibrate_copy_mib << 20
         src = torch.ones(n // 4, dtype=torch.float32, device="cuda")
@@ -615,7 +688,8 @@ def main():
         "plain_per_pair": head["plain_per_pair"], "precision_comparison": head["precision_comparison"],
         "autotune": head["autotune"], "stats": head["stats"], "retest_fraction": head["retest_fraction"],
         "predicates": head["predicates"],
-        "workloads": {k: (brief(v) if k not in ("c5", "mesh_complexity") else v) for k, v in extras.items()},
+        "workloads": {k: (brief(v) if k not in ("c5", "mesh_complexity", "dataset_level") else v)
+                      for k, v in extras.items()},
     }
     if "c5" in extras:
         line["p50_ms"] = extras["c5"]["p50_ms"]

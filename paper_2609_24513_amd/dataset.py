@@ -124,12 +124,29 @@ def _unique(keys, n_keys: int, stream=None):
     return out, cnt
 
 
+MAX_SLOTS = 1 << 30
+
+
 def _pow2(n: int) -> int:
-    return 1 << max(2, int(np.ceil(np.log2(max(n, 1)))))
+    return min(MAX_SLOTS, 1 << max(2, int(np.ceil(np.log2(max(n, 1))))))
+
+
+def auto_cells(A: MeshBlob, B: MeshBlob, per_side: float = 4.0, max_cells: int = 64) -> int:
+    """Grid resolution for the estimate (the paper does not fix it): cells of
+    at least `per_side` mean object sides, so that most objects touch one
+    cell and few share a cell only by straddling its boundary."""
+    b = np.concatenate([A.boxes().cpu().numpy(), B.boxes().cpu().numpy()]).astype(np.float64)
+    b = b[np.all(b[:, 3:] >= b[:, :3], axis=1)]
+    if b.shape[0] == 0:
+        return 1
+    side = float((b[:, 3:] - b[:, :3]).mean())
+    extent = float((b[:, 3:].max(axis=0) - b[:, :3].min(axis=0)).max())
+    return int(min(max_cells, max(1, np.floor(extent / max(per_side * side, 1e-30)))))
 
 
 def join_dataset(A: MeshBlob, B: MeshBlob, DA: DatasetBlob, DB: DatasetBlob, groups_a: int, groups_b: int,
-                 strategy: str = "estimated", fixed_slots: Optional[int] = None, cells: int = 32, stream=None):
+                 strategy: str = "estimated", fixed_slots: Optional[int] = None, cells: Optional[int] = None,
+                 stream=None):
     """Overlap join of datasets A and B by the dataset-level design: A's
     edges against DB and B's edges against DA.  A, B are the per-mesh blobs
     (their edges), DA, DB the dataset-level blobs, groups_a / groups_b bounds
@@ -158,9 +175,11 @@ def join_dataset(A: MeshBlob, B: MeshBlob, DA: DatasetBlob, DB: DatasetBlob, gro
         info["output_bytes"] = 8 * n_keys
     else:
         if strategy == "estimated":
+            cells = cells or auto_cells(A, B)
             est = estimate(A, B, cells, stream=stream)
             slots = _pow2(int(np.ceil(est / LOAD_FACTOR)))
             info["estimate"] = est
+            info["cells"] = cells
         else:
             slots = _pow2(int(fixed_slots or (1 << 27)))
         ev[1].record()
@@ -172,6 +191,8 @@ def join_dataset(A: MeshBlob, B: MeshBlob, DA: DatasetBlob, DB: DatasetBlob, gro
             over = int(ta.stats[6].item()) + int(tb.stats[6].item())
             if over == 0:
                 break
+            if slots >= MAX_SLOTS:
+                raise _lib.PierceError(_lib.PR_E_CAPACITY, "more than %d distinct pairs" % MAX_SLOTS)
             slots *= 2                                      # the table filled up: twice the slots, trace again
             info["relaunches"] += 1
         n_keys = slots

@@ -24,7 +24,7 @@ import numpy as np
 __all__ = [
     "MeshSet", "icosphere", "geodesic_sphere", "capped_tube",
     "make_c1", "make_c2", "make_c3", "make_c4", "make_c5_pool", "c5_queries",
-    "concat_meshes", "uv_sphere", "SWEEP_RINGS", "make_sweep",
+    "concat_meshes", "uv_sphere", "SWEEP_RINGS", "make_sweep", "make_cubes",
 ]
 
 
@@ -591,4 +591,31 @@ def make_sweep(stage: int, seed: int = 6, n: int = 500, n_true: int = 100, side:
     A = concat_meshes([(_f32(c[None, :] + tv), tf) for c in ca])
     B = concat_meshes([(_f32(c[None, :] + tv), tf) for c in np.asarray(cb)])
     return A, B
+
+
+# ---------------------------------------------------------------------------
+# Materialisation study (Section 4.6, Fig. 5): axis-aligned cubes
+# ---------------------------------------------------------------------------
+
+_CUBE_V = np.array([[x, y, z] for x in (0.0, 1.0) for y in (0.0, 1.0) for z in (0.0, 1.0)])
+_CUBE_F = np.array([[0, 1, 3], [0, 3, 2], [4, 6, 7], [4, 7, 5], [0, 4, 5], [0, 5, 1],
+                    [2, 3, 7], [2, 7, 6], [0, 2, 6], [0, 6, 4], [1, 5, 7], [1, 7, 3]], np.int32)
+
+
+def make_cubes(n: int = 50_000, side: float = 30.0, s_lo: float = 1.0, s_hi: float = 2.0, seed: int = 7):
+    """Two datasets of n axis-aligned cubes (12 triangles each), sides
+    U[s_lo, s_hi], lower corners uniform in [0, side]^3; the join selectivity
+    is set by `side` (about ((2 mean side) / side)^3).  Returns (A, B)."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    out = []
+    for _ in range(2):
+        s = rng.uniform(s_lo, s_hi, size=n)
+        c = rng.uniform(0.0, side, size=(n, 3))
+        v = (c[:, None, :] + s[:, None, None] * _CUBE_V[None]).reshape(-1, 3)
+        verts = _f32(v)
+        faces = np.tile(_CUBE_F, (n, 1))
+        vo = np.arange(n + 1, dtype=np.int64) * 8
+        fo = np.arange(n + 1, dtype=np.int64) * 12
+        out.append(MeshSet(verts, faces, vo, fo))
+    return out[0], out[1]
 
