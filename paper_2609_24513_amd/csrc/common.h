@@ -36,7 +36,8 @@ struct BlobHeader {
   int64_t node_cap;   // wide nodes reserved
   int64_t chunk_cap;  // 64-segment groups reserved
   int64_t off_mesh;   // MeshDesc[n_meshes]
-  int64_t off_node;   // node_cap nodes of node_bytes(width)
+  int64_t off_node;   // node_cap nodes of node_bytes(width); per mesh the root comes first and its
+                      // internal children follow it, in child order
   int64_t off_tri;    // f32[f_total][9], leaf order
   int64_t off_triid;  // i32[f_total]: mesh-local face index of each leaf-order triangle
   int64_t off_seg;    // f32[chunk_cap][6][64]: segment endpoints p.xyz, q.xyz, lane-minor

@@ -875,57 +875,97 @@ __global__ void k_init(RefineArgs ra) {
   }
 }
 
-// Per-lane two-level cull of group box g against a target mesh whose root
-// node is loaded in `root`: g must meet a child box of the root and, for an
-// inner child, one of that child's child boxes (every triangle lies inside
-// the boxes of its ancestors).  The second level is read from the wave's LDS
-// copy (`stage_level2`); a child is looked at only when some lane meets its
-// box.
+// The top of a target tree as a frontier of boxes held one per lane: lane
+// j W + d holds child d of node root + 1 + j, and lane c < W also holds root
+// child c.  The builder numbers the root's internal children root + 1,
+// root + 2, ... in child order, so the second level is known from the root's
+// index alone and loads together with the root (nodes numbered after them
+// lie deeper, and their boxes lie inside second-level boxes).  Every triangle
+// lies inside a root leaf-child box or a second-level box, so a box that
+// meets none of the frontier meets no triangle.  Absent entries hold
+// inverted boxes, which meet nothing.
 template <int W>
-__device__ __forceinline__ bool cull2(const float* g, const NodeRegs<W>& root, const Node<W>* l2) {
+struct Frontier {
+  float b2[6];  // second-level box of this lane
+  float b1[6];  // root child box of lane c < W
+  bool leaf1;   // lane c < W: root child c is a leaf
+};
+
+__device__ __forceinline__ bool meet6(const float* g, float lx, float ly, float lz, float hx, float hy, float hz) {
+  return (g[0] <= hx) & (lx <= g[3]) & (g[1] <= hy) & (ly <= g[4]) & (g[2] <= hz) & (lz <= g[5]);
+}
+
+__device__ __forceinline__ float lane_f(float v, int j) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), j));
+}
+
+template <int W>
+__device__ __forceinline__ void load_frontier(Frontier<W>& F, const char* nodes, int32_t troot, int32_t n_nodes) {
+  const int lane = threadIdx.x & 63;
+  const int j = lane / W, d = lane % W;
+  const int32_t n2 = min(W, n_nodes - 1);
+#pragma unroll
+  for (int a = 0; a < 3; ++a) { F.b2[a] = INFINITY; F.b2[3 + a] = -INFINITY; F.b1[a] = INFINITY; F.b1[3 + a] = -INFINITY; }
+  F.leaf1 = false;
+  if (j < n2) {
+    const float* nd = reinterpret_cast<const float*>(nodes + sizeof(Node<W>) * ((int64_t)troot + 1 + j));
+#pragma unroll
+    for (int a = 0; a < 6; ++a) F.b2[a] = nd[a * W + d];
+  }
+  if (lane < W) {
+    const float* nd = reinterpret_cast<const float*>(nodes + sizeof(Node<W>) * (int64_t)troot);
+#pragma unroll
+    for (int a = 0; a < 6; ++a) F.b1[a] = nd[a * W + lane];
+    const int32_t ch = reinterpret_cast<const int32_t*>(nd)[6 * W + lane];
+    F.leaf1 = ch < 0 && ch != kEmpty;
+  }
+}
+
+// Frontier entries (bits of f2 for second-level lanes, of f1 for root
+// lanes) that box g meets, for every lane: one uniform step per entry of
+// the candidate masks.
+template <int W>
+__device__ __forceinline__ void frontier_masks(const float* g, uint64_t f2, uint32_t f1, const Frontier<W>& F,
+                                               uint64_t& m2, uint32_t& m1) {
+  m2 = 0;
+  m1 = 0;
+  for (; f2; f2 &= f2 - 1) {
+    const int j = __builtin_ctzll(f2);
+    if (meet6(g, lane_f(F.b2[0], j), lane_f(F.b2[1], j), lane_f(F.b2[2], j), lane_f(F.b2[3], j),
+              lane_f(F.b2[4], j), lane_f(F.b2[5], j)))
+      m2 |= 1ull << j;
+  }
+  for (; f1; f1 &= f1 - 1) {
+    const int j = __builtin_ctz(f1);
+    if (meet6(g, lane_f(F.b1[0], j), lane_f(F.b1[1], j), lane_f(F.b1[2], j), lane_f(F.b1[3], j),
+              lane_f(F.b1[4], j), lane_f(F.b1[5], j)))
+      m1 |= 1u << j;
+  }
+}
+
+// Whether box g meets one of the frontier entries of masks f2, f1; stops
+// once every active lane has met one.
+template <int W>
+__device__ __forceinline__ bool meets_frontier(const float* g, uint64_t f2, uint32_t f1, const Frontier<W>& F) {
   bool hit = false;
-#pragma unroll
-  for (int c = 0; c < W; ++c) {
-    const int32_t ch = root.ch[c];
-    const bool m1 = ch != kEmpty && box_meet(g, root.lo[0][c], root.lo[1][c], root.lo[2][c], root.hi[0][c],
-                                             root.hi[1][c], root.hi[2][c]);
-    if (ch < 0 || ch == kEmpty) {  // leaf child (or none): its box decides
-      hit = hit || m1;
-      continue;
-    }
-    if (!ballot(m1)) continue;
-    const Node<W>& n2 = l2[c];
-    bool m2 = false;
-#pragma unroll
-    for (int d = 0; d < W; ++d)
-      m2 = m2 || (n2.child[d] != kEmpty &&
-                  box_meet(g, n2.lo[0][d], n2.lo[1][d], n2.lo[2][d], n2.hi[0][d], n2.hi[1][d], n2.hi[2][d]));
-    hit = hit || (m1 && m2);
+  for (; f2; f2 &= f2 - 1) {
+    const int j = __builtin_ctzll(f2);
+    hit = hit | meet6(g, lane_f(F.b2[0], j), lane_f(F.b2[1], j), lane_f(F.b2[2], j), lane_f(F.b2[3], j),
+                      lane_f(F.b2[4], j), lane_f(F.b2[5], j));
+    if (!ballot(!hit)) return hit;
+  }
+  for (; f1; f1 &= f1 - 1) {
+    const int j = __builtin_ctz(f1);
+    hit = hit | meet6(g, lane_f(F.b1[0], j), lane_f(F.b1[1], j), lane_f(F.b1[2], j), lane_f(F.b1[3], j),
+                      lane_f(F.b1[4], j), lane_f(F.b1[5], j));
   }
   return hit;
 }
 
-// Copies the root's internal children (the second level) into the wave's LDS
-// area: one vector load per child, lane k reading dword k, all issued
-// together, so the culling of a unit waits for one round of loads here
-// instead of one per child.
-template <int W>
-__device__ __forceinline__ void stage_level2(const NodeRegs<W>& root, const char* nodes, Node<W>* l2) {
-  const int lane = threadIdx.x & 63;
-  constexpr int kDw = (int)(sizeof(Node<W>) / 4);
-  int32_t v[W];
-#pragma unroll
-  for (int c = 0; c < W; ++c) {
-    const int32_t ch = root.ch[c];
-    v[c] = 0;
-    if (ch >= 0 && ch != kEmpty && lane < kDw) v[c] = reinterpret_cast<const int32_t*>(nodes)[(int64_t)ch * kDw + lane];
-  }
-#pragma unroll
-  for (int c = 0; c < W; ++c)
-    if (lane < kDw) reinterpret_cast<int32_t*>(l2 + c)[lane] = v[c];
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-  __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+__device__ __forceinline__ uint64_t lane_u64(uint64_t v, int j) {
+  const uint32_t lo = __builtin_amdgcn_readlane((int)(uint32_t)v, j);
+  const uint32_t hi = __builtin_amdgcn_readlane((int)(uint32_t)(v >> 32), j);
+  return ((uint64_t)hi << 32) | lo;
 }
 
 constexpr int kCullBuf = 256;  // survivor entries buffered per wave in LDS
@@ -967,17 +1007,16 @@ __device__ void flush_survivors(const int4* buf, int n, int slice, const RefineA
 // Persistent pass, phase 1: one wave per unit (pair, direction), units dealt to the
 // waves in a fixed stride or, with many units per wave, taken from per-XCD
 // shares a few at a time.  The wave validates the pair, tests the source
-// mesh box against the target mesh box and its top two levels, then culls
-// the source groups 64 at a time (one group box per lane, the next 64 boxes
-// loading while the current ones are tested) and buffers the survivors in
-// LDS; full buffers go to the block's queue (blockIdx % kQueues, on
+// mesh box against the target mesh box and the frontier of its top two
+// levels, then culls the source groups 64 at a time (one group box per
+// lane, the next 64 boxes loading while the current ones are tested) and
+// buffers the survivors in LDS; full buffers go to the block's queue (blockIdx % kQueues, on
 // the XCD the block runs on, so phase 2 mostly finds the pair's data in the
 // same L2).  Survivor entry: global group index, unit, target mesh, live
 // segments | FP32-safe flag << 8.
 template <int W, int PREC>
 __global__ __launch_bounds__(kBlock) void k_cull(RefineArgs ra) {
   __shared__ int4 s_buf[kWaves][kCullBuf];
-  __shared__ Node<W> s_l2[kWaves][W];
   const int wv = uni((int32_t)(threadIdx.x >> 6)), lane = threadIdx.x & 63;
   const BlobView A = view_of(ra.blob_a), B = view_of(ra.blob_b);
   if (!blobs_ok(A, B, ra, W)) {
@@ -1013,8 +1052,8 @@ __global__ __launch_bounds__(kBlock) void k_cull(RefineArgs ra) {
     // at least kRunsMin runs, the run boxes are tested first, 64 at a time,
     // and only the groups of the runs that pass are read; fewer runs are
     // read group by group (the extra dependent load of the run level costs
-    // more than it saves there).  The first boxes load while the top of the
-    // target tree is read.
+    // more than it saves there).  The first boxes load together with the
+    // frontier.
     const float* cbox = S.cbox + 8 * (int64_t)chunk_base;
     const float* rbox = S.rbox + 8 * (int64_t)chunk_base;
     const int32_t n_all = (n_chunks + kChunk - 1) / kChunk;
@@ -1027,19 +1066,23 @@ __global__ __launch_bounds__(kBlock) void k_cull(RefineArgs ra) {
 #pragma unroll
       for (int k = 0; k < 6; ++k) g[k] = cp[k];
     }
-    const cptr_t<Node<W>> nodes = cview(reinterpret_cast<const Node<W>*>(T.nodes));
-    NodeRegs<W> root;
-    load_node<W>(root, nodes + troot);
-    // the loop below reads the previous unit's copy until here
-    __builtin_amdgcn_wave_barrier();
-    stage_level2<W>(root, T.nodes, s_l2[wv]);
-    // the whole source mesh against the top two levels (uniform)
-    if (!cull2<W>(sb, root, s_l2[wv])) return;
-    // One loop over items, each 64 boxes (one per lane) tested by the one
-    // call of cull2 (so that it is inlined once): a batch of run boxes, or the
-    // groups of one run.  After a run batch, the groups of its passing runs
-    // follow, then the next batch.  While a run's groups are tested, the next
-    // item's boxes load.
+    Frontier<W> F;
+    load_frontier<W>(F, T.nodes, troot, tmd->n_nodes);
+    // the whole source mesh against the frontier: the entries it meets are
+    // the only ones its runs and groups can meet
+    const uint64_t f2m = ballot(meet6(sb, F.b2[0], F.b2[1], F.b2[2], F.b2[3], F.b2[4], F.b2[5]));
+    const uint32_t f1m = (uint32_t)ballot(F.leaf1 && meet6(sb, F.b1[0], F.b1[1], F.b1[2], F.b1[3], F.b1[4], F.b1[5]));
+    if (!(f2m | f1m)) return;
+    // One loop over items, each 64 boxes (one per lane): a batch of run
+    // boxes, or the groups of one run.  A run batch records, per run, the
+    // frontier entries its box meets; a run's groups are tested against those
+    // only.  After a run batch, the groups of its passing runs follow, then
+    // the next batch.  While a run's groups are tested, the next item's boxes
+    // load.
+    uint64_t rm2 = 0;             // per lane (run of the batch): frontier entries met
+    uint32_t rm1 = 0;
+    uint64_t f2 = f2m;            // entries the groups in g can meet
+    uint32_t f1 = f1m;
     bool runs_item = hier;        // the item in g
     int32_t r0 = 0;               // first run of the current batch
     int32_t cur = 0;              // run of the groups in g
@@ -1067,8 +1110,14 @@ __global__ __launch_bounds__(kBlock) void k_cull(RefineArgs ra) {
         else if (nk == 2) load_runs(r0 + kChunk, gn);
       }
       const int32_t idx = runs_item ? r0 + lane : cur * kChunk + lane;
-      const bool pass = idx < (runs_item ? n_runs : n_chunks) &&
-                        box_meet(g, tb[0], tb[1], tb[2], tb[3], tb[4], tb[5]) && cull2<W>(g, root, s_l2[wv]);
+      bool pass;
+      if (runs_item) {
+        frontier_masks<W>(g, f2m, f1m, F, rm2, rm1);
+        pass = idx < n_runs && box_meet(g, tb[0], tb[1], tb[2], tb[3], tb[4], tb[5]) && (rm2 | rm1) != 0;
+      } else {
+        pass = idx < n_chunks && box_meet(g, tb[0], tb[1], tb[2], tb[3], tb[4], tb[5]) &&
+               meets_frontier<W>(g, f2, f1, F);
+      }
       const uint64_t mask = ballot(pass);
       if (runs_item) {
         rmask = mask;
@@ -1076,6 +1125,8 @@ __global__ __launch_bounds__(kBlock) void k_cull(RefineArgs ra) {
           cur = r0 + __builtin_ctzll(rmask);
           rmask &= rmask - 1;
           runs_item = false;
+          f2 = lane_u64(rm2, cur - r0);
+          f1 = (uint32_t)__builtin_amdgcn_readlane((int)rm1, cur - r0);
           load_groups(cur, g);
         } else if (r0 + kChunk < n_runs) {
           r0 += kChunk;
@@ -1105,6 +1156,10 @@ __global__ __launch_bounds__(kBlock) void k_cull(RefineArgs ra) {
       if (nk == 1) {
         cur = nr;
         rmask &= rmask - 1;
+        if (hier) {
+          f2 = lane_u64(rm2, cur - r0);
+          f1 = (uint32_t)__builtin_amdgcn_readlane((int)rm1, cur - r0);
+        }
       } else {
         r0 += kChunk;
         runs_item = true;

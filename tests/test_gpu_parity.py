@@ -76,6 +76,38 @@ def test_build_metadata_c1(env):
         assert ec[m] == oracle.unique_edges(f).shape[0]
 
 
+def _blob_nodes(blob, W):
+    """(mesh descriptors, node child ids) read back from a blob's bytes."""
+    b = blob.blob.cpu().numpy().view(np.uint8)
+    h = b[:256]
+    n_meshes, off_mesh, off_node = (int(np.frombuffer(h[o:o + 8].tobytes(), np.int64)[0]) for o in (16, 56, 64))
+    desc = np.frombuffer(b[off_mesh:off_mesh + 64 * n_meshes].tobytes(), np.int32).reshape(n_meshes, 16)
+    n_nodes = int((desc[:, 6] + desc[:, 7]).max())
+    node = np.frombuffer(b[off_node:off_node + 32 * W * n_nodes].tobytes(), np.int32).reshape(n_nodes, 8 * W)
+    return desc, node[:, 6 * W:7 * W]
+
+
+def test_root_children_follow_root(env):
+    """Layout the cull relies on: a root's internal children are the nodes
+    right after it, in child order (so the second level is addressed from
+    the root's index alone)."""
+    torch, pa, synth, oracle = env
+    A, _ = synth.make_c1()
+    big = synth.concat_meshes([synth.icosphere(k) for k in (0, 1, 2, 3, 4, 5)])
+    for S in (A, big):
+        for W in (2, 4, 8):
+            for L, builder in ((1, 0), (4, 1), (8, 0)):
+                g = pa.MeshBlob.build(S, width=W, leaf_size=L, builder=builder)
+                desc, child = _blob_nodes(g, W)
+                for m in range(S.n_meshes):
+                    root, n = int(desc[m, 14]), int(desc[m, 7])
+                    if n == 0:
+                        continue
+                    inner = [int(c) for c in child[root] if 0 <= c < 0x7fffffff]
+                    assert inner == list(range(root + 1, root + 1 + len(inner))), (W, L, m)
+                    assert len(inner) <= n - 1
+
+
 def _exp_range_np(S):
     """(lowest, highest) set-bit exponent over the coordinates of every face."""
     v = S.verts.astype(np.float32)
