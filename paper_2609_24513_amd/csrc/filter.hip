@@ -15,12 +15,13 @@
 // larger buffer, as the paper does for its result structure, Section 3.5).
 //
 // Compaction (Section 3.5 result materialisation): pairs whose flag is 1,
-// in input order: one block up to kSmallScan pairs, else a flag pass, a
-// device scan and a scatter.
+// in input order, in tiles of kScanTile pairs: the flag count of every tile,
+// then every tile writes its pairs from the counts of the tiles before it.
+// The prefix sums are the library's own (scan.h).
 #include <hip/hip_runtime.h>
-#include <hipcub/hipcub.hpp>
 
 #include "common.h"
+#include "scan.h"
 
 namespace pr {
 namespace {
@@ -98,8 +99,7 @@ __global__ __launch_bounds__(kScanBlock) void k_keep_small(const void* blob_a, i
                                                            float* box_a, int32_t* cnt_a, const void* blob_b,
                                                            int64_t MB, int32_t* ids_b, float* box_b, int32_t* cnt_b,
                                                            const float* query) {
-  using BlockScan = hipcub::BlockScan<int32_t, kScanBlock>;
-  __shared__ typename BlockScan::TempStorage tmp;
+  __shared__ int32_t s_scan[kScanBlock / 64];
   const bool first = blockIdx.x == 0;
   const MeshDesc* md = meshes_of(first ? blob_a : blob_b);
   const int64_t M = first ? MA : MB;
@@ -125,9 +125,8 @@ __global__ __launch_bounds__(kScanBlock) void k_keep_small(const void* blob_a, i
       }
       keep |= (ok ? 1u : 0u) << i;
     }
-    int32_t pre = 0, total = 0;
-    BlockScan(tmp).ExclusiveSum((int32_t)__popc(keep), pre, total);
-    int32_t pos = running + pre;
+    int32_t total = 0;
+    int32_t pos = running + block_exclusive_sum<kScanBlock>((int32_t)__popc(keep), s_scan, total);
 #pragma unroll
     for (int i = 0; i < kScanItems; ++i)
       if ((keep >> i) & 1u) {
@@ -137,7 +136,6 @@ __global__ __launch_bounds__(kScanBlock) void k_keep_small(const void* blob_a, i
         ++pos;
       }
     running += total;
-    __syncthreads();  // tmp is reused by the next tile
   }
   if (threadIdx.x == 0) *(first ? cnt_a : cnt_b) = running;
 }
@@ -146,8 +144,7 @@ __global__ __launch_bounds__(kScanBlock) void k_keep_small(const void* blob_a, i
 // the total goes to rowoff[rows] and to the caller's count.
 __global__ __launch_bounds__(kScanBlock) void k_rowscan_small(const int64_t* cnt, int64_t rows, int64_t* off,
                                                               int64_t* total_out) {
-  using BlockScan = hipcub::BlockScan<int64_t, kScanBlock>;
-  __shared__ typename BlockScan::TempStorage tmp;
+  __shared__ int64_t s_scan[kScanBlock / 64];
   int64_t running = 0;
   for (int64_t base = 0; base < rows; base += kScanBlock * kScanItems) {
     const int64_t r0 = base + (int64_t)threadIdx.x * kScanItems;
@@ -158,9 +155,8 @@ __global__ __launch_bounds__(kScanBlock) void k_rowscan_small(const int64_t* cnt
       v[i] = r0 + i < rows ? cnt[r0 + i] : 0;
       sum += v[i];
     }
-    int64_t pre = 0, total = 0;
-    BlockScan(tmp).ExclusiveSum(sum, pre, total);
-    int64_t o = running + pre;
+    int64_t total = 0;
+    int64_t o = running + block_exclusive_sum<kScanBlock>(sum, s_scan, total);
 #pragma unroll
     for (int i = 0; i < kScanItems; ++i)
       if (r0 + i < rows) {
@@ -168,7 +164,6 @@ __global__ __launch_bounds__(kScanBlock) void k_rowscan_small(const int64_t* cnt
         o += v[i];
       }
     running += total;
-    __syncthreads();
   }
   if (threadIdx.x == 0) {
     off[rows] = running;
@@ -412,10 +407,8 @@ __device__ __forceinline__ int32_t walk(const PairArgs& a, ColBox* st, int64_t l
 
 template <bool Q, bool WRITE>
 __global__ __launch_bounds__(kPairBlock) void k_pairs(PairArgs a) {
-  using BlockScan = hipcub::BlockScan<int32_t, kPairBlock>;
-  using BlockReduce = hipcub::BlockReduce<int64_t, kPairBlock>;
-  __shared__ typename BlockScan::TempStorage scan_tmp;
-  __shared__ typename BlockReduce::TempStorage red_tmp;
+  __shared__ int64_t s_red[kPairWaves];
+  __shared__ int32_t s_scan[kPairWaves];
   __shared__ ColBox s_col[kPairWaves][64];
   __shared__ int64_t s_base;
   const int lane = threadIdx.x & 63;
@@ -433,15 +426,15 @@ __global__ __launch_bounds__(kPairBlock) void k_pairs(PairArgs a) {
   if (!WRITE) {
     const int32_t n = any ? walk<Q, false>(a, s_col[w], lo, hi, rb, ia, 0) : 0;
     cnt[lane * kPairWaves + w] = n;  // row-major (row, slice)
-    const int32_t t = BlockReduce(red_tmp).Sum((int64_t)n);
-    if (threadIdx.x == 0) a.blocksum[blockIdx.x] = t;
+    const int64_t t = block_sum<kPairBlock>((int64_t)n, s_red);
+    if (threadIdx.x == 0) a.blocksum[blockIdx.x] = (int32_t)t;
     return;
   }
-  int32_t pre = 0, total = 0;
-  BlockScan(scan_tmp).ExclusiveSum(cnt[threadIdx.x], pre, total);
+  int32_t total = 0;
+  const int32_t pre = block_exclusive_sum<kPairBlock>(cnt[threadIdx.x], s_scan, total);
   int64_t before = 0;
   for (int64_t b = threadIdx.x; b < (int64_t)blockIdx.x; b += kPairBlock) before += a.blocksum[b];
-  before = BlockReduce(red_tmp).Sum(before);
+  before = block_sum<kPairBlock>(before, s_red);
   if (threadIdx.x == 0) s_base = before;
   __syncthreads();
   // the offset of (row = lane, slice = w) sits with thread lane * kPairWaves + w
@@ -452,68 +445,74 @@ __global__ __launch_bounds__(kPairBlock) void k_pairs(PairArgs a) {
   if (blockIdx.x == gridDim.x - 1 && threadIdx.x == 0) *a.count = s_base + total;
 }
 
-__global__ void k_total(const int64_t* scan, int64_t n, int64_t* out) { *out = scan[n]; }
 
-__global__ void k_flag_i32(const uint8_t* flags, int64_t n, const int64_t* n_dev, int32_t* f) {
-  const int64_t m = n_dev ? (*n_dev < 0 ? 0 : (*n_dev < n ? *n_dev : n)) : n;
-  int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  for (; i < n; i += (int64_t)gridDim.x * blockDim.x) f[i] = i < m && flags[i] ? 1 : 0;
-  if (blockIdx.x == 0 && threadIdx.x == 0) f[n] = 0;
+__global__ void k_set_i64(int64_t* out, int64_t v) { *out = v; }
+
+__device__ __forceinline__ int64_t clamped_n(int64_t n, const int64_t* n_dev) {
+  return n_dev ? (*n_dev < 0 ? 0 : (*n_dev < n ? *n_dev : n)) : n;
 }
 
-__global__ void k_compact(const int32_t* pairs, const int32_t* f, const int64_t* pos, int64_t n, int32_t* out,
-                          int64_t cap) {
-  int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  for (; i < n; i += (int64_t)gridDim.x * blockDim.x)
-    if (f[i] && pos[i] < cap) {
-      out[2 * pos[i]] = pairs[2 * i];
-      out[2 * pos[i] + 1] = pairs[2 * i + 1];
+// Compaction, pass 1: the number of flagged pairs of each tile (pairs at
+// or beyond the device count, when one is given, are not flagged).
+__global__ __launch_bounds__(kTileThreads) void k_cflag_tiles(const uint8_t* flags, int64_t n, const int64_t* n_dev,
+                                                              int64_t* tsum) {
+  __shared__ int64_t s[kTileThreads / 64];
+  const int64_t m = clamped_n(n, n_dev);
+  const int64_t i0 = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kTileItems;
+  int64_t c = 0;
+#pragma unroll
+  for (int k = 0; k < kTileItems; ++k) c += i0 + k < m && flags[i0 + k] ? 1 : 0;
+  const int64_t t = block_sum<kTileThreads>(c, s);
+  if (threadIdx.x == 0) tsum[blockIdx.x] = t;
+}
+
+// Compaction, pass 2: tile b writes its flagged pairs in order from its
+// offset.  TOP: tsum already holds the tiles' offsets (scanned by
+// k_scan_top, which also wrote the count); otherwise the tile adds up the
+// counts of the tiles before it and the last tile writes the count.
+// kTileItems consecutive pairs per thread; their flagged pairs are read
+// before the scan, so that every load is in flight at once.
+template <bool TOP>
+__global__ __launch_bounds__(kTileThreads) void k_cflag_write(const int32_t* pairs, const uint8_t* flags, int64_t n,
+                                                              const int64_t* n_dev, const int64_t* tsum, int32_t* out,
+                                                              int64_t cap, int64_t* count) {
+  __shared__ int64_t s[kTileThreads / 64];
+  const int64_t m = clamped_n(n, n_dev);
+  const int64_t i0 = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kTileItems;
+  uint32_t f = 0;
+#pragma unroll
+  for (int k = 0; k < kTileItems; ++k) f |= (i0 + k < m && flags[i0 + k] ? 1u : 0u) << k;
+  int32_t pv[kTileItems][2];
+#pragma unroll
+  for (int k = 0; k < kTileItems; ++k)
+    if ((f >> k) & 1u) {
+      pv[k][0] = pairs[2 * (i0 + k)];
+      pv[k][1] = pairs[2 * (i0 + k) + 1];
     }
-}
-
-// Ordered compaction of the flagged pairs in one block (at most kSmallScan
-// pairs), kCompactItems consecutive flags per thread so that up to 16 K pairs
-// take a single block scan: the count goes to *count, output beyond cap is
-// dropped.
-constexpr int kCompactItems = 16;
-
-__global__ __launch_bounds__(kScanBlock) void k_compact_small(const int32_t* pairs, const uint8_t* flags, int64_t n,
-                                                              const int64_t* n_dev, int32_t* out, int64_t cap,
-                                                              int64_t* count) {
-  using BlockScan = hipcub::BlockScan<int32_t, kScanBlock>;
-  __shared__ typename BlockScan::TempStorage tmp;
-  if (n_dev) n = *n_dev < 0 ? 0 : (*n_dev < n ? *n_dev : n);
-  int64_t running = 0;
-  for (int64_t base = 0; base < n; base += kScanBlock * kCompactItems) {
-    const int64_t i0 = base + (int64_t)threadIdx.x * kCompactItems;
-    uint32_t f = 0;
-#pragma unroll
-    for (int i = 0; i < kCompactItems; ++i) f |= (i0 + i < n && flags[i0 + i] ? 1u : 0u) << i;
-    // the flagged pairs are read before the scan (all loads in flight at once)
-    int32_t pv[kCompactItems][2];
-#pragma unroll
-    for (int i = 0; i < kCompactItems; ++i)
-      if ((f >> i) & 1u) {
-        pv[i][0] = pairs[2 * (i0 + i)];
-        pv[i][1] = pairs[2 * (i0 + i) + 1];
-      }
-    int32_t pre = 0, total = 0;
-    BlockScan(tmp).ExclusiveSum((int32_t)__popc(f), pre, total);
-    int64_t pos = running + pre;
-#pragma unroll
-    for (int i = 0; i < kCompactItems; ++i)
-      if ((f >> i) & 1u) {
-        if (pos < cap) {
-          out[2 * pos] = pv[i][0];
-          out[2 * pos + 1] = pv[i][1];
-        }
-        ++pos;
-      }
-    running += total;
-    __syncthreads();
+  int64_t base;
+  if (TOP) {
+    base = tsum[blockIdx.x];
+  } else {
+    int64_t b = 0;
+    for (int64_t j = threadIdx.x; j < (int64_t)blockIdx.x; j += kTileThreads) b += tsum[j];
+    base = block_sum<kTileThreads>(b, s);
   }
-  if (threadIdx.x == 0) *count = running;
+  int64_t all = 0;
+  int64_t pos = base + block_exclusive_sum<kTileThreads>((int64_t)__popc(f), s, all);
+#pragma unroll
+  for (int k = 0; k < kTileItems; ++k)
+    if ((f >> k) & 1u) {
+      if (pos < cap) {
+        out[2 * pos] = pv[k][0];
+        out[2 * pos + 1] = pv[k][1];
+      }
+      ++pos;
+    }
+  if (!TOP && blockIdx.x == gridDim.x - 1 && threadIdx.x == 0) *count = base + all;
 }
+
+// Tiles up to which pass 2 adds up the earlier tiles' counts itself.
+constexpr int64_t kDirectTiles = 1024;
 
 // Concatenation of the leading pairs of n fixed-size regions (the candidate
 // lists that one filter call per query leaves in its own region), in region
@@ -521,8 +520,7 @@ __global__ __launch_bounds__(kScanBlock) void k_compact_small(const int32_t* pai
 // clamped counts of the regions before it, then copies its rows.
 __global__ __launch_bounds__(kBlock) void k_gather(const int32_t* regions, int64_t region_cap, const int64_t* counts,
                                                   int64_t n, int32_t* out, int64_t cap, int64_t* total) {
-  using BlockReduce = hipcub::BlockReduce<int64_t, kBlock>;
-  __shared__ typename BlockReduce::TempStorage tmp;
+  __shared__ int64_t s_red[kBlock / 64];
   __shared__ int64_t s_off;
   const int64_t k = blockIdx.x;
   if (n == 0) {
@@ -535,7 +533,7 @@ __global__ __launch_bounds__(kBlock) void k_gather(const int32_t* regions, int64
   };
   int64_t part = 0;
   for (int64_t j = threadIdx.x; j < k; j += kBlock) part += clamped(j);
-  part = BlockReduce(tmp).Sum(part);
+  part = block_sum<kBlock>(part, s_red);
   if (threadIdx.x == 0) s_off = part;
   __syncthreads();
   const int64_t off = s_off, c = clamped(k);
@@ -553,8 +551,7 @@ struct FilterWs {
   float *box_a, *box_b;
   int64_t *rowcnt, *rowoff;
   int32_t *blocksum, *paircnt;
-  void* tmp;
-  size_t tmp_bytes;
+  int64_t* tsum;  // tile sums of the device-wide scans
 };
 
 int carve_filter(Carve& cv, FilterWs& w, int64_t MA, int64_t MB) {
@@ -571,32 +568,17 @@ int carve_filter(Carve& cv, FilterWs& w, int64_t MA, int64_t MB) {
   w.blocksum = cv.take<int32_t>(kFastGrid);
   const int64_t fast_rows = MA <= kFastRows ? MA : 0;
   w.paircnt = cv.take<int32_t>((fast_rows + kRT - 1) / kRT * kPairBlock);
-  size_t b1 = 0, b2 = 0;
-  int64_t mx = MA > MB ? MA : MB;
-  hipError_t e = hipcub::DeviceScan::ExclusiveSum(nullptr, b1, (int32_t*)nullptr, (int32_t*)nullptr, (int)(mx + 1));
-  if (e != hipSuccess) return hip_fail(e, "hipcub scan size");
-  e = hipcub::DeviceScan::ExclusiveSum(nullptr, b2, (int64_t*)nullptr, (int64_t*)nullptr, (int)(MA + 1));
-  if (e != hipSuccess) return hip_fail(e, "hipcub scan size");
-  w.tmp_bytes = b1 > b2 ? b1 : b2;
-  w.tmp = cv.take<char>((int64_t)w.tmp_bytes);
+  const int64_t mx = MA > MB ? MA : MB;
+  w.tsum = cv.take<int64_t>(scan_tiles_of(mx + 1));
   return PR_OK;
 }
 
 struct CompactWs {
-  int32_t* f;
-  int64_t* pos;
-  void* tmp;
-  size_t tmp_bytes;
+  int64_t* tsum;  // flag count (then offset) of each tile
 };
 
 int carve_compact(Carve& cv, CompactWs& w, int64_t n) {
-  w.f = cv.take<int32_t>(n + 1);
-  w.pos = cv.take<int64_t>(n + 1);
-  size_t b = 0;
-  hipError_t e = hipcub::DeviceScan::ExclusiveSum(nullptr, b, (int32_t*)nullptr, (int64_t*)nullptr, (int)(n + 1));
-  if (e != hipSuccess) return hip_fail(e, "hipcub scan size");
-  w.tmp_bytes = b;
-  w.tmp = cv.take<char>((int64_t)b);
+  w.tsum = cv.take<int64_t>(scan_tiles_of(n) + 1);
   return PR_OK;
 }
 
@@ -629,7 +611,7 @@ extern "C" int filter_aabb_pairs(const void* blob_a, int64_t n_meshes_a, const v
   FilterWs w{};
   int r = carve_filter(cv, w, n_meshes_a, n_meshes_b);
   if (r) return r;
-  if (cv.used > ws_bytes || !w.tmp) { set_error("ws_bytes %zu < required %zu", ws_bytes, cv.used); return PR_E_CAPACITY; }
+  if (cv.used > ws_bytes) { set_error("ws_bytes %zu < required %zu", ws_bytes, cv.used); return PR_E_CAPACITY; }
   const int64_t MA = n_meshes_a, MB = n_meshes_b;
   if (MA > 0 && MB > 0 && MA <= kFastRows && MB <= kFastCols && (!query_box || MA <= kSmallScan)) {
     PairArgs pa{};
@@ -670,8 +652,8 @@ extern "C" int filter_aabb_pairs(const void* blob_a, int64_t n_meshes_a, const v
   } else {
     hipLaunchKernelGGL(k_keep, dim3(grid_for(MA + 1, kBlock)), dim3(kBlock), 0, s, blob_a, MA, query_box, w.flag_a);
     hipLaunchKernelGGL(k_keep, dim3(grid_for(MB + 1, kBlock)), dim3(kBlock), 0, s, blob_b, MB, query_box, w.flag_b);
-    PR_HIP(hipcub::DeviceScan::ExclusiveSum(w.tmp, w.tmp_bytes, w.flag_a, w.pos_a, (int)(MA + 1), s));
-    PR_HIP(hipcub::DeviceScan::ExclusiveSum(w.tmp, w.tmp_bytes, w.flag_b, w.pos_b, (int)(MB + 1), s));
+    PR_HIP(device_exclusive_scan(w.flag_a, w.pos_a, MA + 1, w.tsum, (int64_t*)nullptr, s));
+    PR_HIP(device_exclusive_scan(w.flag_b, w.pos_b, MB + 1, w.tsum, (int64_t*)nullptr, s));
     hipLaunchKernelGGL(k_list, dim3(grid_for(MA, kBlock)), dim3(kBlock), 0, s, blob_a, (const int32_t*)w.flag_a,
                        (const int32_t*)w.pos_a, MA, w.ids_a, w.box_a);
     hipLaunchKernelGGL(k_list, dim3(grid_for(MB, kBlock)), dim3(kBlock), 0, s, blob_b, (const int32_t*)w.flag_b,
@@ -698,9 +680,8 @@ extern "C" int filter_aabb_pairs(const void* blob_a, int64_t n_meshes_a, const v
                        dev_count);
     hipLaunchKernelGGL(k_row_write, dim3(rows_grid), dim3(kBlock), 0, s, ra);
   } else {
-    PR_HIP(hipcub::DeviceScan::ExclusiveSum(w.tmp, w.tmp_bytes, w.rowcnt, w.rowoff, (int)(MA + 1), s));
+    PR_HIP(device_exclusive_scan((const int64_t*)w.rowcnt, w.rowoff, MA + 1, w.tsum, dev_count, s));
     hipLaunchKernelGGL(k_row_write, dim3(rows_grid), dim3(kBlock), 0, s, ra);
-    hipLaunchKernelGGL(k_total, dim3(1), dim3(1), 0, s, (const int64_t*)w.rowoff, MA, dev_count);
   }
   PR_HIP(hipGetLastError());
   return PR_OK;
@@ -729,19 +710,22 @@ extern "C" int compact_pairs(const int32_t* pairs, const uint8_t* flags, int64_t
   CompactWs w{};
   int r = carve_compact(cv, w, n_pairs);
   if (r) return r;
-  if (cv.used > ws_bytes || !w.tmp) { set_error("ws_bytes %zu < required %zu", ws_bytes, cv.used); return PR_E_CAPACITY; }
-  if (n_pairs <= kSmallScan) {
-    hipLaunchKernelGGL(k_compact_small, dim3(1), dim3(kScanBlock), 0, s, pairs, flags, n_pairs, dev_n_pairs, out, cap,
-                       dev_count);
+  if (cv.used > ws_bytes) { set_error("ws_bytes %zu < required %zu", ws_bytes, cv.used); return PR_E_CAPACITY; }
+  const int64_t nt = scan_tiles_of(n_pairs);
+  if (nt == 0) {
+    hipLaunchKernelGGL(k_set_i64, dim3(1), dim3(1), 0, s, dev_count, (int64_t)0);
     PR_HIP(hipGetLastError());
     return PR_OK;
   }
-  hipLaunchKernelGGL(k_flag_i32, dim3(grid_for(n_pairs + 1, kBlock)), dim3(kBlock), 0, s, flags, n_pairs, dev_n_pairs,
-                     w.f);
-  PR_HIP(hipcub::DeviceScan::ExclusiveSum(w.tmp, w.tmp_bytes, w.f, w.pos, (int)(n_pairs + 1), s));
-  hipLaunchKernelGGL(k_compact, dim3(grid_for(n_pairs, kBlock)), dim3(kBlock), 0, s, pairs, (const int32_t*)w.f,
-                     (const int64_t*)w.pos, n_pairs, out, cap);
-  hipLaunchKernelGGL(k_total, dim3(1), dim3(1), 0, s, (const int64_t*)w.pos, n_pairs, dev_count);
+  hipLaunchKernelGGL(k_cflag_tiles, dim3((unsigned)nt), dim3(kTileThreads), 0, s, flags, n_pairs, dev_n_pairs, w.tsum);
+  if (nt <= kDirectTiles) {
+    hipLaunchKernelGGL(k_cflag_write<false>, dim3((unsigned)nt), dim3(kTileThreads), 0, s, pairs, flags, n_pairs,
+                       dev_n_pairs, (const int64_t*)w.tsum, out, cap, dev_count);
+  } else {
+    hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(kTopThreads), 0, s, w.tsum, nt, dev_count);
+    hipLaunchKernelGGL(k_cflag_write<true>, dim3((unsigned)nt), dim3(kTileThreads), 0, s, pairs, flags, n_pairs,
+                       dev_n_pairs, (const int64_t*)w.tsum, out, cap, dev_count);
+  }
   PR_HIP(hipGetLastError());
   return PR_OK;
 }

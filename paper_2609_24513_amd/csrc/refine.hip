@@ -1560,10 +1560,13 @@ __device__ void report(const RefineArgs& ra, pr_refine_stats* out, int32_t* dev_
   const int lane = threadIdx.x & 63;
   if (out) {
     unsigned long long v[S_N];
+    // every load issued before the first reduction
+#pragma unroll
+    for (int k = 0; k < S_N; ++k)
+      v[k] = __hip_atomic_load(ra.stats + kCtrStride * lane + k, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 #pragma unroll
     for (int k = 0; k < S_N; ++k) {
-      unsigned long long x = __hip_atomic_load(ra.stats + kCtrStride * lane + k, __ATOMIC_RELAXED,
-                                               __HIP_MEMORY_SCOPE_AGENT);
+      unsigned long long x = v[k];
       for (int o = 32; o > 0; o >>= 1) {
         const unsigned long long y = __shfl_xor(x, o);
         x = (k == S_MAXV || k == S_MAXL) ? (y > x ? y : x) : x + y;
@@ -1796,7 +1799,7 @@ int refine_run(const void* blob_a, int64_t n_meshes_a, const void* blob_b, int64
     PR_LAUNCH(8, 0); PR_LAUNCH(8, 1); PR_LAUNCH(8, 2); PR_LAUNCH(8, 3);
 #undef PR_LAUNCH
     if (r) return r;
-    const int fb = 1024;  // enough threads for the deferred tests, blocks for the reruns
+    const int fb = 256;  // enough threads for the deferred tests, blocks for the reruns
     if (W == 2) hipLaunchKernelGGL(k_fix<2>, dim3(fb), dim3(kBlock), 0, s, ra);
     else if (W == 4) hipLaunchKernelGGL(k_fix<4>, dim3(fb), dim3(kBlock), 0, s, ra);
     else hipLaunchKernelGGL(k_fix<8>, dim3(fb), dim3(kBlock), 0, s, ra);
