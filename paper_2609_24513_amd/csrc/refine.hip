@@ -272,16 +272,24 @@ struct WaveStack {
   int32_t* lref;
   uint64_t* lmask;
   int32_t top;
-  int32_t lds_first;  // see WaveLds
-  int32_t lds_cap;
+  // entries reg_lo .. reg_lo + kRegStack - 1 live in VGPR lanes 0 .. 63, the
+  // others at LDS index i - lds_lo (plain integers, so that the placement
+  // of an entry is decided by scalar instructions)
+  int32_t reg_lo;
+  int32_t lds_lo;
 };
+
+__device__ __forceinline__ void stack_layout(WaveStack& s, const WaveLds& l) {
+  s.reg_lo = l.lds_first ? l.lds_cap : 0;
+  s.lds_lo = l.lds_first ? 0 : kRegStack;
+}
 
 // Entry i of the stack: in VGPR lane reg_index(i) or at LDS index lds_index(i).
 __device__ __forceinline__ bool in_reg(const WaveStack& s, int32_t i) {
-  return s.lds_first ? i >= s.lds_cap : i < kRegStack;
+  return (uint32_t)(i - s.reg_lo) < (uint32_t)kRegStack;
 }
-__device__ __forceinline__ int32_t reg_index(const WaveStack& s, int32_t i) { return s.lds_first ? i - s.lds_cap : i; }
-__device__ __forceinline__ int32_t lds_index(const WaveStack& s, int32_t i) { return s.lds_first ? i : i - kRegStack; }
+__device__ __forceinline__ int32_t reg_index(const WaveStack& s, int32_t i) { return i - s.reg_lo; }
+__device__ __forceinline__ int32_t lds_index(const WaveStack& s, int32_t i) { return i - s.lds_lo; }
 
 __device__ __forceinline__ void stack_push(WaveStack& s, int32_t ref, uint64_t m) {
   if (in_reg(s, s.top)) {
@@ -704,7 +712,7 @@ __device__ bool trace_core(const BlobView& S, const BlobView& T, int64_t gc, int
   WaveStack stk;
   stk.ref = 0; stk.mlo = 0; stk.mhi = 0;
   stk.lref = o.lds.ref; stk.lmask = o.lds.mask; stk.top = 0;
-  stk.lds_first = o.lds.lds_first; stk.lds_cap = o.lds.lds_cap;
+  stack_layout(stk, o.lds);
   stack_push(stk, root, m0);
   int iter = 0;
   const cptr_t<Node<W>> nodes = cview(reinterpret_cast<const Node<W>*>(T.nodes));
@@ -1015,7 +1023,7 @@ __device__ void flush_survivors(const int4* buf, int n, int slice, const RefineA
 // same L2).  Survivor entry: global group index, unit, target mesh, live
 // segments | FP32-safe flag << 8.
 template <int W, int PREC>
-__global__ __launch_bounds__(kBlock) void k_cull(RefineArgs ra) {
+__global__ __launch_bounds__(kBlock, 7) void k_cull(RefineArgs ra) {
   __shared__ int4 s_buf[kWaves][kCullBuf];
   const int wv = uni((int32_t)(threadIdx.x >> 6)), lane = threadIdx.x & 63;
   const BlobView A = view_of(ra.blob_a), B = view_of(ra.blob_b);
@@ -1083,11 +1091,9 @@ __global__ __launch_bounds__(kBlock) void k_cull(RefineArgs ra) {
     uint32_t rm1 = 0;
     uint64_t f2 = f2m;            // entries the groups in g can meet
     uint32_t f1 = f1m;
-    bool runs_item = hier;        // the item in g
     int32_t r0 = 0;               // first run of the current batch
-    int32_t cur = 0;              // run of the groups in g
-    // passing runs of the batch not yet visited (without the run level:
-    // every run after the first)
+    // passing runs of the batch not yet loaded (without the run level:
+    // every run after the first, whose groups are in g)
     uint64_t rmask = hier ? 0ull : ((1ull << n_all) - 1ull) & ~1ull;
     auto load_runs = [&](int32_t rb, float* dst) {
       const float* cp = rbox + 8 * (int64_t)kChunk * min(rb + lane, n_runs - 1);
@@ -1099,71 +1105,69 @@ __global__ __launch_bounds__(kBlock) void k_cull(RefineArgs ra) {
 #pragma unroll
       for (int k = 0; k < 6; ++k) dst[k] = cp[k];
     };
+    auto next_run = [&]() {
+      const int32_t r = r0 + __builtin_ctzll(rmask);
+      rmask &= rmask - 1;
+      return r;
+    };
+    float g2[6];                  // boxes of the run after next
+    bool batch = hier;            // g holds a batch of run boxes
+    int32_t cur = 0;              // run of the groups in g
     while (true) {
-      // a run's groups: the next item is known before the test
-      int nk = 0;  // 0 none, 1 groups of run nr, 2 run batch r0 + 64
-      int32_t nr = 0;
-      if (!runs_item) {
-        if (rmask) { nk = 1; nr = r0 + __builtin_ctzll(rmask); }
-        else if (r0 + kChunk < n_runs) nk = 2;
-        if (nk == 1) load_groups(nr, gn);
-        else if (nk == 2) load_runs(r0 + kChunk, gn);
-      }
-      const int32_t idx = runs_item ? r0 + lane : cur * kChunk + lane;
-      bool pass;
-      if (runs_item) {
+      if (batch) {
         frontier_masks<W>(g, f2m, f1m, F, rm2, rm1);
-        pass = idx < n_runs && box_meet(g, tb[0], tb[1], tb[2], tb[3], tb[4], tb[5]) && (rm2 | rm1) != 0;
-      } else {
-        pass = idx < n_chunks && box_meet(g, tb[0], tb[1], tb[2], tb[3], tb[4], tb[5]) &&
-               meets_frontier<W>(g, f2, f1, F);
-      }
-      const uint64_t mask = ballot(pass);
-      if (runs_item) {
-        rmask = mask;
-        if (rmask) {
-          cur = r0 + __builtin_ctzll(rmask);
-          rmask &= rmask - 1;
-          runs_item = false;
-          f2 = lane_u64(rm2, cur - r0);
-          f1 = (uint32_t)__builtin_amdgcn_readlane((int)rm1, cur - r0);
-          load_groups(cur, g);
-        } else if (r0 + kChunk < n_runs) {
+        const bool pass = r0 + lane < n_runs && box_meet(g, tb[0], tb[1], tb[2], tb[3], tb[4], tb[5]) &&
+                          (rm2 | rm1) != 0;
+        rmask = ballot(pass);
+        if (!rmask) {
+          if (r0 + kChunk >= n_runs) break;
           r0 += kChunk;
           load_runs(r0, g);
-        } else {
-          break;
+          continue;
         }
-        continue;
+        cur = next_run();
+        load_groups(cur, g);
       }
-      st.add(S_GROUPS, (uint64_t)min(kChunk, n_chunks - cur * kChunk));
-      if (mask) {
-        const int n = __popcll(mask);
-        st.add(S_GBOX, (uint64_t)n);
-        if (nbuf + n > kCullBuf) {
-          flush_survivors(buf, nbuf, slice, ra, st);
-          nbuf = 0;
-        }
-        if (pass) {
-          const int live = min(kChunk, n_edges - idx * kChunk);
-          buf[nbuf + lanes_below(mask)] = make_int4(chunk_base + idx, (int32_t)u, tid, live | (safe ? 256 : 0));
-        }
-        nbuf += n;
-      }
-      if (nk == 0) break;
-#pragma unroll
-      for (int k = 0; k < 6; ++k) g[k] = gn[k];
-      if (nk == 1) {
-        cur = nr;
-        rmask &= rmask - 1;
+      // the groups of the batch's passing runs, with the boxes of the next
+      // two runs loading while a run is tested
+      int32_t n1 = -1, n2 = -1;
+      if (rmask) { n1 = next_run(); load_groups(n1, gn); }
+      if (rmask) { n2 = next_run(); load_groups(n2, g2); }
+      while (true) {
         if (hier) {
           f2 = lane_u64(rm2, cur - r0);
           f1 = (uint32_t)__builtin_amdgcn_readlane((int)rm1, cur - r0);
         }
-      } else {
-        r0 += kChunk;
-        runs_item = true;
+        const int32_t idx = cur * kChunk + lane;
+        const bool pass = idx < n_chunks && box_meet(g, tb[0], tb[1], tb[2], tb[3], tb[4], tb[5]) &&
+                          meets_frontier<W>(g, f2, f1, F);
+        const uint64_t mask = ballot(pass);
+        st.add(S_GROUPS, (uint64_t)min(kChunk, n_chunks - cur * kChunk));
+        if (mask) {
+          const int n = __popcll(mask);
+          st.add(S_GBOX, (uint64_t)n);
+          if (nbuf + n > kCullBuf) {
+            flush_survivors(buf, nbuf, slice, ra, st);
+            nbuf = 0;
+          }
+          if (pass) {
+            const int live = min(kChunk, n_edges - idx * kChunk);
+            buf[nbuf + lanes_below(mask)] = make_int4(chunk_base + idx, (int32_t)u, tid, live | (safe ? 256 : 0));
+          }
+          nbuf += n;
+        }
+        if (n1 < 0) break;
+        cur = n1;
+        n1 = n2;
+        n2 = -1;
+#pragma unroll
+        for (int k = 0; k < 6; ++k) { g[k] = gn[k]; gn[k] = g2[k]; }
+        if (rmask) { n2 = next_run(); load_groups(n2, g2); }
       }
+      if (!hier || r0 + kChunk >= n_runs) break;
+      r0 += kChunk;
+      load_runs(r0, g);
+      batch = true;
     }
   };
   const int64_t nw = (int64_t)gridDim.x * kWaves;
