@@ -628,6 +628,58 @@ __device__ bool trace_segments(const BlobView& S, const BlobView& T, int64_t gc,
   return false;
 }
 
+// The top of a target tree as a frontier of boxes held one per lane: lane
+// j W + d holds child d of node root + 1 + j, and lane c < W also holds root
+// child c.  The builder numbers the root's internal children root + 1,
+// root + 2, ... in child order, so the second level is known from the root's
+// index alone and loads together with the root (nodes numbered after them
+// lie deeper, and their boxes lie inside second-level boxes).  Every triangle
+// lies inside a root leaf-child box or a second-level box, so a box that
+// meets none of the frontier meets no triangle.  Absent entries hold
+// inverted boxes, which meet nothing.
+template <int W>
+struct Frontier {
+  float b2[6];  // second-level box of this lane
+  float b1[6];  // root child box of lane c < W
+  bool leaf1;   // lane c < W: root child c is a leaf
+  int32_t c1;   // lane c < W: reference of root child c
+  int32_t c2;   // reference of this lane's second-level entry (with REFS)
+};
+
+__device__ __forceinline__ bool meet6(const float* g, float lx, float ly, float lz, float hx, float hy, float hz) {
+  return (g[0] <= hx) & (lx <= g[3]) & (g[1] <= hy) & (ly <= g[4]) & (g[2] <= hz) & (lz <= g[5]);
+}
+
+__device__ __forceinline__ float lane_f(float v, int j) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), j));
+}
+
+// With REFS the lanes also hold the child references of their entries.
+template <int W, bool REFS = false>
+__device__ __forceinline__ void load_frontier(Frontier<W>& F, const char* nodes, int32_t troot, int32_t n_nodes) {
+  const int lane = threadIdx.x & 63;
+  const int j = lane / W, d = lane % W;
+  const int32_t n2 = min(W, n_nodes - 1);
+#pragma unroll
+  for (int a = 0; a < 3; ++a) { F.b2[a] = INFINITY; F.b2[3 + a] = -INFINITY; F.b1[a] = INFINITY; F.b1[3 + a] = -INFINITY; }
+  F.leaf1 = false;
+  F.c1 = kEmpty;
+  F.c2 = kEmpty;
+  if (j < n2) {
+    const float* nd = reinterpret_cast<const float*>(nodes + sizeof(Node<W>) * ((int64_t)troot + 1 + j));
+#pragma unroll
+    for (int a = 0; a < 6; ++a) F.b2[a] = nd[a * W + d];
+    if (REFS) F.c2 = reinterpret_cast<const int32_t*>(nd)[6 * W + d];
+  }
+  if (lane < W) {
+    const float* nd = reinterpret_cast<const float*>(nodes + sizeof(Node<W>) * (int64_t)troot);
+#pragma unroll
+    for (int a = 0; a < 6; ++a) F.b1[a] = nd[a * W + lane];
+    F.c1 = reinterpret_cast<const int32_t*>(nd)[6 * W + lane];
+    F.leaf1 = F.c1 < 0 && F.c1 != kEmpty;
+  }
+}
+
 // How one group is traced.
 struct TraceOpts {
   WaveLds lds;
@@ -637,7 +689,15 @@ struct TraceOpts {
   int tq = 0;                  // task list for the hand-over
   BlockShare* sh = nullptr;    // block work sharing
   int seg_max = 0;             // wave-per-segment when at most this many segments meet the root box
+  int32_t n_nodes = 0;         // target's node count: > 0 starts the packet from the frontier
 };
+
+// Frontier entries a group may start from (each a subtree one or two levels
+// below the root); with more, the group starts at the root.  At most 2W - 1
+// entries, so that the stack bound of a root start (W - 1 entries per level)
+// still holds.
+template <int W>
+constexpr int frontier_start_max() { return 2 * W - 1; }
 
 // Traces segment group gc (global index in the source blob, `live` segments)
 // against the target mesh whose root node is `root` and box `tb`.  Returns
@@ -713,7 +773,45 @@ __device__ bool trace_core(const BlobView& S, const BlobView& T, int64_t gc, int
   stk.ref = 0; stk.mlo = 0; stk.mhi = 0;
   stk.lref = o.lds.ref; stk.lmask = o.lds.mask; stk.top = 0;
   stack_layout(stk, o.lds);
-  stack_push(stk, root, m0);
+  bool started = false;
+  if (!cont && o.n_nodes > 1) {
+    // Start below the root: the second-level children whose boxes the group
+    // box meets are tested by every lane and pushed, so the root and the
+    // second-level nodes are not visited.  Lane j W + d holds child d of
+    // node root + 1 + j; only the root's internal children, nodes root + 1
+    // ... root + n_inner, are second-level nodes.  A root with a leaf child
+    // (small meshes) starts at the root.
+    const int j = lane / W, d = lane % W;
+    const int32_t rref = lane < W ? reinterpret_cast<const int32_t*>(T.nodes + sizeof(Node<W>) * (int64_t)root)[6 * W + lane]
+                                  : kEmpty;
+    float e[6] = {INFINITY, INFINITY, INFINITY, -INFINITY, -INFINITY, -INFINITY};
+    int32_t eref = kEmpty;
+    if (j < min(W, o.n_nodes - 1)) {
+      const float* nd = reinterpret_cast<const float*>(T.nodes + sizeof(Node<W>) * ((int64_t)root + 1 + j));
+#pragma unroll
+      for (int a = 0; a < 6; ++a) e[a] = nd[a * W + d];
+      eref = reinterpret_cast<const int32_t*>(nd)[6 * W + d];
+    }
+    const uint64_t inner = ballot(rref >= 0 && rref != kEmpty);
+    const uint64_t leaf = ballot(rref < 0);
+    const int n_inner = __popcll(inner);
+    const uint64_t f = ballot(lane < n_inner * W && eref != kEmpty && meet6(cb, e[0], e[1], e[2], e[3], e[4], e[5]));
+    if (!leaf && __popcll(f) <= frontier_start_max<W>()) {
+      started = true;
+      // visits: the second-level nodes whose child boxes are tested here
+#pragma unroll
+      for (int i = 0; i < W; ++i) gcount.visits += ((f >> (i * W)) & ((1ull << W) - 1ull)) ? 1u : 0u;
+      for (uint64_t fm = f; fm; fm &= fm - 1) {
+        const int k = __builtin_ctzll(fm);
+        const float lx = lane_f(e[0], k), ly = lane_f(e[1], k), lz = lane_f(e[2], k);
+        const float hx = lane_f(e[3], k), hy = lane_f(e[4], k), hz = lane_f(e[5], k);
+        const uint64_t m = safe ? ballot(slab(r, lx, ly, lz, hx, hy, hz)) & m0 : m0;
+        if (m) stack_push(stk, __builtin_amdgcn_readlane(eref, k), m);
+      }
+      if (stk.top == 0) return false;
+    }
+  }
+  if (!started) stack_push(stk, root, m0);
   int iter = 0;
   const cptr_t<Node<W>> nodes = cview(reinterpret_cast<const Node<W>*>(T.nodes));
   // the pair's state is polled every 16 pops; the load is issued one poll
@@ -880,52 +978,6 @@ __global__ void k_init(RefineArgs ra) {
   if (i == 0) {
     *ra.fin_done = 0u;
     *ra.status = PR_OK;
-  }
-}
-
-// The top of a target tree as a frontier of boxes held one per lane: lane
-// j W + d holds child d of node root + 1 + j, and lane c < W also holds root
-// child c.  The builder numbers the root's internal children root + 1,
-// root + 2, ... in child order, so the second level is known from the root's
-// index alone and loads together with the root (nodes numbered after them
-// lie deeper, and their boxes lie inside second-level boxes).  Every triangle
-// lies inside a root leaf-child box or a second-level box, so a box that
-// meets none of the frontier meets no triangle.  Absent entries hold
-// inverted boxes, which meet nothing.
-template <int W>
-struct Frontier {
-  float b2[6];  // second-level box of this lane
-  float b1[6];  // root child box of lane c < W
-  bool leaf1;   // lane c < W: root child c is a leaf
-};
-
-__device__ __forceinline__ bool meet6(const float* g, float lx, float ly, float lz, float hx, float hy, float hz) {
-  return (g[0] <= hx) & (lx <= g[3]) & (g[1] <= hy) & (ly <= g[4]) & (g[2] <= hz) & (lz <= g[5]);
-}
-
-__device__ __forceinline__ float lane_f(float v, int j) {
-  return __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), j));
-}
-
-template <int W>
-__device__ __forceinline__ void load_frontier(Frontier<W>& F, const char* nodes, int32_t troot, int32_t n_nodes) {
-  const int lane = threadIdx.x & 63;
-  const int j = lane / W, d = lane % W;
-  const int32_t n2 = min(W, n_nodes - 1);
-#pragma unroll
-  for (int a = 0; a < 3; ++a) { F.b2[a] = INFINITY; F.b2[3 + a] = -INFINITY; F.b1[a] = INFINITY; F.b1[3 + a] = -INFINITY; }
-  F.leaf1 = false;
-  if (j < n2) {
-    const float* nd = reinterpret_cast<const float*>(nodes + sizeof(Node<W>) * ((int64_t)troot + 1 + j));
-#pragma unroll
-    for (int a = 0; a < 6; ++a) F.b2[a] = nd[a * W + d];
-  }
-  if (lane < W) {
-    const float* nd = reinterpret_cast<const float*>(nodes + sizeof(Node<W>) * (int64_t)troot);
-#pragma unroll
-    for (int a = 0; a < 6; ++a) F.b1[a] = nd[a * W + lane];
-    const int32_t ch = reinterpret_cast<const int32_t*>(nd)[6 * W + lane];
-    F.leaf1 = ch < 0 && ch != kEmpty;
   }
 }
 
@@ -1339,7 +1391,7 @@ __device__ __forceinline__ int seg_max_of(uint32_t table, int32_t n_tris) {
 // takes the pending subtrees that the other waves of its block hand over
 // (`block_help`), so the block's long traversals end together.
 template <int W, int PREC, int SCHED>
-__global__ __launch_bounds__(kBlock, SCHED == 1 ? 7 : 5) void k_trace(RefineArgs ra) {
+__global__ __launch_bounds__(kBlock, SCHED == 1 ? 6 : 5) void k_trace(RefineArgs ra) {
   constexpr int kPop = 4;
   __shared__ uint64_t s_area[kWaves][wave_lds_words<W>()];
   __shared__ BlockShare s_share;
@@ -1397,6 +1449,7 @@ __global__ __launch_bounds__(kBlock, SCHED == 1 ? 7 : 5) void k_trace(RefineArgs
         for (int c = 0; c < 6; ++c) tb[c] = tmd->box[c];
         o.tq = cid;
         o.seg_max = seg_max_of(ra.seg_table, tmd->n_tris);
+        o.n_nodes = tmd->n_nodes;
         trace_core<W, PREC, SCHED>(S, T, it.x, it.w & 0xff, tmd->root, tb, pair, dir, (it.w & 256) != 0, ra, st, o);
       }
     }
