@@ -200,10 +200,12 @@ def roofline_of(st: dict, W: int, kern_ms: float, workload: str, L: int = 0, sch
     traffic = None
     path = TRAFFIC_FILE % workload
     if os.path.exists(path):
-        tr = json.load(open(path))
-        if (tr.get("kernel_source_sha") == kernel_source_sha() and tr.get("workload") == workload
-                and (tr.get("bvh_width"), tr.get("leaf_size"), tr.get("schedule")) == (W, L, sched)):
-            traffic = tr.get("hbm_bytes_per_launch")
+        doc = json.load(open(path))
+        sha = kernel_source_sha()
+        for tr in doc.get("entries", [doc]):
+            if (tr.get("kernel_source_sha") == sha and tr.get("workload") == workload
+                    and (tr.get("bvh_width"), tr.get("leaf_size"), tr.get("schedule")) == (W, L, sched)):
+                traffic = tr.get("hbm_bytes_per_launch")
     return {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS, "traffic": traffic, "kernel": "k_cull + k_trace",
             "kernel_ms": kern_ms, "algorithmic_bytes": int(alg), "loaded_bytes_model": int(loaded),
@@ -588,7 +590,7 @@ def main():
     ap.add_argument("--workload", default="c3", help="headline workload: c3 (default), c2, c4, c2-small, c1, c5")
     ap.add_argument("--width", type=int, default=8, help="BVH width (the autotuner keeps it unless another "
                                                            "configuration is more than 3%% faster)")
-    ap.add_argument("--leaf", type=int, default=2)
+    ap.add_argument("--leaf", type=int, default=1)
     ap.add_argument("--precision", type=int, default=0)
     ap.add_argument("--schedule", type=int, default=1, help="0 auto, 1 wave-per-pair, 2 wave-per-segment")
     ap.add_argument("--trace-budget", type=int, default=0,
