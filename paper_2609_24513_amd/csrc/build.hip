@@ -24,6 +24,8 @@
 #include <hip/hip_runtime.h>
 #include <hipcub/hipcub.hpp>
 
+#include "scan.h"
+
 #include <climits>
 #include <cstdio>
 
@@ -34,6 +36,9 @@ namespace pr {
 namespace {
 
 constexpr int kBlock = 256;
+// threads of the one-block-per-mesh kernels (refit, collapse): the largest
+// mesh's block is the end of those launches
+constexpr int kMeshBlock = 1024;
 
 __device__ __forceinline__ uint32_t spread10(uint32_t v) {
   v &= 0x3ffu;
@@ -122,6 +127,7 @@ struct BuildArgs {
   int64_t* chunk_scan;   // [M+1] scanned group counts
   char* tnodes;          // [node_cap] nodes at bound-sized offsets, before compaction
   int64_t* ncount;       // [M+1] nodes used per mesh, then scanned
+  int64_t* tsum;         // tile sums of the prefix sums
 };
 
 // ---- step 1 ---------------------------------------------------------------
@@ -356,7 +362,7 @@ __device__ __forceinline__ void child_info(const BuildArgs& a, int32_t c, const 
 // One block per mesh: every climb of a mesh stays inside one workgroup, so
 // workgroup-scope acquire/release on the visit counters orders the box
 // writes without device-wide cache maintenance.
-__global__ void k_refit(BuildArgs a, const int32_t* sorted_face) {
+__global__ __launch_bounds__(kMeshBlock) void k_refit(BuildArgs a, const int32_t* sorted_face) {
   if (*a.status != INT_MAX) return;  // invalid input: the blob is not built
   for (int64_t m = blockIdx.x; m < a.n_meshes; m += gridDim.x) {
     const int64_t f0 = a.face_off[m], f1 = a.face_off[m + 1];
@@ -469,7 +475,7 @@ __device__ void collapse_item(const BuildArgs& a, Node<W>* nodes, int64_t nb, in
 }
 
 template <int W>
-__global__ void k_collapse(BuildArgs a, const int64_t* node_base_scan) {
+__global__ __launch_bounds__(kMeshBlock) void k_collapse(BuildArgs a, const int64_t* node_base_scan) {
   __shared__ int32_t s_used, s_tail, s_depth, s_over;
   if (*a.status != INT_MAX) return;  // invalid input: the blob is not built
   Node<W>* nodes = reinterpret_cast<Node<W>*>(a.tnodes);
@@ -860,8 +866,9 @@ int carve_ws(Carve& cv, BuildArgs& a, int64_t M, int64_t F, int64_t node_cap, in
   a.nscan = cv.take<int64_t>(M + 1);
   a.chunk_scan = cv.take<int64_t>(M + 1);
   a.ncount = cv.take<int64_t>(M + 1);
+  a.tsum = cv.take<int64_t>(scan_tiles_of((E3 > M ? E3 : M) + 1) + 1);
   a.tnodes = cv.take<char>(node_cap * node_bytes(W));
-  // temp storage for the library sorts and scans
+  // temp storage for the library sorts
   size_t need = 0, b = 0;
   int eb = end_bit_for(M);
   hipError_t e;
@@ -875,12 +882,6 @@ int carve_ws(Carve& cv, BuildArgs& a, int64_t M, int64_t F, int64_t node_cap, in
   e = hipcub::DeviceRadixSort::SortPairs(nullptr, b, (uint64_t*)nullptr, (uint64_t*)nullptr, (int32_t*)nullptr,
                                          (int32_t*)nullptr, (int)(E3 > 0 ? E3 : 1), 0, eb);
   if (e != hipSuccess) return hip_fail(e, "hipcub SortPairs size");
-  need = need > b ? need : b;
-  e = hipcub::DeviceScan::ExclusiveSum(nullptr, b, (int32_t*)nullptr, (int32_t*)nullptr, (int)(E3 + 1));
-  if (e != hipSuccess) return hip_fail(e, "hipcub scan size");
-  need = need > b ? need : b;
-  e = hipcub::DeviceScan::ExclusiveSum(nullptr, b, (int64_t*)nullptr, (int64_t*)nullptr, (int)(M + 1));
-  if (e != hipSuccess) return hip_fail(e, "hipcub scan size");
   need = need > b ? need : b;
   *sort_bytes = need;
   *sort_tmp = cv.take<char>((int64_t)need);
@@ -994,17 +995,17 @@ extern "C" int build_mesh_bvh(const float* verts, const int64_t* vert_off, const
     hipLaunchKernelGGL(k_morton, dim3(gF), dim3(kBlock), 0, s, a);
     PR_HIP(hipcub::DeviceRadixSort::SortPairs(tmp, tmp_bytes, a.key0, a.key1, a.val0, a.val1, (int)F, 0, eb, s));
     hipLaunchKernelGGL(k_karras, dim3(gF), dim3(kBlock), 0, s, a, (const uint64_t*)a.key1);
-    hipLaunchKernelGGL(k_refit, dim3((int)(M < 65536 ? M : 65536)), dim3(kBlock), 0, s, a, (const int32_t*)a.val1);
+    hipLaunchKernelGGL(k_refit, dim3((int)(M < 65536 ? M : 65536)), dim3(kMeshBlock), 0, s, a, (const int32_t*)a.val1);
   }
   if (M > 0) {
     hipLaunchKernelGGL(k_node_bound, dim3(gM), dim3(kBlock), 0, s, a);
-    PR_HIP(hipcub::DeviceScan::ExclusiveSum(tmp, tmp_bytes, a.nbound, a.nscan, (int)(M + 1), s));
+    PR_HIP(device_exclusive_scan((const int64_t*)a.nbound, a.nscan, M + 1, a.tsum, (int64_t*)nullptr, s));
     const int gC = (int)(M < 65536 ? M : 65536);  // one block per mesh
-    if (W == 2) hipLaunchKernelGGL(k_collapse<2>, dim3(gC), dim3(kBlock), 0, s, a, (const int64_t*)a.nscan);
-    else if (W == 4) hipLaunchKernelGGL(k_collapse<4>, dim3(gC), dim3(kBlock), 0, s, a, (const int64_t*)a.nscan);
-    else hipLaunchKernelGGL(k_collapse<8>, dim3(gC), dim3(kBlock), 0, s, a, (const int64_t*)a.nscan);
+    if (W == 2) hipLaunchKernelGGL(k_collapse<2>, dim3(gC), dim3(kMeshBlock), 0, s, a, (const int64_t*)a.nscan);
+    else if (W == 4) hipLaunchKernelGGL(k_collapse<4>, dim3(gC), dim3(kMeshBlock), 0, s, a, (const int64_t*)a.nscan);
+    else hipLaunchKernelGGL(k_collapse<8>, dim3(gC), dim3(kMeshBlock), 0, s, a, (const int64_t*)a.nscan);
     hipLaunchKernelGGL(k_node_count, dim3(gM), dim3(kBlock), 0, s, a);
-    PR_HIP(hipcub::DeviceScan::ExclusiveSum(tmp, tmp_bytes, a.ncount, a.nbound, (int)(M + 1), s));
+    PR_HIP(device_exclusive_scan((const int64_t*)a.ncount, a.nbound, M + 1, a.tsum, (int64_t*)nullptr, s));
     const int gMB = (int)(M < 65536 ? M : 65536);
     if (W == 2) hipLaunchKernelGGL(k_node_copy<2>, dim3(gMB), dim3(kBlock), 0, s, a, (const int64_t*)a.nbound);
     else if (W == 4) hipLaunchKernelGGL(k_node_copy<4>, dim3(gMB), dim3(kBlock), 0, s, a, (const int64_t*)a.nbound);
@@ -1017,14 +1018,14 @@ extern "C" int build_mesh_bvh(const float* verts, const int64_t* vert_off, const
     PR_HIP(hipcub::DeviceRadixSort::SortKeys(tmp, tmp_bytes, a.ekey0, a.ekey1, (int)E3, 0, 64, s));
     hipLaunchKernelGGL(k_edge_flag, dim3(gE), dim3(kBlock), 0, s, a, (const uint64_t*)a.ekey1, E3);
     hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(64), 0, s, a.eflag + E3, 1, 0);
-    PR_HIP(hipcub::DeviceScan::ExclusiveSum(tmp, tmp_bytes, a.eflag, a.epos, (int)(E3 + 1), s));
+    PR_HIP(device_exclusive_scan((const int32_t*)a.eflag, a.epos, E3 + 1, a.tsum, (int64_t*)nullptr, s));
     hipLaunchKernelGGL(k_edge_compact, dim3(gE), dim3(kBlock), 0, s, a, (const uint64_t*)a.ekey1, E3);
     PR_HIP(hipcub::DeviceRadixSort::SortPairs(tmp, tmp_bytes, a.ekey0, a.ekey2, a.eval0, a.eval1, (int)E3, 0, eb, s));
     hipLaunchKernelGGL(k_edge_ranges, dim3(gE), dim3(kBlock), 0, s, a, (const uint64_t*)a.ekey2, E3);
   }
   if (M > 0) {
     hipLaunchKernelGGL(k_chunk_counts, dim3(gM), dim3(kBlock), 0, s, a);
-    PR_HIP(hipcub::DeviceScan::ExclusiveSum(tmp, tmp_bytes, a.cscan, a.chunk_scan, (int)(M + 1), s));
+    PR_HIP(device_exclusive_scan((const int64_t*)a.cscan, a.chunk_scan, M + 1, a.tsum, (int64_t*)nullptr, s));
     hipLaunchKernelGGL(k_mesh_chunks, dim3(gM), dim3(kBlock), 0, s, a, (const int64_t*)a.chunk_scan);
   }
   if (F > 0) {

@@ -25,6 +25,8 @@
 #include <hip/hip_runtime.h>
 #include <hipcub/hipcub.hpp>
 
+#include "scan.h"
+
 #include <algorithm>
 #include <climits>
 #include <cmath>
@@ -611,17 +613,15 @@ T* take(char*& p, size_t& left, int64_t n) {
 }
 
 size_t unique_ws(int64_t n) {
-  size_t sort_tmp = 0, scan_tmp = 0;
+  size_t sort_tmp = 0;
   hipcub::DeviceRadixSort::SortKeys(nullptr, sort_tmp, (const uint64_t*)nullptr, (uint64_t*)nullptr, (int)n);
-  hipcub::DeviceScan::ExclusiveSum(nullptr, scan_tmp, (const uint32_t*)nullptr, (uint64_t*)nullptr, (int)n);
+  const size_t scan_tmp = (size_t)(8 * (scan_tiles_of(n) + 1));
   return (size_t)align256(8 * n) + (size_t)align256(4 * n) + (size_t)align256(8 * n) +
          (size_t)align256((int64_t)std::max(sort_tmp, scan_tmp)) + 1024;
 }
 
 size_t trace_ws(int64_t groups) {
-  size_t scan_tmp = 0;
-  hipcub::DeviceScan::ExclusiveSum(nullptr, scan_tmp, (const uint64_t*)nullptr, (uint64_t*)nullptr,
-                                   (int)(groups + 1));
+  const size_t scan_tmp = (size_t)(8 * (scan_tiles_of(groups + 1) + 1));
   return (size_t)align256(8 * (groups + 1)) + (size_t)align256(8 * kXcd * kCtrWords) + (size_t)align256(8 * D_N) +
          256 + 256 + (size_t)align256(4 * (groups > 0 ? groups : 1)) + (size_t)align256((int64_t)scan_tmp) + 1024;
 }
@@ -691,7 +691,6 @@ extern "C" int dataset_trace(const void* src_blob, int64_t n_src_objects, const 
   int32_t* status = take<int32_t>(p, left, 64);
   uint32_t* xcount = take<uint32_t>(p, left, 64);
   uint32_t* xlist = take<uint32_t>(p, left, max_groups);
-  size_t scan_bytes = left;
   void* scan_tmp = p;
   TraceArgs a{};
   a.src = (const char*)src_blob;
@@ -726,7 +725,7 @@ extern "C" int dataset_trace(const void* src_blob, int64_t n_src_objects, const 
     return PR_OK;
   }
   if (op == 1) {
-    PR_HIP(hipcub::DeviceScan::ExclusiveSum(scan_tmp, scan_bytes, counts, offsets, (int)max_groups, s));
+    PR_HIP(device_exclusive_scan((const uint64_t*)counts, offsets, max_groups, (int64_t*)scan_tmp, (int64_t*)nullptr, s));
   }
   int dev = 0;
   PR_HIP(hipGetDevice(&dev));
@@ -745,7 +744,7 @@ extern "C" int dataset_trace(const void* src_blob, int64_t n_src_objects, const 
 #undef PR_DT
   if (op == 0) {
     // offsets of every group and, at [max_groups], the total
-    PR_HIP(hipcub::DeviceScan::ExclusiveSum(scan_tmp, scan_bytes, counts, offsets, (int)(max_groups + 1), s));
+    PR_HIP(device_exclusive_scan((const uint64_t*)counts, offsets, max_groups + 1, (int64_t*)scan_tmp, (int64_t*)nullptr, s));
   }
   hipLaunchKernelGGL(k_dreport, dim3(1), dim3(64), 0, s, (const unsigned long long*)stats, (const int32_t*)status,
                      (const uint64_t*)offsets, max_groups, dev_stats, dev_status, dev_n, op);
@@ -785,8 +784,7 @@ extern "C" int pairs_unique(const uint64_t* keys, int64_t n_keys, int32_t* out_p
   PR_HIP(hipcub::DeviceRadixSort::SortKeys(tmp, tmp_bytes, keys, sorted, (int)n_keys, 0, 64, s));
   hipLaunchKernelGGL(k_unique_flags, dim3(grid_for(n_keys, 256)), dim3(256), 0, s, (const uint64_t*)sorted, n_keys,
                      flags);
-  tmp_bytes = left;
-  PR_HIP(hipcub::DeviceScan::ExclusiveSum(tmp, tmp_bytes, flags, pos, (int)n_keys, s));
+  PR_HIP(device_exclusive_scan((const uint32_t*)flags, pos, n_keys, (int64_t*)tmp, (int64_t*)nullptr, s));
   hipLaunchKernelGGL(k_unique_write, dim3(grid_for(n_keys, 256)), dim3(256), 0, s, (const uint64_t*)sorted, n_keys,
                      (const uint32_t*)flags, (const uint64_t*)pos, out_pairs, out_cap, dev_count);
   PR_HIP(hipGetLastError());

@@ -11,6 +11,7 @@
 #include <cstdint>
 
 namespace pr {
+namespace {  // each translation unit keeps its own copy of the kernels
 
 constexpr int kTileThreads = 256;
 constexpr int kTileItems = 16;
@@ -135,4 +136,5 @@ inline hipError_t device_exclusive_scan(const TI* in, TO* out, int64_t n, int64_
   return hipGetLastError();
 }
 
+}  // namespace
 }  // namespace pr
