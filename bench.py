@@ -480,6 +480,8 @@ def serve_bench(args) -> dict:
         s1 = serve.latency_summary(served)
         s1["batches"] = srv.batches
         s1["max_slots_in_flight"] = srv.max_in_flight
+        s1["slots"] = len(srv.slots)
+        s1["slot_bytes"] = srv.slot_bytes
         plain_trace = [serve.Request(r.rid, r.t_arrival, r.box) for r in trace[:args.plain_requests]]
         plain = serve.run_plain(gr, gs, plain_trace)
         s2 = serve.latency_summary(plain)

@@ -118,6 +118,9 @@ struct RefineArgs {
   int32_t share;              // waves of a block share pending stack entries (1 = on)
   int32_t lds_stack;          // 1: the packet traversal's stack lives wholly in LDS
   uint32_t seg_table;         // per target-size bucket: wave-per-segment limit (bytes)
+  int32_t* order;             // [P] pairs in cull order (heaviest cost class first), when `ordered`
+  uint32_t* ord_cnt;          // kCostClasses class sizes, then kCostClasses fill counters
+  int32_t ordered;            // 1: the cull takes its units in `order`
 };
 
 constexpr int kSlices = 8;     // one pop counter per XCD
@@ -126,6 +129,7 @@ constexpr int kSlices = 8;     // one pop counter per XCD
 // to the 8 XCDs); 8 queues per XCD keep the atomics on each queue's counters
 // below the memory-side serialisation rate.
 constexpr int kQueues = 64;
+constexpr int kCostClasses = 8;  // cost classes of the cull order (powers of two of the groups)
 // Continuation tasks (optional): a group still running after kBudget
 // traversal steps hands its pending stack entries over to a third kernel, so
 // that the few long groups are spread over many waves instead of ending the
@@ -967,6 +971,7 @@ __global__ void k_init(RefineArgs ra) {
     ra.ctr[kCtrStride * i] = 0ull;
     ra.qcount[kQCtrStride * i] = 0u;
   }
+  if (i < 2 * kCostClasses) ra.ord_cnt[i] = 0u;
   if (i < kQueues) {
     ra.surv_cnt[kCtrStride * i] = 0ull;
     ra.surv_pop[kCtrStride * i] = 0ull;
@@ -978,6 +983,57 @@ __global__ void k_init(RefineArgs ra) {
   if (i == 0) {
     *ra.fin_done = 0u;
     *ra.status = PR_OK;
+  }
+}
+
+// Cull order: many units per wave are taken from shares a few at a time, and
+// a share ends with the units taken last; pairs are therefore culled in
+// decreasing cost class (the two meshes' groups), so the last units taken are
+// short.  Class sizes, then places; within a class the order is arbitrary
+// (the results do not depend on it).
+__device__ __forceinline__ int cost_class(const BlobView& A, const BlobView& B, const RefineArgs& ra, int64_t p) {
+  int32_t i, j;
+  if (!pair_ok(ra, p, i, j)) return kCostClasses - 1;
+  const int64_t c = (int64_t)A.mesh[i].n_chunks + B.mesh[j].n_chunks;
+  // class 0: 4,096 groups or more, then one class per halving, the last below 64
+  const int lg = c > 0 ? 63 - __builtin_clzll((uint64_t)c) : 0;
+  return lg >= 12 ? 0 : (lg <= 5 ? kCostClasses - 1 : 12 - lg);
+}
+
+__global__ void k_order_count(RefineArgs ra) {
+  __shared__ uint32_t s_cnt[kCostClasses];
+  if (threadIdx.x < kCostClasses) s_cnt[threadIdx.x] = 0u;
+  __syncthreads();
+  const BlobView A = view_of(ra.blob_a), B = view_of(ra.blob_b);
+  const int64_t np = npairs(ra);
+  for (int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; p < np; p += (int64_t)gridDim.x * blockDim.x)
+    atomicAdd(&s_cnt[cost_class(A, B, ra, p)], 1u);
+  __syncthreads();
+  if (threadIdx.x < kCostClasses && s_cnt[threadIdx.x]) atomicAdd(ra.ord_cnt + threadIdx.x, s_cnt[threadIdx.x]);
+}
+
+// Each block places blockDim pairs per step: ranks within the block from LDS
+// counters, one range per class reserved with one atomic.
+__global__ void k_order_place(RefineArgs ra) {
+  __shared__ uint32_t s_cnt[kCostClasses], s_off[kCostClasses];
+  const BlobView A = view_of(ra.blob_a), B = view_of(ra.blob_b);
+  const int64_t np = npairs(ra);
+  uint32_t cbase[kCostClasses];
+  cbase[0] = 0u;
+  for (int k = 1; k < kCostClasses; ++k) cbase[k] = cbase[k - 1] + ra.ord_cnt[k - 1];
+  for (int64_t b0 = blockIdx.x * (int64_t)blockDim.x; b0 < np; b0 += (int64_t)gridDim.x * blockDim.x) {
+    if (threadIdx.x < kCostClasses) s_cnt[threadIdx.x] = 0u;
+    __syncthreads();
+    const int64_t p = b0 + threadIdx.x;
+    const bool live = p < np;
+    const int c = live ? cost_class(A, B, ra, p) : 0;
+    const uint32_t r = live ? atomicAdd(&s_cnt[c], 1u) : 0u;
+    __syncthreads();
+    if (threadIdx.x < kCostClasses && s_cnt[threadIdx.x])
+      s_off[threadIdx.x] = atomicAdd(ra.ord_cnt + kCostClasses + threadIdx.x, s_cnt[threadIdx.x]);
+    __syncthreads();
+    if (live) ra.order[cbase[c] + s_off[c] + r] = (int32_t)p;
+    __syncthreads();  // s_cnt / s_off are rewritten by the next step
   }
 }
 
@@ -1241,13 +1297,17 @@ __global__ __launch_bounds__(kBlock, 7) void k_cull(RefineArgs ra) {
       cull_unit(u, ia, jb);
     }
   } else {
-    // many units per wave, of uneven cost: cut into one contiguous share per
-    // XCD, from which the waves of that XCD take kCullGrab units at a time
-    // (the next grab in flight while the current units are culled), so a
-    // block that starts late or draws large meshes takes fewer
+    // many units per wave, of uneven cost: one share per XCD, from which the
+    // waves of that XCD take kCullGrab units at a time (the next grab in
+    // flight while the current units are culled), so a block that starts
+    // late or draws large meshes takes fewer.  With the cull order, share xs
+    // holds pairs xs, xs + nsl, ... of the order (both directions of each),
+    // the costliest first; otherwise a contiguous range of units.
     const int nsl = gridDim.x < (unsigned)kSlices ? 1 : kSlices;
     const int xs = (int)(blockIdx.x % nsl);
-    const int64_t slo = U * xs / nsl, shi = U * (xs + 1) / nsl;
+    const int64_t np = U >> 1;
+    const int64_t slo = ra.ordered ? 0 : U * xs / nsl;
+    const int64_t shi = ra.ordered ? 2 * ((np - xs + nsl - 1) / nsl) : U * (xs + 1) / nsl;
     unsigned long long* const uctr = ra.ctr + kCtrStride * xs;
     unsigned long long g0 = 0;
     if (lane == 0) g0 = atomicAdd(uctr, (unsigned long long)kCullGrab);
@@ -1258,9 +1318,11 @@ __global__ __launch_bounds__(kBlock, 7) void k_cull(RefineArgs ra) {
       const int64_t ue = ub + kCullGrab < shi ? ub + kCullGrab : shi;
       int64_t pl = -1;
       int32_t ia = 0, jb = 0;
-      for (int64_t u = ub; u < ue; ++u) {
-        if ((u >> 1) != pl) {
-          pl = u >> 1;
+      for (int64_t k = ub; k < ue; ++k) {
+        const int64_t pk = ra.ordered ? (int64_t)ra.order[xs + nsl * (k >> 1)] : (k >> 1);
+        const int64_t u = 2 * pk + (k & 1);
+        if (pk != pl) {
+          pl = pk;
           ia = pairs[2 * pl];
           jb = pairs[2 * pl + 1];
         }
@@ -1691,6 +1753,8 @@ void carve(Carve& cv, RefineArgs& ra, int64_t P, uint32_t qcap, uint32_t surv_ca
   ra.surv_cnt = cv.take<unsigned long long>(kQueues * kCtrStride);
   ra.surv_pop = cv.take<unsigned long long>(kQueues * kCtrStride);
   ra.surv = cv.take<int4>((int64_t)kQueues * surv_cap);
+  ra.order = cv.take<int32_t>(P);
+  ra.ord_cnt = cv.take<uint32_t>(64);
   if (with_tasks) {  // continuation task lists: only with a step budget
     ra.task_cap = kTaskCap;
     ra.tasks = cv.take<int4>((int64_t)kQueues * kTaskCap);
@@ -1780,6 +1844,13 @@ int launch(RefineArgs& ra, const pr_refine_params* prm, hipStream_t s) {
     const int per_cull = blocks_per_cu<k_cull<W, PREC>>(dev);
     if (cus <= 0 || per <= 0 || per_cull <= 0) { set_error("device attribute query failed"); return PR_E_DEVICE; }
     const int blocks = prm->grid_blocks > 0 ? prm->grid_blocks : cus * per;
+    // many units per wave: the cull takes them heaviest class first
+    const int64_t cull_waves = (int64_t)cus * per_cull * kWaves;
+    ra.ordered = 2 * P > kCullStatic * cull_waves ? 1 : 0;
+    if (ra.ordered) {
+      hipLaunchKernelGGL(k_order_count, dim3(grid_for(P, kBlock)), dim3(kBlock), 0, s, ra);
+      hipLaunchKernelGGL(k_order_place, dim3(grid_for(P, kBlock)), dim3(kBlock), 0, s, ra);
+    }
     int r = launch_ra(k_cull<W, PREC>, cus * per_cull, s, ra, eb, nullptr);
     hipEvent_t et = ra.budget > 0 ? nullptr : ee;
     if (r == PR_OK) {

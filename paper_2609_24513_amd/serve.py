@@ -6,12 +6,15 @@ surfaces share a point.  The loop keeps both datasets' BVH blobs in HBM and
 runs without blocking the host:
 
   * arrivals go to a FIFO;
-  * a batch is opened whenever a slot (a HIP stream with preallocated device
-    buffers) is free: it admits waiting requests in arrival order while the
-    HBM reserved by in-flight requests stays within the budget (a request
-    reserves room for `max_pairs` candidate pairs; when nothing is in flight
-    one request is always admitted, so nothing waits forever and nothing is
-    dropped);
+  * a slot is a HIP stream with its own device buffers (candidate regions,
+    the gathered batch, flags, filter and refine workspaces), all allocated
+    when the server starts; the HBM budget is spent on slots: the server
+    opens as many slots as the budget holds (at least one, at most `slots`),
+    so the device memory of the batches in flight never exceeds the budget
+    (beyond the one slot every server needs);
+  * a batch is opened whenever a slot is free: it admits up to
+    max_req_per_batch waiting requests in arrival order (nothing waits while
+    a slot is free, nothing is dropped);
   * the batch's query boxes go to the device in one asynchronous copy; each
     admitted request's candidate filter writes its own region of the slot,
     the regions are concatenated on the device with the counts left there
@@ -105,7 +108,8 @@ class _Slot:
         self.event = None
 
     def bytes(self) -> int:
-        t = [self.region, self.counts, self.batch, self.flags, self.fws, self.rws]
+        t = [self.region, self.counts, self.batch, self.flags, self.fws, self.rws, self.boxes, self.status,
+             self.total]
         return int(sum(x.numel() * x.element_size() for x in t))
 
 
@@ -127,12 +131,13 @@ class JoinServer:
             cfg2 = copy.copy(self.cfg)
             cfg2.survivor_cap = int(min(1 << 24, max(1 << 16, gmax * max_req_per_batch * max_pairs)))
             self.cfg = cfg2
-        self.slots = [_Slot(torch, pa, R, S, max_req_per_batch, max_pairs, self.cfg) for _ in range(slots)]
         self.hbm_budget = int(hbm_budget)
-        # device bytes a request holds while in flight: its pair region, gathered
-        # pairs, flags and refine workspace share
-        self.req_bytes = max_pairs * (8 + 8 + 1) + self.slots[0].rws.numel() // max(1, max_req_per_batch)
-        self.in_flight_bytes = 0
+        first = _Slot(torch, pa, R, S, max_req_per_batch, max_pairs, self.cfg)
+        self.slot_bytes = first.bytes()
+        n_slots = int(min(max(1, slots), max(1, self.hbm_budget // max(1, self.slot_bytes))))
+        self.slots = [first] + [_Slot(torch, pa, R, S, max_req_per_batch, max_pairs, self.cfg)
+                                for _ in range(n_slots - 1)]
+        self.in_flight_bytes = 0      # device bytes of the slots with a batch in flight
         self.batches = 0
         self.max_in_flight = 0
         self.oversized = 0      # requests beyond max_pairs, answered on their own
@@ -194,7 +199,7 @@ class JoinServer:
                 r.pairs = pairs[a:b]
                 r.flags = flags[a:b]
                 r.t_done = now
-        self.in_flight_bytes -= self.req_bytes * len(slot.reqs)
+        self.in_flight_bytes -= self.slot_bytes
         slot.reqs = []
         slot.phase = 0
         slot.event = None
@@ -238,12 +243,9 @@ class JoinServer:
                 if slot.phase == 0 and pending:
                     batch = []
                     while pending and len(batch) < self.max_req:
-                        fits = self.in_flight_bytes + self.req_bytes <= self.hbm_budget
-                        if not fits and (self.in_flight_bytes > 0 or batch):
-                            break
                         batch.append(pending.popleft())
-                        self.in_flight_bytes += self.req_bytes
                     if batch:
+                        self.in_flight_bytes += self.slot_bytes
                         self._start(slot, batch)
                         self.batches += 1
                         progressed = True

@@ -35,6 +35,8 @@ def test_served_equals_alone(pool, budget):
     R, S, gr, gs = pool
     trace = serve.make_trace(R.aabbs(), S.aabbs(), 80, lam=3000.0, seed=11, k_hi=1500.0, space=29.0)
     srv = serve.JoinServer(gr, gs, max_req_per_batch=8, slots=3, hbm_budget=budget)
+    # the budget is spent on slots: as many as it holds, at least one
+    assert len(srv.slots) == max(1, min(3, budget // srv.slot_bytes))
     out = srv.run(trace)
     assert all(r.t_done >= r.t_arrival for r in out)
     assert srv.batches >= 2
