@@ -470,21 +470,30 @@ __device__ __forceinline__ int leaf_test(f3 p, f3 q, f3 a, f3 b, f3 c, bool safe
 // FP32 filter left open (bits of `amb`, triangle first + bit * stride) go to
 // the exact grid tier; decided ones leave `amb` and hits enter `hit`.  n32
 // and ngrid count the FP32-uncertain tests and those decided here.
-template <int PREC>
-__device__ __forceinline__ void grid_tier(f3 p, f3 q, const float* tris, int32_t first, int stride, uint32_t& hit,
-                                          uint32_t& amb, uint32_t& n32, uint32_t& ngrid) {
-  n32 += (uint32_t)__popc(amb);
-  if (PREC != 3) return;
+// The exact tests of one lane, out of line: the expansion arithmetic keeps
+// its registers to itself instead of raising the traversal loop's.  Returns
+// the still-uncertain bits; hits are added to *hit, decisions to *ngrid.
+__device__ __noinline__ uint32_t grid_decide(f3 p, f3 q, const float* tris, int32_t first, int stride, uint32_t amb,
+                                             uint32_t* hit, uint32_t* ngrid) {
   for (uint32_t m = amb; m; m &= m - 1) {
     const int k = __builtin_ctz(m);
     const float* tp = tris + 9 * (int64_t)(first + k * stride);
     const int g = seg_tri_grid(p, q, tri_vertex(tp, 0), tri_vertex(tp, 1), tri_vertex(tp, 2));
     if (g != kAmbig) {
-      ++ngrid;
+      ++*ngrid;
       amb &= ~(1u << k);
-      if (g == kHit) hit |= 1u << k;
+      if (g == kHit) *hit |= 1u << k;
     }
   }
+  return amb;
+}
+
+template <int PREC>
+__device__ __forceinline__ void grid_tier(f3 p, f3 q, const float* tris, int32_t first, int stride, uint32_t& hit,
+                                          uint32_t& amb, uint32_t& n32, uint32_t& ngrid) {
+  n32 += (uint32_t)__popc(amb);
+  if (PREC != 3) return;
+  amb = grid_decide(p, q, tris, first, stride, amb, &hit, &ngrid);
 }
 
 // Wave sum of a per-lane count.
@@ -740,7 +749,7 @@ __device__ bool trace_core(const BlobView& S, const BlobView& T, int64_t gc, int
   bool cont = m0 != 0;
   if (m0 == 0) {
     st.add(S_SEG, (uint64_t)live);
-    m0 = ballot(valid && slab(r, tb[0], tb[1], tb[2], tb[3], tb[4], tb[5]));
+    m0 = ballot(valid && (tb == nullptr || slab(r, tb[0], tb[1], tb[2], tb[3], tb[4], tb[5])));
     if (m0 == 0) return false;
     if (SCHED != 1 && o.seg_max > 0 && o.lds.seg && __popcll(m0) <= o.seg_max) {
       st.add(S_GTRAV, 1);
@@ -1084,6 +1093,10 @@ __device__ __forceinline__ uint64_t lane_u64(uint64_t v, int j) {
   return ((uint64_t)hi << 32) | lo;
 }
 
+__device__ __forceinline__ int size_bucket(int32_t n_tris) {
+  return n_tris < (1 << 10) ? 0 : (n_tris < (1 << 13) ? 1 : (n_tris < (1 << 16) ? 2 : 3));
+}
+
 constexpr int kCullBuf = 256;  // survivor entries buffered per wave in LDS
 constexpr int kRunsMin = 4;    // runs of 64 groups from which the cull tests run boxes first
 // Multiplier of the pop-order permutation of a survivor queue; a prime above
@@ -1128,8 +1141,10 @@ __device__ void flush_survivors(const int4* buf, int n, int slice, const RefineA
 // lane, the next 64 boxes loading while the current ones are tested) and
 // buffers the survivors in LDS; full buffers go to the block's queue (blockIdx % kQueues, on
 // the XCD the block runs on, so phase 2 mostly finds the pair's data in the
-// same L2).  Survivor entry: global group index, unit, target mesh, live
-// segments | FP32-safe flag << 8.
+// same L2).  Survivor entry: global group index, unit, target root node,
+// live segments | FP32-safe flag << 8 | target size bucket << 9 | target
+// node count (at most 2^21 - 1) << 11, so that the tracing wave needs no
+// descriptor.
 template <int W, int PREC>
 __global__ __launch_bounds__(kBlock, 7) void k_cull(RefineArgs ra) {
   __shared__ int4 s_buf[kWaves][kCullBuf];
@@ -1163,6 +1178,7 @@ __global__ __launch_bounds__(kBlock, 7) void k_cull(RefineArgs ra) {
     const int32_t troot = tmd->root;
     const int32_t n_chunks = smd->n_chunks, n_edges = smd->n_edges, chunk_base = smd->chunk_base;
     const bool safe = (smd->flags & tmd->flags & kMeshSafe) != 0;
+    const int32_t tword = (safe ? 256 : 0) | (size_bucket(tmd->n_tris) << 9) | (min(tmd->n_nodes, (1 << 21) - 1) << 11);
     if (troot == kEmpty || n_chunks <= 0 || !box_meet(sb, tb[0], tb[1], tb[2], tb[3], tb[4], tb[5])) return;
     // Groups come in runs of 64 (one per lane), each with a run box.  With
     // at least kRunsMin runs, the run boxes are tested first, 64 at a time,
@@ -1260,7 +1276,7 @@ __global__ __launch_bounds__(kBlock, 7) void k_cull(RefineArgs ra) {
           }
           if (pass) {
             const int live = min(kChunk, n_edges - idx * kChunk);
-            buf[nbuf + lanes_below(mask)] = make_int4(chunk_base + idx, (int32_t)u, tid, live | (safe ? 256 : 0));
+            buf[nbuf + lanes_below(mask)] = make_int4(chunk_base + idx, (int32_t)u, troot, live | tword);
           }
           nbuf += n;
         }
@@ -1432,13 +1448,6 @@ __device__ void block_help(const BlobView& A, const BlobView& B, const RefineArg
 // mesh: below 2^10, 2^13, 2^16, and larger) and the per-bucket limit on the
 // segments of a group that meet the target box for the group to be traced
 // wave-per-segment (byte k of the table).
-__device__ __forceinline__ int size_bucket(int32_t n_tris) {
-  return n_tris < (1 << 10) ? 0 : (n_tris < (1 << 13) ? 1 : (n_tris < (1 << 16) ? 2 : 3));
-}
-__device__ __forceinline__ int seg_max_of(uint32_t table, int32_t n_tris) {
-  return (int)((table >> (8 * size_bucket(n_tris))) & 0xffu);
-}
-
 // Persistent pass, phase 2: waves pop surviving groups kPop at a time from the
 // queue of their block (blockIdx % kQueues, on the XCD whose phase-1 blocks
 // filled it) and trace them; a wave leaves a queue after its first empty pop
@@ -1505,14 +1514,22 @@ __global__ __launch_bounds__(kBlock, SCHED == 1 ? 6 : 5) void k_trace(RefineArgs
         if (first_decided && pair == first_pair) continue;
         const BlobView& S = dir == 0 ? A : B;
         const BlobView& T = dir == 0 ? B : A;
-        const cptr_t<MeshDesc> tmd = cview(T.mesh) + it.z;
-        float tb[6];
-#pragma unroll
-        for (int c = 0; c < 6; ++c) tb[c] = tmd->box[c];
         o.tq = cid;
-        o.seg_max = seg_max_of(ra.seg_table, tmd->n_tris);
-        o.n_nodes = tmd->n_nodes;
-        trace_core<W, PREC, SCHED>(S, T, it.x, it.w & 0xff, tmd->root, tb, pair, dir, (it.w & 256) != 0, ra, st, o);
+        o.n_nodes = (int32_t)((uint32_t)it.w >> 11);
+        if (SCHED == 1) {
+          // the entry names the target's root and node count: no descriptor
+          // read, and no target-box test (the frontier entries lie inside it)
+          o.seg_max = 0;
+          trace_core<W, PREC, SCHED>(S, T, it.x, it.w & 0xff, it.z, nullptr, pair, dir, (it.w & 256) != 0, ra, st, o);
+        } else {
+          const int32_t tid = ra.pairs[2 * pair + (dir == 0 ? 1 : 0)];
+          const cptr_t<MeshDesc> tmd = cview(T.mesh) + tid;
+          float tb[6];
+#pragma unroll
+          for (int c = 0; c < 6; ++c) tb[c] = tmd->box[c];
+          o.seg_max = (int)((ra.seg_table >> (8 * ((it.w >> 9) & 3))) & 0xffu);
+          trace_core<W, PREC, SCHED>(S, T, it.x, it.w & 0xff, it.z, tb, pair, dir, (it.w & 256) != 0, ra, st, o);
+        }
       }
     }
   }
