@@ -114,7 +114,6 @@ struct RefineArgs {
   unsigned long long* task_cnt;  // kQueues fill counters (stride kCtrStride)
   unsigned long long* task_pop;  // kQueues pop counters (stride kCtrStride)
   int32_t budget;             // traversal steps before a group hands its stack over (0 = none)
-  unsigned int* fin_done;     // blocks of k_finalize that have finished
   int32_t share;              // waves of a block share pending stack entries (1 = on)
   int32_t lds_stack;          // 1: the packet traversal's stack lives wholly in LDS
   uint32_t seg_table;         // per target-size bucket: wave-per-segment limit (bytes)
@@ -990,7 +989,6 @@ __global__ void k_init(RefineArgs ra) {
     }
   }
   if (i == 0) {
-    *ra.fin_done = 0u;
     *ra.status = PR_OK;
   }
 }
@@ -1730,10 +1728,10 @@ __device__ void report(const RefineArgs& ra, pr_refine_stats* out, int32_t* dev_
     *dev_status = __hip_atomic_load(ra.status, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// Flags from the pair states; the block that finishes last (every block
-// fences its updates, then counts itself done) writes the report.
-__global__ __launch_bounds__(kBlock) void k_finalize(RefineArgs ra, pr_refine_stats* out, int32_t* dev_status) {
-  __shared__ uint32_t s_last;
+// Flags from the pair states and the intersecting-pair count; the report
+// follows as a kernel of its own (the launch boundary orders the counts
+// without device-wide fences in every block).
+__global__ __launch_bounds__(kBlock) void k_finalize(RefineArgs ra) {
   int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   unsigned long long cnt = 0;
   const int64_t np = npairs(ra);
@@ -1744,14 +1742,6 @@ __global__ __launch_bounds__(kBlock) void k_finalize(RefineArgs ra, pr_refine_st
   }
   for (int o = 32; o > 0; o >>= 1) cnt += __shfl_xor(cnt, o);
   if ((threadIdx.x & 63) == 0 && cnt) atomicAdd(stat_copy(ra.stats) + S_TRUE, cnt);
-  __threadfence();
-  __syncthreads();
-  if (threadIdx.x == 0) s_last = atomicAdd(ra.fin_done, 1u) == gridDim.x - 1 ? 1u : 0u;
-  __syncthreads();
-  if (s_last && threadIdx.x < 64) {
-    __threadfence();
-    report(ra, out, dev_status);
-  }
 }
 
 // The report alone (no pairs).
@@ -1765,7 +1755,6 @@ void carve(Carve& cv, RefineArgs& ra, int64_t P, uint32_t qcap, uint32_t surv_ca
   ra.qcount = cv.take<uint32_t>(kSlices * kQCtrStride);
   ra.stats = cv.take<unsigned long long>(kStatCopies * kCtrStride);
   ra.status = cv.take<int32_t>(1);
-  ra.fin_done = cv.take<unsigned int>(64);
   ra.queue = cv.take<int4>((int64_t)kSlices * ((qcap + kSlices - 1) / kSlices));
   ra.surv_cnt = cv.take<unsigned long long>(kQueues * kCtrStride);
   ra.surv_pop = cv.take<unsigned long long>(kQueues * kCtrStride);
@@ -1948,7 +1937,8 @@ int refine_run(const void* blob_a, int64_t n_meshes_a, const void* blob_b, int64
     if (W == 2) hipLaunchKernelGGL(k_fix<2>, dim3(fb), dim3(kBlock), 0, s, ra);
     else if (W == 4) hipLaunchKernelGGL(k_fix<4>, dim3(fb), dim3(kBlock), 0, s, ra);
     else hipLaunchKernelGGL(k_fix<8>, dim3(fb), dim3(kBlock), 0, s, ra);
-    hipLaunchKernelGGL(k_finalize, dim3(grid_for(n_pairs, kBlock)), dim3(kBlock), 0, s, ra, dev_stats, dev_status);
+    hipLaunchKernelGGL(k_finalize, dim3(grid_for(n_pairs, kBlock)), dim3(kBlock), 0, s, ra);
+    hipLaunchKernelGGL(k_report, dim3(1), dim3(64), 0, s, ra, dev_stats, dev_status);
   } else {
     hipLaunchKernelGGL(k_report, dim3(1), dim3(64), 0, s, ra, dev_stats, dev_status);
   }
