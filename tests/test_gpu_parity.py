@@ -321,11 +321,13 @@ def test_c3_scaled_all_widths_and_schedules(env):
 
 
 def test_many_units_per_wave_cull(env):
-    """60,000 pairs (120,000 units, more than eight per culling wave on this
-    GPU), so that the culling waves take their units a few at a time from
-    per-XCD shares: every box-overlapping tetrahedron pair, mixed with random
-    pairs and repeats, against the oracle in FP32-filter and exact modes."""
+    """60,000 pairs (120,000 units, more than eight per culling wave even
+    with every CU at its maximum of 32 waves), so that the culling waves take
+    their units a few at a time from per-XCD shares in cost order: every
+    box-overlapping tetrahedron pair, mixed with random pairs and repeats,
+    against the oracle in FP32-filter and exact modes."""
     torch, pa, synth, oracle = env
+    assert 2 * 60_000 > 8 * 32 * torch.cuda.get_device_properties(0).multi_processor_count
     A, B = _tetra_set(synth, 600, 31, 6.0), _tetra_set(synth, 600, 32, 6.0)
     cand = oracle.candidate_pairs(oracle.mesh_boxes(A), oracle.mesh_boxes(B)).astype(np.int32)
     rng = np.random.default_rng(3)
