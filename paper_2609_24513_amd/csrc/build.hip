@@ -128,7 +128,72 @@ struct BuildArgs {
   char* tnodes;          // [node_cap] nodes at bound-sized offsets, before compaction
   int64_t* ncount;       // [M+1] nodes used per mesh, then scanned
   int64_t* tsum;         // tile sums of the prefix sums
+  int32_t* morder;       // [M] meshes in decreasing size class (the per-mesh kernels' order)
+  int32_t* mcnt;         // [kSizeClasses][order blocks] meshes of each class in each block
+  int64_t* mpos;         // the same, scanned
 };
+
+// The per-mesh kernels (refit, collapse, node copy) give each mesh one
+// block, and a launch ends with its largest mesh; blocks therefore take the
+// meshes in decreasing size class (powers of two of the face count), index
+// order within a class: a stable counting sort of kMeshOrdTile meshes per
+// block (class counts, a scan, then each mesh's place).
+constexpr int kSizeClasses = 8;
+constexpr int kMeshOrdTile = 1024;  // meshes per block of the order kernels (4 per thread)
+
+// ---- mesh order ----------------------------------------------------------------
+
+__device__ __forceinline__ int size_class(const BuildArgs& a, int64_t m) {
+  const int64_t n = a.face_off[m + 1] - a.face_off[m];
+  const int lg = n > 0 ? 63 - __builtin_clzll((uint64_t)n) : 0;
+  return lg >= 16 ? 0 : (lg <= 9 ? kSizeClasses - 1 : 16 - lg);
+}
+
+// Per thread: the classes of its 4 meshes (kSizeClasses for none) and its
+// count of each class, 16 bits a class (classes 0-3 in w0, 4-7 in w1).
+__device__ __forceinline__ void mesh_items(const BuildArgs& a, int* cls, uint64_t& w0, uint64_t& w1) {
+  const int64_t m0 = blockIdx.x * (int64_t)kMeshOrdTile + 4 * (int64_t)threadIdx.x;
+  w0 = 0;
+  w1 = 0;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const int c = m0 + k < a.n_meshes ? size_class(a, m0 + k) : kSizeClasses;
+    cls[k] = c;
+    if (c < 4) w0 += 1ull << (16 * c);
+    else if (c < kSizeClasses) w1 += 1ull << (16 * (c - 4));
+  }
+}
+
+__global__ __launch_bounds__(256) void k_mesh_order_count(BuildArgs a, int64_t nb) {
+  __shared__ uint64_t s[4];
+  int cls[4];
+  uint64_t w0, w1;
+  mesh_items(a, cls, w0, w1);
+  const uint64_t t0 = block_sum<256>(w0, s), t1 = block_sum<256>(w1, s);
+  if (threadIdx.x < kSizeClasses) {
+    const uint64_t t = threadIdx.x < 4 ? t0 >> (16 * threadIdx.x) : t1 >> (16 * (threadIdx.x - 4));
+    a.mcnt[threadIdx.x * nb + blockIdx.x] = (int32_t)(t & 0xffffu);
+  }
+}
+
+__global__ __launch_bounds__(256) void k_mesh_order_place(BuildArgs a, int64_t nb) {
+  __shared__ uint64_t s[4];
+  int cls[4];
+  uint64_t w0, w1;
+  mesh_items(a, cls, w0, w1);
+  uint64_t t0, t1;
+  const uint64_t e0 = block_exclusive_sum<256>(w0, s, t0), e1 = block_exclusive_sum<256>(w1, s, t1);
+  const int64_t m0 = blockIdx.x * (int64_t)kMeshOrdTile + 4 * (int64_t)threadIdx.x;
+  uint32_t seen = 0;  // this thread's earlier meshes, 4 bits a class
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const int c = cls[k];
+    if (c >= kSizeClasses) continue;
+    const uint64_t before = c < 4 ? (e0 >> (16 * c)) & 0xffffu : (e1 >> (16 * (c - 4))) & 0xffffu;
+    a.morder[a.mpos[c * nb + blockIdx.x] + (int64_t)before + ((seen >> (4 * c)) & 0xfu)] = (int32_t)(m0 + k);
+    seen += 1u << (4 * c);
+  }
+}
 
 // ---- step 1 ---------------------------------------------------------------
 
@@ -364,7 +429,8 @@ __device__ __forceinline__ void child_info(const BuildArgs& a, int32_t c, const 
 // writes without device-wide cache maintenance.
 __global__ __launch_bounds__(kMeshBlock) void k_refit(BuildArgs a, const int32_t* sorted_face) {
   if (*a.status != INT_MAX) return;  // invalid input: the blob is not built
-  for (int64_t m = blockIdx.x; m < a.n_meshes; m += gridDim.x) {
+  for (int64_t mi = blockIdx.x; mi < a.n_meshes; mi += gridDim.x) {
+    const int64_t m = a.morder[mi];
     const int64_t f0 = a.face_off[m], f1 = a.face_off[m + 1];
     for (int64_t g = f0 + threadIdx.x; g < f1; g += blockDim.x) {
       int32_t p = a.lparent[g];
@@ -479,7 +545,8 @@ __global__ __launch_bounds__(kMeshBlock) void k_collapse(BuildArgs a, const int6
   __shared__ int32_t s_used, s_tail, s_depth, s_over;
   if (*a.status != INT_MAX) return;  // invalid input: the blob is not built
   Node<W>* nodes = reinterpret_cast<Node<W>*>(a.tnodes);
-  for (int64_t m = blockIdx.x; m < a.n_meshes; m += gridDim.x) {
+  for (int64_t mi = blockIdx.x; mi < a.n_meshes; mi += gridDim.x) {
+    const int64_t m = a.morder[mi];
     const int n = a.mesh[m].n_tris;
     const int64_t fbase = a.face_off[m];
     const int64_t nb = node_base_scan[m];
@@ -557,7 +624,8 @@ __global__ void k_node_copy(BuildArgs a, const int64_t* new_base) {
   if (*a.status != INT_MAX) return;  // invalid input: the blob is not built
   const Node<W>* src = reinterpret_cast<const Node<W>*>(a.tnodes);
   Node<W>* dst = reinterpret_cast<Node<W>*>(a.nodes);
-  for (int64_t m = blockIdx.x; m < a.n_meshes; m += gridDim.x) {
+  for (int64_t mi = blockIdx.x; mi < a.n_meshes; mi += gridDim.x) {
+    const int64_t m = a.morder[mi];
     const int32_t old_base = a.mesh[m].node_base;
     const int32_t n = a.mesh[m].n_nodes;
     const int64_t nb = new_base[m];
@@ -867,6 +935,9 @@ int carve_ws(Carve& cv, BuildArgs& a, int64_t M, int64_t F, int64_t node_cap, in
   a.chunk_scan = cv.take<int64_t>(M + 1);
   a.ncount = cv.take<int64_t>(M + 1);
   a.tsum = cv.take<int64_t>(scan_tiles_of((E3 > M ? E3 : M) + 1) + 1);
+  a.morder = cv.take<int32_t>(M);
+  a.mcnt = cv.take<int32_t>(kSizeClasses * ((M + kMeshOrdTile - 1) / kMeshOrdTile));
+  a.mpos = cv.take<int64_t>(kSizeClasses * ((M + kMeshOrdTile - 1) / kMeshOrdTile));
   a.tnodes = cv.take<char>(node_cap * node_bytes(W));
   // temp storage for the library sorts
   size_t need = 0, b = 0;
@@ -991,6 +1062,13 @@ extern "C" int build_mesh_bvh(const float* verts, const int64_t* vert_off, const
     hipLaunchKernelGGL(k_tri_prep, dim3(gF < 4096 ? gF : 4096), dim3(kBlock), 0, s, a);
   }
   if (M > 0) hipLaunchKernelGGL(k_mesh_box, dim3((int)(M < 65536 ? M : 65536)), dim3(kBlock), 0, s, a);
+  if (M > 0) {
+    // the per-mesh kernels below take the meshes largest first
+    const int64_t nbm = (M + kMeshOrdTile - 1) / kMeshOrdTile;
+    hipLaunchKernelGGL(k_mesh_order_count, dim3((unsigned)nbm), dim3(256), 0, s, a, nbm);
+    PR_HIP(device_exclusive_scan((const int32_t*)a.mcnt, a.mpos, kSizeClasses * nbm, a.tsum, (int64_t*)nullptr, s));
+    hipLaunchKernelGGL(k_mesh_order_place, dim3((unsigned)nbm), dim3(256), 0, s, a, nbm);
+  }
   if (F > 0) {
     hipLaunchKernelGGL(k_morton, dim3(gF), dim3(kBlock), 0, s, a);
     PR_HIP(hipcub::DeviceRadixSort::SortPairs(tmp, tmp_bytes, a.key0, a.key1, a.val0, a.val1, (int)F, 0, eb, s));
