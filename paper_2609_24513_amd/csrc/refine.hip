@@ -1461,7 +1461,6 @@ __device__ void block_help(const BlobView& A, const BlobView& B, const RefineArg
 // (`block_help`), so the block's long traversals end together.
 template <int W, int PREC, int SCHED>
 __global__ __launch_bounds__(kBlock, SCHED == 1 ? 6 : 5) void k_trace(RefineArgs ra) {
-  constexpr int kPop = 4;
   __shared__ uint64_t s_area[kWaves][wave_lds_words<W>()];
   __shared__ BlockShare s_share;
   const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -1493,6 +1492,11 @@ __global__ __launch_bounds__(kBlock, SCHED == 1 ? 6 : 5) void k_trace(RefineArgs
     const int cid = few ? home + j * (int)gridDim.x : (home + j * kSlices) % kQueues;
     const uint64_t filled = ra.surv_cnt[kCtrStride * cid];
     const uint64_t n = filled < ra.surv_cap ? filled : ra.surv_cap;
+    // groups popped at a time: 8 from queues long enough to give every wave
+    // that drains them dozens of batches, else 4 (the last batches of a
+    // short queue set its end)
+    const uint64_t qwaves = (uint64_t)gridDim.x * kWaves / kQueues + 1;
+    const int kPop = n >= 64 * qwaves ? 8 : 4;
     const uint64_t slots = (n + kPop - 1) / kPop;
     const cptr_t<int32_t> q = cview(reinterpret_cast<const int32_t*>(ra.surv + (int64_t)cid * ra.surv_cap));
     for (;;) {
@@ -1501,15 +1505,15 @@ __global__ __launch_bounds__(kBlock, SCHED == 1 ? 6 : 5) void k_trace(RefineArgs
       const uint64_t k = uni64(k0);
       if (k >= n) break;
       const uint64_t e0 = ((k / kPop) * kSpread % slots) * kPop;
-      const uint64_t kend = e0 + kPop < n ? e0 + kPop : n;
-      // the batch's groups mostly belong to one pair: when its first pair is
-      // already decided, those groups are dropped before their segments load
-      const int32_t first_pair = q[4 * e0 + 1] >> 1;
-      const bool first_decided = load_state(ra.state + first_pair) != 0u;
-      for (uint64_t e = e0; e < kend; ++e) {
+      const int cnt = (int)((e0 + kPop < n ? e0 + kPop : n) - e0);
+      // lane j < cnt reads entry e0 + j and its pair's state, all at once:
+      // groups of pairs already decided are dropped before their segments load
+      const int32_t unit_l = lane < cnt ? q[4 * (e0 + lane) + 1] : 0;
+      const bool todo_l = lane < cnt && load_state(ra.state + (unit_l >> 1)) == 0u;
+      for (uint64_t todo = ballot(todo_l); todo; todo &= todo - 1) {
+        const uint64_t e = e0 + __builtin_ctzll(todo);
         const int4 it = make_int4(q[4 * e], q[4 * e + 1], q[4 * e + 2], q[4 * e + 3]);
         const int32_t pair = it.y >> 1, dir = it.y & 1;
-        if (first_decided && pair == first_pair) continue;
         const BlobView& S = dir == 0 ? A : B;
         const BlobView& T = dir == 0 ? B : A;
         o.tq = cid;
