@@ -612,12 +612,15 @@ T* take(char*& p, size_t& left, int64_t n) {
   return r;
 }
 
-size_t unique_ws(int64_t n) {
+int unique_ws(int64_t n, size_t* bytes) {
   size_t sort_tmp = 0;
-  hipcub::DeviceRadixSort::SortKeys(nullptr, sort_tmp, (const uint64_t*)nullptr, (uint64_t*)nullptr, (int)n);
+  const hipError_t e =
+      hipcub::DeviceRadixSort::SortKeys(nullptr, sort_tmp, (const uint64_t*)nullptr, (uint64_t*)nullptr, (int)n, 0, 64);
+  if (e != hipSuccess) return hip_fail(e, "hipcub SortKeys size");
   const size_t scan_tmp = (size_t)(8 * (scan_tiles_of(n) + 1));
-  return (size_t)align256(8 * n) + (size_t)align256(4 * n) + (size_t)align256(8 * n) +
-         (size_t)align256((int64_t)std::max(sort_tmp, scan_tmp)) + 1024;
+  *bytes = (size_t)align256(8 * n) + (size_t)align256(4 * n) + (size_t)align256(8 * n) +
+           (size_t)align256((int64_t)std::max(sort_tmp, scan_tmp)) + 1024;
+  return PR_OK;
 }
 
 size_t trace_ws(int64_t groups) {
@@ -755,8 +758,7 @@ extern "C" int dataset_trace(const void* src_blob, int64_t n_src_objects, const 
 extern "C" int pairs_unique_ws_bytes(int64_t n_keys, size_t* ws_bytes) {
   if (n_keys < 0 || !ws_bytes) { set_error("bad argument"); return PR_E_ARG; }
   if (n_keys >= INT_MAX) { set_error("n_keys %lld beyond 2^31", (long long)n_keys); return PR_E_UNSUPPORTED; }
-  *ws_bytes = unique_ws(n_keys);
-  return PR_OK;
+  return unique_ws(n_keys, ws_bytes);
 }
 
 extern "C" int pairs_unique(const uint64_t* keys, int64_t n_keys, int32_t* out_pairs, int64_t out_cap,
@@ -766,7 +768,10 @@ extern "C" int pairs_unique(const uint64_t* keys, int64_t n_keys, int32_t* out_p
     return PR_E_ARG;
   }
   if (n_keys >= INT_MAX) { set_error("n_keys beyond 2^31"); return PR_E_UNSUPPORTED; }
-  if (ws_bytes < unique_ws(n_keys)) { set_error("ws_bytes %zu < required %zu", ws_bytes, unique_ws(n_keys)); return PR_E_CAPACITY; }
+  size_t need = 0;
+  const int r = unique_ws(n_keys, &need);
+  if (r != PR_OK) return r;
+  if (ws_bytes < need) { set_error("ws_bytes %zu < required %zu", ws_bytes, need); return PR_E_CAPACITY; }
   hipStream_t s = (hipStream_t)stream;
   char* p = (char*)ws;
   size_t left = ws_bytes;
