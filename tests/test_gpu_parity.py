@@ -429,14 +429,17 @@ def _c3_expected(A, B, pairs):
 
 def test_c3_full_size_against_oracle(env):
     """The batching workload at full size (50,000 pairs, faces up to 100,000
-    per mesh), one persistent launch per schedule: every pair checked."""
+    per mesh), one persistent launch per configuration: first the one the
+    benchmark times (W = 8, L = 1, wave-per-pair, with the cull order and the
+    per-XCD grabs that 100,000 units take), then every schedule and builder at
+    W = 4, L = 4; every pair checked."""
     torch, pa, synth, oracle = env
     A, B, pairs = synth.make_c3()
     want = _c3_expected(A, B, pairs)
     assert want.shape[0] == 50_000 and 0 < want.sum() < 50_000
-    for sc, bld in ((1, 0), (2, 0), (0, 0), (1, 1)):
-        got, st = _run(env, A, B, pairs, persistent=1, schedule=sc, builder=bld)
-        assert int((got != want).sum()) == 0, sc
+    for w, lf, sc, bld in ((8, 1, 1, 0), (4, 4, 1, 0), (4, 4, 2, 0), (4, 4, 0, 0), (4, 4, 1, 1)):
+        got, st = _run(env, A, B, pairs, width=w, leaf=lf, persistent=1, schedule=sc, builder=bld)
+        assert int((got != want).sum()) == 0, (w, lf, sc, bld)
         assert st["pairs_true"] == int(want.sum())
 
 
