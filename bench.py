@@ -198,6 +198,7 @@ def roofline_of(st: dict, W: int, kern_ms: float, workload: str, L: int = 0, sch
               + 28 * W * st["node_visits"] + 36 * st["tri_fetches"])
     achieved = alg / (kern_ms * 1e-3) / 1e9
     traffic = None
+    valu = None
     path = TRAFFIC_FILE % workload
     if os.path.exists(path):
         doc = json.load(open(path))
@@ -206,10 +207,13 @@ def roofline_of(st: dict, W: int, kern_ms: float, workload: str, L: int = 0, sch
             if (tr.get("kernel_source_sha") == sha and tr.get("workload") == workload
                     and (tr.get("bvh_width"), tr.get("leaf_size"), tr.get("schedule")) == (W, L, sched)):
                 traffic = tr.get("hbm_bytes_per_launch")
+                valu = tr.get("valu_use")
+    # valu_use: share of SIMD cycles issuing vector instructions, per kernel,
+    # from the profiled run's counters (4 x SQ_INSTS_VALU / SIMD cycles)
     return {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS, "traffic": traffic, "kernel": "k_cull + k_trace",
             "kernel_ms": kern_ms, "algorithmic_bytes": int(alg), "loaded_bytes_model": int(loaded),
-            "loaded_gbs": loaded / (kern_ms * 1e-3) / 1e9}
+            "loaded_gbs": loaded / (kern_ms * 1e-3) / 1e9, "valu_use": valu}
 
 
 def predicate_bench(torch, pa, ga, gb, pairs, cfg_kw: dict, reps: int = 5) -> dict:
