@@ -92,81 +92,99 @@ __global__ void k_boxes_all(const void* blob_a, int64_t MA, int32_t* ids_a, floa
 
 // With a query box: ordered compaction of the meshes that meet it, one
 // dataset per block (block 0: A, block 1: B), for datasets of at most
-// kSmallScan meshes: tiles of kScanBlock * kScanItems meshes (each thread
-// reads its meshes' box and size once), a block scan of the per-thread
-// counts, ids and boxes written in index order; the count goes to cnt.
+// kSmallScan meshes.  Thread t takes meshes t, t + kScanBlock, ... (one
+// coalesced load per wave and tile, issued ahead of their use) and keeps
+// one bit per tile; the waves' counts per tile go to LDS, one block scan
+// over them (tile-major, one entry per thread) gives every kept mesh its
+// position in index order, and the kept meshes' boxes are read again and
+// written with their ids; the count goes to cnt.
+constexpr int kKeepWaves = kScanBlock / 64;
+static_assert(kSmallScan / kScanBlock * kKeepWaves == kScanBlock, "one (tile, wave) count per thread");
+static_assert(kSmallScan / kScanBlock <= 64, "one keep bit per tile");
+
 __global__ __launch_bounds__(kScanBlock) void k_keep_small(const void* blob_a, int64_t MA, int32_t* ids_a,
                                                            float* box_a, int32_t* cnt_a, const void* blob_b,
                                                            int64_t MB, int32_t* ids_b, float* box_b, int32_t* cnt_b,
                                                            const float* query) {
-  __shared__ int32_t s_scan[kScanBlock / 64];
+  __shared__ int32_t s_cnt[kScanBlock];  // (tile, wave) counts, then their offsets
+  __shared__ int32_t s_scan[kKeepWaves];
   const bool first = blockIdx.x == 0;
   const MeshDesc* md = meshes_of(first ? blob_a : blob_b);
   const int64_t M = first ? MA : MB;
   int32_t* ids = first ? ids_a : ids_b;
   float* boxes = first ? box_a : box_b;
+  const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
   float q[6];
 #pragma unroll
   for (int c = 0; c < 6; ++c) q[c] = query[c];
-  int32_t running = 0;
-  for (int64_t base = 0; base < M; base += kScanBlock * kScanItems) {
-    const int64_t m0 = base + (int64_t)threadIdx.x * kScanItems;
-    float bx[kScanItems][6];
-    uint32_t keep = 0;
-#pragma unroll
-    for (int i = 0; i < kScanItems; ++i) {
-      const int64_t m = m0 + i;
-      bool ok = false;
-      if (m < M) {
-        const float4* p4 = reinterpret_cast<const float4*>(md + m);
-        const float4 u = p4[0], v = p4[1], w = p4[2];  // box, node base/count, tri base/count
-        bx[i][0] = u.x; bx[i][1] = u.y; bx[i][2] = u.z; bx[i][3] = u.w; bx[i][4] = v.x; bx[i][5] = v.y;
-        ok = __float_as_int(w.y) > 0 && meet(bx[i], q);
-      }
-      keep |= (ok ? 1u : 0u) << i;
+  const int ntiles = (int)((M + kScanBlock - 1) / kScanBlock);  // at most 64 (M <= kSmallScan)
+  uint64_t bits = 0;
+#pragma unroll 4
+  for (int k = 0; k < ntiles; ++k) {
+    const int64_t m = (int64_t)k * kScanBlock + t;
+    bool ok = false;
+    if (m < M) {
+      const float4* p4 = reinterpret_cast<const float4*>(md + m);
+      const float4 u = p4[0], v = p4[1], w = p4[2];  // box, node base/count, tri base/count
+      const float b[6] = {u.x, u.y, u.z, u.w, v.x, v.y};
+      ok = __float_as_int(w.y) > 0 && meet(b, q);
     }
-    int32_t total = 0;
-    int32_t pos = running + block_exclusive_sum<kScanBlock>((int32_t)__popc(keep), s_scan, total);
-#pragma unroll
-    for (int i = 0; i < kScanItems; ++i)
-      if ((keep >> i) & 1u) {
-        ids[pos] = (int32_t)(m0 + i);
-#pragma unroll
-        for (int c = 0; c < 6; ++c) boxes[6 * (int64_t)pos + c] = bx[i][c];
-        ++pos;
-      }
-    running += total;
+    bits |= (ok ? 1ull : 0ull) << k;
+    const uint64_t bm = __ballot(ok);
+    if (lane == 0) s_cnt[k * kKeepWaves + wv] = __popcll(bm);
   }
-  if (threadIdx.x == 0) *(first ? cnt_a : cnt_b) = running;
+  __syncthreads();
+  const bool entry = t < ntiles * kKeepWaves;
+  int32_t total = 0;
+  const int32_t off = block_exclusive_sum<kScanBlock>(entry ? s_cnt[t] : 0, s_scan, total);
+  if (entry) s_cnt[t] = off;  // each thread rewrites only its own entry
+  __syncthreads();
+  for (int k = 0; k < ntiles; ++k) {
+    const bool ok = (bits >> k) & 1ull;
+    const uint64_t bm = __ballot(ok);
+    if (ok) {
+      const int64_t m = (int64_t)k * kScanBlock + t;
+      const int32_t pos = s_cnt[k * kKeepWaves + wv] +
+                          (int32_t)__builtin_amdgcn_mbcnt_hi((uint32_t)(bm >> 32),
+                                                             __builtin_amdgcn_mbcnt_lo((uint32_t)bm, 0u));
+      ids[pos] = (int32_t)m;
+#pragma unroll
+      for (int c = 0; c < 6; ++c) boxes[6 * (int64_t)pos + c] = md[m].box[c];
+    }
+  }
+  if (t == 0) *(first ? cnt_a : cnt_b) = total;
 }
 
-// Exclusive scan of the row counts (at most kSmallScan rows) in one block;
-// the total goes to rowoff[rows] and to the caller's count.
-__global__ __launch_bounds__(kScanBlock) void k_rowscan_small(const int64_t* cnt, int64_t rows, int64_t* off,
-                                                              int64_t* total_out) {
+// Exclusive scan of the row counts (at most kSmallScan rows) in one block,
+// over the first *n_live rows only (the kept rows); the total goes to
+// off[n] (n the rows scanned) and to the caller's count.
+__global__ __launch_bounds__(kScanBlock) void k_rowscan_small(const int64_t* cnt, int64_t rows, const int32_t* n_live,
+                                                              int64_t* off, int64_t* total_out) {
   __shared__ int64_t s_scan[kScanBlock / 64];
+  const int64_t live = *n_live;
+  const int64_t n = live < 0 ? 0 : (live < rows ? live : rows);
   int64_t running = 0;
-  for (int64_t base = 0; base < rows; base += kScanBlock * kScanItems) {
+  for (int64_t base = 0; base < n; base += kScanBlock * kScanItems) {
     const int64_t r0 = base + (int64_t)threadIdx.x * kScanItems;
     int64_t v[kScanItems];
     int64_t sum = 0;
 #pragma unroll
     for (int i = 0; i < kScanItems; ++i) {
-      v[i] = r0 + i < rows ? cnt[r0 + i] : 0;
+      v[i] = r0 + i < n ? cnt[r0 + i] : 0;
       sum += v[i];
     }
     int64_t total = 0;
     int64_t o = running + block_exclusive_sum<kScanBlock>(sum, s_scan, total);
 #pragma unroll
     for (int i = 0; i < kScanItems; ++i)
-      if (r0 + i < rows) {
+      if (r0 + i < n) {
         off[r0 + i] = o;
         o += v[i];
       }
     running += total;
   }
   if (threadIdx.x == 0) {
-    off[rows] = running;
+    off[n] = running;
     *total_out = running;
   }
 }
@@ -180,6 +198,7 @@ struct RowArgs {
   const int32_t* nb;
   const float* query;
   int64_t rows;       // capacity of the row arrays (n_meshes_a)
+  bool live_only;     // counts only for the kept rows (the scan reads no more)
   int64_t* rowcnt;    // [rows + 1]
   const int64_t* rowoff;
   int32_t* pairs;
@@ -217,7 +236,8 @@ __global__ __launch_bounds__(kBlock) void k_row_count(RowArgs r) {
   __shared__ float tile[6][kTile];
   const int32_t na = *r.na, nb = *r.nb;
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  const int64_t groups = (r.rows + kRowsPerBlock - 1) / kRowsPerBlock;
+  const int64_t nrows = r.live_only ? (na < r.rows ? (int64_t)na : r.rows) : r.rows;
+  const int64_t groups = (nrows + kRowsPerBlock - 1) / kRowsPerBlock;
   for (int64_t g = blockIdx.x; g < groups; g += gridDim.x) {
     const int64_t row = g * kRowsPerBlock + wv;
     const bool live = row < na;
@@ -239,9 +259,9 @@ __global__ __launch_bounds__(kBlock) void k_row_count(RowArgs r) {
       }
     }
     for (int o = 32; o > 0; o >>= 1) cnt += __shfl_xor(cnt, o);
-    if (lane == 0 && row < r.rows) r.rowcnt[row] = (int64_t)cnt;
+    if (lane == 0 && row < nrows) r.rowcnt[row] = (int64_t)cnt;
   }
-  if (blockIdx.x == 0 && threadIdx.x == 0) r.rowcnt[r.rows] = 0;
+  if (!r.live_only && blockIdx.x == 0 && threadIdx.x == 0) r.rowcnt[r.rows] = 0;
 }
 
 __global__ __launch_bounds__(kBlock) void k_row_write(RowArgs r) {
@@ -668,6 +688,7 @@ extern "C" int filter_aabb_pairs(const void* blob_a, int64_t n_meshes_a, const v
   ra.na = w.pos_a + MA;
   ra.nb = w.pos_b + MB;
   ra.rows = MA;
+  ra.live_only = MA <= kSmallScan;
   ra.rowcnt = w.rowcnt;
   ra.rowoff = w.rowoff;
   ra.pairs = pairs;
@@ -676,8 +697,8 @@ extern "C" int filter_aabb_pairs(const void* blob_a, int64_t n_meshes_a, const v
   const int rows_grid = (int)(row_groups < 2048 ? (row_groups > 0 ? row_groups : 1) : 2048);
   hipLaunchKernelGGL(k_row_count, dim3(rows_grid), dim3(kBlock), 0, s, ra);
   if (MA <= kSmallScan) {
-    hipLaunchKernelGGL(k_rowscan_small, dim3(1), dim3(kScanBlock), 0, s, (const int64_t*)w.rowcnt, MA, w.rowoff,
-                       dev_count);
+    hipLaunchKernelGGL(k_rowscan_small, dim3(1), dim3(kScanBlock), 0, s, (const int64_t*)w.rowcnt, MA,
+                       (const int32_t*)(w.pos_a + MA), w.rowoff, dev_count);
     hipLaunchKernelGGL(k_row_write, dim3(rows_grid), dim3(kBlock), 0, s, ra);
   } else {
     PR_HIP(device_exclusive_scan((const int64_t*)w.rowcnt, w.rowoff, MA + 1, w.tsum, dev_count, s));

@@ -21,9 +21,12 @@ runs without blocking the host:
     (gather_pair_regions), and the concatenation is refined in ONE persistent
     launch that reads the count on the device: the whole batch is enqueued at
     once, with no host round trip;
-  * when the slot's stream has finished, the counts, flags and pairs are read
-    back; a request completes then, and its latency is completion time minus
-    arrival time.
+  * the counts, the status and the batch's pairs and flags (up to
+    max_pairs per admitted request, an upper bound of the batch size) go
+    back to pinned host buffers by asynchronous copies enqueued behind the
+    refinement; when the slot's stream has finished, the results are read
+    from those buffers with no further device transfer; a request completes
+    then, and its latency is completion time minus arrival time.
 
 Batches on different slots overlap on the device, and new requests are
 admitted while earlier ones are still running.  The per-request plain path
@@ -92,6 +95,7 @@ class _Slot:
         self.batch = torch.empty((cap, 2), dtype=torch.int32, device="cuda")
         self.flags = torch.empty(cap, dtype=torch.uint8, device="cuda")
         self.flags_h = torch.zeros(cap, dtype=torch.uint8, pin_memory=True)
+        self.batch_h = torch.zeros((cap, 2), dtype=torch.int32, pin_memory=True)
         self.status = torch.zeros(1, dtype=torch.int32, device="cuda")
         self.status_h = torch.zeros(1, dtype=torch.int32, pin_memory=True)
         self.total = torch.zeros(1, dtype=torch.int64, device="cuda")
@@ -174,6 +178,10 @@ class JoinServer:
                       stream=slot.stream)
             slot.counts_h[:len(reqs)].copy_(slot.counts[:len(reqs)], non_blocking=True)
             slot.status_h.copy_(slot.status, non_blocking=True)
+            # every request holds at most max_pairs candidates in the batch
+            m = len(reqs) * self.max_pairs
+            slot.batch_h[:m].copy_(slot.batch[:m], non_blocking=True)
+            slot.flags_h[:m].copy_(slot.flags[:m], non_blocking=True)
             slot.event = torch.cuda.Event()
             slot.event.record(slot.stream)
 
@@ -184,8 +192,9 @@ class JoinServer:
         n = int(offsets[-1])
         if n and int(slot.status_h.item()) != 0:
             raise RuntimeError("refine status %d" % int(slot.status_h.item()))
-        flags = slot.flags[:n].cpu().numpy() if n else np.zeros(0, np.uint8)
-        pairs = slot.batch[:n].cpu().numpy() if n else np.zeros((0, 2), np.int32)
+        # copied out of the pinned buffers, which the slot's next batch reuses
+        flags = slot.flags_h[:n].numpy().copy()
+        pairs = slot.batch_h[:n].numpy().copy()
         for k, r in enumerate(slot.reqs):
             if raw[k] > self.max_pairs:
                 # more candidates than a slot region holds: this request's

@@ -182,7 +182,8 @@ def _tetra_set_with_empties(synth, n, seed, side, every=7):
     return synth.MeshSet(v, f, off, off.copy())
 
 
-@pytest.mark.parametrize("na,nb", [(1, 1), (17, 4096), (65_537, 300), (131_072, 40), (131_073, 30), (500, 4_097)])
+@pytest.mark.parametrize("na,nb", [(1, 1), (17, 4096), (65_536, 4_097), (65_537, 300), (131_072, 40), (131_073, 30),
+                                   (500, 4_097)])
 def test_filter_row_block_path_limits(env, na, nb):
     """Row and column counts on both sides of the limits of the 64-rows-per-block
     path (4,096 columns, 131,072 rows; with a query box 65,536 rows), with empty
