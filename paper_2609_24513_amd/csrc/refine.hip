@@ -1809,7 +1809,12 @@ constexpr uint32_t kQcapStatic = 1u << 18, kScapStatic = 1u << 21;
 template <typename K>
 int launch_ra(K kernel, int blocks, hipStream_t s, RefineArgs& ra, hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr) {
   void* args[] = {&ra};
-  PR_HIP(hipExtLaunchKernel(reinterpret_cast<const void*>(kernel), dim3(blocks), dim3(kBlock), args, 0, s, e0, e1, 0));
+  // the plain launch when no event rides on the dispatch (it is also the
+  // form a stream capture records)
+  if (!e0 && !e1)
+    PR_HIP(hipLaunchKernel(reinterpret_cast<const void*>(kernel), dim3(blocks), dim3(kBlock), args, 0, s));
+  else
+    PR_HIP(hipExtLaunchKernel(reinterpret_cast<const void*>(kernel), dim3(blocks), dim3(kBlock), args, 0, s, e0, e1, 0));
   return PR_OK;
 }
 

@@ -99,6 +99,8 @@ class _Slot:
         self.status = torch.zeros(1, dtype=torch.int32, device="cuda")
         self.status_h = torch.zeros(1, dtype=torch.int32, pin_memory=True)
         self.total = torch.zeros(1, dtype=torch.int64, device="cuda")
+        self.stats = torch.zeros(len(pa.STATS_FIELDS), dtype=torch.int64, device="cuda")
+        self.graphs = {}        # batch size -> captured HIP graph of the batch's device work
         # query boxes of a batch: filled on the host, one asynchronous copy
         self.boxes_h = torch.zeros((max_req, 6), dtype=torch.float32, pin_memory=True)
         self.boxes = torch.empty((max_req, 6), dtype=torch.float32, device="cuda")
@@ -121,7 +123,7 @@ class JoinServer:
     """Continuous-batching server over two resident MeshBlobs (see module doc)."""
 
     def __init__(self, R, S, max_req_per_batch: int = 32, max_pairs: int = 5000, slots: int = 3,
-                 hbm_budget: int = 1 << 30, cfg=None):
+                 hbm_budget: int = 1 << 30, cfg=None, graphs: bool = True):
         import torch
         import paper_2609_24513_amd as pa
         self.torch, self.pa = torch, pa
@@ -146,42 +148,83 @@ class JoinServer:
         self.max_in_flight = 0
         self.oversized = 0      # requests beyond max_pairs, answered on their own
         self._t0 = None
+        self.graphs = graphs and self._capture()
 
     # --- phases ------------------------------------------------------------
-    def _start(self, slot: _Slot, reqs: List[Request]):
-        """Enqueues the whole batch on the slot's stream with no host round
-        trip: one filter per query into its region, the regions concatenated
-        on the device (gather_pair_regions), one refinement of the
-        concatenation with the device count, then the counts and status
-        copied back."""
+    def _enqueue(self, slot: _Slot, n: int):
+        """The device work of a batch of n requests whose query boxes are in
+        slot.boxes_h[:n], on the slot's stream with no host round trip: the
+        boxes copied in, one filter per query into its region, the regions
+        concatenated on the device (gather_pair_regions), one refinement of
+        the concatenation with the device count, then the counts, status,
+        pairs and flags copied back to pinned host buffers.  Every buffer
+        is the slot's own, so the same work can be captured once per batch
+        size and replayed."""
         torch, pa, lib = self.torch, self.pa, _lib.load()
+        cap = slot.batch.shape[0]
+        with torch.cuda.stream(slot.stream):
+            sp = int(slot.stream.cuda_stream)
+            slot.boxes[:n].copy_(slot.boxes_h[:n], non_blocking=True)
+            for k in range(n):
+                _lib.check(lib.filter_aabb_pairs(
+                    self.R.ptr, self.R.n_meshes, self.S.ptr, self.S.n_meshes, slot.boxes.data_ptr() + 24 * k,
+                    slot.region.data_ptr() + k * self.max_pairs * 8, self.max_pairs,
+                    slot.counts.data_ptr() + 8 * k, slot.fws.data_ptr(), slot.fws.numel(), sp))
+            _lib.check(lib.gather_pair_regions(slot.region.data_ptr(), self.max_pairs, slot.counts.data_ptr(),
+                                               n, slot.batch.data_ptr(), cap, slot.total.data_ptr(), sp))
+            cfg = copy.copy(self.cfg)
+            cfg.n_dev = slot.total
+            pa.refine(self.R, self.S, slot.batch, cfg, ws=slot.rws, flags=slot.flags, stats=slot.stats,
+                      status=slot.status, stream=slot.stream)
+            slot.counts_h[:n].copy_(slot.counts[:n], non_blocking=True)
+            slot.status_h.copy_(slot.status, non_blocking=True)
+            # every request holds at most max_pairs candidates in the batch
+            m = n * self.max_pairs
+            slot.batch_h[:m].copy_(slot.batch[:m], non_blocking=True)
+            slot.flags_h[:m].copy_(slot.flags[:m], non_blocking=True)
+
+    def _capture(self) -> bool:
+        """Captures each slot's batch work for every batch size (HIP graphs:
+        one launch per batch instead of one per kernel and copy).  A batch of
+        each slot runs eagerly first, so that the library's per-device
+        queries are cached outside the capture.  Returns False (eager
+        batches) if the runtime refuses a capture."""
+        torch = self.torch
+        for slot in self.slots:
+            slot.boxes_h[0] = 3e38  # a point far outside every mesh box: no candidates
+            self._enqueue(slot, 1)
+        torch.cuda.synchronize()
+        try:
+            for slot in self.slots:
+                for n in range(1, self.max_req + 1):
+                    g = torch.cuda.CUDAGraph()
+                    with torch.cuda.graph(g, stream=slot.stream, capture_error_mode="thread_local"):
+                        self._enqueue(slot, n)
+                    slot.graphs[n] = g
+        except RuntimeError:
+            torch.cuda.synchronize()
+            for slot in self.slots:
+                slot.graphs = {}
+            return False
+        torch.cuda.synchronize()
+        return True
+
+    def _start(self, slot: _Slot, reqs: List[Request]):
+        """Enqueues the whole batch on the slot's stream: its captured graph
+        (or the same work eagerly), then the completion event."""
+        torch = self.torch
         slot.reqs = reqs
         slot.phase = 1
         # the slot is free, so its previous box copy has completed
         bh = slot.boxes_h.numpy()
         for k, r in enumerate(reqs):
             bh[k] = r.box
-        cap = slot.batch.shape[0]
+        n = len(reqs)
         with torch.cuda.stream(slot.stream):
-            sp = int(slot.stream.cuda_stream)
-            slot.boxes[:len(reqs)].copy_(slot.boxes_h[:len(reqs)], non_blocking=True)
-            for k, r in enumerate(reqs):
-                _lib.check(lib.filter_aabb_pairs(
-                    self.R.ptr, self.R.n_meshes, self.S.ptr, self.S.n_meshes, slot.boxes.data_ptr() + 24 * k,
-                    slot.region.data_ptr() + k * self.max_pairs * 8, self.max_pairs,
-                    slot.counts.data_ptr() + 8 * k, slot.fws.data_ptr(), slot.fws.numel(), sp))
-            _lib.check(lib.gather_pair_regions(slot.region.data_ptr(), self.max_pairs, slot.counts.data_ptr(),
-                                               len(reqs), slot.batch.data_ptr(), cap, slot.total.data_ptr(), sp))
-            cfg = copy.copy(self.cfg)
-            cfg.n_dev = slot.total
-            pa.refine(self.R, self.S, slot.batch, cfg, ws=slot.rws, flags=slot.flags, status=slot.status,
-                      stream=slot.stream)
-            slot.counts_h[:len(reqs)].copy_(slot.counts[:len(reqs)], non_blocking=True)
-            slot.status_h.copy_(slot.status, non_blocking=True)
-            # every request holds at most max_pairs candidates in the batch
-            m = len(reqs) * self.max_pairs
-            slot.batch_h[:m].copy_(slot.batch[:m], non_blocking=True)
-            slot.flags_h[:m].copy_(slot.flags[:m], non_blocking=True)
+            if self.graphs:
+                slot.graphs[n].replay()
+            else:
+                self._enqueue(slot, n)
             slot.event = torch.cuda.Event()
             slot.event.record(slot.stream)
 

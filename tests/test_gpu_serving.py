@@ -116,6 +116,27 @@ def test_oversized_request_not_truncated(pool):
     _check_against_oracle(R, S, out)
 
 
+def test_graph_batches_match_eager(pool):
+    """Batches replayed from the captured graphs (several replays of each
+    batch size, with the loop's own host work and synchronisations between
+    them) against the same trace served eagerly, request by request, and
+    against the oracle."""
+    from paper_2609_24513_amd import serve
+    R, S, gr, gs = pool
+    trace = serve.make_trace(R.aabbs(), S.aabbs(), 40, lam=2000.0, seed=15, k_hi=800.0, space=29.0)
+    g = serve.JoinServer(gr, gs, max_req_per_batch=4, slots=2)
+    assert g.graphs and all(len(s.graphs) == 4 for s in g.slots)
+    a = g.run([serve.Request(r.rid, r.t_arrival, r.box) for r in trace], realtime=False)
+    assert g.batches >= 10
+    e = serve.JoinServer(gr, gs, max_req_per_batch=4, slots=2, graphs=False)
+    assert not e.graphs
+    b = e.run([serve.Request(r.rid, r.t_arrival, r.box) for r in trace], realtime=False)
+    for x, y in zip(a, b):
+        assert x.rid == y.rid
+        assert np.array_equal(x.pairs, y.pairs) and np.array_equal(x.flags, y.flags), x.rid
+    _check_against_oracle(R, S, a)
+
+
 def test_plain_path_same_results(pool):
     from paper_2609_24513_amd import serve
     R, S, gr, gs = pool
