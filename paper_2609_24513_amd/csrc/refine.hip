@@ -971,9 +971,12 @@ __device__ __forceinline__ bool blobs_ok(const BlobView& A, const BlobView& B, c
 
 // ---- setup --------------------------------------------------------------------
 
+// Pair states are cleared for the pairs processed only (every kernel bounds
+// its pairs by the device count).
 __global__ void k_init(RefineArgs ra) {
   int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  for (int64_t p = i; p < ra.n_pairs; p += (int64_t)gridDim.x * blockDim.x) ra.state[p] = 0u;
+  const int64_t np = npairs(ra);
+  for (int64_t p = i; p < np; p += (int64_t)gridDim.x * blockDim.x) ra.state[p] = 0u;
   if (i < kStatCopies * S_N) ra.stats[kCtrStride * (i / S_N) + i % S_N] = 0ull;
   if (i < kSlices) {
     ra.ctr[kCtrStride * i] = 0ull;
@@ -1932,8 +1935,9 @@ int refine_run(const void* blob_a, int64_t n_meshes_a, const void* blob_b, int64
   ra.share = params->trace_budget == 0 && budget == 0 ? 1 : 0;
   ra.lds_stack = params->lds_stack;
   ra.seg_table = seg_table_of(params);
-  hipLaunchKernelGGL(k_init, dim3(grid_for(n_pairs > kStatCopies * S_N ? n_pairs : kStatCopies * S_N, kBlock)),
-                     dim3(kBlock), 0, s, ra);
+  const int64_t init_items = n_pairs > kStatCopies * S_N ? n_pairs : kStatCopies * S_N;
+  const int64_t init_blocks = grid_for(init_items, kBlock);
+  hipLaunchKernelGGL(k_init, dim3((unsigned)(init_blocks < 1024 ? init_blocks : 1024)), dim3(kBlock), 0, s, ra);
   if (n_pairs > 0) {
     const int W = params->bvh_width, PREC = params->precision;
 #define PR_LAUNCH(w, q) if (W == w && PREC == q) r = launch<w, q>(ra, params, s)
