@@ -90,63 +90,69 @@ __global__ void k_boxes_all(const void* blob_a, int64_t MA, int32_t* ids_a, floa
   }
 }
 
-// With a query box: ordered compaction of the meshes that meet it, one
-// dataset per block (block 0: A, block 1: B), for datasets of at most
-// kSmallScan meshes.  Thread t takes meshes t, t + kScanBlock, ... (one
-// coalesced load per wave and tile, issued ahead of their use) and keeps
-// one bit per tile; the waves' counts per tile go to LDS, one block scan
-// over them (tile-major, one entry per thread) gives every kept mesh its
-// position in index order, and the kept meshes' boxes are read again and
-// written with their ids; the count goes to cnt.
+// With a query box: ordered compaction of the meshes that meet it, for
+// datasets of at most kSmallScan meshes, in two launches.  k_keep_bits tests
+// every mesh of both datasets, one per thread on as many blocks as there are
+// tiles of kScanBlock meshes, and stores each wave's ballot (bit l of entry
+// tile * kKeepWaves + wave: mesh tile * kScanBlock + wave * 64 + l).
+// k_keep_small, one block per dataset (block 0: A, block 1: B), scans the
+// entries' counts (one entry per thread) and writes the kept meshes' ids and
+// boxes in index order; the count goes to cnt.
 constexpr int kKeepWaves = kScanBlock / 64;
-static_assert(kSmallScan / kScanBlock * kKeepWaves == kScanBlock, "one (tile, wave) count per thread");
-static_assert(kSmallScan / kScanBlock <= 64, "one keep bit per tile");
+constexpr int kKeepEntries = (int)(kSmallScan / 64);  // ballot words of a dataset
+static_assert(kKeepEntries == kScanBlock, "one ballot word per thread of the scan block");
 
-__global__ __launch_bounds__(kScanBlock) void k_keep_small(const void* blob_a, int64_t MA, int32_t* ids_a,
-                                                           float* box_a, int32_t* cnt_a, const void* blob_b,
-                                                           int64_t MB, int32_t* ids_b, float* box_b, int32_t* cnt_b,
-                                                           const float* query) {
-  __shared__ int32_t s_cnt[kScanBlock];  // (tile, wave) counts, then their offsets
+__global__ __launch_bounds__(kScanBlock) void k_keep_bits(const void* blob_a, int64_t MA, const void* blob_b,
+                                                          int64_t MB, const float* query, uint64_t* bits_a,
+                                                          uint64_t* bits_b) {
+  const int64_t tiles_a = (MA + kScanBlock - 1) / kScanBlock;
+  const bool first = (int64_t)blockIdx.x < tiles_a;
+  const int64_t tile = first ? (int64_t)blockIdx.x : (int64_t)blockIdx.x - tiles_a;
+  const MeshDesc* md = meshes_of(first ? blob_a : blob_b);
+  const int64_t M = first ? MA : MB;
+  const int64_t m = tile * kScanBlock + threadIdx.x;
+  bool ok = false;
+  if (m < M) {
+    const float4* p4 = reinterpret_cast<const float4*>(md + m);
+    const float4 u = p4[0], v = p4[1], w = p4[2];  // box, node base/count, tri base/count
+    const float b[6] = {u.x, u.y, u.z, u.w, v.x, v.y};
+    float q[6];
+#pragma unroll
+    for (int c = 0; c < 6; ++c) q[c] = query[c];
+    ok = __float_as_int(w.y) > 0 && meet(b, q);
+  }
+  const uint64_t bm = __ballot(ok);
+  if ((threadIdx.x & 63) == 0) (first ? bits_a : bits_b)[tile * kKeepWaves + (threadIdx.x >> 6)] = bm;
+}
+
+__global__ __launch_bounds__(kScanBlock) void k_keep_small(const void* blob_a, int64_t MA, const uint64_t* bits_a,
+                                                           int32_t* ids_a, float* box_a, int32_t* cnt_a,
+                                                           const void* blob_b, int64_t MB, const uint64_t* bits_b,
+                                                           int32_t* ids_b, float* box_b, int32_t* cnt_b) {
+  __shared__ uint64_t s_bits[kScanBlock];
+  __shared__ int32_t s_off[kScanBlock];
   __shared__ int32_t s_scan[kKeepWaves];
   const bool first = blockIdx.x == 0;
   const MeshDesc* md = meshes_of(first ? blob_a : blob_b);
   const int64_t M = first ? MA : MB;
+  const uint64_t* bits = first ? bits_a : bits_b;
   int32_t* ids = first ? ids_a : ids_b;
   float* boxes = first ? box_a : box_b;
   const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
-  float q[6];
-#pragma unroll
-  for (int c = 0; c < 6; ++c) q[c] = query[c];
   const int ntiles = (int)((M + kScanBlock - 1) / kScanBlock);  // at most 64 (M <= kSmallScan)
-  uint64_t bits = 0;
+  const uint64_t word = t < ntiles * kKeepWaves ? bits[t] : 0ull;
+  s_bits[t] = word;
+  int32_t total = 0;
+  const int32_t off = block_exclusive_sum<kScanBlock>((int32_t)__popcll(word), s_scan, total);
+  s_off[t] = off;
+  __syncthreads();
 #pragma unroll 4
   for (int k = 0; k < ntiles; ++k) {
-    const int64_t m = (int64_t)k * kScanBlock + t;
-    bool ok = false;
-    if (m < M) {
-      const float4* p4 = reinterpret_cast<const float4*>(md + m);
-      const float4 u = p4[0], v = p4[1], w = p4[2];  // box, node base/count, tri base/count
-      const float b[6] = {u.x, u.y, u.z, u.w, v.x, v.y};
-      ok = __float_as_int(w.y) > 0 && meet(b, q);
-    }
-    bits |= (ok ? 1ull : 0ull) << k;
-    const uint64_t bm = __ballot(ok);
-    if (lane == 0) s_cnt[k * kKeepWaves + wv] = __popcll(bm);
-  }
-  __syncthreads();
-  const bool entry = t < ntiles * kKeepWaves;
-  int32_t total = 0;
-  const int32_t off = block_exclusive_sum<kScanBlock>(entry ? s_cnt[t] : 0, s_scan, total);
-  if (entry) s_cnt[t] = off;  // each thread rewrites only its own entry
-  __syncthreads();
-  for (int k = 0; k < ntiles; ++k) {
-    const bool ok = (bits >> k) & 1ull;
-    const uint64_t bm = __ballot(ok);
-    if (ok) {
+    const int e = k * kKeepWaves + wv;
+    const uint64_t wd = s_bits[e];
+    if ((wd >> lane) & 1ull) {
       const int64_t m = (int64_t)k * kScanBlock + t;
-      const int32_t pos = s_cnt[k * kKeepWaves + wv] +
-                          (int32_t)__builtin_amdgcn_mbcnt_hi((uint32_t)(bm >> 32),
-                                                             __builtin_amdgcn_mbcnt_lo((uint32_t)bm, 0u));
+      const int32_t pos = s_off[e] + (int32_t)__popcll(wd & ((1ull << lane) - 1ull));
       ids[pos] = (int32_t)m;
 #pragma unroll
       for (int c = 0; c < 6; ++c) boxes[6 * (int64_t)pos + c] = md[m].box[c];
@@ -572,6 +578,7 @@ struct FilterWs {
   int64_t *rowcnt, *rowoff;
   int32_t *blocksum, *paircnt;
   int64_t* tsum;  // tile sums of the device-wide scans
+  uint64_t *keep_a, *keep_b;  // query-box ballots of the single-block keep path
 };
 
 int carve_filter(Carve& cv, FilterWs& w, int64_t MA, int64_t MB) {
@@ -590,7 +597,21 @@ int carve_filter(Carve& cv, FilterWs& w, int64_t MA, int64_t MB) {
   w.paircnt = cv.take<int32_t>((fast_rows + kRT - 1) / kRT * kPairBlock);
   const int64_t mx = MA > MB ? MA : MB;
   w.tsum = cv.take<int64_t>(scan_tiles_of(mx + 1));
+  w.keep_a = cv.take<uint64_t>(kKeepEntries);
+  w.keep_b = cv.take<uint64_t>(kKeepEntries);
   return PR_OK;
+}
+
+// The meshes of both datasets (each of at most kSmallScan) that meet the
+// query box: ids, boxes and counts in the filter workspace.
+void launch_keep_small(hipStream_t s, const void* blob_a, int64_t MA, const void* blob_b, int64_t MB,
+                       const float* query, const FilterWs& w) {
+  const int64_t tiles = (MA + kScanBlock - 1) / kScanBlock + (MB + kScanBlock - 1) / kScanBlock;
+  if (tiles > 0)
+    hipLaunchKernelGGL(k_keep_bits, dim3((unsigned)tiles), dim3(kScanBlock), 0, s, blob_a, MA, blob_b, MB, query,
+                       w.keep_a, w.keep_b);
+  hipLaunchKernelGGL(k_keep_small, dim3(2), dim3(kScanBlock), 0, s, blob_a, MA, (const uint64_t*)w.keep_a, w.ids_a,
+                     w.box_a, w.pos_a + MA, blob_b, MB, (const uint64_t*)w.keep_b, w.ids_b, w.box_b, w.pos_b + MB);
 }
 
 struct CompactWs {
@@ -649,8 +670,7 @@ extern "C" int filter_aabb_pairs(const void* blob_a, int64_t n_meshes_a, const v
       hipLaunchKernelGGL((k_pairs<false, false>), dim3(grid), dim3(kPairBlock), 0, s, pa);
       hipLaunchKernelGGL((k_pairs<false, true>), dim3(grid), dim3(kPairBlock), 0, s, pa);
     } else {
-      hipLaunchKernelGGL(k_keep_small, dim3(2), dim3(kScanBlock), 0, s, blob_a, MA, w.ids_a, w.box_a, w.pos_a + MA,
-                         blob_b, MB, w.ids_b, w.box_b, w.pos_b + MB, query_box);
+      launch_keep_small(s, blob_a, MA, blob_b, MB, query_box, w);
       pa.box_a = w.box_a;
       pa.box_b = w.box_b;
       pa.ids_a = w.ids_a;
@@ -667,8 +687,7 @@ extern "C" int filter_aabb_pairs(const void* blob_a, int64_t n_meshes_a, const v
     hipLaunchKernelGGL(k_boxes_all, dim3(grid_for(MA + MB, kBlock)), dim3(kBlock), 0, s, blob_a, MA, w.ids_a,
                        w.box_a, w.pos_a + MA, blob_b, MB, w.ids_b, w.box_b, w.pos_b + MB);
   } else if (MA <= kSmallScan && MB <= kSmallScan) {
-    hipLaunchKernelGGL(k_keep_small, dim3(2), dim3(kScanBlock), 0, s, blob_a, MA, w.ids_a, w.box_a, w.pos_a + MA,
-                       blob_b, MB, w.ids_b, w.box_b, w.pos_b + MB, query_box);
+    launch_keep_small(s, blob_a, MA, blob_b, MB, query_box, w);
   } else {
     hipLaunchKernelGGL(k_keep, dim3(grid_for(MA + 1, kBlock)), dim3(kBlock), 0, s, blob_a, MA, query_box, w.flag_a);
     hipLaunchKernelGGL(k_keep, dim3(grid_for(MB + 1, kBlock)), dim3(kBlock), 0, s, blob_b, MB, query_box, w.flag_b);
