@@ -174,8 +174,10 @@ class JoinServer:
                                                n, slot.batch.data_ptr(), cap, slot.total.data_ptr(), sp))
             cfg = copy.copy(self.cfg)
             cfg.n_dev = slot.total
-            pa.refine(self.R, self.S, slot.batch, cfg, ws=slot.rws, flags=slot.flags, stats=slot.stats,
-                      status=slot.status, stream=slot.stream)
+            # a batch of n requests holds at most n * max_pairs pairs: the
+            # launch is sized for that many (small batches skip the cull order)
+            pa.refine(self.R, self.S, slot.batch[:n * self.max_pairs], cfg, ws=slot.rws, flags=slot.flags,
+                      stats=slot.stats, status=slot.status, stream=slot.stream)
             slot.counts_h[:n].copy_(slot.counts[:n], non_blocking=True)
             slot.status_h.copy_(slot.status, non_blocking=True)
             # every request holds at most max_pairs candidates in the batch
