@@ -306,9 +306,11 @@ class JoinServer:
                     busy = sum(1 for s in self.slots if s.phase)
                     self.max_in_flight = max(self.max_in_flight, busy)
             if not progressed:
-                # spin while a batch is on the device (its completion is
-                # picked up at once); sleep only while waiting for arrivals
-                time.sleep(0 if any(s.phase for s in self.slots) else 0.0001)
+                # the loop spins (yielding the interpreter lock each turn), so
+                # that arrivals and completions are picked up at once: a timed
+                # sleep would add its length and the timer slack to the
+                # latency of a request arriving meanwhile
+                time.sleep(0)
         return list(trace)
 
     def query_alone(self, box: np.ndarray):
