@@ -20,7 +20,9 @@ runs without blocking the host:
     the regions are concatenated on the device with the counts left there
     (gather_pair_regions), and the concatenation is refined in ONE persistent
     launch that reads the count on the device: the whole batch is enqueued at
-    once, with no host round trip;
+    once, with no host round trip; this work is captured once per slot and
+    batch size as a HIP graph when the server starts, so a batch is one
+    graph launch;
   * the counts, the status and the batch's pairs and flags (up to
     max_pairs per admitted request, an upper bound of the batch size) go
     back to pinned host buffers by asynchronous copies enqueued behind the
@@ -29,7 +31,8 @@ runs without blocking the host:
     then, and its latency is completion time minus arrival time.
 
 Batches on different slots overlap on the device, and new requests are
-admitted while earlier ones are still running.  The per-request plain path
+admitted while earlier ones are still running.  The loop never sleeps: it
+spins on arrivals and completions.  The per-request plain path
 (`run_plain`) serves the same trace first-in first-out, one request at a
 time, with one refinement launch per candidate pair.
 """
