@@ -241,6 +241,35 @@ def test_compact_matches_numpy(env, n):
     assert np.array_equal(got, pairs[flags == 1])
 
 
+@pytest.mark.parametrize("n", [5_000, 65_536, 100_003])
+def test_compact_device_count_and_capacity(env, n):
+    """Compaction through the C ABI with a device pair count below n and an
+    output capacity below the flagged count: the first cap flagged pairs
+    (in input order) are written and the exact count is reported."""
+    import ctypes
+    from paper_2609_24513_amd import _lib
+    torch, pa, synth, oracle = env
+    rng = np.random.default_rng(n + 1)
+    pairs = rng.integers(0, 1 << 20, size=(n, 2)).astype(np.int32)
+    flags = (rng.random(n) < 0.4).astype(np.uint8)
+    live = n - n // 7
+    want = pairs[:live][flags[:live] == 1]
+    cap = want.shape[0] // 2
+    lib = _lib.load()
+    wb = ctypes.c_size_t(0)
+    _lib.check(lib.compact_pairs_ws_bytes(n, ctypes.byref(wb)))
+    ws = torch.empty(max(256, wb.value), dtype=torch.uint8, device="cuda")
+    p_d, f_d = torch.as_tensor(pairs).cuda(), torch.as_tensor(flags).cuda()
+    nd = torch.tensor([live], dtype=torch.int64, device="cuda")
+    out = torch.full((cap, 2), -1, dtype=torch.int32, device="cuda")
+    cnt = torch.zeros(1, dtype=torch.int64, device="cuda")
+    _lib.check(lib.compact_pairs(p_d.data_ptr(), f_d.data_ptr(), n, nd.data_ptr(), out.data_ptr(), cap,
+                                 cnt.data_ptr(), ws.data_ptr(), ws.numel(), torch.cuda.current_stream().cuda_stream))
+    torch.cuda.synchronize()
+    assert int(cnt.item()) == want.shape[0]
+    assert np.array_equal(out.cpu().numpy(), want[:cap])
+
+
 def test_filter_query_box_and_capacity(env):
     torch, pa, synth, oracle = env
     A, B = synth.make_c1(seed=4, n=40)
