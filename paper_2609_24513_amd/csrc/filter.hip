@@ -96,8 +96,8 @@ __global__ void k_boxes_all(const void* blob_a, int64_t MA, int32_t* ids_a, floa
 // tiles of kScanBlock meshes, and stores each wave's ballot (bit l of entry
 // tile * kKeepWaves + wave: mesh tile * kScanBlock + wave * 64 + l).
 // k_keep_small, one block per dataset (block 0: A, block 1: B), scans the
-// entries' counts (one entry per thread) and writes the kept meshes' ids and
-// boxes in index order; the count goes to cnt.
+// entries' counts (one entry per thread) and each thread writes the kept
+// meshes of its entry, ids and boxes, in index order; the count goes to cnt.
 constexpr int kKeepWaves = kScanBlock / 64;
 constexpr int kKeepEntries = (int)(kSmallScan / 64);  // ballot words of a dataset
 static_assert(kKeepEntries == kScanBlock, "one ballot word per thread of the scan block");
@@ -129,8 +129,6 @@ __global__ __launch_bounds__(kScanBlock) void k_keep_small(const void* blob_a, i
                                                            int32_t* ids_a, float* box_a, int32_t* cnt_a,
                                                            const void* blob_b, int64_t MB, const uint64_t* bits_b,
                                                            int32_t* ids_b, float* box_b, int32_t* cnt_b) {
-  __shared__ uint64_t s_bits[kScanBlock];
-  __shared__ int32_t s_off[kScanBlock];
   __shared__ int32_t s_scan[kKeepWaves];
   const bool first = blockIdx.x == 0;
   const MeshDesc* md = meshes_of(first ? blob_a : blob_b);
@@ -138,25 +136,19 @@ __global__ __launch_bounds__(kScanBlock) void k_keep_small(const void* blob_a, i
   const uint64_t* bits = first ? bits_a : bits_b;
   int32_t* ids = first ? ids_a : ids_b;
   float* boxes = first ? box_a : box_b;
-  const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
+  const int t = threadIdx.x;
   const int ntiles = (int)((M + kScanBlock - 1) / kScanBlock);  // at most 64 (M <= kSmallScan)
-  const uint64_t word = t < ntiles * kKeepWaves ? bits[t] : 0ull;
-  s_bits[t] = word;
+  // entry t covers meshes 64 t ... 64 t + 63 (tile t / kKeepWaves, wave
+  // t % kKeepWaves), so the entries' order is the meshes' order
+  uint64_t word = t < ntiles * kKeepWaves ? bits[t] : 0ull;
   int32_t total = 0;
-  const int32_t off = block_exclusive_sum<kScanBlock>((int32_t)__popcll(word), s_scan, total);
-  s_off[t] = off;
-  __syncthreads();
-#pragma unroll 4
-  for (int k = 0; k < ntiles; ++k) {
-    const int e = k * kKeepWaves + wv;
-    const uint64_t wd = s_bits[e];
-    if ((wd >> lane) & 1ull) {
-      const int64_t m = (int64_t)k * kScanBlock + t;
-      const int32_t pos = s_off[e] + (int32_t)__popcll(wd & ((1ull << lane) - 1ull));
-      ids[pos] = (int32_t)m;
+  int32_t pos = block_exclusive_sum<kScanBlock>((int32_t)__popcll(word), s_scan, total);
+  for (; word; word &= word - 1) {
+    const int64_t m = 64 * (int64_t)t + __builtin_ctzll(word);
+    ids[pos] = (int32_t)m;
 #pragma unroll
-      for (int c = 0; c < 6; ++c) boxes[6 * (int64_t)pos + c] = md[m].box[c];
-    }
+    for (int c = 0; c < 6; ++c) boxes[6 * (int64_t)pos + c] = md[m].box[c];
+    ++pos;
   }
   if (t == 0) *(first ? cnt_a : cnt_b) = total;
 }
